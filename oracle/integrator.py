@@ -1,0 +1,108 @@
+"""Particle-mesh step and ray step, FP64 (test infrastructure only).
+
+One co-evolution step n follows Alg. 1 of the paper (reverse-time co-evolution)
+with the fused leapfrog described in ``oracle.tables``:
+
+1. paint the matter at boundary n onto the mesh and solve for grad(phi)   (pm_force)
+2. kick the matter with that force, then drift it to boundary n + 1       (matter_step)
+3. kick the rays over lens shell n at their current angle, then drift      (ray_step)
+
+Matter state: displacement s = x - q from the Lagrangian lattice point q and
+momentum p, both (P, 3) in (x, y, z) order, particle i = (iz * np + iy) * np + ix at
+q = (ix, iy, iz) * box / np.
+Ray state: angular displacement dth = theta - theta0 and momentum p, both (M, 2),
+ray i = iy * Mx + ix at pixel centre theta0 = ((ix + 1/2) - Mx/2, (iy + 1/2) - My/2) * mu.
+"""
+import numpy as np
+
+from . import mesh
+
+
+def lattice(n_p, box):
+    """Lagrangian lattice points q (P, 3) in particle index order."""
+    g = np.arange(n_p) * (box / n_p)
+    qz, qy, qx = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
+
+
+def pixel_angles(mx, my, fov_x, fov_y):
+    """Pixel-centre angles theta0 (M, 2) in ray index order."""
+    mux, muy = fov_x / mx, fov_y / my
+    tx = ((np.arange(mx) + 0.5) - mx / 2.0) * mux
+    ty = ((np.arange(my) + 0.5) - my / 2.0) * muy
+    gy, gx = np.meshgrid(ty, tx, indexing="ij")
+    return np.stack([gx.ravel(), gy.ravel()], axis=1)
+
+
+def density_contrast(pos, n, box):
+    """delta_w = rho_w / rho_bar_w - 1 of unit-weight CIC paint."""
+    rho = mesh.cic_paint(pos, n, box)
+    return rho / (len(pos) / n ** 3) - 1.0
+
+
+def pm_force(pos, n, box):
+    """Paint + Poisson gradient: returns (G_x, G_y, G_z) meshes and delta."""
+    delta = density_contrast(pos, n, box)
+    return mesh.poisson_gradient(delta, box), delta
+
+
+def matter_step(s, p, q, grads, K, D, box):
+    """Kick p += K g(q + s), then drift s += D p (one fused-leapfrog matter step)."""
+    x = q + s
+    g = np.stack([mesh.cic_readout(G, x, box) for G in grads], axis=1)
+    p = p + K * g
+    s = s + D * p
+    return s, p
+
+
+def ray_kick(dth, theta0, gx, gy, planes, observer_xy, box):
+    """Sum over the shell's planes of w_j * bilinear(G_perp on plane j)(X_obs + r_j theta)."""
+    n = gx.shape[0]
+    theta = theta0 + dth
+    dp = np.zeros_like(dth)
+    for j, chi_j, w in planes:
+        m = j % n
+        xy = np.asarray(observer_xy, float)[None, :] + chi_j * theta
+        dp[:, 0] += w * mesh.bilinear_readout(gx[m], xy, box)
+        dp[:, 1] += w * mesh.bilinear_readout(gy[m], xy, box)
+    return dp
+
+
+def ray_step(dth, p, theta0, gx, gy, planes, d, observer_xy, box):
+    """Kick over the lens shell at the current angle, then drift dth += d p."""
+    p = p + ray_kick(dth, theta0, gx, gy, planes, observer_xy, box)
+    dth = dth + d * p
+    return dth, p
+
+
+def ray_step_analytic(dth, p, theta0, grad_perp, planes, d, observer_xy):
+    """Same step with an analytic transverse gradient grad_perp(X, Y, chi) -> (gx, gy).
+
+    Used by pins that separate the integrator from the mesh."""
+    theta = theta0 + dth
+    dp = np.zeros_like(dth)
+    for j, chi_j, w in planes:
+        xy = np.asarray(observer_xy, float)[None, :] + chi_j * theta
+        gx, gy = grad_perp(xy[:, 0], xy[:, 1], chi_j)
+        dp[:, 0] += w * gx
+        dp[:, 1] += w * gy
+    p = p + dp
+    return dth + d * p, p
+
+
+def coevolve(s, p, q, dth, pr, theta0, tab, n, box, observer, steps=None,
+             matter=True, on_step=None):
+    """Run co-evolution steps (default 0..N-1) over the tables ``tab``.
+
+    ``on_step(n, s, p, dth, pr)`` is called after each step (e.g. to record kappa)."""
+    steps = range(tab.n_steps) if steps is None else steps
+    for k in steps:
+        grads, _ = pm_force(q + s, n, box)
+        if matter:
+            s, p = matter_step(s, p, q, grads, tab.K[k], tab.D[k], box)
+        if dth is not None:
+            dth, pr = ray_step(dth, pr, theta0, grads[0], grads[1], tab.planes[k], tab.d[k],
+                               observer[:2], box)
+        if on_step is not None:
+            on_step(k, s, p, dth, pr)
+    return s, p, dth, pr

@@ -1,0 +1,124 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds workload descriptions (sizes, cosmological parameters, schedules)
+and seeded random inputs only. It contains none of the method's arithmetic: no
+painting, no Poisson solve, no growth factors, no integrator. Both the oracle side
+and the GPU side receive what it produces as plain arrays.
+
+Workloads (sizes follow the paper's tests, Secs. 5.1-5.2, scaled to one GPU):
+
+* ``pointlens``: static point lens, M = 1e15 Msun/h at the centre of a 512 Mpc/h
+  periodic box, 128^3 mesh (float64), observer on the z = 0 face, lens at 256 Mpc/h,
+  sources at 512 Mpc/h, 64 x 64 rays over 10 x 10 degrees, 256 uniform steps in chi.
+* ``lcdm256``: one LambdaCDM realisation, 256^3 particles on a 256^3 float32 mesh,
+  box 400 Mpc/h replicated along the line of sight, 64 co-evolution steps uniform in a
+  from a = 1 to a = 0.5, 512^2 rays over 5 x 5 degrees.
+* ``adjoint128``: 128^3 particles and mesh, box 200 Mpc/h, 32 steps, 256^2 rays over
+  4 x 4 degrees.
+* ``large1024``: 512^3 particles on a 1024^3 mesh, box 1000 Mpc/h, 100 steps to
+  a = 1/3, 2048^2 rays over 10 x 10 degrees.
+* ``tiny``: small instances for the oracle-speed parity tests.
+"""
+import math
+
+import numpy as np
+
+DEG = math.pi / 180.0
+
+
+def uniform_a_schedule(a_start, a_end, n_steps):
+    """Scale factors a_0..a_N spaced uniformly (the paper steps a by a fixed Delta a)."""
+    return np.linspace(a_start, a_end, n_steps + 1)
+
+
+def uniform_chi_schedule(chi_end, n_steps):
+    return np.linspace(0.0, chi_end, n_steps + 1)
+
+
+def pointlens():
+    return dict(name="pointlens", mesh_n=128, box=512.0, ptcl_n=1, static=True,
+                mass=1e15, lens=(256.0, 256.0, 256.0), observer=(256.0, 256.0, 0.0),
+                chi_s=512.0, ray_n=64, fov=10.0 * DEG,
+                sched=uniform_chi_schedule(512.0, 256), dtype="f64")
+
+
+def lcdm(mesh_n=256, ptcl_n=256, box=400.0, ray_n=512, fov_deg=5.0, n_steps=64,
+         a_end=0.5, omega_m=0.3, sigma8=0.8, h=0.7, n_s=0.96, omega_b=0.045, seed=0,
+         name="lcdm256", dtype="f32"):
+    return dict(name=name, mesh_n=mesh_n, box=box, ptcl_n=ptcl_n, static=False,
+                observer=(0.5 * box, 0.5 * box, 0.0), ray_n=ray_n, fov=fov_deg * DEG,
+                omega_m=omega_m, sigma8=sigma8, h=h, n_s=n_s, omega_b=omega_b,
+                a_init=1.0 / 64.0, sched=uniform_a_schedule(1.0, a_end, n_steps),
+                fwd_sched=uniform_a_schedule(1.0 / 64.0, 1.0, n_steps), seed=seed, dtype=dtype)
+
+
+def lcdm256():
+    return lcdm()
+
+
+def adjoint128():
+    return lcdm(mesh_n=128, ptcl_n=128, box=200.0, ray_n=256, fov_deg=4.0, n_steps=32,
+                name="adjoint128")
+
+
+def large1024():
+    return lcdm(mesh_n=1024, ptcl_n=512, box=1000.0, ray_n=2048, fov_deg=10.0, n_steps=100,
+                a_end=1.0 / 3.0, name="large1024")
+
+
+def tiny(mesh_n=32, ptcl_n=32, box=50.0, ray_n=32, fov_deg=1.0, n_steps=8, seed=0):
+    return lcdm(mesh_n=mesh_n, ptcl_n=ptcl_n, box=box, ray_n=ray_n, fov_deg=fov_deg,
+                n_steps=n_steps, seed=seed, name=f"tiny{mesh_n}")
+
+
+def white_noise(seed, n):
+    """Unit white noise [z, y, x] (float64) from numpy's PCG64 stream."""
+    return np.random.default_rng(seed).standard_normal((n, n, n))
+
+
+def clustered_displacements(seed, ptcl_n, box, n_halos=None, sigma_field=None):
+    """Synthetic particle displacements s (P, 3) with halo-like clustering.
+
+    Recipe (a workload shape, not a physical model): every particle gets a smooth
+    random offset (sum of a few random Fourier modes, rms ``sigma_field`` Mpc/h);
+    then ``n_halos`` centres are drawn uniformly, each with a Lagrangian radius drawn
+    from a power law between 2 and 12 lattice spacings, and the particles of that
+    Lagrangian sphere are pulled to ``0.15 * r^1.5`` of their distance (normalised to
+    the radius), so a few per cent of the mesh cells hold tens to hundreds of particles
+    and most others are emptied, as in an evolved dark-matter field."""
+    rng = np.random.default_rng(seed)
+    spacing = box / ptcl_n
+    n_halos = max(4, ptcl_n ** 3 // 4096) if n_halos is None else n_halos
+    sigma_field = 3.0 * spacing if sigma_field is None else sigma_field
+    g = np.arange(ptcl_n) * spacing
+    qz, qy, qx = np.meshgrid(g, g, g, indexing="ij")
+    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
+    s = np.zeros_like(q)
+    for _ in range(6):
+        k = 2.0 * np.pi / box * rng.integers(1, 5, size=3) * rng.choice([-1, 1], size=3)
+        amp = rng.normal(size=3) * sigma_field / math.sqrt(6.0)
+        ph = rng.uniform(0, 2 * np.pi)
+        s += np.sin(q @ k + ph)[:, None] * amp[None, :]
+    centres = rng.uniform(0, box, size=(n_halos, 3))
+    radii = spacing * 2.0 * (6.0 ** rng.uniform(0, 1, size=n_halos))
+    for c, r in zip(centres, radii):
+        d = q - c
+        d -= box * np.round(d / box)
+        dist = np.linalg.norm(d, axis=1)
+        sel = dist < r
+        if not np.any(sel):
+            continue
+        x = dist[sel] / r
+        scale = 0.15 * np.sqrt(x)        # new distance = 0.15 r x^1.5
+        s[sel] += (scale - 1.0)[:, None] * d[sel]
+    return s
+
+
+def random_momenta(seed, n, rms):
+    return np.random.default_rng(seed + 7919).normal(scale=rms, size=(n, 3))
+
+
+def random_rays(seed, n_rays, dth_rms, p_rms):
+    """Ray state (dth, p), each (M, 2), with given rms values."""
+    rng = np.random.default_rng(seed + 104729)
+    return rng.normal(scale=dth_rms, size=(n_rays, 2)), rng.normal(scale=p_rms, size=(n_rays, 2))
