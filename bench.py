@@ -1,0 +1,209 @@
+"""Benchmark of the HRT hot path on one MI355X.
+
+Workload (lcdm256): one LambdaCDM realisation, 256^3 particles on a 256^3 float32 mesh,
+box 400 Mpc/h replicated along the line of sight, 512^2 rays over 5 x 5 degrees,
+64 co-evolution steps uniform in a from 1 to 0.5 (sources at z = 1, chi_s = 2312.7 Mpc/h).
+A step is one pm_step (paint, FFT Poisson solve, gradient, matter kick-drift) plus one
+ray_step (plane-sum kick over the lens shell, drift); the convergence map is taken
+at the source plane (every 64th step). Steps beyond 64 continue cyclically through the
+schedule from the current state.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints one JSON line. ``value`` is co-evolution ray-steps/s (rays x steps / wall time of
+the timed steps, inputs resident in HBM). Per-kernel times come from HIP events recorded
+on the library's stream around every launch inside the timed region.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(name, n, P, nrays):
+    """Compulsory HBM bytes of one launch of kernel `name` (each input read once,
+    each output written once)."""
+    n3 = n ** 3
+    spec = (n // 2 + 1) * n * n * 8          # complex64 half spectrum
+    nbins = n3 // 64
+    return {
+        "bin_count": 12 * P,                           # read s
+        "bin_scan": 12 * nbins,                        # read counts, write offsets + cursors
+        "bin_scatter": 12 * P + 16 * P,                # read s, write binned (fraction, cell)
+        "paint_tiles": 16 * P + 4 * n3,                # read binned particles, write delta
+        "fft_x_r2c": 4 * n3 + spec,
+        "fft_y_fwd": 2 * spec,
+        "fft_z_poisson": 2 * spec,
+        "fft_y_inv": 2 * spec,
+        "fft_x_c2r": spec + 4 * n3,
+        "fd4_gradient": 4 * n3 + 12 * n3,              # read phi, write (G_x, G_y), G_z
+        "matter_kd": 48 * P + 12 * n3,                 # read+write s, p; read G
+        "ray_step": 32 * nrays,                        # read+write dth, p
+        "convergence": 12 * nrays,                     # read dth, write kappa
+    }[name]
+
+
+def cpu_baseline():
+    """Oracle (FP64 NumPy) time for one co-evolution step on a bounded sample."""
+    import synth
+    from oracle import integrator, tables
+    cfg = synth.lcdm(mesh_n=128, ptcl_n=128, box=200.0, ray_n=256, fov_deg=5.0, n_steps=64,
+                     name="lcdm128-sample")
+    s = synth.clustered_displacements(0, 128, 200.0)
+    p = synth.random_momenta(0, len(s), 3.0)
+    q = integrator.lattice(128, 200.0)
+    tab = tables.build_cosmo(cfg["sched"], 0.3, 128, 200.0, 0.0)
+    th0 = integrator.pixel_angles(256, 256, cfg["fov"], cfg["fov"])
+    dth = np.zeros_like(th0)
+    pr = np.zeros_like(th0)
+    n = 20
+    t0 = time.perf_counter()
+    grads, _ = integrator.pm_force(q + s, 128, 200.0)
+    integrator.matter_step(s, p, q, grads, tab.K[n], tab.D[n], 200.0)
+    t1 = time.perf_counter()
+    integrator.ray_step(dth, pr, th0, grads[0], grads[1], tab.planes[n], tab.d[n],
+                        cfg["observer"][:2], 200.0)
+    t2 = time.perf_counter()
+    # scale to the 256^3 / 512^2 workload: PM work x 8 (particles and nodes), ray work x 4
+    # (rays; the plane count per shell depends only on the cell size, which is the same)
+    t_full = 8.0 * (t1 - t0) + 4.0 * (t2 - t1)
+    return {"value": 512 * 512 / t_full, "unit": "ray-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle co-evolution step at 128^3 particles/mesh, box 200 Mpc/h, "
+                       f"256^2 rays over 5 deg (same cell and field): PM {t1 - t0:.1f} s, "
+                       f"rays {t2 - t1:.2f} s; scaled x8 (PM) and x4 (rays) to the 256^3 / 512^2 "
+                       f"workload; numpy single-threaded"),
+            "pm_step_ms": 8.0 * (t1 - t0) * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
+              "one MI355X; multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2405_12913_amd import hrt
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    hrt.lib()                                   # fail loudly if the HIP library is missing
+
+    cfg = synth.lcdm256()
+    n, np_, box, nr = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
+    P, nrays = np_ ** 3, nr * nr
+    N = len(cfg["sched"]) - 1
+    print(f"[bench] generating {np_}^3 clustered particles", file=sys.stderr, flush=True)
+    s0 = synth.clustered_displacements(args.seed, np_, box).astype(np.float32)
+    p0 = synth.random_momenta(args.seed, P, 3.0).astype(np.float32)
+    dev = torch.device("cuda:0")
+    s_init = [torch.tensor(np.ascontiguousarray(s0[:, d]), device=dev) for d in range(3)]
+    p_init = [torch.tensor(np.ascontiguousarray(p0[:, d]), device=dev) for d in range(3)]
+    s = [t.clone() for t in s_init]
+    p = [t.clone() for t in p_init]
+    dth = [torch.zeros(nrays, device=dev) for _ in range(2)]
+    pr = [torch.zeros(nrays, device=dev) for _ in range(2)]
+    kappa = torch.empty(nrays, device=dev)
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=N, sched=cfg["sched"], ray_nx=nr,
+                         ray_ny=nr, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
+                         omega_m=cfg["omega_m"], dtype="f32", device="cuda:0")
+
+    def step(k):
+        m = k % N
+        sim.pm_step(s, p, m)
+        sim.ray_step(dth, pr, m)
+        if m == N - 1:
+            sim.ray_convergence(dth, kappa)
+
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    for a, b in zip(s + p, s_init + p_init):
+        a.copy_(b)
+    for t in dth + pr:
+        t.zero_()
+    torch.cuda.synchronize()
+
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    sim.profile_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(sim.stream)
+    for k in range(args.steps):
+        step(k)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    elapsed_ms = start.elapsed_time(stop)
+    prof = sim.profile_read()
+    sim.profile_enable(False)
+    assert torch.isfinite(dth[0]).all() and torch.isfinite(s[0]).all()
+
+    kernels = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_ms = ms / cnt
+        b = algorithmic_bytes(name, n, P, nrays)
+        kernels[name] = {"launches": cnt, "avg_ms": round(avg_ms, 5), "total_ms": round(ms, 3),
+                         "alg_bytes": b, "alg_GBps": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+    pm_names = ["bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
+                "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd"]
+    pm_ms = sum(prof[k][0] for k in pm_names) / args.steps
+    ray_ms = prof["ray_step"][0] / max(prof["ray_step"][1], 1)
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    dk = kernels[dom]
+    achieved = dk["alg_bytes"] / (dk["avg_ms"] * 1e-3) / 1e9
+
+    out = {
+        "metric": "ray-steps/s + PM step ms at 256^3 mesh, % HBM peak",
+        "value": nrays * args.steps / (elapsed_ms * 1e-3),
+        "unit": "ray-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded clustered particle displacements and momenta; rays start at "
+                "theta0 with zero momentum)",
+        "config": {"workload": "lcdm256: LambdaCDM PM + HRT, 256^3 particles on a 256^3 mesh, box "
+                               "400 Mpc/h replicated, 512^2 rays over 5x5 deg, 64 steps a=1->0.5",
+                   "mesh": n, "particles": P, "rays": nrays, "box": box, "schedule_steps": N},
+        "pm_step_ms": round(pm_ms, 4),
+        "ray_step_ms": round(ray_ms, 4),
+        "ray_kernel_ray_steps_per_s": nrays / (ray_ms * 1e-3),
+        "host_wall_s": round(wall, 4),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * hrt.h - C ABI of the MI355X (gfx950) Hamiltonian ray tracing hot path.
+ *
+ * One particle-mesh (PM) gravity step co-evolved with light rays, following
+ * Zhou et al., "A Hamiltonian, post-Born, three-dimensional, on-the-fly ray
+ * tracing algorithm for gravitational lensing" (arXiv:2405.12913):
+ *   pm_force        CIC paint + FFT Poisson solve + gradient   (Sec. 2 Poisson eq.; Sec. 4.1-4.2)
+ *   pm_step         pm_force + matter kick and drift           (Alg. 1, nbody_reverse_step)
+ *   ray_step        ray kick over one lens shell + ray drift   (Eqs. symp_1-3, kick, drift)
+ *   ray_convergence kappa (gamma1, gamma2, omega) from finite  (Eqs. A, obs_first_set,
+ *                   differences of the ray deflections          obs_second_set)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All device pointers are caller-owned. The library never allocates device memory:
+ *   its scratch (meshes, FFT buffers, sort bins, step tables) lives in one
+ *   caller-allocated workspace of hrt_workspace_bytes() bytes that must stay alive and
+ *   untouched until hrt_destroy().
+ * - Every GPU entry point only enqueues work on the stream given to hrt_init and
+ *   returns without synchronising the host. Calls on one context are not thread-safe
+ *   and must be issued in order; results are ready after the stream synchronises.
+ * - Return value: HRT_OK (0) or a negative hrt_status; hrt_last_error() gives a text.
+ *   Invalid arguments are reported before anything is enqueued.
+ * - Floating point type of every state array and output is the config's dtype
+ *   (HRT_F32 -> float, HRT_F64 -> double).
+ * - Mesh layout: n^3 nodes at x = i * box/n, row-major [z][y][x], the line of sight is
+ *   +z. Particle i = (iz*np + iy)*np + ix has Lagrangian position
+ *   q = (ix, iy, iz) * box/np; the state stores the displacement s = x - q and the
+ *   momentum p = a^2 dx/dt / H0 (Mpc/h). Ray i = iy*Mx + ix sits at the pixel centre
+ *   theta0 = ((ix + 1/2) - Mx/2, (iy + 1/2) - My/2) * fov/M (radians); the state stores
+ *   dth = theta - theta0 and the canonical momentum p with d theta/d chi = p / chi^2.
+ * - Determinism: no floating-point atomics anywhere; two runs give identical bits.
+ */
+#ifndef HRT_H
+#define HRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HRT_OK = 0,
+    HRT_EINVAL = -1,        /* invalid argument or configuration                    */
+    HRT_ENOMEM = -2,        /* workspace too small                                   */
+    HRT_EDEVICE = -3,       /* a HIP call or kernel launch failed                    */
+    HRT_ESTATE = -4,        /* call not valid in the context's state                 */
+    HRT_EUNSUPPORTED = -5   /* valid request this build does not implement           */
+} hrt_status;
+
+enum { HRT_F32 = 0, HRT_F64 = 1 };
+
+/* flags */
+enum {
+    HRT_STATIC = 1          /* static point-lens run: a = 1, sched holds chi_n, the mesh
+                               source is unit-weight particles of mass static_mass each */
+};
+
+typedef struct {
+    int32_t mesh_n;         /* n: power of two, 16 <= n <= 1024                         */
+    int32_t ptcl_n;         /* np particles per side, n % np == 0 (np = 1: one particle) */
+    int32_t ray_nx, ray_ny; /* Mx, My >= 3 (0 = no rays)                                */
+    int32_t n_steps;        /* N >= 1                                                    */
+    int32_t dtype;          /* HRT_F32 or HRT_F64                                        */
+    int32_t flags;          /* HRT_STATIC or 0                                           */
+    int32_t reserved;       /* must be 0                                                 */
+    double box;             /* periodic box side L [Mpc/h]                               */
+    double fov_x, fov_y;    /* field of view [rad]                                       */
+    double observer[3];     /* observer position in box coordinates [Mpc/h]              */
+    double omega_m;         /* matter density (flat LambdaCDM, no radiation)             */
+    double static_mass;     /* M [Msun/h] per particle when HRT_STATIC                   */
+    const double *sched;    /* N+1 host values: a_0..a_N (cosmological, any direction,
+                               0 < a <= 1) or chi_0..chi_N [Mpc/h] when HRT_STATIC;
+                               copied at hrt_init                                        */
+} hrt_config;
+
+typedef struct { void *s[3]; void *p[3]; } hrt_matter;   /* device SoA, np^3 each (x, y, z) */
+typedef struct { void *dth[2]; void *p[2]; } hrt_rays;   /* device SoA, Mx*My each (x, y)   */
+
+typedef struct hrt_ctx hrt_ctx;
+
+/* Bytes of device workspace needed for cfg. Pure host function. */
+int hrt_workspace_bytes(const hrt_config *cfg, size_t *bytes);
+
+/* Validates cfg, builds the FP64 step tables on the host and uploads them into the
+ * workspace (synchronously). stream is a hipStream_t (NULL = default stream).
+ * The context keeps no pointer to cfg or cfg->sched. */
+int hrt_init(const hrt_config *cfg, void *workspace, size_t ws_bytes, void *stream, hrt_ctx **out);
+
+/* Frees the host-side context (does not touch the caller's device memory). */
+int hrt_destroy(hrt_ctx *ctx);
+
+/* Text of the last error of ctx, or of the last failed hrt_init when ctx is NULL. */
+const char *hrt_last_error(const hrt_ctx *ctx);
+
+/* Paint the matter at boundary `step` (0 <= step <= N) onto the mesh, solve
+ * grad^2 phi = delta (delta = rho/rho_bar - 1, Sec. 2 Poisson equation without its
+ * prefactor, which the step tables carry) and store G = grad(phi) in the workspace.
+ * m->p may be NULL. */
+int pm_force(hrt_ctx *ctx, const hrt_matter *m, int step);
+
+/* pm_force, then the matter kick p += K_step * G(q + s) and drift s += D_step * p
+ * (fused leapfrog; step N is the closing half-kick with no drift). Not valid with
+ * HRT_STATIC (returns HRT_ESTATE). */
+int pm_step(hrt_ctx *ctx, const hrt_matter *m, int step);
+
+/* Kick the rays over lens shell `step` with the G left by the last pm_force/pm_step,
+ * evaluated at the current angles, then drift (step N: closing half-kick, no drift).
+ * Each shell plane j contributes w_j * bilinear(G_x, G_y on mesh plane j mod n) at
+ * X_obs + chi_j * theta. */
+int ray_step(hrt_ctx *ctx, const hrt_rays *r, int step);
+
+/* Finite-difference distortion matrix of the deflections over the pixel grid
+ * (central inside, second-order one-sided on the edges) and kappa, gamma1, gamma2,
+ * omega of Eq. obs_first_set. Outputs are device arrays of Mx*My values; any output
+ * except kappa may be NULL. */
+int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *kappa, void *gamma1,
+                    void *gamma2, void *omega);
+
+/* Device pointer to an internal mesh in the workspace, valid until hrt_destroy:
+ * HRT_MESH_DELTA (n^3, after pm_force: delta), HRT_MESH_PHI (n^3: phi),
+ * HRT_MESH_GXY (n^3 interleaved (G_x, G_y) pairs), HRT_MESH_GZ (n^3: G_z). */
+enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GXY = 2, HRT_MESH_GZ = 3 };
+int hrt_mesh_ptr(const hrt_ctx *ctx, int which, void **ptr);
+
+/* Host-only step tables for cfg (no GPU use), for checking the table builder.
+ * Sizes: a, chi, K, D, d: N+1 doubles each; plane_begin, plane_count: N+1 ints;
+ * plane_mesh (int), plane_chi, plane_w (double): up to max_planes entries.
+ * *n_planes receives the total number of shell-plane entries; HRT_ENOMEM if it
+ * exceeds max_planes (then only *n_planes is written). Any array may be NULL. */
+int hrt_tables(const hrt_config *cfg, double *a, double *chi, double *K, double *D,
+               double *d, int32_t *plane_begin, int32_t *plane_count, int32_t *plane_mesh,
+               double *plane_chi, double *plane_w, int32_t max_planes, int32_t *n_planes);
+
+/* Optional per-kernel timing with HIP events recorded on the context's stream around
+ * every kernel launch (for measurement; off by default). hrt_profile_enable(ctx, 1)
+ * clears the totals and starts recording, 0 stops. hrt_profile_read synchronises the
+ * stream and writes, for kernel ids 0..n-1, the summed milliseconds and launch counts.
+ * hrt_kernel_name(id) names kernel id (NULL past the last id, HRT_NUM_KERNELS). */
+enum { HRT_NUM_KERNELS = 13 };
+int hrt_profile_enable(hrt_ctx *ctx, int on);
+int hrt_profile_read(hrt_ctx *ctx, double *total_ms, int64_t *launches, int n);
+const char *hrt_kernel_name(int id);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRT_H */

@@ -1,0 +1,90 @@
+// Internal declarations of the HRT library (not part of the public ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/hrt.h"
+
+namespace hrt {
+
+// Per-step scalars and shell plane lists, all FP64 on the host (see tables.cpp).
+struct StepTables {
+    std::vector<double> a, chi, K, D, d;     // N+1 each
+    std::vector<int32_t> plane_begin, plane_count;   // N+1 each
+    std::vector<int32_t> plane_mesh;         // mesh plane index (j mod n) per entry
+    std::vector<double> plane_chi, plane_w;  // chi_j and weight w_j per entry
+};
+
+// Fills t for cfg; returns HRT_OK or an error with a message in err.
+int build_tables(const hrt_config &cfg, StepTables &t, std::string &err);
+int validate_config(const hrt_config &cfg, std::string &err);
+
+// Device-side plane entry (one per shell plane).
+struct PlaneEntry {
+    double chi;        // comoving distance of the plane [Mpc/h]
+    double w;          // kick weight
+    int32_t mesh;      // mesh plane index
+    int32_t pad;
+};
+
+// Workspace carve-up, identical in hrt_workspace_bytes and hrt_init.
+struct Layout {
+    size_t mesh_r, spec, gxy, gz, twiddle, bins, cursor, sorted, planes, total;
+    int64_t nbins;
+};
+Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
+
+}  // namespace hrt
+
+namespace hrt {
+// Kernel ids for the optional per-kernel HIP-event timing (hrt_profile_*).
+enum KernelId {
+    K_BIN_COUNT = 0, K_BIN_SCAN, K_BIN_SCATTER, K_PAINT, K_FFT_X_R2C, K_FFT_Y_FWD, K_FFT_Z_POISSON,
+    K_FFT_Y_INV, K_FFT_X_C2R, K_GRADIENT, K_MATTER_KD, K_RAY_STEP, K_CONVERGENCE, K_COUNT
+};
+struct ProfRecord {
+    int id;
+    hipEvent_t start, stop;
+};
+}  // namespace hrt
+
+struct hrt_ctx {
+    hrt_config cfg;
+    std::vector<double> sched;
+    hipStream_t stream = nullptr;
+    int n = 0, np = 0, mx = 0, my = 0, N = 0;
+    bool f64 = false, is_static = false;
+    double cell = 0, box = 0;
+    hrt::StepTables tab;
+    hrt::Layout lay;
+    char *ws = nullptr;
+    int fixed_bits = 0;          // paint fixed-point fraction bits
+    int force_step = -1;         // boundary of the G currently in the workspace
+    std::string err;
+    // per-kernel timing (off unless hrt_profile_enable)
+    bool prof = false;
+    std::vector<hrt::ProfRecord> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    hipEvent_t prof_open = nullptr;
+    double prof_ms[hrt::K_COUNT] = {};
+    int64_t prof_n[hrt::K_COUNT] = {};
+    ~hrt_ctx();
+};
+
+// Kernel launchers (defined in the .hip files). Each returns hipSuccess or the error.
+namespace hrt {
+void prof_begin(hrt_ctx *c);           // record a start event when profiling is on
+void prof_end(hrt_ctx *c, int id);     // record the stop event of kernel `id`
+hipError_t launch_paint(hrt_ctx *c, const hrt_matter *m);
+hipError_t launch_poisson(hrt_ctx *c);
+hipError_t launch_gradient(hrt_ctx *c);
+hipError_t launch_matter_kd(hrt_ctx *c, const hrt_matter *m, double K, double D);
+hipError_t launch_ray_step(hrt_ctx *c, const hrt_rays *r, int begin, int count, double d);
+hipError_t launch_convergence(hrt_ctx *c, const hrt_rays *r, void *kappa, void *g1, void *g2,
+                              void *om);
+}  // namespace hrt

@@ -1,0 +1,230 @@
+// Host FP64 step tables: background cosmology, matter kick/drift factors, ray drift
+// factors and the lens-shell plane lists with their kick weights.
+//
+// Paper passages: Poisson prefactor (3/2) Omega_m H0^2 / a (Sec. 2); flat universe,
+// r = chi (Sec. 2); KDK ray integrator with kick and drift operators (Sec. 3.1,
+// Eqs. symp_1-3, kick_notimecor, drift); growth correction of the potential inside a
+// shell (Sec. 3.2, Eq. kick); mesh points of the 3D mesh inside the lens shell
+// chi_a <= chi < chi_b carry the kick (Sec. 4.2).
+//
+// Readings (fused leapfrog, half points, shell membership) are stated next to each
+// function. Integrals use adaptive Gauss-Kronrod (7/15) on substituted integrands
+// a = t^2 that are smooth down to a = 0.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+
+#include "hrt_internal.h"
+
+namespace hrt {
+namespace {
+
+constexpr double kC = 299792.458;             // km/s
+constexpr double kCH0 = kC / 100.0;           // c/H0 [Mpc/h]
+constexpr double kG = 4.30091e-9;             // Mpc (km/s)^2 / Msun
+constexpr double kGoverC2 = kG / (kC * kC);   // Mpc/h per Msun/h
+constexpr double kPi = 3.14159265358979323846;
+
+// Gauss-Kronrod 15-point nodes and weights (the 7-point Gauss rule is embedded).
+const double kXgk[8] = {0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+                        0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+                        0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+                        0.207784955007898467600689403773245, 0.0};
+const double kWgk[8] = {0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+                        0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+                        0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+                        0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+const double kWg[4] = {0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+                       0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+double gk15(const std::function<double(double)> &f, double a, double b, double *err) {
+    double c = 0.5 * (a + b), h = 0.5 * (b - a);
+    double fc = f(c);
+    double rk = fc * kWgk[7], rg = fc * kWg[3];
+    for (int j = 0; j < 7; ++j) {
+        double x = h * kXgk[j];
+        double f1 = f(c - x), f2 = f(c + x);
+        rk += kWgk[j] * (f1 + f2);
+        if (j % 2 == 1) rg += kWg[j / 2] * (f1 + f2);
+    }
+    *err = std::fabs((rk - rg) * h);
+    return rk * h;
+}
+
+double integrate_rec(const std::function<double(double)> &f, double a, double b, double tol,
+                     int depth) {
+    double err;
+    double r = gk15(f, a, b, &err);
+    if (err <= tol || depth > 40) return r;
+    double m = 0.5 * (a + b);
+    return integrate_rec(f, a, m, 0.5 * tol, depth + 1) + integrate_rec(f, m, b, 0.5 * tol, depth + 1);
+}
+
+double integrate(const std::function<double(double)> &f, double a, double b) {
+    if (a == b) return 0.0;
+    double err;
+    double guess = std::fabs(gk15(f, a, b, &err));
+    double tol = std::max(guess, 1e-300) * 1e-15;
+    return integrate_rec(f, a, b, tol, 0);
+}
+
+struct Cosmo {
+    double om, ol;
+    double E(double a) const { return std::sqrt(om / (a * a * a) + ol); }
+    // int_{a0}^{a1} da / (a^2 E) with a = t^2:  2 dt / sqrt(om + ol t^6)
+    double kick(double a0, double a1) const {
+        return integrate([this](double t) { return 2.0 / std::sqrt(om + ol * std::pow(t, 6)); },
+                         std::sqrt(a0), std::sqrt(a1));
+    }
+    // int_{a0}^{a1} da / (a^3 E) with a = t^2:  2 dt / (t^2 sqrt(om + ol t^6))
+    double drift(double a0, double a1) const {
+        return integrate(
+            [this](double t) { return 2.0 / (t * t * std::sqrt(om + ol * std::pow(t, 6))); },
+            std::sqrt(a0), std::sqrt(a1));
+    }
+    double chi(double a) const { return kCH0 * kick(a, 1.0); }
+    // a(chi): Newton on chi(a) - chi (d chi/da = -c/H0 / (a^2 E)), safeguarded by bisection.
+    double a_of_chi(double x) const {
+        if (x == 0.0) return 1.0;
+        double lo = 1e-8, hi = 1.0, a = 0.5;
+        for (int it = 0; it < 200; ++it) {
+            double g = chi(a) - x;          // decreasing in a
+            if (g > 0) lo = a; else hi = a;
+            double an = a + g / (kCH0 / (a * a * E(a)));
+            if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+            if (std::fabs(an - a) <= 1e-16 * a) { a = an; break; }
+            a = an;
+        }
+        return a;
+    }
+    // D1(a) = (5 om / 2) E(a) int_0^a da'/(a' E)^3, with a' = t^2: 2 t^4 (om + ol t^6)^(-3/2)
+    double D1(double a) const {
+        double I = integrate([this](double t) {
+            double t2 = t * t;
+            return 2.0 * t2 * t2 / std::pow(om + ol * t2 * t2 * t2, 1.5);
+        }, 0.0, std::sqrt(a));
+        return 2.5 * om * E(a) * I;
+    }
+};
+
+// Planes j with lo <= j*cell - z_obs < hi (lo/hi sorted): shells are half-open in
+// absolute chi, so a schedule run backwards selects exactly the same planes.
+void shell_planes(double x0, double x1, double cell, double z_obs, std::vector<int64_t> &out) {
+    double a = std::min(x0, x1), b = std::max(x0, x1);
+    int64_t j0 = (int64_t)std::floor((a + z_obs) / cell) - 1;
+    int64_t j1 = (int64_t)std::ceil((b + z_obs) / cell) + 1;
+    out.clear();
+    for (int64_t j = j0; j <= j1; ++j) {
+        double c = (double)j * cell - z_obs;
+        if (a <= c && c < b) out.push_back(j);
+    }
+}
+
+}  // namespace
+
+int validate_config(const hrt_config &c, std::string &err) {
+    auto bad = [&](const char *m) { err = m; return HRT_EINVAL; };
+    if (c.mesh_n < 16 || c.mesh_n > 1024 || (c.mesh_n & (c.mesh_n - 1)))
+        return bad("mesh_n must be a power of two in [16, 1024]");
+    if (c.ptcl_n < 1 || c.mesh_n % c.ptcl_n) return bad("ptcl_n must be >= 1 and divide mesh_n");
+    if (!((c.ray_nx == 0 && c.ray_ny == 0) || (c.ray_nx >= 3 && c.ray_ny >= 3)))
+        return bad("ray_nx and ray_ny must both be 0 or both >= 3");
+    if ((int64_t)c.ray_nx * c.ray_ny > (int64_t)1 << 26) return bad("too many rays");
+    if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
+    if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
+    if (c.flags & ~HRT_STATIC) return bad("unknown flag");
+    if (c.reserved != 0) return bad("reserved must be 0");
+    if (!(c.box > 0) || !std::isfinite(c.box)) return bad("box must be positive");
+    if (c.ray_nx > 0 && (!(c.fov_x > 0) || !(c.fov_y > 0) || c.fov_x > 1.0 || c.fov_y > 1.0))
+        return bad("fov must be in (0, 1] rad");
+    if (!c.sched) return bad("sched is NULL");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(c.observer[i])) return bad("observer must be finite");
+    if (c.flags & HRT_STATIC) {
+        if (!(c.static_mass > 0)) return bad("static_mass must be positive");
+        for (int i = 0; i <= c.n_steps; ++i)
+            if (!(c.sched[i] >= 0) || !std::isfinite(c.sched[i])) return bad("chi schedule must be >= 0");
+    } else {
+        if (!(c.omega_m > 0 && c.omega_m <= 1)) return bad("omega_m must be in (0, 1]");
+        for (int i = 0; i <= c.n_steps; ++i)
+            if (!(c.sched[i] > 0 && c.sched[i] <= 1)) return bad("a schedule must be in (0, 1]");
+    }
+    return HRT_OK;
+}
+
+// Fused leapfrog tables (step n runs boundary n -> n+1; step N is the closing
+// half-kick). Half points are arithmetic means clipped at both ends.
+int build_tables(const hrt_config &c, StepTables &t, std::string &err) {
+    int rc = validate_config(c, err);
+    if (rc) return rc;
+    const int N = c.n_steps;
+    const double cell = c.box / c.mesh_n;
+    const double z_obs = c.observer[2];
+    const bool stat = (c.flags & HRT_STATIC) != 0;
+    t = StepTables();
+    t.a.assign(N + 1, 1.0);
+    t.chi.assign(N + 1, 0.0);
+    t.K.assign(N + 1, 0.0);
+    t.D.assign(N + 1, 0.0);
+    t.d.assign(N + 1, 0.0);
+    t.plane_begin.assign(N + 1, 0);
+    t.plane_count.assign(N + 1, 0);
+    Cosmo cos{c.omega_m, 1.0 - c.omega_m};
+    std::vector<double> D1n;
+    if (stat) {
+        for (int i = 0; i <= N; ++i) t.chi[i] = c.sched[i];
+    } else {
+        for (int i = 0; i <= N; ++i) {
+            t.a[i] = c.sched[i];
+            t.chi[i] = cos.chi(t.a[i]);
+        }
+        for (int n = 0; n <= N; ++n) {
+            double alo = n == 0 ? t.a[0] : 0.5 * (t.a[n - 1] + t.a[n]);
+            double ahi = n == N ? t.a[N] : 0.5 * (t.a[n] + t.a[n + 1]);
+            t.K[n] = -1.5 * c.omega_m * cos.kick(alo, ahi);
+            t.D[n] = n < N ? cos.drift(t.a[n], t.a[n + 1]) : 0.0;
+        }
+        if (c.ray_nx > 0) {
+            D1n.resize(N + 1);
+            for (int n = 0; n <= N; ++n) D1n[n] = cos.D1(t.a[n]);
+        }
+    }
+    if (c.ray_nx == 0) return HRT_OK;
+    const double rho_bar = std::pow((double)c.ptcl_n, 3) / std::pow((double)c.mesh_n, 3);
+    const double static_pref = -8.0 * kPi * kGoverC2 * c.static_mass * rho_bar / (cell * cell);
+    std::vector<int64_t> js;
+    for (int n = 0; n <= N; ++n) {
+        double rmid = n < N ? 0.5 * (t.chi[n] + t.chi[n + 1]) : 0.0;
+        t.d[n] = n < N ? (t.chi[n + 1] - t.chi[n]) / (rmid * rmid) : 0.0;
+        double lo = n == 0 ? t.chi[0] : 0.5 * (t.chi[n - 1] + t.chi[n]);
+        double hi = n == N ? t.chi[N] : 0.5 * (t.chi[n] + t.chi[n + 1]);
+        double sgn = hi >= lo ? 1.0 : -1.0;
+        shell_planes(lo, hi, cell, z_obs, js);
+        t.plane_begin[n] = (int32_t)t.plane_chi.size();
+        for (int64_t j : js) {
+            double cj = (double)j * cell - z_obs;
+            if (!(cj > 0.0)) continue;            // r = 0 carries no weight
+            double w;
+            if (stat) {
+                w = sgn * static_pref * cj;
+            } else {
+                double aj = cos.a_of_chi(cj);
+                w = sgn * (-3.0 * c.omega_m * cell * cj * cos.D1(aj)) / (kCH0 * kCH0 * D1n[n] * aj);
+            }
+            int64_t m = j % c.mesh_n;
+            if (m < 0) m += c.mesh_n;
+            t.plane_mesh.push_back((int32_t)m);
+            t.plane_chi.push_back(cj);
+            t.plane_w.push_back(w);
+        }
+        t.plane_count[n] = (int32_t)t.plane_chi.size() - t.plane_begin[n];
+        if (t.plane_chi.size() > (size_t)1 << 28) {
+            err = "too many shell planes";
+            return HRT_EINVAL;
+        }
+    }
+    return HRT_OK;
+}
+
+}  // namespace hrt

@@ -1,0 +1,233 @@
+"""Thin ctypes binding of the HRT C ABI (include/hrt.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libhrt.so. PyTorch provides device memory (state arrays, the workspace) and the
+stream. If the library has not been built, importing works but every call raises.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_size_t, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhrt.so")
+
+HRT_OK, HRT_EINVAL, HRT_ENOMEM, HRT_EDEVICE, HRT_ESTATE, HRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+HRT_F32, HRT_F64 = 0, 1
+HRT_STATIC = 1
+HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GXY, HRT_MESH_GZ = 0, 1, 2, 3
+
+HRT_NUM_KERNELS = 13
+
+EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
+            "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",
+            "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name")
+
+
+class HrtConfig(ctypes.Structure):
+    _fields_ = [("mesh_n", c_int32), ("ptcl_n", c_int32), ("ray_nx", c_int32), ("ray_ny", c_int32),
+                ("n_steps", c_int32), ("dtype", c_int32), ("flags", c_int32), ("reserved", c_int32),
+                ("box", c_double), ("fov_x", c_double), ("fov_y", c_double),
+                ("observer", c_double * 3), ("omega_m", c_double), ("static_mass", c_double),
+                ("sched", POINTER(c_double))]
+
+
+class HrtMatter(ctypes.Structure):
+    _fields_ = [("s", c_void_p * 3), ("p", c_void_p * 3)]
+
+
+class HrtRays(ctypes.Structure):
+    _fields_ = [("dth", c_void_p * 2), ("p", c_void_p * 2)]
+
+
+class HRTError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhrt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HRTError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build() or python -m paper_2405_12913_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = POINTER
+        L.hrt_workspace_bytes.argtypes = [P(HrtConfig), P(c_size_t)]
+        L.hrt_init.argtypes = [P(HrtConfig), c_void_p, c_size_t, c_void_p, P(c_void_p)]
+        L.hrt_destroy.argtypes = [c_void_p]
+        L.hrt_last_error.argtypes = [c_void_p]
+        L.hrt_last_error.restype = ctypes.c_char_p
+        L.pm_force.argtypes = [c_void_p, P(HrtMatter), c_int]
+        L.pm_step.argtypes = [c_void_p, P(HrtMatter), c_int]
+        L.ray_step.argtypes = [c_void_p, P(HrtRays), c_int]
+        L.ray_convergence.argtypes = [c_void_p, P(HrtRays), c_void_p, c_void_p, c_void_p, c_void_p]
+        L.hrt_mesh_ptr.argtypes = [c_void_p, c_int, P(c_void_p)]
+        L.hrt_tables.argtypes = [P(HrtConfig)] + [P(c_double)] * 5 + [P(c_int32)] * 3 + \
+            [P(c_double)] * 2 + [c_int32, P(c_int32)]
+        L.hrt_profile_enable.argtypes = [c_void_p, c_int]
+        L.hrt_profile_read.argtypes = [c_void_p, P(c_double), P(ctypes.c_int64), c_int]
+        L.hrt_kernel_name.argtypes = [c_int]
+        L.hrt_kernel_name.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("hrt_last_error", "hrt_kernel_name"):
+                getattr(L, name).restype = c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != HRT_OK:
+        msg = lib().hrt_last_error(ctx).decode()
+        raise HRTError(f"hrt status {rc}: {msg}")
+
+
+def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
+                observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0):
+    """hrt_config from keyword arguments; returns (config, schedule array kept alive)."""
+    sched = np.ascontiguousarray(sched, dtype=np.float64)
+    if len(sched) != n_steps + 1:
+        raise ValueError("sched must have n_steps + 1 entries")
+    cfg = HrtConfig()
+    cfg.mesh_n, cfg.ptcl_n, cfg.ray_nx, cfg.ray_ny = mesh_n, ptcl_n, ray_nx, ray_ny
+    cfg.n_steps = n_steps
+    cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
+    cfg.flags = HRT_STATIC if static else 0
+    cfg.reserved = 0
+    cfg.box, cfg.fov_x, cfg.fov_y = box, fov_x, fov_y
+    for i in range(3):
+        cfg.observer[i] = observer[i]
+    cfg.omega_m, cfg.static_mass = omega_m, static_mass
+    cfg.sched = sched.ctypes.data_as(POINTER(c_double))
+    return cfg, sched
+
+
+def hrt_workspace_bytes(cfg):
+    out = c_size_t(0)
+    _check(lib().hrt_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def hrt_tables(cfg):
+    """Host step tables as a dict of numpy arrays (no GPU use)."""
+    N1 = cfg.n_steps + 1
+    arrs = {k: np.zeros(N1) for k in ("a", "chi", "K", "D", "d")}
+    pb = np.zeros(N1, np.int32)
+    pc = np.zeros(N1, np.int32)
+    n_planes = c_int32(0)
+    dp = lambda a: a.ctypes.data_as(POINTER(c_double))
+    ip = lambda a: a.ctypes.data_as(POINTER(c_int32))
+    rc = lib().hrt_tables(ctypes.byref(cfg), dp(arrs["a"]), dp(arrs["chi"]), dp(arrs["K"]),
+                          dp(arrs["D"]), dp(arrs["d"]), ip(pb), ip(pc), None, None, None, 0,
+                          ctypes.byref(n_planes))
+    if rc not in (HRT_OK, HRT_ENOMEM):
+        _check(rc)
+    m = max(n_planes.value, 1)
+    pm, pchi, pw = np.zeros(m, np.int32), np.zeros(m), np.zeros(m)
+    _check(lib().hrt_tables(ctypes.byref(cfg), None, None, None, None, None, None, None, ip(pm),
+                            dp(pchi), dp(pw), m, ctypes.byref(n_planes)))
+    k = n_planes.value
+    arrs.update(plane_begin=pb, plane_count=pc, plane_mesh=pm[:k], plane_chi=pchi[:k], plane_w=pw[:k])
+    return arrs
+
+
+def _ptr(t, dtype, numel, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{what}: expected contiguous {dtype} with {numel} elements, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+class Simulation:
+    """One HRT context: workspace, step tables and the C-ABI calls on the current stream."""
+
+    def __init__(self, *, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0,
+                 fov_y=0.0, observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False,
+                 static_mass=0.0, device="cuda"):
+        import torch
+        self.cfg, self._sched = make_config(
+            mesh_n=mesh_n, box=box, ptcl_n=ptcl_n, n_steps=n_steps, sched=sched, ray_nx=ray_nx,
+            ray_ny=ray_ny, fov_x=fov_x, fov_y=fov_y, observer=observer, omega_m=omega_m,
+            dtype=dtype, static=static, static_mass=static_mass)
+        self.dtype = torch.float64 if self.cfg.dtype == HRT_F64 else torch.float32
+        self.device = torch.device(device)
+        self.n_particles = ptcl_n ** 3
+        self.n_rays = ray_nx * ray_ny
+        self.ws_bytes = hrt_workspace_bytes(self.cfg)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = c_void_p(0)
+        _check(lib().hrt_init(ctypes.byref(self.cfg), c_void_p(self.workspace.data_ptr()),
+                              self.ws_bytes, c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    def close(self):
+        if self.ctx is not None and self.ctx.value:
+            lib().hrt_destroy(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _matter(self, s, p=None):
+        m = HrtMatter()
+        for d in range(3):
+            m.s[d] = _ptr(s[d], self.dtype, self.n_particles, "s")
+            m.p[d] = _ptr(p[d], self.dtype, self.n_particles, "p") if p is not None else None
+        return m
+
+    def _rays(self, dth, p):
+        r = HrtRays()
+        for d in range(2):
+            r.dth[d] = _ptr(dth[d], self.dtype, self.n_rays, "dth")
+            r.p[d] = _ptr(p[d], self.dtype, self.n_rays, "p")
+        return r
+
+    def pm_force(self, s, step):
+        _check(lib().pm_force(self.ctx, ctypes.byref(self._matter(s)), step), self.ctx)
+
+    def pm_step(self, s, p, step):
+        _check(lib().pm_step(self.ctx, ctypes.byref(self._matter(s, p)), step), self.ctx)
+
+    def ray_step(self, dth, p, step):
+        _check(lib().ray_step(self.ctx, ctypes.byref(self._rays(dth, p)), step), self.ctx)
+
+    def ray_convergence(self, dth, kappa, gamma1=None, gamma2=None, omega=None):
+        r = HrtRays()
+        for d in range(2):
+            r.dth[d] = _ptr(dth[d], self.dtype, self.n_rays, "dth")
+            r.p[d] = None
+        outs = [None if t is None else c_void_p(_ptr(t, self.dtype, self.n_rays, "output"))
+                for t in (kappa, gamma1, gamma2, omega)]
+        _check(lib().ray_convergence(self.ctx, ctypes.byref(r), *outs), self.ctx)
+
+    def profile_enable(self, on=True):
+        _check(lib().hrt_profile_enable(self.ctx, 1 if on else 0), self.ctx)
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} recorded since profile_enable(True)."""
+        ms = (c_double * HRT_NUM_KERNELS)()
+        cnt = (ctypes.c_int64 * HRT_NUM_KERNELS)()
+        _check(lib().hrt_profile_read(self.ctx, ms, cnt, HRT_NUM_KERNELS), self.ctx)
+        return {lib().hrt_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(HRT_NUM_KERNELS)}
+
+    def mesh(self, which):
+        """View of an internal mesh in the workspace ([n, n, n] or [n, n, n, 2] for G_xy)."""
+        ptr = c_void_p(0)
+        _check(lib().hrt_mesh_ptr(self.ctx, which, ctypes.byref(ptr)), self.ctx)
+        n = self.cfg.mesh_n
+        comps = 2 if which == HRT_MESH_GXY else 1
+        esize = 8 if self.dtype.is_floating_point and self.cfg.dtype == HRT_F64 else 4
+        off = ptr.value - self.workspace.data_ptr()
+        nbytes = n ** 3 * comps * esize
+        v = self.workspace[off:off + nbytes].view(self.dtype)
+        return v.view(n, n, n, 2) if comps == 2 else v.view(n, n, n)

@@ -80,38 +80,42 @@ def clustered_displacements(seed, ptcl_n, box, n_halos=None, sigma_field=None):
     """Synthetic particle displacements s (P, 3) with halo-like clustering.
 
     Recipe (a workload shape, not a physical model): every particle gets a smooth
-    random offset (sum of a few random Fourier modes, rms ``sigma_field`` Mpc/h);
-    then ``n_halos`` centres are drawn uniformly, each with a Lagrangian radius drawn
-    from a power law between 2 and 12 lattice spacings, and the particles of that
-    Lagrangian sphere are pulled to ``0.15 * r^1.5`` of their distance (normalised to
-    the radius), so a few per cent of the mesh cells hold tens to hundreds of particles
-    and most others are emptied, as in an evolved dark-matter field."""
+    random offset (sum of six random Fourier modes, rms ``sigma_field`` Mpc/h); then
+    ``n_halos`` centres are drawn uniformly, each with a Lagrangian radius drawn
+    log-uniformly between 2 and 12 lattice spacings, and the particles of that
+    Lagrangian sphere are pulled in to 0.15 r x^1.5 (x = distance / radius), so a few
+    per cent of the mesh cells hold tens to hundreds of particles and many others are
+    emptied, as in an evolved dark-matter field."""
     rng = np.random.default_rng(seed)
-    spacing = box / ptcl_n
-    n_halos = max(4, ptcl_n ** 3 // 4096) if n_halos is None else n_halos
+    n = ptcl_n
+    spacing = box / n
+    n_halos = max(4, n ** 3 // 4096) if n_halos is None else n_halos
     sigma_field = 3.0 * spacing if sigma_field is None else sigma_field
-    g = np.arange(ptcl_n) * spacing
-    qz, qy, qx = np.meshgrid(g, g, g, indexing="ij")
-    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
-    s = np.zeros_like(q)
+    g = np.arange(n) * spacing
+    s = np.zeros((3, n, n, n))
     for _ in range(6):
         k = 2.0 * np.pi / box * rng.integers(1, 5, size=3) * rng.choice([-1, 1], size=3)
         amp = rng.normal(size=3) * sigma_field / math.sqrt(6.0)
         ph = rng.uniform(0, 2 * np.pi)
-        s += np.sin(q @ k + ph)[:, None] * amp[None, :]
+        wave = np.sin(k[0] * g[None, None, :] + k[1] * g[None, :, None] + k[2] * g[:, None, None] + ph)
+        for d in range(3):
+            s[d] += amp[d] * wave
     centres = rng.uniform(0, box, size=(n_halos, 3))
     radii = spacing * 2.0 * (6.0 ** rng.uniform(0, 1, size=n_halos))
     for c, r in zip(centres, radii):
-        d = q - c
-        d -= box * np.round(d / box)
-        dist = np.linalg.norm(d, axis=1)
-        sel = dist < r
-        if not np.any(sel):
-            continue
-        x = dist[sel] / r
-        scale = 0.15 * np.sqrt(x)        # new distance = 0.15 r x^1.5
-        s[sel] += (scale - 1.0)[:, None] * d[sel]
-    return s
+        lo = np.floor((c - r) / spacing).astype(int)
+        hi = np.ceil((c + r) / spacing).astype(int)
+        idx = [np.arange(lo[d], hi[d] + 1) for d in range(3)]
+        dq = [idx[d] * spacing - c[d] for d in range(3)]          # unwrapped offsets
+        iz, iy, ix = np.ix_(idx[2] % n, idx[1] % n, idx[0] % n)
+        dz, dy, dx = np.ix_(dq[2], dq[1], dq[0])
+        dist = np.sqrt(dx * dx + dy * dy + dz * dz)
+        x = np.minimum(dist / r, 1.0)
+        fac = np.where(dist < r, 0.15 * np.sqrt(x) - 1.0, 0.0)
+        s[0][iz, iy, ix] += fac * dx
+        s[1][iz, iy, ix] += fac * dy
+        s[2][iz, iy, ix] += fac * dz
+    return s.reshape(3, -1).T.copy()
 
 
 def random_momenta(seed, n, rms):

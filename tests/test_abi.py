@@ -1,0 +1,100 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function declared
+in include/hrt.h, validates configurations, and its host FP64 step tables (Sec. 3.1-3.2
+kick/drift factors, lens shells and plane weights) agree with the oracle's."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import tables
+from paper_2405_12913_amd import hrt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hrt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(\w+)\s*\([^;{]*\)\s*;", src)) - {"if", "while"})
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert set(names) == set(hrt.EXPORTED)
+    lib = hrt.lib()
+    for name in names:
+        assert hasattr(lib, name)
+    out = subprocess.run(["nm", "-D", "--defined-only", hrt.LIB_PATH], capture_output=True, text=True).stdout
+    for name in names:
+        assert re.search(rf"\bT {name}$", out, flags=re.M), name
+
+
+def _cosmo_cfg(a, mesh_n=32, box=100.0, rays=(16, 16), z_obs=0.0, om=0.3):
+    return hrt.make_config(mesh_n=mesh_n, box=box, ptcl_n=mesh_n // 2, n_steps=len(a) - 1, sched=a,
+                           ray_nx=rays[0], ray_ny=rays[1], fov_x=0.02, fov_y=0.02,
+                           observer=(box / 2, box / 2, z_obs), omega_m=om)
+
+
+@pytest.mark.parametrize("a,z_obs", [(np.linspace(1.0, 0.5, 17), 0.0), (np.linspace(1.0, 0.6, 9), 1.3),
+                                     (np.linspace(0.6, 1.0, 9), 0.0)])
+def test_host_tables_match_oracle(a, z_obs):
+    cfg, keep = _cosmo_cfg(a, z_obs=z_obs)
+    t = hrt.hrt_tables(cfg)
+    o = tables.build_cosmo(a, 0.3, 32, 100.0, z_obs)
+    np.testing.assert_allclose(t["chi"], o.chi, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(t["K"], o.K, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(t["D"], o.D, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(t["d"], o.d, rtol=1e-12, atol=1e-18)
+    for n in range(len(a)):
+        b, c = t["plane_begin"][n], t["plane_count"][n]
+        assert c == len(o.planes[n])
+        for k, (j, chi_j, w) in enumerate(o.planes[n]):
+            assert t["plane_mesh"][b + k] == j % 32
+            assert t["plane_chi"][b + k] == pytest.approx(chi_j, rel=1e-14)
+            assert t["plane_w"][b + k] == pytest.approx(w, rel=1e-11)
+
+
+def test_host_tables_static_point_lens():
+    cfg = synth.pointlens()
+    c, keep = hrt.make_config(mesh_n=cfg["mesh_n"], box=cfg["box"], ptcl_n=1, n_steps=256,
+                              sched=cfg["sched"], ray_nx=64, ray_ny=64, fov_x=cfg["fov"],
+                              fov_y=cfg["fov"], observer=cfg["observer"], dtype="f64", static=True,
+                              static_mass=cfg["mass"])
+    t = hrt.hrt_tables(c)
+    o = tables.build_static(cfg["sched"], cfg["mesh_n"], cfg["box"], 0.0, cfg["mass"], 1)
+    np.testing.assert_allclose(t["d"], o.d, rtol=1e-14)
+    flat = [(j % 128, chi, w) for plist in o.planes for (j, chi, w) in plist]
+    assert len(flat) == len(t["plane_chi"]) == 127
+    np.testing.assert_allclose(t["plane_w"], [w for _, _, w in flat], rtol=1e-13)
+    np.testing.assert_array_equal(t["plane_mesh"], [m for m, _, _ in flat])
+
+
+def test_large_config_table_sizes():
+    cfg = synth.lcdm256()
+    c, keep = hrt.make_config(mesh_n=256, box=400.0, ptcl_n=256, n_steps=64, sched=cfg["sched"],
+                              ray_nx=512, ray_ny=512, fov_x=cfg["fov"], fov_y=cfg["fov"],
+                              observer=cfg["observer"], omega_m=0.3)
+    t = hrt.hrt_tables(c)
+    assert abs(t["chi"][-1] - 2312.7) < 0.1
+    assert len(t["plane_chi"]) == int(t["chi"][-1] / (400.0 / 256))    # every plane in (0, chi_s)
+    nbytes = hrt.hrt_workspace_bytes(c)
+    assert 0.5e9 < nbytes < 2e9
+
+
+@pytest.mark.parametrize("field,value", [("mesh_n", 48), ("mesh_n", 8), ("ptcl_n", 3), ("n_steps", 0),
+                                         ("dtype", 7), ("ray_nx", 2), ("reserved", 1), ("flags", 8)])
+def test_invalid_configs_are_rejected(field, value):
+    cfg, keep = _cosmo_cfg(np.linspace(1.0, 0.5, 5))
+    setattr(cfg, field, value)
+    with pytest.raises(hrt.HRTError, match="status -1"):
+        hrt.hrt_workspace_bytes(cfg)
+
+
+def test_bad_schedule_rejected():
+    cfg, keep = _cosmo_cfg(np.array([1.0, 0.8, 1.2]))
+    with pytest.raises(hrt.HRTError, match="a schedule"):
+        hrt.hrt_workspace_bytes(cfg)
