@@ -10,9 +10,13 @@ schedule from the current state.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
-Prints one JSON line. ``value`` is co-evolution ray-steps/s (rays x steps / wall time of
-the timed steps, inputs resident in HBM). Per-kernel times come from HIP events recorded
-on the library's stream around every launch inside the timed region.
+Prints one JSON line. ``value`` is co-evolution ray-steps/s (rays x steps / time of the
+timed steps between two HIP events on the library's stream, inputs resident in HBM).
+The same K steps are then run again from the same initial state with the library's
+per-kernel HIP events switched on (they add ~10 us of idle time between launches, so
+they stay out of the first pass); ``kernels`` and ``roofline`` come from that pass.
+``--calibrate-copy`` adds a plain 512 MiB device-to-device copy outside both passes, as
+the reference kernel for scaling rocprofv3 byte counters.
 """
 import argparse
 import json
@@ -91,6 +95,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
@@ -131,20 +136,21 @@ def main():
         if m == N - 1:
             sim.ray_convergence(dth, kappa)
 
+    def reset():
+        torch.cuda.synchronize()
+        for a, b in zip(s + p, s_init + p_init):
+            a.copy_(b)
+        for t in dth + pr:
+            t.zero_()
+        torch.cuda.synchronize()
+
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     for k in range(args.warmup):
         step(k)
-    torch.cuda.synchronize()
-    for a, b in zip(s + p, s_init + p_init):
-        a.copy_(b)
-    for t in dth + pr:
-        t.zero_()
-    torch.cuda.synchronize()
+    reset()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    sim.profile_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(sim.stream)
     for k in range(args.steps):
@@ -153,9 +159,23 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     elapsed_ms = start.elapsed_time(stop)
+    assert torch.isfinite(dth[0]).all() and torch.isfinite(s[0]).all()
+
+    if args.calibrate_copy:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    print(f"[bench] per-kernel pass, {args.steps} steps", file=sys.stderr, flush=True)
+    reset()
+    sim.profile_enable(True)
+    for k in range(args.steps):
+        step(k)
     prof = sim.profile_read()
     sim.profile_enable(False)
-    assert torch.isfinite(dth[0]).all() and torch.isfinite(s[0]).all()
 
     kernels = {}
     for name, (ms, cnt) in prof.items():
@@ -191,6 +211,7 @@ def main():
                                "400 Mpc/h replicated, 512^2 rays over 5x5 deg, 64 steps a=1->0.5",
                    "mesh": n, "particles": P, "rays": nrays, "box": box, "schedule_steps": N},
         "pm_step_ms": round(pm_ms, 4),
+        "pm_step_ms_note": "sum of the PM kernels' HIP-event times per step (per-kernel pass)",
         "ray_step_ms": round(ray_ms, 4),
         "ray_kernel_ray_steps_per_s": nrays / (ray_ms * 1e-3),
         "host_wall_s": round(wall, 4),

@@ -121,8 +121,8 @@ int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *kappa, void *gamma1,
 
 /* Device pointer to an internal mesh in the workspace, valid until hrt_destroy:
  * HRT_MESH_DELTA (n^3, after pm_force: delta), HRT_MESH_PHI (n^3: phi),
- * HRT_MESH_GXY (n^3 interleaved (G_x, G_y) pairs), HRT_MESH_GZ (n^3: G_z). */
-enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GXY = 2, HRT_MESH_GZ = 3 };
+ * HRT_MESH_GRAD (n^3 interleaved quadruples (G_x, G_y, G_z, 0)). */
+enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GRAD = 2 };
 int hrt_mesh_ptr(const hrt_ctx *ctx, int which, void **ptr);
 
 /* Host-only step tables for cfg (no GPU use), for checking the table builder.

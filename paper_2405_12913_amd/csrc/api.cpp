@@ -28,8 +28,7 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
     L.mesh_r = take(2 * n3 * T);                        // delta, then phi
     L.spec = take((n / 2 + 1) * n * n * 2 * T);
-    L.gxy = take(n3 * 2 * T);
-    L.gz = take(n3 * T);
+    L.grad = take(n3 * 4 * T);                          // (G_x, G_y, G_z, 0) per node
     L.twiddle = take(n * 2 * T);
     L.bins = take((size_t)(L.nbins + L.nbins + 1 + nblk + 1) * 4);
     L.cursor = take((size_t)L.nbins * 4);
@@ -317,8 +316,7 @@ extern "C" int hrt_mesh_ptr(const hrt_ctx *c, int which, void **ptr) {
     switch (which) {
         case HRT_MESH_DELTA: *ptr = c->ws + c->lay.mesh_r; return HRT_OK;
         case HRT_MESH_PHI: *ptr = c->ws + c->lay.mesh_r + n3 * T; return HRT_OK;
-        case HRT_MESH_GXY: *ptr = c->ws + c->lay.gxy; return HRT_OK;
-        case HRT_MESH_GZ: *ptr = c->ws + c->lay.gz; return HRT_OK;
+        case HRT_MESH_GRAD: *ptr = c->ws + c->lay.grad; return HRT_OK;
         default: return HRT_EINVAL;
     }
 }

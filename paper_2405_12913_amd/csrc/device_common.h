@@ -18,6 +18,12 @@ __device__ __forceinline__ c2<T> cmul(c2<T> a, c2<T> b) {
     return c2<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
+__host__ __device__ inline int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
 // Cell index and fraction of particle i along one axis: u = i_lattice * ratio + s / cell.
 // The integer part of s / cell is split off first so the fraction keeps the precision
 // of the displacement rather than of the absolute coordinate.
@@ -34,24 +40,64 @@ __device__ __forceinline__ void axis_cell(T s, int lattice, int ratio, T inv_cel
     }
 }
 
-// Wave-aggregated atomic add of 1 on counter[key] for every active lane with key >= 0.
-// Returns the lane's slot (old counter value + its rank among lanes with equal key).
-// All 64 lanes of the wave must call it (inactive lanes pass key = -1).
+// Wave-aggregated atomic increment of counter[key] for every lane with key >= 0.
+// The loop only groups equal keys (ballot per distinct key); afterwards the group
+// leaders issue their atomics together in one instruction, so a wave pays one atomic
+// round trip whatever the number of distinct keys. Returns the lane's slot (old counter
+// value + rank among the lanes with the same key) when WANT_SLOT, else -1.
+// All 64 lanes of the wave must call it (lanes without work pass key = -1).
+template <bool WANT_SLOT>
 __device__ __forceinline__ int wave_aggregated_increment(unsigned int *counter, int key) {
     const int lane = __lane_id();
     unsigned long long remaining = __ballot(key >= 0);
-    int slot = -1;
+    int leader_of_mine = lane, rank = 0;
+    unsigned int count = 0;
     while (remaining) {
         const int leader = __ffsll((long long)remaining) - 1;
         const int lkey = __shfl(key, leader);
         const unsigned long long grp = __ballot(key == lkey);
-        unsigned int base = 0;
-        if (lane == leader) base = atomicAdd(&counter[lkey], (unsigned int)__popcll(grp));
-        base = __shfl(base, leader);
-        if (key == lkey) slot = (int)base + __popcll(grp & ((1ull << lane) - 1ull));
+        if (key == lkey) {
+            leader_of_mine = leader;
+            rank = __popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) count = (unsigned int)__popcll(grp);
         remaining &= ~grp;
     }
-    return slot;
+    if (!WANT_SLOT) {
+        if (count) atomicAdd(&counter[key], count);
+        return -1;
+    }
+    unsigned int base = 0;
+    if (count) base = atomicAdd(&counter[key], count);
+    base = __shfl(base, leader_of_mine);
+    return key >= 0 ? (int)base + rank : -1;
+}
+
+// Streaming accesses that are touched once per kernel use non-temporal loads and stores so
+// they do not evict gathered data (mesh nodes) from L2.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
+
+// Particle handled by (logical block b, thread t) of a 256-thread block. With np >= 16 a
+// block covers a 16 x 16 patch of one Lagrangian plane and a wave a 16 x 4 strip, so a
+// wave's particles fall into few mesh tiles and read few mesh rows; smaller lattices use
+// plain linear order.
+__device__ __forceinline__ int particle_of(int b, int t, int lnp) {
+    if (lnp < 4) return b * 256 + t;
+    const int pb = 1 << (lnp - 4);
+    const int bx = b & (pb - 1), by = (b >> (lnp - 4)) & (pb - 1), z = b >> (2 * (lnp - 4));
+    return (((z << lnp) + (by << 4) + (t >> 4)) << lnp) + (bx << 4) + (t & 15);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on XCD w % 8).
+// Kernels whose neighbouring blocks share data remap w so that each XCD processes one
+// contiguous range of logical blocks and the shared data stays in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int nblocks) {
+    const int w = blockIdx.x, x = w & 7, k = w >> 3;
+    const int per = nblocks >> 3, rem = nblocks & 7;
+    return x * per + (x < rem ? x : rem) + k;
 }
 
 }  // namespace hrt

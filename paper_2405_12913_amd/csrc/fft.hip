@@ -228,12 +228,13 @@ __global__ __launch_bounds__(kThreads) void z_poisson_kernel(c2<T> *__restrict__
     }
 }
 
+// One lane per node, x fastest; blocks XCD-remapped so the +-2 neighbour rows and
+// planes a block reads are mostly in its own XCD's L2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(const T *__restrict__ phi,
-                                                                c2<T> *__restrict__ gxy,
-                                                                T *__restrict__ gz, int n,
+                                                                v4<T> *__restrict__ g, int n,
                                                                 int log2n, T inv12cell) {
-    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t idx = (int64_t)xcd_block(gridDim.x) * kThreads + threadIdx.x;
     if (idx >= ((int64_t)1 << (3 * log2n))) return;
     const int m = n - 1;
     const int x = (int)(idx & m), y = (int)((idx >> log2n) & m), z = (int)(idx >> (2 * log2n));
@@ -245,8 +246,12 @@ __global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(const T *__restr
                  (phi[row + ((x + 2) & m)] - phi[row + ((x - 2) & m)]);
     const T dy = T(8) * (at(x, y + 1, z) - at(x, y - 1, z)) - (at(x, y + 2, z) - at(x, y - 2, z));
     const T dz = T(8) * (at(x, y, z + 1) - at(x, y, z - 1)) - (at(x, y, z + 2) - at(x, y, z - 2));
-    gxy[idx] = c2<T>{dx * inv12cell, dy * inv12cell};
-    gz[idx] = dz * inv12cell;
+    v4<T> out;
+    out.x = dx * inv12cell;
+    out.y = dy * inv12cell;
+    out.z = dz * inv12cell;
+    out.w = T(0);
+    g[idx] = out;
 }
 
 template <typename T, int N>
@@ -303,8 +308,7 @@ hipError_t gradient_impl(hrt_ctx *c) {
     const int64_t nodes = (int64_t)n * n * n;
     prof_begin(c);
     fd4_gradient_kernel<T><<<(int)((nodes + kThreads - 1) / kThreads), kThreads, 0, c->stream>>>(
-        phi, reinterpret_cast<c2<T> *>(c->ws + c->lay.gxy), reinterpret_cast<T *>(c->ws + c->lay.gz),
-        n, log2n, (T)(1.0 / (12.0 * c->cell)));
+        phi, reinterpret_cast<v4<T> *>(c->ws + c->lay.grad), n, log2n, (T)(1.0 / (12.0 * c->cell)));
     prof_end(c, K_GRADIENT);
     return hipGetLastError();
 }

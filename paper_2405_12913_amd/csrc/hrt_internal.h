@@ -34,7 +34,7 @@ struct PlaneEntry {
 
 // Workspace carve-up, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
-    size_t mesh_r, spec, gxy, gz, twiddle, bins, cursor, sorted, planes, total;
+    size_t mesh_r, spec, grad, twiddle, bins, cursor, sorted, planes, total;
     int64_t nbins;
 };
 Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);

@@ -21,16 +21,18 @@ namespace {
 constexpr int kTile = 8;
 constexpr int kThreads = 256;
 
+// np is a power of two (it divides the power-of-two mesh size): lattice indices by shifts.
 template <typename T>
 __device__ __forceinline__ void particle_cell(const T *__restrict__ sx, const T *__restrict__ sy,
-                                              const T *__restrict__ sz, int64_t i, int np,
+                                              const T *__restrict__ sz, int i, int lnp,
                                               int ratio, T inv_cell, int nmask, int c[3], T f[3]) {
-    const int ix = (int)(i % np);
-    const int iy = (int)((i / np) % np);
-    const int iz = (int)(i / ((int64_t)np * np));
-    axis_cell<T>(sx[i], ix, ratio, inv_cell, nmask, c[0], f[0]);
-    axis_cell<T>(sy[i], iy, ratio, inv_cell, nmask, c[1], f[1]);
-    axis_cell<T>(sz[i], iz, ratio, inv_cell, nmask, c[2], f[2]);
+    const int pm = (1 << lnp) - 1;
+    const int ix = i & pm;
+    const int iy = (i >> lnp) & pm;
+    const int iz = i >> (2 * lnp);
+    axis_cell<T>(ld_stream(sx + i), ix, ratio, inv_cell, nmask, c[0], f[0]);
+    axis_cell<T>(ld_stream(sy + i), iy, ratio, inv_cell, nmask, c[1], f[1]);
+    axis_cell<T>(ld_stream(sz + i), iz, ratio, inv_cell, nmask, c[2], f[2]);
 }
 
 __device__ __forceinline__ int bin_key(const int c[3], int nt) {
@@ -40,32 +42,32 @@ __device__ __forceinline__ int bin_key(const int c[3], int nt) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bin_count_kernel(
-    const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int64_t P, int np,
+    const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int P, int lnp,
     int ratio, T inv_cell, int n, unsigned int *__restrict__ count) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int i = particle_of(blockIdx.x, threadIdx.x, lnp);
     int key = -1;
     if (i < P) {
         int c[3];
         T f[3];
-        particle_cell<T>(sx, sy, sz, i, np, ratio, inv_cell, n - 1, c, f);
+        particle_cell<T>(sx, sy, sz, i, lnp, ratio, inv_cell, n - 1, c, f);
         key = bin_key(c, n / kTile);
     }
-    wave_aggregated_increment(count, key);
+    wave_aggregated_increment<false>(count, key);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(
-    const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int64_t P, int np,
+    const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int P, int lnp,
     int ratio, T inv_cell, int n, unsigned int *__restrict__ cursor, v4<T> *__restrict__ sorted) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int i = particle_of(blockIdx.x, threadIdx.x, lnp);
     int key = -1;
     int c[3] = {0, 0, 0};
     T f[3] = {0, 0, 0};
     if (i < P) {
-        particle_cell<T>(sx, sy, sz, i, np, ratio, inv_cell, n - 1, c, f);
+        particle_cell<T>(sx, sy, sz, i, lnp, ratio, inv_cell, n - 1, c, f);
         key = bin_key(c, n / kTile);
     }
-    const int slot = wave_aggregated_increment(cursor, key);
+    const int slot = wave_aggregated_increment<true>(cursor, key);
     if (i < P) {
         const int lcell = ((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7);
         v4<T> e;
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(
     __shared__ int rstart[27], rpre[28];
     __shared__ signed char rd[27][3];
     const int nt = n / kTile;
-    const int t = blockIdx.x;
+    const int t = xcd_block(nt * nt * nt);
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     for (int k = threadIdx.x; k < 512; k += kThreads) acc[k] = 0ull;
     if (threadIdx.x == 0) {
@@ -217,20 +219,28 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(
     __syncthreads();
     for (int k = threadIdx.x; k < 512; k += kThreads) {
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        delta[((size_t)z * n + y) * n + x] = (T)((double)acc[k] * inv_scale_rho - 1.0);
+        st_stream((T)((double)acc[k] * inv_scale_rho - 1.0), delta + ((size_t)z * n + y) * n + x);
     }
 }
 
+// One lane per particle, particles in Lagrangian order; blocks are XCD-remapped so
+// neighbouring particle rows (which read the same mesh rows) share one L2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void matter_kd_kernel(
     T *__restrict__ sx, T *__restrict__ sy, T *__restrict__ sz, T *__restrict__ px,
-    T *__restrict__ py, T *__restrict__ pz, const c2<T> *__restrict__ gxy, const T *__restrict__ gz,
-    int64_t P, int np, int ratio, T inv_cell, int n, T K, T D) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    T *__restrict__ py, T *__restrict__ pz, const v4<T> *__restrict__ g, int P, int lnp, int ratio,
+    T inv_cell, int n, T K, T D) {
+    const int i = particle_of(xcd_block(gridDim.x), threadIdx.x, lnp);
     if (i >= P) return;
     int c[3];
     T f[3];
-    particle_cell<T>(sx, sy, sz, i, np, ratio, inv_cell, n - 1, c, f);
+    const T s0 = ld_stream(sx + i), s1 = ld_stream(sy + i), s2 = ld_stream(sz + i);
+    {
+        const int pm = (1 << lnp) - 1;
+        axis_cell<T>(s0, i & pm, ratio, inv_cell, n - 1, c[0], f[0]);
+        axis_cell<T>(s1, (i >> lnp) & pm, ratio, inv_cell, n - 1, c[1], f[1]);
+        axis_cell<T>(s2, i >> (2 * lnp), ratio, inv_cell, n - 1, c[2], f[2]);
+    }
     T gx = 0, gy = 0, gzz = 0;
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz) {
@@ -244,27 +254,29 @@ __global__ __launch_bounds__(kThreads) void matter_kd_kernel(
             for (int cx = 0; cx < 2; ++cx) {
                 const int x = (c[0] + cx) & (n - 1);
                 const T w = wyz * (cx ? f[0] : T(1) - f[0]);
-                const size_t node = ((size_t)z * n + y) * n + x;
-                const c2<T> g = gxy[node];
-                gx += w * g.x;
-                gy += w * g.y;
-                gzz += w * gz[node];
+                const v4<T> gv = g[((size_t)z * n + y) * n + x];
+                gx += w * gv.x;
+                gy += w * gv.y;
+                gzz += w * gv.z;
             }
         }
     }
-    const T npx = px[i] + K * gx, npy = py[i] + K * gy, npz = pz[i] + K * gzz;
-    px[i] = npx;
-    py[i] = npy;
-    pz[i] = npz;
-    sx[i] += D * npx;
-    sy[i] += D * npy;
-    sz[i] += D * npz;
+    const T npx = ld_stream(px + i) + K * gx;
+    const T npy = ld_stream(py + i) + K * gy;
+    const T npz = ld_stream(pz + i) + K * gzz;
+    st_stream(npx, px + i);
+    st_stream(npy, py + i);
+    st_stream(npz, pz + i);
+    st_stream(s0 + D * npx, sx + i);
+    st_stream(s1 + D * npy, sy + i);
+    st_stream(s2 + D * npz, sz + i);
 }
 
 template <typename T>
 hipError_t paint_impl(hrt_ctx *c, const hrt_matter *m) {
     const int n = c->n, np = c->np;
-    const int64_t P = (int64_t)np * np * np;
+    const int P = np * np * np;
+    const int lnp = ilog2(np);
     const int ratio = n / np;
     const T inv_cell = (T)(1.0 / c->cell);
     const int64_t nbins = c->lay.nbins;
@@ -278,10 +290,10 @@ hipError_t paint_impl(hrt_ctx *c, const hrt_matter *m) {
     const T *sy = static_cast<const T *>(m->s[1]);
     const T *sz = static_cast<const T *>(m->s[2]);
     hipStream_t st = c->stream;
-    const int pblocks = (int)((P + kThreads - 1) / kThreads);
+    const int pblocks = (P + kThreads - 1) / kThreads;
     prof_begin(c);
     fill_u32_kernel<<<(int)((nbins + 255) / 256), 256, 0, st>>>(count, nbins, 0u);
-    bin_count_kernel<T><<<pblocks, kThreads, 0, st>>>(sx, sy, sz, P, np, ratio, inv_cell, n, count);
+    bin_count_kernel<T><<<pblocks, kThreads, 0, st>>>(sx, sy, sz, P, lnp, ratio, inv_cell, n, count);
     prof_end(c, K_BIN_COUNT);
     const int nblk = (int)((nbins + 1023) / 1024);
     prof_begin(c);
@@ -290,8 +302,8 @@ hipError_t paint_impl(hrt_ctx *c, const hrt_matter *m) {
     scan_add_kernel<<<(int)((nbins + 255) / 256), 256, 0, st>>>(offs, nbins, sums, nblk, cursor);
     prof_end(c, K_BIN_SCAN);
     prof_begin(c);
-    bin_scatter_kernel<T><<<pblocks, kThreads, 0, st>>>(sx, sy, sz, P, np, ratio, inv_cell, n, cursor,
-                                                         sorted);
+    bin_scatter_kernel<T><<<pblocks, kThreads, 0, st>>>(sx, sy, sz, P, lnp, ratio, inv_cell, n,
+                                                         cursor, sorted);
     prof_end(c, K_BIN_SCATTER);
     const double scale = std::ldexp(1.0, c->fixed_bits);
     const double rho_bar = (double)P / ((double)n * n * n);
@@ -306,14 +318,13 @@ hipError_t paint_impl(hrt_ctx *c, const hrt_matter *m) {
 template <typename T>
 hipError_t matter_impl(hrt_ctx *c, const hrt_matter *m, double K, double D) {
     const int n = c->n, np = c->np;
-    const int64_t P = (int64_t)np * np * np;
-    const c2<T> *gxy = reinterpret_cast<const c2<T> *>(c->ws + c->lay.gxy);
-    const T *gz = reinterpret_cast<const T *>(c->ws + c->lay.gz);
+    const int P = np * np * np;
+    const v4<T> *g = reinterpret_cast<const v4<T> *>(c->ws + c->lay.grad);
     prof_begin(c);
-    matter_kd_kernel<T><<<(int)((P + kThreads - 1) / kThreads), kThreads, 0, c->stream>>>(
+    matter_kd_kernel<T><<<(P + kThreads - 1) / kThreads, kThreads, 0, c->stream>>>(
         static_cast<T *>(m->s[0]), static_cast<T *>(m->s[1]), static_cast<T *>(m->s[2]),
-        static_cast<T *>(m->p[0]), static_cast<T *>(m->p[1]), static_cast<T *>(m->p[2]), gxy, gz, P,
-        np, n / np, (T)(1.0 / c->cell), n, (T)K, (T)D);
+        static_cast<T *>(m->p[0]), static_cast<T *>(m->p[1]), static_cast<T *>(m->p[2]), g, P,
+        ilog2(np), n / np, (T)(1.0 / c->cell), n, (T)K, (T)D);
     prof_end(c, K_MATTER_KD);
     return hipGetLastError();
 }

@@ -24,10 +24,10 @@ constexpr int kThreads = 256;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void ray_step_kernel(
     T *__restrict__ dthx, T *__restrict__ dthy, T *__restrict__ px, T *__restrict__ py,
-    const PlaneEntry *__restrict__ planes, int begin, int count, const c2<T> *__restrict__ gxy,
+    const PlaneEntry *__restrict__ planes, int begin, int count, const v4<T> *__restrict__ g,
     int n, double inv_cell, double obsx, double obsy, int mx, int nrays, double mux, double muy,
     double half_mx, double half_my, T d) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int i = xcd_block(gridDim.x) * kThreads + threadIdx.x;
     if (i >= nrays) return;
     const int ix = i % mx, iy = i / mx;
     const double thx = ((ix + 0.5) - half_mx) * mux + (double)dthx[i];
@@ -42,9 +42,9 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(
         const T fx = (T)(X - flx), fy = (T)(Y - fly);
         const int x0 = (int)((int64_t)flx & m), y0 = (int)((int64_t)fly & m);
         const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
-        const c2<T> *plane = gxy + (size_t)pe.mesh * n * n;
-        const c2<T> g00 = plane[(size_t)y0 * n + x0], g01 = plane[(size_t)y0 * n + x1];
-        const c2<T> g10 = plane[(size_t)y1 * n + x0], g11 = plane[(size_t)y1 * n + x1];
+        const v4<T> *plane = g + (size_t)pe.mesh * n * n;
+        const v4<T> g00 = plane[(size_t)y0 * n + x0], g01 = plane[(size_t)y0 * n + x1];
+        const v4<T> g10 = plane[(size_t)y1 * n + x0], g11 = plane[(size_t)y1 * n + x1];
         const T w00 = (T(1) - fx) * (T(1) - fy), w01 = fx * (T(1) - fy);
         const T w10 = (T(1) - fx) * fy, w11 = fx * fy;
         const T gx = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
@@ -97,7 +97,7 @@ hipError_t ray_impl(hrt_ctx *c, const hrt_rays *r, int begin, int count, double 
     ray_step_kernel<T><<<(nrays + kThreads - 1) / kThreads, kThreads, 0, c->stream>>>(
         static_cast<T *>(r->dth[0]), static_cast<T *>(r->dth[1]), static_cast<T *>(r->p[0]),
         static_cast<T *>(r->p[1]), reinterpret_cast<const PlaneEntry *>(c->ws + c->lay.planes), begin,
-        count, reinterpret_cast<const c2<T> *>(c->ws + c->lay.gxy), c->n, 1.0 / c->cell,
+        count, reinterpret_cast<const v4<T> *>(c->ws + c->lay.grad), c->n, 1.0 / c->cell,
         c->cfg.observer[0], c->cfg.observer[1], c->mx, nrays, c->cfg.fov_x / c->mx,
         c->cfg.fov_y / c->my, 0.5 * c->mx, 0.5 * c->my, (T)d);
     prof_end(c, K_RAY_STEP);

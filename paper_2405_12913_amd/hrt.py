@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhrt.so")
 HRT_OK, HRT_EINVAL, HRT_ENOMEM, HRT_EDEVICE, HRT_ESTATE, HRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 HRT_F32, HRT_F64 = 0, 1
 HRT_STATIC = 1
-HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GXY, HRT_MESH_GZ = 0, 1, 2, 3
+HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
 HRT_NUM_KERNELS = 13
 
@@ -221,13 +221,13 @@ class Simulation:
         return {lib().hrt_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(HRT_NUM_KERNELS)}
 
     def mesh(self, which):
-        """View of an internal mesh in the workspace ([n, n, n] or [n, n, n, 2] for G_xy)."""
+        """View of an internal mesh in the workspace ([n, n, n], or [n, n, n, 4] for G)."""
         ptr = c_void_p(0)
         _check(lib().hrt_mesh_ptr(self.ctx, which, ctypes.byref(ptr)), self.ctx)
         n = self.cfg.mesh_n
-        comps = 2 if which == HRT_MESH_GXY else 1
+        comps = 4 if which == HRT_MESH_GRAD else 1
         esize = 8 if self.dtype.is_floating_point and self.cfg.dtype == HRT_F64 else 4
         off = ptr.value - self.workspace.data_ptr()
         nbytes = n ** 3 * comps * esize
         v = self.workspace[off:off + nbytes].view(self.dtype)
-        return v.view(n, n, n, 2) if comps == 2 else v.view(n, n, n)
+        return v.view(n, n, n, 4) if comps == 4 else v.view(n, n, n)
