@@ -3,6 +3,9 @@
 Workload (lcdm256): one LambdaCDM realisation, 256^3 particles on a 256^3 float32 mesh,
 box 400 Mpc/h replicated along the line of sight, 512^2 rays over 5 x 5 degrees,
 64 co-evolution steps uniform in a from 1 to 0.5 (sources at z = 1, chi_s = 2312.7 Mpc/h).
+Input (untimed set-up on the GPU): seeded unit white noise -> 2LPT at a = 1/64
+(Eisenstein-Hu no-wiggle spectrum, Omega_m = 0.3, sigma_8 = 0.8, h = 0.7, n_s = 0.96) ->
+64 forward PM steps to a = 1 and the closing half-kick, giving an evolved field.
 A step is one pm_step (paint, FFT Poisson solve, gradient, matter kick-drift) plus one
 ray_step (plane-sum kick over the lens shell, drift); the convergence map is taken
 at the source plane (every 64th step). Steps beyond 64 continue cyclically through the
@@ -114,12 +117,23 @@ def main():
     n, np_, box, nr = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
     P, nrays = np_ ** 3, nr * nr
     N = len(cfg["sched"]) - 1
-    print(f"[bench] generating {np_}^3 clustered particles", file=sys.stderr, flush=True)
-    s0 = synth.clustered_displacements(args.seed, np_, box).astype(np.float32)
-    p0 = synth.random_momenta(args.seed, P, 3.0).astype(np.float32)
     dev = torch.device("cuda:0")
-    s_init = [torch.tensor(np.ascontiguousarray(s0[:, d]), device=dev) for d in range(3)]
-    p_init = [torch.tensor(np.ascontiguousarray(p0[:, d]), device=dev) for d in range(3)]
+    print(f"[bench] initial conditions: {np_}^3 2LPT at a=1/64, forward PM to a=1", file=sys.stderr,
+          flush=True)
+    noise = torch.tensor(synth.white_noise(args.seed, np_).astype(np.float32).ravel(), device=dev)
+    s_init = [torch.empty(P, device=dev) for _ in range(3)]
+    p_init = [torch.empty(P, device=dev) for _ in range(3)]
+    fwd = cfg["fwd_sched"]
+    sim_f = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(fwd) - 1, sched=fwd,
+                           omega_m=cfg["omega_m"], dtype="f32", device="cuda:0")
+    sim_f.ic_2lpt(noise, s_init, p_init, hrt.ic_params(omega_b=cfg["omega_b"], h=cfg["h"],
+                                                       n_s=cfg["n_s"], sigma8=cfg["sigma8"],
+                                                       a=fwd[0]))
+    for k in range(len(fwd)):          # steps 0..N-1 and the closing half-kick N
+        sim_f.pm_step(s_init, p_init, k)
+    torch.cuda.synchronize()
+    sim_f.close()
+    del sim_f, noise
     s = [t.clone() for t in s_init]
     p = [t.clone() for t in p_init]
     dth = [torch.zeros(nrays, device=dev) for _ in range(2)]
@@ -205,8 +219,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded clustered particle displacements and momenta; rays start at "
-                "theta0 with zero momentum)",
+        "data": "synthetic: seeded white noise -> 2LPT at a=1/64 -> 64 forward PM steps on the GPU "
+                "(untimed); rays start at theta0 with zero momentum",
         "config": {"workload": "lcdm256: LambdaCDM PM + HRT, 256^3 particles on a 256^3 mesh, box "
                                "400 Mpc/h replicated, 512^2 rays over 5x5 deg, 64 steps a=1->0.5",
                    "mesh": n, "particles": P, "rays": nrays, "box": box, "schedule_steps": N},

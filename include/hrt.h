@@ -134,6 +134,32 @@ int hrt_tables(const hrt_config *cfg, double *a, double *chi, double *K, double 
                double *d, int32_t *plane_begin, int32_t *plane_count, int32_t *plane_mesh,
                double *plane_chi, double *plane_w, int32_t max_planes, int32_t *n_planes);
 
+/* Initial conditions (support for the cosmological runs; the paper starts from 2LPT at
+ * a = 1/64, Sec. 5.2, without giving the recipe). Linear spectrum at a = 1:
+ * P(k) = A k^n_s T(k)^2 with the Eisenstein & Hu (1998) no-wiggle transfer function and A
+ * fixed by sigma8 (top-hat of 8 Mpc/h); field on the particle lattice
+ * delta_k = FFT(noise)_k sqrt(P(k) / (box/np)^3) (k = 0 removed); second-order Lagrangian
+ * displacement s = D1 s1 + D2 s2 with s1 = -grad phi1, grad^2 phi1 = delta,
+ * s2 = grad phi2, grad^2 phi2 = sum_{i<j} (phi1_ii phi1_jj - phi1_ij^2), growth factors from
+ * the growth ODEs normalised to D1(1) = 1, and p = a^2 E(a) (f1 D1 s1 + f2 D2 s2). */
+typedef struct {
+    double omega_b;         /* baryon density parameter (transfer-function shape only) */
+    double h;               /* H0 / (100 km/s/Mpc)                                      */
+    double n_s;             /* primordial spectral index                                */
+    double sigma8;          /* rms linear density contrast in 8 Mpc/h spheres at a = 1  */
+    double t_cmb;           /* CMB temperature [K]                                      */
+    double a;               /* scale factor of the returned state, 0 < a <= 1           */
+} hrt_ic_params;
+
+/* Writes the 2LPT state at scale factor ic->a into out (all six arrays) from the unit
+ * white noise `noise` (device, np^3 values of the config's dtype, layout [z][y][x]). Uses
+ * the workspace as scratch (it overwrites the force mesh). Needs 16 <= np. */
+int hrt_ic_2lpt(hrt_ctx *ctx, const void *noise, const hrt_ic_params *ic, const hrt_matter *out);
+
+/* Host-only: out[0..5] = amplitude A, D1(a), f1(a), D2(a), f2(a), D1(1) (growth factors
+ * with D1 -> a deep in matter domination) for cfg and ic. */
+int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out);
+
 /* Optional per-kernel timing with HIP events recorded on the context's stream around
  * every kernel launch (for measurement; off by default). hrt_profile_enable(ctx, 1)
  * clears the totals and starts recording, 0 stops. hrt_profile_read synchronises the

@@ -28,6 +28,8 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
     L.mesh_r = take(2 * n3 * T);                        // delta, then phi
     L.spec = take((n / 2 + 1) * n * n * 2 * T);
+    const size_t np = (size_t)cfg.ptcl_n;
+    L.spec2 = take((np / 2 + 1) * np * np * 2 * T);      // second spectrum for the initial conditions
     L.grad = take(n3 * 4 * T);                          // (G_x, G_y, G_z, 0) per node
     L.twiddle = take(n * 2 * T);
     L.bins = take((size_t)(L.nbins + L.nbins + 1 + nblk + 1) * 4);
@@ -307,6 +309,36 @@ extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *kappa, void 
     if (c->mx == 0) return fail(c, HRT_ESTATE, "configuration has no rays");
     if (!r || !r->dth[0] || !r->dth[1] || !kappa) return fail(c, HRT_EINVAL, "NULL argument");
     return check_hip(c, hrt::launch_convergence(c, r, kappa, gamma1, gamma2, omega), "convergence");
+}
+
+extern "C" int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out) {
+    if (!cfg || !ic || !out) return fail(nullptr, HRT_EINVAL, "NULL argument");
+    std::string err;
+    int rc = hrt::validate_config(*cfg, err);
+    if (rc) return fail(nullptr, rc, err);
+    hrt::IcParams p;
+    rc = hrt::ic_params(*cfg, *ic, p, err);
+    if (rc) return fail(nullptr, rc, err);
+    out[0] = p.amp;
+    out[1] = p.D1;
+    out[2] = p.f1;
+    out[3] = p.D2;
+    out[4] = p.f2;
+    out[5] = p.D1_today;
+    return HRT_OK;
+}
+
+extern "C" int hrt_ic_2lpt(hrt_ctx *c, const void *noise, const hrt_ic_params *ic, const hrt_matter *out) {
+    if (!c) return HRT_EINVAL;
+    if (!noise || !ic) return fail(c, HRT_EINVAL, "NULL argument");
+    if (int rc = check_matter(c, out, true)) return rc;
+    if (c->np < 16) return fail(c, HRT_EUNSUPPORTED, "initial conditions need ptcl_n >= 16");
+    hrt::IcParams p;
+    std::string err;
+    if (int rc = hrt::ic_params(c->cfg, *ic, p, err)) return fail(c, rc, err);
+    if (int rc = check_hip(c, hrt::launch_ic(c, noise, p, out), "initial conditions")) return rc;
+    c->force_step = -1;          // the force mesh was used as scratch
+    return HRT_OK;
 }
 
 extern "C" int hrt_mesh_ptr(const hrt_ctx *c, int which, void **ptr) {

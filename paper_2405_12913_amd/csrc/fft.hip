@@ -96,10 +96,12 @@ struct Cfg {
     static constexpr int LINES = ELEMS / N;                        // y and z passes
 };
 
+// tws: stride of the twiddle table (its size over N) when transforming a lattice smaller
+// than the mesh the table was built for.
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_r2c_kernel(const T *__restrict__ in,
                                                          c2<T> *__restrict__ out,
-                                                         const c2<T> *__restrict__ tw) {
+                                                         const c2<T> *__restrict__ tw, int tws) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
     const int row0 = blockIdx.x * ROWS;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(const T *__restrict__ i
         buf[r * LS + m] = reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + r) * N)[m];
     }
     __syncthreads();
-    fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, N / L);
+    fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, tws * (N / L));
     // split step: X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) W_N^k (Z[k] - conj Z[L-k]),
     // each thread owns the pair (k, L-k); X[L] (Nyquist) comes from Z[0].
     for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(const T *__restrict__ i
         c2<T> *line = buf + r * LS;
         const c2<T> zk = line[k];
         const c2<T> zp = line[k == 0 ? 0 : L - k];
-        const c2<T> w = tw[k];
+        const c2<T> w = tw[k * tws];
         // A = zk + conj(zp), B = zk - conj(zp); X[k] = A/2 - (i/2) w B
         const c2<T> A{zk.x + zp.x, zk.y - zp.y}, B{zk.x - zp.x, zk.y + zp.y};
         const c2<T> wB = cmul<T>(w, B);
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(const T *__restrict__ i
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_c2r_kernel(const c2<T> *__restrict__ in,
                                                          T *__restrict__ out,
-                                                         const c2<T> *__restrict__ tw) {
+                                                         const c2<T> *__restrict__ tw, int tws) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
     const int row0 = blockIdx.x * ROWS;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(const c2<T> *__restrict
         const int r = e / (L / 2 + 1), k = e % (L / 2 + 1);
         c2<T> *line = buf + r * LS;
         const c2<T> xk = line[k], xp = line[L - k];
-        const c2<T> w = tw[k];
+        const c2<T> w = tw[k * tws];
         const c2<T> wc{w.x, -w.y};
         const c2<T> A{xk.x + xp.x, xk.y - xp.y}, B{xk.x - xp.x, xk.y + xp.y};
         const c2<T> wB = cmul<T>(wc, B);
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(const c2<T> *__restrict
         }
     }
     __syncthreads();
-    fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, N / L);
+    fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, tws * (N / L));
     for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
         const int r = e / L, m = e % L;
         reinterpret_cast<c2<T> *>(out + (size_t)(row0 + r) * N)[m] = buf[r * LS + m];
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(const c2<T> *__restrict
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kThreads) void y_lines_kernel(c2<T> *__restrict__ data,
                                                            const c2<T> *__restrict__ tw,
-                                                           int total_lines) {
+                                                           int total_lines, int tws) {
     constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
     __shared__ c2<T> buf[LINES * LS];
     const int l0 = blockIdx.x * LINES;
@@ -189,19 +191,18 @@ __global__ __launch_bounds__(kThreads) void y_lines_kernel(c2<T> *__restrict__ d
         if (l0 + li < total_lines) buf[li * LS + m] = data[(size_t)(l0 + li) * N + m];
     }
     __syncthreads();
-    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, 1);
+    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int li = e / N, m = e % N;
         if (l0 + li < total_lines) data[(size_t)(l0 + li) * N + m] = buf[li * LS + m];
     }
 }
 
-// Forward FFT along z, Green's function, inverse FFT along z. Line l = kx * N + y.
-template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void z_poisson_kernel(c2<T> *__restrict__ data,
-                                                             const c2<T> *__restrict__ tw,
-                                                             int total_lines, double kf2,
-                                                             double inv_n3) {
+// FFT along z alone (forward or inverse), line l = kx * N + y, element stride N.
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(kThreads) void z_lines_kernel(c2<T> *__restrict__ data,
+                                                           const c2<T> *__restrict__ tw,
+                                                           int total_lines, int tws) {
     constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
     __shared__ c2<T> buf[LINES * LS];
     const int l0 = blockIdx.x * LINES;
@@ -210,7 +211,28 @@ __global__ __launch_bounds__(kThreads) void z_poisson_kernel(c2<T> *__restrict__
         if (l < total_lines) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
     }
     __syncthreads();
-    fft_stage<T, N, LINES, false, 1>(buf, LS, tw, 1);
+    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, tws);
+    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
+        const int z = e / LINES, li = e % LINES, l = l0 + li;
+        if (l < total_lines) data[((size_t)(l / N) * N + z) * N + (l % N)] = buf[li * LS + z];
+    }
+}
+
+// Forward FFT along z, Green's function, inverse FFT along z. Line l = kx * N + y.
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void z_poisson_kernel(c2<T> *__restrict__ data,
+                                                             const c2<T> *__restrict__ tw,
+                                                             int total_lines, double kf2,
+                                                             double inv_n3, int tws) {
+    constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
+    __shared__ c2<T> buf[LINES * LS];
+    const int l0 = blockIdx.x * LINES;
+    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
+        const int z = e / LINES, li = e % LINES, l = l0 + li;
+        if (l < total_lines) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
+    }
+    __syncthreads();
+    fft_stage<T, N, LINES, false, 1>(buf, LS, tw, tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int li = e / N, kz = e % N, l = l0 + li;
         const int kx = l / N, ky = l % N;
@@ -221,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void z_poisson_kernel(c2<T> *__restrict__
         buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
     }
     __syncthreads();
-    fft_stage<T, N, LINES, true, 1>(buf, LS, tw, 1);
+    fft_stage<T, N, LINES, true, 1>(buf, LS, tw, tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int z = e / LINES, li = e % LINES, l = l0 + li;
         if (l < total_lines) data[((size_t)(l / N) * N + z) * N + (l % N)] = buf[li * LS + z];
@@ -267,22 +289,174 @@ hipError_t poisson_n(hrt_ctx *c) {
     const int lblocks = (total_lines + LINES - 1) / LINES;
     const double kf = 2.0 * 3.14159265358979323846 / c->box;
     prof_begin(c);
-    x_r2c_kernel<T, N><<<xblocks, kThreads, 0, st>>>(delta, spec, tw);
+    x_r2c_kernel<T, N><<<xblocks, kThreads, 0, st>>>(delta, spec, tw, 1);
     prof_end(c, K_FFT_X_R2C);
     prof_begin(c);
-    y_lines_kernel<T, N, false><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines);
+    y_lines_kernel<T, N, false><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines, 1);
     prof_end(c, K_FFT_Y_FWD);
     prof_begin(c);
     z_poisson_kernel<T, N><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines, kf * kf,
-                                                          1.0 / ((double)N * N * N));
+                                                          1.0 / ((double)N * N * N), 1);
     prof_end(c, K_FFT_Z_POISSON);
     prof_begin(c);
-    y_lines_kernel<T, N, true><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines);
+    y_lines_kernel<T, N, true><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines, 1);
     prof_end(c, K_FFT_Y_INV);
     prof_begin(c);
-    x_c2r_kernel<T, N><<<xblocks, kThreads, 0, st>>>(spec, phi, tw);
+    x_c2r_kernel<T, N><<<xblocks, kThreads, 0, st>>>(spec, phi, tw, 1);
     prof_end(c, K_FFT_X_C2R);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Initial conditions: Gaussian field with the Eisenstein-Hu no-wiggle spectrum and its
+// 2LPT displacements (standard recipe; the paper starts from 2LPT at a = 1/64, Sec. 5.2).
+// Spectra use the transposed layout [kx][kz][ky] left by the forward passes. Derivatives
+// use i k_d with the Nyquist wavenumber zeroed; second derivatives apply it twice.
+
+enum { OP_PHI1 = 0, OP_GRAD = 1, OP_HESS = 2, OP_INVLAP = 3 };
+
+__device__ __forceinline__ double eh_nowiggle(double k, const IcParams &p) {
+    const double ks = 0.43 * k * p.h * p.s_sound;
+    const double gamma_eff = p.omega_m * p.h * (p.alpha + (1.0 - p.alpha) / (1.0 + ks * ks * ks * ks));
+    const double q = k * p.theta2 / gamma_eff;
+    const double l0 = log(2.0 * 2.718281828459045 + 1.8 * q);
+    const double c0 = 14.2 + 731.0 / (1.0 + 62.5 * q);
+    return l0 / (l0 + c0 * q * q);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void spec_op_kernel(const c2<T> *__restrict__ in,
+                                                           c2<T> *__restrict__ out, int op, int a,
+                                                           int b, double scale, IcParams p) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= (int64_t)(N / 2 + 1) * N * N) return;
+    const int iky = (int)(e % N), ikz = (int)((e / N) % N), ikx = (int)(e / ((int64_t)N * N));
+    const int fy = iky <= N / 2 ? iky : iky - N, fz = ikz <= N / 2 ? ikz : ikz - N;
+    const double kf = p.kf;
+    const double k2 = kf * kf * (double)(ikx * ikx + fy * fy + fz * fz);
+    // derivative wavenumbers with the Nyquist entry zeroed
+    const double kd[3] = {ikx == N / 2 ? 0.0 : kf * ikx, iky == N / 2 ? 0.0 : kf * fy,
+                          ikz == N / 2 ? 0.0 : kf * fz};
+    const c2<T> v = in[e];
+    double re = 0.0, im = 0.0;        // factor re + i im
+    if (k2 > 0.0) {
+        if (op == OP_PHI1) {
+            const double k = sqrt(k2), t = eh_nowiggle(k, p);
+            re = -sqrt(p.amp * pow(k, p.n_s) * t * t / p.cell_volume) / k2 * scale;
+        } else if (op == OP_GRAD) {
+            im = kd[a] * scale;
+        } else if (op == OP_HESS) {
+            re = -kd[a] * kd[b] * scale;
+        } else {
+            re = -scale / k2;
+        }
+    }
+    out[e] = c2<T>{(T)(re * v.x - im * v.y), (T)(re * v.y + im * v.x)};
+}
+
+template <typename T>
+__global__ void lpt_source_diag_kernel(const T *__restrict__ A, const T *__restrict__ B,
+                                       const T *__restrict__ C, T *__restrict__ src, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < P) src[i] = A[i] * B[i] + A[i] * C[i] + B[i] * C[i];
+}
+
+template <typename T>
+__global__ void lpt_source_off_kernel(const T *__restrict__ t, T *__restrict__ src, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < P) src[i] -= t[i] * t[i];
+}
+
+// s = g1 s1 + g2 s2, p = m1 s1 + m2 s2 (s holds s1, p holds s2 on entry)
+template <typename T>
+__global__ void lpt_combine_kernel(T *__restrict__ s, T *__restrict__ p, int64_t P, double g1,
+                                   double g2, double m1, double m2) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < P) {
+        const double a = s[i], b = p[i];
+        s[i] = (T)(g1 * a + g2 * b);
+        p[i] = (T)(m1 * a + m2 * b);
+    }
+}
+
+template <typename T, int N>
+void fwd3d(hrt_ctx *c, const T *real_in, c2<T> *spec, int tws) {
+    constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
+    const int total_lines = (N / 2 + 1) * N, lblocks = (total_lines + LINES - 1) / LINES;
+    const c2<T> *tw = reinterpret_cast<const c2<T> *>(c->ws + c->lay.twiddle);
+    x_r2c_kernel<T, N><<<N * N / XROWS, kThreads, 0, c->stream>>>(real_in, spec, tw, tws);
+    y_lines_kernel<T, N, false><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
+    z_lines_kernel<T, N, false><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
+}
+
+template <typename T, int N>
+void inv3d(hrt_ctx *c, c2<T> *spec, T *real_out, int tws) {
+    constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
+    const int total_lines = (N / 2 + 1) * N, lblocks = (total_lines + LINES - 1) / LINES;
+    const c2<T> *tw = reinterpret_cast<const c2<T> *>(c->ws + c->lay.twiddle);
+    z_lines_kernel<T, N, true><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
+    y_lines_kernel<T, N, true><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
+    x_c2r_kernel<T, N><<<N * N / XROWS, kThreads, 0, c->stream>>>(spec, real_out, tw, tws);
+}
+
+template <typename T, int N>
+hipError_t ic_n(hrt_ctx *c, const T *noise, const IcParams &p, const hrt_matter *m) {
+    const int tws = c->n / N;
+    const int64_t P = (int64_t)N * N * N;
+    const int64_t ns = (int64_t)(N / 2 + 1) * N * N;
+    const int sblocks = (int)((ns + kThreads - 1) / kThreads), pblocks = (int)((P + kThreads - 1) / kThreads);
+    c2<T> *base = reinterpret_cast<c2<T> *>(c->ws + c->lay.spec2);
+    c2<T> *work = reinterpret_cast<c2<T> *>(c->ws + c->lay.spec);
+    T *scratch = reinterpret_cast<T *>(c->ws + c->lay.grad);        // 4 lattices of P values
+    T *A = scratch, *B = scratch + P, *C = scratch + 2 * P, *tmp = scratch + 3 * P;
+    T *src = reinterpret_cast<T *>(c->ws + c->lay.mesh_r);
+    T *s[3] = {static_cast<T *>(m->s[0]), static_cast<T *>(m->s[1]), static_cast<T *>(m->s[2])};
+    T *q[3] = {static_cast<T *>(m->p[0]), static_cast<T *>(m->p[1]), static_cast<T *>(m->p[2])};
+    const double inv_n3 = 1.0 / (double)P;
+    hipStream_t st = c->stream;
+    fwd3d<T, N>(c, noise, base, tws);
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_PHI1, 0, 0, 1.0, p);
+    for (int d = 0; d < 3; ++d) {          // s1 = -grad phi1
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, -inv_n3, p);
+        inv3d<T, N>(c, work, s[d], tws);
+    }
+    T *diag[3] = {A, B, C};
+    for (int d = 0; d < 3; ++d) {
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, d, d, inv_n3, p);
+        inv3d<T, N>(c, work, diag[d], tws);
+    }
+    lpt_source_diag_kernel<T><<<pblocks, kThreads, 0, st>>>(A, B, C, src, P);
+    const int off[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int k = 0; k < 3; ++k) {
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, off[k][0], off[k][1],
+                                                           inv_n3, p);
+        inv3d<T, N>(c, work, tmp, tws);
+        lpt_source_off_kernel<T><<<pblocks, kThreads, 0, st>>>(tmp, src, P);
+    }
+    fwd3d<T, N>(c, src, base, tws);
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_INVLAP, 0, 0, 1.0, p);
+    for (int d = 0; d < 3; ++d) {          // s2 = +grad phi2, parked in the momentum arrays
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, inv_n3, p);
+        inv3d<T, N>(c, work, q[d], tws);
+    }
+    for (int d = 0; d < 3; ++d)
+        lpt_combine_kernel<T><<<pblocks, kThreads, 0, st>>>(s[d], q[d], P, p.g1, p.g2, p.m1, p.m2);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t ic_impl(hrt_ctx *c, const void *noise, const IcParams &p, const hrt_matter *m) {
+    const T *nz = static_cast<const T *>(noise);
+    switch (c->np) {
+        case 16: return ic_n<T, 16>(c, nz, p, m);
+        case 32: return ic_n<T, 32>(c, nz, p, m);
+        case 64: return ic_n<T, 64>(c, nz, p, m);
+        case 128: return ic_n<T, 128>(c, nz, p, m);
+        case 256: return ic_n<T, 256>(c, nz, p, m);
+        case 512: return ic_n<T, 512>(c, nz, p, m);
+        case 1024: return ic_n<T, 1024>(c, nz, p, m);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -317,6 +491,10 @@ hipError_t gradient_impl(hrt_ctx *c) {
 
 hipError_t launch_poisson(hrt_ctx *c) {
     return c->f64 ? poisson_impl<double>(c) : poisson_impl<float>(c);
+}
+
+hipError_t launch_ic(hrt_ctx *c, const void *noise, const IcParams &p, const hrt_matter *m) {
+    return c->f64 ? ic_impl<double>(c, noise, p, m) : ic_impl<float>(c, noise, p, m);
 }
 
 hipError_t launch_gradient(hrt_ctx *c) {

@@ -24,6 +24,17 @@ struct StepTables {
 int build_tables(const hrt_config &cfg, StepTables &t, std::string &err);
 int validate_config(const hrt_config &cfg, std::string &err);
 
+// Everything the device needs for the 2LPT initial conditions (host FP64, see tables.cpp).
+struct IcParams {
+    double kf;              // 2 pi / box
+    double cell_volume;     // (box / np)^3
+    double amp, n_s;        // P(k) = amp k^n_s T(k)^2, sigma_8 normalised at a = 1
+    double omega_m, h, s_sound, alpha, theta2;   // Eisenstein-Hu no-wiggle parameters
+    double g1, g2, m1, m2;  // s = g1 s1 + g2 s2, p = m1 s1 + m2 s2 at the requested a
+    double D1, f1, D2, f2, D1_today;   // growth factors (reported by hrt_ic_factors)
+};
+int ic_params(const hrt_config &cfg, const hrt_ic_params &in, IcParams &out, std::string &err);
+
 // Device-side plane entry (one per shell plane).
 struct PlaneEntry {
     double chi;        // comoving distance of the plane [Mpc/h]
@@ -34,7 +45,7 @@ struct PlaneEntry {
 
 // Workspace carve-up, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
-    size_t mesh_r, spec, grad, twiddle, bins, cursor, sorted, planes, total;
+    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, total;
     int64_t nbins;
 };
 Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
@@ -83,6 +94,7 @@ void prof_end(hrt_ctx *c, int id);     // record the stop event of kernel `id`
 hipError_t launch_paint(hrt_ctx *c, const hrt_matter *m);
 hipError_t launch_poisson(hrt_ctx *c);
 hipError_t launch_gradient(hrt_ctx *c);
+hipError_t launch_ic(hrt_ctx *c, const void *noise, const IcParams &p, const hrt_matter *m);
 hipError_t launch_matter_kd(hrt_ctx *c, const hrt_matter *m, double K, double D);
 hipError_t launch_ray_step(hrt_ctx *c, const hrt_rays *r, int begin, int count, double d);
 hipError_t launch_convergence(hrt_ctx *c, const hrt_rays *r, void *kappa, void *g1, void *g2,

@@ -52,21 +52,36 @@ double gk15(const std::function<double(double)> &f, double a, double b, double *
     return rk * h;
 }
 
-double integrate_rec(const std::function<double(double)> &f, double a, double b, double tol,
-                     int depth) {
-    double err;
-    double r = gk15(f, a, b, &err);
-    if (err <= tol || depth > 40) return r;
-    double m = 0.5 * (a + b);
-    return integrate_rec(f, a, m, 0.5 * tol, depth + 1) + integrate_rec(f, m, b, 0.5 * tol, depth + 1);
-}
-
+// Global adaptive quadrature: keep bisecting the sub-interval with the largest error
+// estimate until the summed error is below 1e-14 of the result (or 1e-300 absolute), with
+// at most 2000 sub-intervals, so the cost is bounded whatever the integrand.
 double integrate(const std::function<double(double)> &f, double a, double b) {
     if (a == b) return 0.0;
+    struct Piece { double a, b, val, err; };
+    std::vector<Piece> pieces;
+    pieces.reserve(2048);
     double err;
-    double guess = std::fabs(gk15(f, a, b, &err));
-    double tol = std::max(guess, 1e-300) * 1e-15;
-    return integrate_rec(f, a, b, tol, 0);
+    double val = gk15(f, a, b, &err);
+    pieces.push_back({a, b, val, err});
+    for (int it = 0; it < 2000; ++it) {
+        double total = 0.0, total_err = 0.0;
+        size_t worst = 0;
+        for (size_t i = 0; i < pieces.size(); ++i) {
+            total += pieces[i].val;
+            total_err += pieces[i].err;
+            if (pieces[i].err > pieces[worst].err) worst = i;
+        }
+        if (total_err <= std::max(1e-14 * std::fabs(total), 1e-300)) break;
+        const Piece p = pieces[worst];
+        const double m = 0.5 * (p.a + p.b);
+        double e1, e2;
+        const double v1 = gk15(f, p.a, m, &e1), v2 = gk15(f, m, p.b, &e2);
+        pieces[worst] = {p.a, m, v1, e1};
+        pieces.push_back({m, p.b, v2, e2});
+    }
+    double total = 0.0;
+    for (const Piece &p : pieces) total += p.val;
+    return total;
 }
 
 struct Cosmo {
@@ -121,7 +136,106 @@ void shell_planes(double x0, double x1, double cell, double z_obs, std::vector<i
     }
 }
 
+// Growth ODEs in ln a (' = d/dln a, Om(a) = om a^-3 / E^2):
+//   D1'' + (2 + dlnE/dlna) D1' - 1.5 Om(a) D1 = 0
+//   D2'' + (2 + dlnE/dlna) D2' - 1.5 Om(a) D2 = -1.5 Om(a) D1^2
+// from deep matter domination (D1 = a, D2 = -3/7 a^2), classical RK4 in ln a.
+void growth_rk4(double om, double a_end, double out[4]) {
+    const double ol = 1.0 - om;
+    auto rhs = [&](double lna, const double *y, double *dy) {
+        const double a = std::exp(lna);
+        const double e2 = om / (a * a * a) + ol;
+        const double oma = om / (a * a * a) / e2;
+        const double dlnE = -1.5 * oma;
+        dy[0] = y[1];
+        dy[1] = -(2.0 + dlnE) * y[1] + 1.5 * oma * y[0];
+        dy[2] = y[3];
+        dy[3] = -(2.0 + dlnE) * y[3] + 1.5 * oma * y[2] - 1.5 * oma * y[0] * y[0];
+    };
+    const double a0 = 1e-5;
+    double y[4] = {a0, a0, -3.0 / 7.0 * a0 * a0, -6.0 / 7.0 * a0 * a0};
+    const double x0 = std::log(a0), x1 = std::log(a_end);
+    const int steps = 20000;
+    const double h = (x1 - x0) / steps;
+    double k1[4], k2[4], k3[4], k4[4], t[4];
+    for (int s = 0; s < steps; ++s) {
+        const double x = x0 + s * h;
+        rhs(x, y, k1);
+        for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k1[i];
+        rhs(x + 0.5 * h, t, k2);
+        for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k2[i];
+        rhs(x + 0.5 * h, t, k3);
+        for (int i = 0; i < 4; ++i) t[i] = y[i] + h * k3[i];
+        rhs(x + h, t, k4);
+        for (int i = 0; i < 4; ++i) y[i] += h / 6.0 * (k1[i] + 2 * k2[i] + 2 * k3[i] + k4[i]);
+    }
+    out[0] = y[0];
+    out[1] = y[1] / y[0];
+    out[2] = y[2];
+    out[3] = y[3] / y[2];
+}
+
 }  // namespace
+
+// Eisenstein & Hu (1998) no-wiggle transfer function parameters (their Eqs. 26, 31),
+// sigma_8 normalisation (top-hat of 8 Mpc/h at a = 1) and the 2LPT growth factors.
+int ic_params(const hrt_config &c, const hrt_ic_params &in, IcParams &p, std::string &err) {
+    if (c.flags & HRT_STATIC) { err = "initial conditions need a cosmological configuration"; return HRT_ESTATE; }
+    if (!(in.a > 0 && in.a <= 1) || !(in.h > 0) || !(in.sigma8 > 0) || !(in.omega_b >= 0) ||
+        !(in.omega_b < c.omega_m) || !(in.t_cmb > 0) || !std::isfinite(in.n_s)) {
+        err = "invalid initial-condition parameters";
+        return HRT_EINVAL;
+    }
+    const double om = c.omega_m, h = in.h;
+    const double theta = in.t_cmb / 2.7, om_h2 = om * h * h, ob_h2 = in.omega_b * h * h;
+    const double fb = in.omega_b / om;
+    p.omega_m = om;
+    p.h = h;
+    p.n_s = in.n_s;
+    p.s_sound = 44.5 * std::log(9.83 / om_h2) / std::sqrt(1.0 + 10.0 * std::pow(ob_h2, 0.75));
+    p.alpha = 1.0 - 0.328 * std::log(431.0 * om_h2) * fb + 0.38 * std::log(22.3 * om_h2) * fb * fb;
+    p.theta2 = theta * theta;
+    auto transfer = [&](double k) {
+        const double ks = 0.43 * k * h * p.s_sound;
+        const double ge = om * h * (p.alpha + (1.0 - p.alpha) / (1.0 + ks * ks * ks * ks));
+        const double q = k * p.theta2 / ge;
+        const double l0 = std::log(2.0 * 2.718281828459045 + 1.8 * q);
+        const double c0 = 14.2 + 731.0 / (1.0 + 62.5 * q);
+        return l0 / (l0 + c0 * q * q);
+    };
+    const double R = 8.0;
+    auto integrand = [&](double lnk) {
+        const double k = std::exp(lnk), x = k * R;
+        const double w = 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+        const double tk = transfer(k);
+        return k * k * k * std::pow(k, in.n_s) * tk * tk * w * w;
+    };
+    // split the range so the adaptive rule follows the top-hat's oscillations
+    double s2 = 0.0;
+    const double lo = std::log(1e-5), hi = std::log(1e3);
+    const int pieces = 64;
+    for (int i = 0; i < pieces; ++i)
+        s2 += integrate(integrand, lo + (hi - lo) * i / pieces, lo + (hi - lo) * (i + 1) / pieces);
+    s2 /= 2.0 * kPi * kPi;
+    p.amp = in.sigma8 * in.sigma8 / s2;
+    const double box = c.box;
+    p.kf = 2.0 * kPi / box;
+    p.cell_volume = std::pow(box / c.ptcl_n, 3);
+    double ga[4], g0[4];
+    growth_rk4(om, in.a, ga);
+    growth_rk4(om, 1.0, g0);
+    p.D1 = ga[0];
+    p.f1 = ga[1];
+    p.D2 = ga[2];
+    p.f2 = ga[3];
+    p.D1_today = g0[0];
+    p.g1 = ga[0] / g0[0];
+    p.g2 = ga[2] / (g0[0] * g0[0]);
+    const double mom = in.a * in.a * std::sqrt(om / (in.a * in.a * in.a) + 1.0 - om);
+    p.m1 = mom * ga[1] * p.g1;
+    p.m2 = mom * ga[3] * p.g2;
+    return HRT_OK;
+}
 
 int validate_config(const hrt_config &c, std::string &err) {
     auto bad = [&](const char *m) { err = m; return HRT_EINVAL; };

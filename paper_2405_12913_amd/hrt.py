@@ -21,7 +21,8 @@ HRT_NUM_KERNELS = 13
 
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
             "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",
-            "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name")
+            "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
+            "hrt_ic_factors")
 
 
 class HrtConfig(ctypes.Structure):
@@ -38,6 +39,15 @@ class HrtMatter(ctypes.Structure):
 
 class HrtRays(ctypes.Structure):
     _fields_ = [("dth", c_void_p * 2), ("p", c_void_p * 2)]
+
+
+class HrtIcParams(ctypes.Structure):
+    _fields_ = [("omega_b", c_double), ("h", c_double), ("n_s", c_double), ("sigma8", c_double),
+                ("t_cmb", c_double), ("a", c_double)]
+
+
+def ic_params(*, omega_b=0.045, h=0.7, n_s=0.96, sigma8=0.8, t_cmb=2.7255, a=1.0 / 64.0):
+    return HrtIcParams(omega_b, h, n_s, sigma8, t_cmb, a)
 
 
 class HRTError(RuntimeError):
@@ -70,6 +80,8 @@ def lib():
             [P(c_double)] * 2 + [c_int32, P(c_int32)]
         L.hrt_profile_enable.argtypes = [c_void_p, c_int]
         L.hrt_profile_read.argtypes = [c_void_p, P(c_double), P(ctypes.c_int64), c_int]
+        L.hrt_ic_2lpt.argtypes = [c_void_p, c_void_p, P(HrtIcParams), P(HrtMatter)]
+        L.hrt_ic_factors.argtypes = [P(HrtConfig), P(HrtIcParams), P(c_double)]
         L.hrt_kernel_name.argtypes = [c_int]
         L.hrt_kernel_name.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -132,6 +144,13 @@ def hrt_tables(cfg):
     k = n_planes.value
     arrs.update(plane_begin=pb, plane_count=pc, plane_mesh=pm[:k], plane_chi=pchi[:k], plane_w=pw[:k])
     return arrs
+
+
+def hrt_ic_factors(cfg, ic):
+    """(A, D1(a), f1(a), D2(a), f2(a), D1(1)) of the initial conditions (host only)."""
+    out = (c_double * 6)()
+    _check(lib().hrt_ic_factors(ctypes.byref(cfg), ctypes.byref(ic), out))
+    return tuple(out)
 
 
 def _ptr(t, dtype, numel, what):
@@ -209,6 +228,12 @@ class Simulation:
         outs = [None if t is None else c_void_p(_ptr(t, self.dtype, self.n_rays, "output"))
                 for t in (kappa, gamma1, gamma2, omega)]
         _check(lib().ray_convergence(self.ctx, ctypes.byref(r), *outs), self.ctx)
+
+    def ic_2lpt(self, noise, s, p, ic):
+        """2LPT state at ic.a from unit white noise (device tensor, np^3, [z][y][x])."""
+        nz = _ptr(noise, self.dtype, self.n_particles, "noise")
+        _check(lib().hrt_ic_2lpt(self.ctx, c_void_p(nz), ctypes.byref(ic),
+                                 ctypes.byref(self._matter(s, p))), self.ctx)
 
     def profile_enable(self, on=True):
         _check(lib().hrt_profile_enable(self.ctx, 1 if on else 0), self.ctx)

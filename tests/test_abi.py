@@ -98,3 +98,18 @@ def test_bad_schedule_rejected():
     cfg, keep = _cosmo_cfg(np.array([1.0, 0.8, 1.2]))
     with pytest.raises(hrt.HRTError, match="a schedule"):
         hrt.hrt_workspace_bytes(cfg)
+
+
+@pytest.mark.parametrize("om,a", [(0.3, 1 / 64), (0.25, 0.5), (1.0, 0.1)])
+def test_ic_factors_match_oracle(om, a):
+    from oracle import cosmo, ic
+    cfg, keep = _cosmo_cfg(np.linspace(1.0, 0.5, 5), om=om)
+    icp = hrt.ic_params(a=a)
+    amp, d1, f1, d2, f2, d1_today = hrt.hrt_ic_factors(cfg, icp)
+    shape = lambda k: np.asarray(k, float) ** 0.96 * ic.eh_nowiggle_transfer(k, om, 0.045, 0.7) ** 2
+    amp_o = (0.8 / ic.sigma_R(shape)) ** 2
+    assert amp == pytest.approx(amp_o, rel=1e-8)
+    D1, F1, D2, F2 = cosmo.growth_ode([a, 1.0], om)
+    assert d1 == pytest.approx(D1[0], rel=1e-9) and d1_today == pytest.approx(D1[1], rel=1e-9)
+    assert f1 == pytest.approx(F1[0], rel=1e-9) and f2 == pytest.approx(F2[0], rel=1e-9)
+    assert d2 == pytest.approx(D2[0], rel=1e-9)

@@ -203,3 +203,28 @@ def test_static_point_lens_parity(dtype):
     k_o = observables.convergence(d_o, M, M, cfg["fov"] / M, cfg["fov"] / M)
     k_g = kap.double().cpu().numpy().reshape(M, M)
     assert np.sqrt(np.mean((k_g - k_o) ** 2)) / np.sqrt(np.mean(k_o ** 2)) < (1e-9 if dtype == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("n,np_,dtype", [(32, 32, "f32"), (64, 32, "f32"), (32, 16, "f64")])
+def test_ic_2lpt_parity(n, np_, dtype):
+    import torch
+    from oracle import ic
+    from paper_2405_12913_amd import hrt
+    say(f"case 2LPT initial conditions n={n} np={np_} {dtype}")
+    box = np_ * 3.0
+    cfg = synth.tiny(mesh_n=n, ptcl_n=np_, box=box, ray_n=0, n_steps=4)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=4, sched=cfg["fwd_sched"][:5],
+                         omega_m=0.3, dtype=dtype)
+    noise = synth.white_noise(7, np_)
+    noise = noise.astype(np.float32).astype(np.float64) if dtype == "f32" else noise
+    nz = torch.tensor(noise.ravel(), dtype=tdt, device="cuda")
+    s = [torch.empty(np_ ** 3, dtype=tdt, device="cuda") for _ in range(3)]
+    p = [torch.empty(np_ ** 3, dtype=tdt, device="cuda") for _ in range(3)]
+    a = 1.0 / 64.0
+    sim.ic_2lpt(nz, s, p, hrt.ic_params(a=a))
+    torch.cuda.synchronize()
+    s_o, p_o = ic.lpt_state(noise, box, a, 0.3, 0.045, 0.7, 0.96, 0.8)
+    tol = 1e-9 if dtype == "f64" else 2e-5
+    assert rel_l2(Case.host(s), s_o) < tol
+    assert rel_l2(Case.host(p), p_o) < tol
