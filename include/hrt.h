@@ -30,6 +30,11 @@
  *   theta0 = ((ix + 1/2) - Mx/2, (iy + 1/2) - My/2) * fov/M (radians); the state stores
  *   dth = theta - theta0 and the canonical momentum p with d theta/d chi = p / chi^2.
  * - Determinism: no floating-point atomics anywhere; two runs give identical bits.
+ * - Batches: a context holds n_cfg >= 1 realisations (different seeds, cosmologies, mesh
+ *   sizes and ray grids; they must share dtype, n_steps, flags and whether they have
+ *   rays). Every step entry point then takes arrays of n_cfg state structs and launches
+ *   each kernel type once for all realisations (once per mesh size for the FFT passes).
+ *   Results per realisation are bit-identical to running it alone.
  */
 #ifndef HRT_H
 #define HRT_H
@@ -81,13 +86,15 @@ typedef struct { void *dth[2]; void *p[2]; } hrt_rays;   /* device SoA, Mx*My ea
 
 typedef struct hrt_ctx hrt_ctx;
 
-/* Bytes of device workspace needed for cfg. Pure host function. */
-int hrt_workspace_bytes(const hrt_config *cfg, size_t *bytes);
+/* Bytes of device workspace needed for the n_cfg configurations cfg[0..n_cfg-1].
+ * Pure host function. */
+int hrt_workspace_bytes(const hrt_config *cfg, int n_cfg, size_t *bytes);
 
-/* Validates cfg, builds the FP64 step tables on the host and uploads them into the
- * workspace (synchronously). stream is a hipStream_t (NULL = default stream).
+/* Validates cfg[0..n_cfg-1], builds the FP64 step tables on the host and uploads them
+ * into the workspace (synchronously). stream is a hipStream_t (NULL = default stream).
  * The context keeps no pointer to cfg or cfg->sched. */
-int hrt_init(const hrt_config *cfg, void *workspace, size_t ws_bytes, void *stream, hrt_ctx **out);
+int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes, void *stream,
+             hrt_ctx **out);
 
 /* Frees the host-side context (does not touch the caller's device memory). */
 int hrt_destroy(hrt_ctx *ctx);
@@ -98,7 +105,7 @@ const char *hrt_last_error(const hrt_ctx *ctx);
 /* Paint the matter at boundary `step` (0 <= step <= N) onto the mesh, solve
  * grad^2 phi = delta (delta = rho/rho_bar - 1, Sec. 2 Poisson equation without its
  * prefactor, which the step tables carry) and store G = grad(phi) in the workspace.
- * m->p may be NULL. */
+ * m points to n_cfg states; their p arrays may be NULL. */
 int pm_force(hrt_ctx *ctx, const hrt_matter *m, int step);
 
 /* pm_force, then the matter kick p += K_step * G(q + s) and drift s += D_step * p
@@ -114,16 +121,27 @@ int ray_step(hrt_ctx *ctx, const hrt_rays *r, int step);
 
 /* Finite-difference distortion matrix of the deflections over the pixel grid
  * (central inside, second-order one-sided on the edges) and kappa, gamma1, gamma2,
- * omega of Eq. obs_first_set. Outputs are device arrays of Mx*My values; any output
- * except kappa may be NULL. */
-int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *kappa, void *gamma1,
-                    void *gamma2, void *omega);
+ * omega of Eq. obs_first_set. Each output is an array of n_cfg device pointers to
+ * Mx*My values of the realisation; gamma1, gamma2 and omega may be NULL (the ray
+ * momenta in r may be NULL too). */
+int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *const *gamma1,
+                    void *const *gamma2, void *const *omega);
 
-/* Device pointer to an internal mesh in the workspace, valid until hrt_destroy:
- * HRT_MESH_DELTA (n^3, after pm_force: delta), HRT_MESH_PHI (n^3: phi),
+/* Captures steps first_step .. first_step+n_steps-1 (pm_step then ray_step for every
+ * realisation; with HRT_STATIC one pm_force then ray_steps; r may be NULL for matter
+ * only) into a HIP graph held by the context, replacing any previous one. Nothing runs
+ * during capture; hrt_graph_launch replays the whole sequence with one launch on the
+ * context's stream. The state arrays and workspace must stay the same between capture and
+ * replays. Profiling must be off while capturing. */
+int hrt_graph_capture(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step,
+                      int n_steps);
+int hrt_graph_launch(hrt_ctx *ctx);
+
+/* Device pointer to an internal mesh of realisation `realisation`, valid until
+ * hrt_destroy: HRT_MESH_DELTA (n^3, after pm_force: delta), HRT_MESH_PHI (n^3: phi),
  * HRT_MESH_GRAD (n^3 interleaved quadruples (G_x, G_y, G_z, 0)). */
 enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GRAD = 2 };
-int hrt_mesh_ptr(const hrt_ctx *ctx, int which, void **ptr);
+int hrt_mesh_ptr(const hrt_ctx *ctx, int realisation, int which, void **ptr);
 
 /* Host-only step tables for cfg (no GPU use), for checking the table builder.
  * Sizes: a, chi, K, D, d: N+1 doubles each; plane_begin, plane_count: N+1 ints;
@@ -151,10 +169,12 @@ typedef struct {
     double a;               /* scale factor of the returned state, 0 < a <= 1           */
 } hrt_ic_params;
 
-/* Writes the 2LPT state at scale factor ic->a into out (all six arrays) from the unit
- * white noise `noise` (device, np^3 values of the config's dtype, layout [z][y][x]). Uses
- * the workspace as scratch (it overwrites the force mesh). Needs 16 <= np. */
-int hrt_ic_2lpt(hrt_ctx *ctx, const void *noise, const hrt_ic_params *ic, const hrt_matter *out);
+/* Writes the 2LPT state of realisation `realisation` at scale factor ic->a into out (all
+ * six arrays) from the unit white noise `noise` (device, np^3 values of the config's
+ * dtype, layout [z][y][x]). Uses that realisation's workspace as scratch (it overwrites
+ * the force mesh). Needs 16 <= np. */
+int hrt_ic_2lpt(hrt_ctx *ctx, int realisation, const void *noise, const hrt_ic_params *ic,
+                const hrt_matter *out);
 
 /* Host-only: out[0..5] = amplitude A, D1(a), f1(a), D2(a), f2(a), D1(1) (growth factors
  * with D1 -> a deep in matter domination) for cfg and ic. */

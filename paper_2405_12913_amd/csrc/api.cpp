@@ -91,6 +91,7 @@ void prof_end(hrt_ctx *c, int id) {
 }  // namespace hrt
 
 hrt_ctx::~hrt_ctx() {
+    if (graph) hipGraphExecDestroy(graph);
     for (const hrt::ProfRecord &r : prof_pending) {
         hipEventDestroy(r.start);
         hipEventDestroy(r.stop);
@@ -141,13 +142,37 @@ static int check_hip(hrt_ctx *c, hipError_t e, const char *what) {
     return fail(c, HRT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-extern "C" int hrt_workspace_bytes(const hrt_config *cfg, size_t *bytes) {
+// Realisation r's part of a batched workspace starts at the sum of the previous parts.
+static int batch_layouts(const hrt_config *cfg, int n_cfg, std::vector<hrt::StepTables> *tabs,
+                         std::vector<hrt::Layout> &lays, std::string &err) {
+    if (!cfg || n_cfg < 1) { err = "need at least one configuration"; return HRT_EINVAL; }
+    lays.clear();
+    if (tabs) tabs->assign(n_cfg, hrt::StepTables());
+    for (int r = 0; r < n_cfg; ++r) {
+        const hrt_config &c0 = cfg[0], &c = cfg[r];
+        if (c.dtype != c0.dtype || c.n_steps != c0.n_steps || c.flags != c0.flags ||
+            (c.ray_nx > 0) != (c0.ray_nx > 0)) {
+            err = "batched configurations must share dtype, n_steps, flags and whether they have rays";
+            return HRT_EINVAL;
+        }
+        hrt::StepTables t;
+        int rc = hrt::build_tables(c, t, err);
+        if (rc) return rc;
+        lays.push_back(hrt::make_layout(c, (int64_t)t.plane_chi.size()));
+        if (tabs) (*tabs)[r] = std::move(t);
+    }
+    return HRT_OK;
+}
+
+extern "C" int hrt_workspace_bytes(const hrt_config *cfg, int n_cfg, size_t *bytes) {
     if (!cfg || !bytes) return fail(nullptr, HRT_EINVAL, "NULL argument");
-    hrt::StepTables t;
+    std::vector<hrt::Layout> lays;
     std::string err;
-    int rc = hrt::build_tables(*cfg, t, err);
+    int rc = batch_layouts(cfg, n_cfg, nullptr, lays, err);
     if (rc) return fail(nullptr, rc, err);
-    *bytes = hrt::make_layout(*cfg, (int64_t)t.plane_chi.size()).total;
+    size_t total = 0;
+    for (const hrt::Layout &L : lays) total += L.total;
+    *bytes = total;
     return HRT_OK;
 }
 
@@ -180,70 +205,75 @@ extern "C" int hrt_tables(const hrt_config *cfg, double *a, double *chi, double 
     return HRT_OK;
 }
 
-extern "C" int hrt_init(const hrt_config *cfg, void *workspace, size_t ws_bytes, void *stream,
-                        hrt_ctx **out) {
+extern "C" int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes,
+                        void *stream, hrt_ctx **out) {
     if (!cfg || !out) return fail(nullptr, HRT_EINVAL, "NULL argument");
     *out = nullptr;
+    std::vector<hrt::StepTables> tabs;
+    std::vector<hrt::Layout> lays;
+    std::string err;
+    int rc = batch_layouts(cfg, n_cfg, &tabs, lays, err);
+    if (rc) return fail(nullptr, rc, err);
+    size_t total = 0;
+    for (const hrt::Layout &L : lays) total += L.total;
+    if (!workspace || ws_bytes < total)
+        return fail(nullptr, HRT_ENOMEM, "workspace missing or smaller than hrt_workspace_bytes()");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(nullptr, HRT_EINVAL, "workspace must be 256-byte aligned");
     hrt_ctx *c = new (std::nothrow) hrt_ctx();
     if (!c) return fail(nullptr, HRT_ENOMEM, "host allocation failed");
-    std::string err;
-    int rc = hrt::build_tables(*cfg, c->tab, err);
-    if (rc) {
-        delete c;
-        return fail(nullptr, rc, err);
-    }
-    c->cfg = *cfg;
-    c->sched.assign(cfg->sched, cfg->sched + cfg->n_steps + 1);
-    c->cfg.sched = c->sched.data();
-    c->n = cfg->mesh_n;
-    c->np = cfg->ptcl_n;
-    c->mx = cfg->ray_nx;
-    c->my = cfg->ray_ny;
-    c->N = cfg->n_steps;
-    c->f64 = cfg->dtype == HRT_F64;
-    c->is_static = (cfg->flags & HRT_STATIC) != 0;
-    c->box = cfg->box;
-    c->cell = cfg->box / cfg->mesh_n;
     c->stream = static_cast<hipStream_t>(stream);
-    c->lay = hrt::make_layout(*cfg, (int64_t)c->tab.plane_chi.size());
-    if (!workspace || ws_bytes < c->lay.total) {
-        delete c;
-        return fail(nullptr, HRT_ENOMEM, "workspace missing or smaller than hrt_workspace_bytes()");
+    c->N = cfg[0].n_steps;
+    c->f64 = cfg[0].dtype == HRT_F64;
+    c->is_static = (cfg[0].flags & HRT_STATIC) != 0;
+    c->has_rays = cfg[0].ray_nx > 0;
+    c->re.resize(n_cfg);
+    char *ws = static_cast<char *>(workspace);
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < n_cfg && e == hipSuccess; ++r) {
+        hrt::Real &re = c->re[r];
+        re.cfg = cfg[r];
+        re.sched.assign(cfg[r].sched, cfg[r].sched + cfg[r].n_steps + 1);
+        re.cfg.sched = re.sched.data();
+        re.n = cfg[r].mesh_n;
+        re.np = cfg[r].ptcl_n;
+        re.mx = cfg[r].ray_nx;
+        re.my = cfg[r].ray_ny;
+        re.box = cfg[r].box;
+        re.cell = cfg[r].box / cfg[r].mesh_n;
+        re.tab = std::move(tabs[r]);
+        re.lay = lays[r];
+        re.ws = ws;
+        ws += lays[r].total;
+        // Fixed-point fraction bits for the paint: the largest node sum (all particles
+        // on one node) must stay below 2^62.
+        const double P = std::pow((double)re.np, 3);
+        re.fixed_bits = std::min(52, 62 - (int)std::ceil(std::log2(std::max(P, 1.0))));
+        // twiddles W_n^m = exp(-2 pi i m / n) and plane entries
+        const int n = re.n;
+        std::vector<double> twd(2 * n);
+        for (int m = 0; m < n; ++m) {
+            const double ang = -2.0 * 3.14159265358979323846 * m / n;
+            twd[2 * m] = std::cos(ang);
+            twd[2 * m + 1] = std::sin(ang);
+        }
+        std::vector<char> twbuf(2 * n * (c->f64 ? 8 : 4));
+        if (c->f64) {
+            std::memcpy(twbuf.data(), twd.data(), twbuf.size());
+        } else {
+            float *f = reinterpret_cast<float *>(twbuf.data());
+            for (int k = 0; k < 2 * n; ++k) f[k] = (float)twd[k];
+        }
+        std::vector<hrt::PlaneEntry> pe(re.tab.plane_chi.size());
+        for (size_t k = 0; k < pe.size(); ++k)
+            pe[k] = hrt::PlaneEntry{re.tab.plane_chi[k], re.tab.plane_w[k], re.tab.plane_mesh[k], 0};
+        e = hipMemcpyAsync(re.ws + re.lay.twiddle, twbuf.data(), twbuf.size(), hipMemcpyHostToDevice,
+                           c->stream);
+        if (e == hipSuccess && !pe.empty())
+            e = hipMemcpyAsync(re.ws + re.lay.planes, pe.data(), pe.size() * sizeof(hrt::PlaneEntry),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
-    if (reinterpret_cast<uintptr_t>(workspace) % 256) {
-        delete c;
-        return fail(nullptr, HRT_EINVAL, "workspace must be 256-byte aligned");
-    }
-    c->ws = static_cast<char *>(workspace);
-    const double P = std::pow((double)c->np, 3);
-    // Fixed-point fraction bits for the paint: the largest node sum (all particles on
-    // one node) must stay below 2^62.
-    c->fixed_bits = std::min(52, 62 - (int)std::ceil(std::log2(std::max(P, 1.0))));
-
-    // twiddles W_n^m = exp(-2 pi i m / n) and plane entries
-    const int n = c->n;
-    std::vector<double> twd(2 * n);
-    for (int m = 0; m < n; ++m) {
-        const double ang = -2.0 * 3.14159265358979323846 * m / n;
-        twd[2 * m] = std::cos(ang);
-        twd[2 * m + 1] = std::sin(ang);
-    }
-    std::vector<char> twbuf(2 * n * (c->f64 ? 8 : 4));
-    if (c->f64) {
-        std::memcpy(twbuf.data(), twd.data(), twbuf.size());
-    } else {
-        float *f = reinterpret_cast<float *>(twbuf.data());
-        for (int k = 0; k < 2 * n; ++k) f[k] = (float)twd[k];
-    }
-    std::vector<hrt::PlaneEntry> pe(c->tab.plane_chi.size());
-    for (size_t k = 0; k < pe.size(); ++k)
-        pe[k] = hrt::PlaneEntry{c->tab.plane_chi[k], c->tab.plane_w[k], c->tab.plane_mesh[k], 0};
-    hipError_t e = hipMemcpyAsync(c->ws + c->lay.twiddle, twbuf.data(), twbuf.size(),
-                                  hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && !pe.empty())
-        e = hipMemcpyAsync(c->ws + c->lay.planes, pe.data(), pe.size() * sizeof(hrt::PlaneEntry),
-                           hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::string msg = std::string("table upload failed: ") + hipGetErrorString(e);
         delete c;
@@ -264,10 +294,22 @@ extern "C" const char *hrt_last_error(const hrt_ctx *ctx) {
 
 static int check_matter(hrt_ctx *c, const hrt_matter *m, bool need_p) {
     if (!m) return fail(c, HRT_EINVAL, "NULL matter state");
-    for (int d = 0; d < 3; ++d) {
-        if (!m->s[d]) return fail(c, HRT_EINVAL, "NULL displacement array");
-        if (need_p && !m->p[d]) return fail(c, HRT_EINVAL, "NULL momentum array");
-    }
+    for (size_t r = 0; r < c->re.size(); ++r)
+        for (int d = 0; d < 3; ++d) {
+            if (!m[r].s[d]) return fail(c, HRT_EINVAL, "NULL displacement array");
+            if (need_p && !m[r].p[d]) return fail(c, HRT_EINVAL, "NULL momentum array");
+        }
+    return HRT_OK;
+}
+
+static int check_rays(hrt_ctx *c, const hrt_rays *r, bool need_p) {
+    if (!c->has_rays) return fail(c, HRT_ESTATE, "configuration has no rays");
+    if (!r) return fail(c, HRT_EINVAL, "NULL ray state");
+    for (size_t k = 0; k < c->re.size(); ++k)
+        for (int d = 0; d < 2; ++d) {
+            if (!r[k].dth[d]) return fail(c, HRT_EINVAL, "NULL ray deflection array");
+            if (need_p && !r[k].p[d]) return fail(c, HRT_EINVAL, "NULL ray momentum array");
+        }
     return HRT_OK;
 }
 
@@ -275,7 +317,10 @@ extern "C" int pm_force(hrt_ctx *c, const hrt_matter *m, int step) {
     if (!c) return HRT_EINVAL;
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
     if (int rc = check_matter(c, m, false)) return rc;
-    if (int rc = check_hip(c, hrt::launch_paint(c, m), "paint")) return rc;
+    hrt::StepArgs a;
+    a.m = m;
+    a.step = step;
+    if (int rc = check_hip(c, hrt::launch_paint(c, a), "paint")) return rc;
     if (int rc = check_hip(c, hrt::launch_poisson(c), "poisson")) return rc;
     if (int rc = check_hip(c, hrt::launch_gradient(c), "gradient")) return rc;
     c->force_step = step;
@@ -287,28 +332,78 @@ extern "C" int pm_step(hrt_ctx *c, const hrt_matter *m, int step) {
     if (c->is_static) return fail(c, HRT_ESTATE, "pm_step is not valid for a static run");
     if (int rc = check_matter(c, m, true)) return rc;
     if (int rc = pm_force(c, m, step)) return rc;
-    return check_hip(c, hrt::launch_matter_kd(c, m, c->tab.K[step], c->tab.D[step]), "matter kick-drift");
+    hrt::StepArgs a;
+    a.m = m;
+    a.step = step;
+    return check_hip(c, hrt::launch_matter_kd(c, a), "matter kick-drift");
 }
 
 extern "C" int ray_step(hrt_ctx *c, const hrt_rays *r, int step) {
     if (!c) return HRT_EINVAL;
-    if (c->mx == 0) return fail(c, HRT_ESTATE, "configuration has no rays");
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
-    if (!r || !r->dth[0] || !r->dth[1] || !r->p[0] || !r->p[1])
-        return fail(c, HRT_EINVAL, "NULL ray array");
+    if (int rc = check_rays(c, r, true)) return rc;
     if (c->force_step < 0) return fail(c, HRT_ESTATE, "no force mesh yet: call pm_force or pm_step first");
     if (!c->is_static && c->force_step != step)
         return fail(c, HRT_ESTATE, "ray_step must follow pm_step/pm_force of the same step");
-    return check_hip(c, hrt::launch_ray_step(c, r, c->tab.plane_begin[step], c->tab.plane_count[step],
-                                             c->tab.d[step]), "ray step");
+    hrt::StepArgs a;
+    a.r = r;
+    a.step = step;
+    return check_hip(c, hrt::launch_ray_step(c, a), "ray step");
 }
 
-extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *kappa, void *gamma1,
-                               void *gamma2, void *omega) {
+extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *const *kappa,
+                               void *const *gamma1, void *const *gamma2, void *const *omega) {
     if (!c) return HRT_EINVAL;
-    if (c->mx == 0) return fail(c, HRT_ESTATE, "configuration has no rays");
-    if (!r || !r->dth[0] || !r->dth[1] || !kappa) return fail(c, HRT_EINVAL, "NULL argument");
-    return check_hip(c, hrt::launch_convergence(c, r, kappa, gamma1, gamma2, omega), "convergence");
+    if (int rc = check_rays(c, r, false)) return rc;
+    if (!kappa) return fail(c, HRT_EINVAL, "NULL kappa");
+    for (size_t k = 0; k < c->re.size(); ++k)
+        if (!kappa[k]) return fail(c, HRT_EINVAL, "NULL kappa array");
+    hrt::StepArgs a;
+    a.r = r;
+    a.kappa = kappa;
+    a.g1 = gamma1;
+    a.g2 = gamma2;
+    a.om = omega;
+    return check_hip(c, hrt::launch_convergence(c, a), "convergence");
+}
+
+extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
+                                 int first_step, int n_steps) {
+    if (!c) return HRT_EINVAL;
+    if (c->prof) return fail(c, HRT_ESTATE, "switch profiling off before capturing a graph");
+    if (n_steps < 1 || first_step < 0 || first_step + n_steps > c->N + 1)
+        return fail(c, HRT_EINVAL, "captured steps out of range [0, n_steps]");
+    if (int rc = check_matter(c, m, !c->is_static)) return rc;
+    if (r)
+        if (int rc = check_rays(c, r, true)) return rc;
+    if (c->graph) {
+        hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    hipStream_t cap = nullptr, user = c->stream;
+    if (int rc = check_hip(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream"))
+        return rc;
+    c->stream = cap;
+    int rc = check_hip(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    for (int k = first_step; rc == HRT_OK && k < first_step + n_steps; ++k) {
+        rc = c->is_static ? (k == first_step ? pm_force(c, m, k) : HRT_OK) : pm_step(c, m, k);
+        if (rc == HRT_OK && r) rc = ray_step(c, r, k);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    c->stream = user;
+    if (rc == HRT_OK) rc = check_hip(c, e, "end capture");
+    if (rc == HRT_OK) rc = check_hip(c, hipGraphInstantiate(&c->graph, graph, nullptr, nullptr, 0),
+                                     "graph instantiate");
+    if (graph) hipGraphDestroy(graph);
+    hipStreamDestroy(cap);
+    return rc;
+}
+
+extern "C" int hrt_graph_launch(hrt_ctx *c) {
+    if (!c) return HRT_EINVAL;
+    if (!c->graph) return fail(c, HRT_ESTATE, "no captured graph");
+    return check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
 }
 
 extern "C" int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out) {
@@ -328,27 +423,34 @@ extern "C" int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, do
     return HRT_OK;
 }
 
-extern "C" int hrt_ic_2lpt(hrt_ctx *c, const void *noise, const hrt_ic_params *ic, const hrt_matter *out) {
+extern "C" int hrt_ic_2lpt(hrt_ctx *c, int realisation, const void *noise, const hrt_ic_params *ic,
+                           const hrt_matter *out) {
     if (!c) return HRT_EINVAL;
-    if (!noise || !ic) return fail(c, HRT_EINVAL, "NULL argument");
-    if (int rc = check_matter(c, out, true)) return rc;
-    if (c->np < 16) return fail(c, HRT_EUNSUPPORTED, "initial conditions need ptcl_n >= 16");
+    if (realisation < 0 || realisation >= (int)c->re.size())
+        return fail(c, HRT_EINVAL, "realisation index out of range");
+    if (!noise || !ic || !out) return fail(c, HRT_EINVAL, "NULL argument");
+    for (int d = 0; d < 3; ++d)
+        if (!out->s[d] || !out->p[d]) return fail(c, HRT_EINVAL, "NULL output array");
+    const hrt::Real &re = c->re[realisation];
+    if (re.np < 16) return fail(c, HRT_EUNSUPPORTED, "initial conditions need ptcl_n >= 16");
     hrt::IcParams p;
     std::string err;
-    if (int rc = hrt::ic_params(c->cfg, *ic, p, err)) return fail(c, rc, err);
-    if (int rc = check_hip(c, hrt::launch_ic(c, noise, p, out), "initial conditions")) return rc;
+    if (int rc = hrt::ic_params(re.cfg, *ic, p, err)) return fail(c, rc, err);
+    if (int rc = check_hip(c, hrt::launch_ic(c, realisation, noise, p, out), "initial conditions"))
+        return rc;
     c->force_step = -1;          // the force mesh was used as scratch
     return HRT_OK;
 }
 
-extern "C" int hrt_mesh_ptr(const hrt_ctx *c, int which, void **ptr) {
-    if (!c || !ptr) return HRT_EINVAL;
+extern "C" int hrt_mesh_ptr(const hrt_ctx *c, int realisation, int which, void **ptr) {
+    if (!c || !ptr || realisation < 0 || realisation >= (int)c->re.size()) return HRT_EINVAL;
+    const hrt::Real &re = c->re[realisation];
     const size_t T = c->f64 ? 8 : 4;
-    const size_t n3 = (size_t)c->n * c->n * c->n;
+    const size_t n3 = (size_t)re.n * re.n * re.n;
     switch (which) {
-        case HRT_MESH_DELTA: *ptr = c->ws + c->lay.mesh_r; return HRT_OK;
-        case HRT_MESH_PHI: *ptr = c->ws + c->lay.mesh_r + n3 * T; return HRT_OK;
-        case HRT_MESH_GRAD: *ptr = c->ws + c->lay.grad; return HRT_OK;
+        case HRT_MESH_DELTA: *ptr = re.ws + re.lay.mesh_r; return HRT_OK;
+        case HRT_MESH_PHI: *ptr = re.ws + re.lay.mesh_r + n3 * T; return HRT_OK;
+        case HRT_MESH_GRAD: *ptr = re.ws + re.lay.grad; return HRT_OK;
         default: return HRT_EINVAL;
     }
 }

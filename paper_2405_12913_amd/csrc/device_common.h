@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "hrt_internal.h"
+
 namespace hrt {
 
 template <typename T>
@@ -98,6 +100,13 @@ __device__ __forceinline__ int xcd_block(int nblocks) {
     const int w = blockIdx.x, x = w & 7, k = w >> 3;
     const int per = nblocks >> 3, rem = nblocks & 7;
     return x * per + (x < rem ? x : rem) + k;
+}
+
+// Realisation owning logical block blk (uniform over the block).
+__device__ __forceinline__ int real_of(const BlockMap &m, int blk) {
+    int r = 0;
+    while (r + 1 < m.R && blk >= m.start[r + 1]) ++r;
+    return r;
 }
 
 }  // namespace hrt

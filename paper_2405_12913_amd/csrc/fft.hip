@@ -14,8 +14,11 @@
 // then fd4_gradient: G = grad(phi) by fourth-order central differences (the gradient
 // reading adopted for this method; it is exact on lattice modes up to its transfer
 // function and leaves no Nyquist odd-even artefact next to unresolved sources).
+// Realisations of equal mesh size share one launch per pass (block b belongs to
+// realisation b / blocks_per_realisation); the gradient covers all realisations at once.
+#include <algorithm>
+
 #include "device_common.h"
-#include "hrt_internal.h"
 
 namespace hrt {
 namespace {
@@ -96,26 +99,41 @@ struct Cfg {
     static constexpr int LINES = ELEMS / N;                        // y and z passes
 };
 
+// Per-launch arguments of the FFT passes: realisations of one mesh size N.
+template <typename T>
+struct FftBatch {
+    const T *rin[kMaxBatch];       // x_r2c input rows
+    T *rout[kMaxBatch];            // x_c2r output rows
+    c2<T> *spec[kMaxBatch];        // transposed spectrum [kx][z][y]
+    const c2<T> *tw[kMaxBatch];    // twiddles W_table^m
+    double kf2[kMaxBatch];         // (2 pi / box)^2
+    int tws;                       // twiddle-table stride (table size / N)
+    int bpr;                       // blocks per realisation
+};
+
 // tws: stride of the twiddle table (its size over N) when transforming a lattice smaller
 // than the mesh the table was built for.
 template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void x_r2c_kernel(const T *__restrict__ in,
-                                                         c2<T> *__restrict__ out,
-                                                         const c2<T> *__restrict__ tw, int tws) {
+__global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
-    const int row0 = blockIdx.x * ROWS;
+    const int r = blockIdx.x / fb.bpr;
+    const T *__restrict__ in = fb.rin[r];
+    c2<T> *__restrict__ out = fb.spec[r];
+    const c2<T> *__restrict__ tw = fb.tw[r];
+    const int tws = fb.tws;
+    const int row0 = (blockIdx.x % fb.bpr) * ROWS;
     for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
-        const int r = e / L, m = e % L;
-        buf[r * LS + m] = reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + r) * N)[m];
+        const int rr = e / L, m = e % L;
+        buf[rr * LS + m] = reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + rr) * N)[m];
     }
     __syncthreads();
     fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, tws * (N / L));
     // split step: X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) W_N^k (Z[k] - conj Z[L-k]),
     // each thread owns the pair (k, L-k); X[L] (Nyquist) comes from Z[0].
     for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
-        const int r = e / (L / 2 + 1), k = e % (L / 2 + 1);
-        c2<T> *line = buf + r * LS;
+        const int rr = e / (L / 2 + 1), k = e % (L / 2 + 1);
+        c2<T> *line = buf + rr * LS;
         const c2<T> zk = line[k];
         const c2<T> zp = line[k == 0 ? 0 : L - k];
         const c2<T> w = tw[k * tws];
@@ -134,29 +152,32 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(const T *__restrict__ i
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ROWS * (L + 1); e += kThreads) {
-        const int kx = e / ROWS, r = e % ROWS;
-        const int row = row0 + r, z = row / N, y = row % N;
-        out[((size_t)kx * N + z) * N + y] = buf[r * LS + kx];
+        const int kx = e / ROWS, rr = e % ROWS;
+        const int row = row0 + rr, z = row / N, y = row % N;
+        out[((size_t)kx * N + z) * N + y] = buf[rr * LS + kx];
     }
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void x_c2r_kernel(const c2<T> *__restrict__ in,
-                                                         T *__restrict__ out,
-                                                         const c2<T> *__restrict__ tw, int tws) {
+__global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
-    const int row0 = blockIdx.x * ROWS;
+    const int r = blockIdx.x / fb.bpr;
+    const c2<T> *__restrict__ in = fb.spec[r];
+    T *__restrict__ out = fb.rout[r];
+    const c2<T> *__restrict__ tw = fb.tw[r];
+    const int tws = fb.tws;
+    const int row0 = (blockIdx.x % fb.bpr) * ROWS;
     for (int e = threadIdx.x; e < ROWS * (L + 1); e += kThreads) {
-        const int kx = e / ROWS, r = e % ROWS;
-        const int row = row0 + r, z = row / N, y = row % N;
-        buf[r * LS + kx] = in[((size_t)kx * N + z) * N + y];
+        const int kx = e / ROWS, rr = e % ROWS;
+        const int row = row0 + rr, z = row / N, y = row % N;
+        buf[rr * LS + kx] = in[((size_t)kx * N + z) * N + y];
     }
     __syncthreads();
     // Z[k] = (X[k] + conj X[L-k]) + i W_N^{-k} (X[k] - conj X[L-k]), pairs (k, L-k)
     for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
-        const int r = e / (L / 2 + 1), k = e % (L / 2 + 1);
-        c2<T> *line = buf + r * LS;
+        const int rr = e / (L / 2 + 1), k = e % (L / 2 + 1);
+        c2<T> *line = buf + rr * LS;
         const c2<T> xk = line[k], xp = line[L - k];
         const c2<T> w = tw[k * tws];
         const c2<T> wc{w.x, -w.y};
@@ -173,91 +194,93 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(const c2<T> *__restrict
     __syncthreads();
     fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, tws * (N / L));
     for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
-        const int r = e / L, m = e % L;
-        reinterpret_cast<c2<T> *>(out + (size_t)(row0 + r) * N)[m] = buf[r * LS + m];
+        const int rr = e / L, m = e % L;
+        reinterpret_cast<c2<T> *>(out + (size_t)(row0 + rr) * N)[m] = buf[rr * LS + m];
     }
 }
 
 // FFT along y of the transposed spectrum C[kx][z][y]: lines are contiguous.
 template <typename T, int N, bool INV>
-__global__ __launch_bounds__(kThreads) void y_lines_kernel(c2<T> *__restrict__ data,
-                                                           const c2<T> *__restrict__ tw,
-                                                           int total_lines, int tws) {
+__global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
     constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
+    constexpr int TOTAL = (N / 2 + 1) * N;
     __shared__ c2<T> buf[LINES * LS];
-    const int l0 = blockIdx.x * LINES;
+    const int r = blockIdx.x / fb.bpr;
+    c2<T> *__restrict__ data = fb.spec[r];
+    const int l0 = (blockIdx.x % fb.bpr) * LINES;
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int li = e / N, m = e % N;
-        if (l0 + li < total_lines) buf[li * LS + m] = data[(size_t)(l0 + li) * N + m];
+        if (l0 + li < TOTAL) buf[li * LS + m] = data[(size_t)(l0 + li) * N + m];
     }
     __syncthreads();
-    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, tws);
+    fft_stage<T, N, LINES, INV, 1>(buf, LS, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int li = e / N, m = e % N;
-        if (l0 + li < total_lines) data[(size_t)(l0 + li) * N + m] = buf[li * LS + m];
+        if (l0 + li < TOTAL) data[(size_t)(l0 + li) * N + m] = buf[li * LS + m];
     }
 }
 
-// FFT along z alone (forward or inverse), line l = kx * N + y, element stride N.
-template <typename T, int N, bool INV>
-__global__ __launch_bounds__(kThreads) void z_lines_kernel(c2<T> *__restrict__ data,
-                                                           const c2<T> *__restrict__ tw,
-                                                           int total_lines, int tws) {
+// FFT along z; MODE 0: forward, 1: inverse, 2: forward, multiply by -1/(k^2 n^3) (k = 0
+// -> 0), inverse. Line l = kx * N + y, element stride N.
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
     constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
+    constexpr int TOTAL = (N / 2 + 1) * N;
     __shared__ c2<T> buf[LINES * LS];
-    const int l0 = blockIdx.x * LINES;
+    const int r = blockIdx.x / fb.bpr;
+    c2<T> *__restrict__ data = fb.spec[r];
+    const c2<T> *__restrict__ tw = fb.tw[r];
+    const int l0 = (blockIdx.x % fb.bpr) * LINES;
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int z = e / LINES, li = e % LINES, l = l0 + li;
-        if (l < total_lines) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
+        if (l < TOTAL) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
     }
     __syncthreads();
-    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, tws);
+    fft_stage<T, N, LINES, MODE == 1, 1>(buf, LS, tw, fb.tws);
+    if constexpr (MODE == 2) {
+        const double kf2 = fb.kf2[r], inv_n3 = 1.0 / ((double)N * N * N);
+        for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
+            const int li = e / N, kz = e % N, l = l0 + li;
+            const int kx = l / N, ky = l % N;
+            const int fy = ky <= N / 2 ? ky : ky - N, fz = kz <= N / 2 ? kz : kz - N;
+            const double k2 = kf2 * (double)(kx * kx + fy * fy + fz * fz);
+            const T g = k2 > 0.0 ? (T)(-inv_n3 / k2) : T(0);
+            c2<T> v = buf[li * LS + kz];
+            buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
+        }
+        __syncthreads();
+        fft_stage<T, N, LINES, true, 1>(buf, LS, tw, fb.tws);
+    }
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int z = e / LINES, li = e % LINES, l = l0 + li;
-        if (l < total_lines) data[((size_t)(l / N) * N + z) * N + (l % N)] = buf[li * LS + z];
+        if (l < TOTAL) data[((size_t)(l / N) * N + z) * N + (l % N)] = buf[li * LS + z];
     }
 }
 
-// Forward FFT along z, Green's function, inverse FFT along z. Line l = kx * N + y.
-template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void z_poisson_kernel(c2<T> *__restrict__ data,
-                                                             const c2<T> *__restrict__ tw,
-                                                             int total_lines, double kf2,
-                                                             double inv_n3, int tws) {
-    constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
-    __shared__ c2<T> buf[LINES * LS];
-    const int l0 = blockIdx.x * LINES;
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int z = e / LINES, li = e % LINES, l = l0 + li;
-        if (l < total_lines) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
-    }
-    __syncthreads();
-    fft_stage<T, N, LINES, false, 1>(buf, LS, tw, tws);
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int li = e / N, kz = e % N, l = l0 + li;
-        const int kx = l / N, ky = l % N;
-        const int fy = ky <= N / 2 ? ky : ky - N, fz = kz <= N / 2 ? kz : kz - N;
-        const double k2 = kf2 * (double)(kx * kx + fy * fy + fz * fz);
-        const T g = k2 > 0.0 ? (T)(-inv_n3 / k2) : T(0);
-        c2<T> v = buf[li * LS + kz];
-        buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
-    }
-    __syncthreads();
-    fft_stage<T, N, LINES, true, 1>(buf, LS, tw, tws);
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int z = e / LINES, li = e % LINES, l = l0 + li;
-        if (l < total_lines) data[((size_t)(l / N) * N + z) * N + (l % N)] = buf[li * LS + z];
-    }
-}
+template <typename T>
+struct GradR {
+    const T *phi;
+    v4<T> *g;
+    int n, log2n;
+    T inv12cell;
+};
+template <typename T>
+struct GradBatch {
+    BlockMap map;
+    GradR<T> r[kMaxBatch];
+};
 
 // One lane per node, x fastest; blocks XCD-remapped so the +-2 neighbour rows and
 // planes a block reads are mostly in its own XCD's L2.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(const T *__restrict__ phi,
-                                                                v4<T> *__restrict__ g, int n,
-                                                                int log2n, T inv12cell) {
-    const int64_t idx = (int64_t)xcd_block(gridDim.x) * kThreads + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(GradBatch<T> b) {
+    const int blk = xcd_block(gridDim.x);
+    const int r = real_of(b.map, blk);
+    const GradR<T> &a = b.r[r];
+    const int64_t idx = (int64_t)(blk - b.map.start[r]) * kThreads + threadIdx.x;
+    const int n = a.n, log2n = a.log2n;
     if (idx >= ((int64_t)1 << (3 * log2n))) return;
+    const T *__restrict__ phi = a.phi;
     const int m = n - 1;
     const int x = (int)(idx & m), y = (int)((idx >> log2n) & m), z = (int)(idx >> (2 * log2n));
     const size_t row = ((size_t)z * n + y) * n;
@@ -269,41 +292,115 @@ __global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(const T *__restr
     const T dy = T(8) * (at(x, y + 1, z) - at(x, y - 1, z)) - (at(x, y + 2, z) - at(x, y - 2, z));
     const T dz = T(8) * (at(x, y, z + 1) - at(x, y, z - 1)) - (at(x, y, z + 2) - at(x, y, z - 2));
     v4<T> out;
-    out.x = dx * inv12cell;
-    out.y = dy * inv12cell;
-    out.z = dz * inv12cell;
+    out.x = dx * a.inv12cell;
+    out.y = dy * a.inv12cell;
+    out.z = dz * a.inv12cell;
     out.w = T(0);
-    g[idx] = out;
+    a.g[idx] = out;
 }
 
 template <typename T, int N>
-hipError_t poisson_n(hrt_ctx *c) {
-    const T *delta = reinterpret_cast<const T *>(c->ws + c->lay.mesh_r);
-    T *phi = reinterpret_cast<T *>(c->ws + c->lay.mesh_r) + (size_t)N * N * N;
-    c2<T> *spec = reinterpret_cast<c2<T> *>(c->ws + c->lay.spec);
-    const c2<T> *tw = reinterpret_cast<const c2<T> *>(c->ws + c->lay.twiddle);
+FftBatch<T> fft_batch(hrt_ctx *c, const std::vector<int> &ids, int bpr, int tws) {
+    FftBatch<T> fb{};
+    fb.tws = tws;
+    fb.bpr = bpr;
+    for (size_t k = 0; k < ids.size(); ++k) {
+        const Real &re = c->re[ids[k]];
+        const size_t n3 = (size_t)re.n * re.n * re.n;
+        fb.rin[k] = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r);
+        fb.rout[k] = reinterpret_cast<T *>(re.ws + re.lay.mesh_r) + n3;
+        fb.spec[k] = reinterpret_cast<c2<T> *>(re.ws + re.lay.spec);
+        fb.tw[k] = reinterpret_cast<const c2<T> *>(re.ws + re.lay.twiddle);
+        const double kf = 2.0 * 3.14159265358979323846 / re.box;
+        fb.kf2[k] = kf * kf;
+    }
+    return fb;
+}
+
+template <typename T, int N>
+hipError_t poisson_n(hrt_ctx *c, const std::vector<int> &ids) {
     hipStream_t st = c->stream;
     constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
-    const int xblocks = N * N / XROWS;
-    const int total_lines = (N / 2 + 1) * N;
-    const int lblocks = (total_lines + LINES - 1) / LINES;
-    const double kf = 2.0 * 3.14159265358979323846 / c->box;
+    const int xb = N * N / XROWS;
+    const int lb = ((N / 2 + 1) * N + LINES - 1) / LINES;
+    const int R = (int)ids.size();
+    FftBatch<T> fx = fft_batch<T, N>(c, ids, xb, 1), fl = fft_batch<T, N>(c, ids, lb, 1);
     prof_begin(c);
-    x_r2c_kernel<T, N><<<xblocks, kThreads, 0, st>>>(delta, spec, tw, 1);
+    x_r2c_kernel<T, N><<<xb * R, kThreads, 0, st>>>(fx);
     prof_end(c, K_FFT_X_R2C);
     prof_begin(c);
-    y_lines_kernel<T, N, false><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines, 1);
+    y_lines_kernel<T, N, false><<<lb * R, kThreads, 0, st>>>(fl);
     prof_end(c, K_FFT_Y_FWD);
     prof_begin(c);
-    z_poisson_kernel<T, N><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines, kf * kf,
-                                                          1.0 / ((double)N * N * N), 1);
+    z_lines_kernel<T, N, 2><<<lb * R, kThreads, 0, st>>>(fl);
     prof_end(c, K_FFT_Z_POISSON);
     prof_begin(c);
-    y_lines_kernel<T, N, true><<<lblocks, kThreads, 0, st>>>(spec, tw, total_lines, 1);
+    y_lines_kernel<T, N, true><<<lb * R, kThreads, 0, st>>>(fl);
     prof_end(c, K_FFT_Y_INV);
     prof_begin(c);
-    x_c2r_kernel<T, N><<<xblocks, kThreads, 0, st>>>(spec, phi, tw, 1);
+    x_c2r_kernel<T, N><<<xb * R, kThreads, 0, st>>>(fx);
     prof_end(c, K_FFT_X_C2R);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t poisson_size(hrt_ctx *c, int n, const std::vector<int> &ids) {
+    switch (n) {
+        case 16: return poisson_n<T, 16>(c, ids);
+        case 32: return poisson_n<T, 32>(c, ids);
+        case 64: return poisson_n<T, 64>(c, ids);
+        case 128: return poisson_n<T, 128>(c, ids);
+        case 256: return poisson_n<T, 256>(c, ids);
+        case 512: return poisson_n<T, 512>(c, ids);
+        case 1024: return poisson_n<T, 1024>(c, ids);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t poisson_impl(hrt_ctx *c) {
+    // group realisations by mesh size, in order of first appearance, <= kMaxBatch per launch
+    std::vector<int> sizes;
+    for (const Real &re : c->re)
+        if (std::find(sizes.begin(), sizes.end(), re.n) == sizes.end()) sizes.push_back(re.n);
+    for (int n : sizes) {
+        std::vector<int> ids;
+        for (int r = 0; r < (int)c->re.size(); ++r) {
+            if (c->re[r].n != n) continue;
+            ids.push_back(r);
+            if ((int)ids.size() == kMaxBatch) {
+                if (hipError_t e = poisson_size<T>(c, n, ids)) return e;
+                ids.clear();
+            }
+        }
+        if (!ids.empty())
+            if (hipError_t e = poisson_size<T>(c, n, ids)) return e;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gradient_impl(hrt_ctx *c) {
+    const int nre = (int)c->re.size();
+    for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
+        const int R = std::min(kMaxBatch, nre - r0);
+        GradBatch<T> b{};
+        b.map.R = R;
+        b.map.start[0] = 0;
+        for (int k = 0; k < R; ++k) {
+            const Real &re = c->re[r0 + k];
+            const size_t n3 = (size_t)re.n * re.n * re.n;
+            b.r[k].phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + n3;
+            b.r[k].g = reinterpret_cast<v4<T> *>(re.ws + re.lay.grad);
+            b.r[k].n = re.n;
+            b.r[k].log2n = ilog2(re.n);
+            b.r[k].inv12cell = (T)(1.0 / (12.0 * re.cell));
+            b.map.start[k + 1] = b.map.start[k] + (int)((n3 + kThreads - 1) / kThreads);
+        }
+        prof_begin(c);
+        fd4_gradient_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        prof_end(c, K_GRADIENT);
+    }
     return hipGetLastError();
 }
 
@@ -379,65 +476,80 @@ __global__ void lpt_combine_kernel(T *__restrict__ s, T *__restrict__ p, int64_t
     }
 }
 
+// 3D transforms of one lattice of size N (the IC's particle lattice) in a realisation's
+// workspace; tws = mesh size / N.
 template <typename T, int N>
-void fwd3d(hrt_ctx *c, const T *real_in, c2<T> *spec, int tws) {
+void fwd3d(hrt_ctx *c, int r, const T *real_in, c2<T> *spec, int tws) {
     constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
-    const int total_lines = (N / 2 + 1) * N, lblocks = (total_lines + LINES - 1) / LINES;
-    const c2<T> *tw = reinterpret_cast<const c2<T> *>(c->ws + c->lay.twiddle);
-    x_r2c_kernel<T, N><<<N * N / XROWS, kThreads, 0, c->stream>>>(real_in, spec, tw, tws);
-    y_lines_kernel<T, N, false><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
-    z_lines_kernel<T, N, false><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
+    const int xb = N * N / XROWS, lb = ((N / 2 + 1) * N + LINES - 1) / LINES;
+    FftBatch<T> fb{};
+    fb.tws = tws;
+    fb.rin[0] = real_in;
+    fb.spec[0] = spec;
+    fb.tw[0] = reinterpret_cast<const c2<T> *>(c->re[r].ws + c->re[r].lay.twiddle);
+    fb.bpr = xb;
+    x_r2c_kernel<T, N><<<xb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = lb;
+    y_lines_kernel<T, N, false><<<lb, kThreads, 0, c->stream>>>(fb);
+    z_lines_kernel<T, N, 0><<<lb, kThreads, 0, c->stream>>>(fb);
 }
 
 template <typename T, int N>
-void inv3d(hrt_ctx *c, c2<T> *spec, T *real_out, int tws) {
+void inv3d(hrt_ctx *c, int r, c2<T> *spec, T *real_out, int tws) {
     constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
-    const int total_lines = (N / 2 + 1) * N, lblocks = (total_lines + LINES - 1) / LINES;
-    const c2<T> *tw = reinterpret_cast<const c2<T> *>(c->ws + c->lay.twiddle);
-    z_lines_kernel<T, N, true><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
-    y_lines_kernel<T, N, true><<<lblocks, kThreads, 0, c->stream>>>(spec, tw, total_lines, tws);
-    x_c2r_kernel<T, N><<<N * N / XROWS, kThreads, 0, c->stream>>>(spec, real_out, tw, tws);
+    const int xb = N * N / XROWS, lb = ((N / 2 + 1) * N + LINES - 1) / LINES;
+    FftBatch<T> fb{};
+    fb.tws = tws;
+    fb.rout[0] = real_out;
+    fb.spec[0] = spec;
+    fb.tw[0] = reinterpret_cast<const c2<T> *>(c->re[r].ws + c->re[r].lay.twiddle);
+    fb.bpr = lb;
+    z_lines_kernel<T, N, 1><<<lb, kThreads, 0, c->stream>>>(fb);
+    y_lines_kernel<T, N, true><<<lb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = xb;
+    x_c2r_kernel<T, N><<<xb, kThreads, 0, c->stream>>>(fb);
 }
 
 template <typename T, int N>
-hipError_t ic_n(hrt_ctx *c, const T *noise, const IcParams &p, const hrt_matter *m) {
-    const int tws = c->n / N;
+hipError_t ic_n(hrt_ctx *c, int r, const T *noise, const IcParams &p, const hrt_matter *m) {
+    const Real &re = c->re[r];
+    const int tws = re.n / N;
     const int64_t P = (int64_t)N * N * N;
     const int64_t ns = (int64_t)(N / 2 + 1) * N * N;
     const int sblocks = (int)((ns + kThreads - 1) / kThreads), pblocks = (int)((P + kThreads - 1) / kThreads);
-    c2<T> *base = reinterpret_cast<c2<T> *>(c->ws + c->lay.spec2);
-    c2<T> *work = reinterpret_cast<c2<T> *>(c->ws + c->lay.spec);
-    T *scratch = reinterpret_cast<T *>(c->ws + c->lay.grad);        // 4 lattices of P values
+    c2<T> *base = reinterpret_cast<c2<T> *>(re.ws + re.lay.spec2);
+    c2<T> *work = reinterpret_cast<c2<T> *>(re.ws + re.lay.spec);
+    T *scratch = reinterpret_cast<T *>(re.ws + re.lay.grad);        // 4 lattices of P values
     T *A = scratch, *B = scratch + P, *C = scratch + 2 * P, *tmp = scratch + 3 * P;
-    T *src = reinterpret_cast<T *>(c->ws + c->lay.mesh_r);
+    T *src = reinterpret_cast<T *>(re.ws + re.lay.mesh_r);
     T *s[3] = {static_cast<T *>(m->s[0]), static_cast<T *>(m->s[1]), static_cast<T *>(m->s[2])};
     T *q[3] = {static_cast<T *>(m->p[0]), static_cast<T *>(m->p[1]), static_cast<T *>(m->p[2])};
     const double inv_n3 = 1.0 / (double)P;
     hipStream_t st = c->stream;
-    fwd3d<T, N>(c, noise, base, tws);
+    fwd3d<T, N>(c, r, noise, base, tws);
     spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_PHI1, 0, 0, 1.0, p);
     for (int d = 0; d < 3; ++d) {          // s1 = -grad phi1
         spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, -inv_n3, p);
-        inv3d<T, N>(c, work, s[d], tws);
+        inv3d<T, N>(c, r, work, s[d], tws);
     }
     T *diag[3] = {A, B, C};
     for (int d = 0; d < 3; ++d) {
         spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, d, d, inv_n3, p);
-        inv3d<T, N>(c, work, diag[d], tws);
+        inv3d<T, N>(c, r, work, diag[d], tws);
     }
     lpt_source_diag_kernel<T><<<pblocks, kThreads, 0, st>>>(A, B, C, src, P);
     const int off[3][2] = {{0, 1}, {0, 2}, {1, 2}};
     for (int k = 0; k < 3; ++k) {
         spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, off[k][0], off[k][1],
                                                            inv_n3, p);
-        inv3d<T, N>(c, work, tmp, tws);
+        inv3d<T, N>(c, r, work, tmp, tws);
         lpt_source_off_kernel<T><<<pblocks, kThreads, 0, st>>>(tmp, src, P);
     }
-    fwd3d<T, N>(c, src, base, tws);
+    fwd3d<T, N>(c, r, src, base, tws);
     spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_INVLAP, 0, 0, 1.0, p);
     for (int d = 0; d < 3; ++d) {          // s2 = +grad phi2, parked in the momentum arrays
         spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, inv_n3, p);
-        inv3d<T, N>(c, work, q[d], tws);
+        inv3d<T, N>(c, r, work, q[d], tws);
     }
     for (int d = 0; d < 3; ++d)
         lpt_combine_kernel<T><<<pblocks, kThreads, 0, st>>>(s[d], q[d], P, p.g1, p.g2, p.m1, p.m2);
@@ -445,46 +557,18 @@ hipError_t ic_n(hrt_ctx *c, const T *noise, const IcParams &p, const hrt_matter 
 }
 
 template <typename T>
-hipError_t ic_impl(hrt_ctx *c, const void *noise, const IcParams &p, const hrt_matter *m) {
+hipError_t ic_impl(hrt_ctx *c, int r, const void *noise, const IcParams &p, const hrt_matter *m) {
     const T *nz = static_cast<const T *>(noise);
-    switch (c->np) {
-        case 16: return ic_n<T, 16>(c, nz, p, m);
-        case 32: return ic_n<T, 32>(c, nz, p, m);
-        case 64: return ic_n<T, 64>(c, nz, p, m);
-        case 128: return ic_n<T, 128>(c, nz, p, m);
-        case 256: return ic_n<T, 256>(c, nz, p, m);
-        case 512: return ic_n<T, 512>(c, nz, p, m);
-        case 1024: return ic_n<T, 1024>(c, nz, p, m);
+    switch (c->re[r].np) {
+        case 16: return ic_n<T, 16>(c, r, nz, p, m);
+        case 32: return ic_n<T, 32>(c, r, nz, p, m);
+        case 64: return ic_n<T, 64>(c, r, nz, p, m);
+        case 128: return ic_n<T, 128>(c, r, nz, p, m);
+        case 256: return ic_n<T, 256>(c, r, nz, p, m);
+        case 512: return ic_n<T, 512>(c, r, nz, p, m);
+        case 1024: return ic_n<T, 1024>(c, r, nz, p, m);
         default: return hipErrorInvalidValue;
     }
-}
-
-template <typename T>
-hipError_t poisson_impl(hrt_ctx *c) {
-    switch (c->n) {
-        case 16: return poisson_n<T, 16>(c);
-        case 32: return poisson_n<T, 32>(c);
-        case 64: return poisson_n<T, 64>(c);
-        case 128: return poisson_n<T, 128>(c);
-        case 256: return poisson_n<T, 256>(c);
-        case 512: return poisson_n<T, 512>(c);
-        case 1024: return poisson_n<T, 1024>(c);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t gradient_impl(hrt_ctx *c) {
-    const int n = c->n;
-    int log2n = 0;
-    while ((1 << log2n) < n) ++log2n;
-    const T *phi = reinterpret_cast<const T *>(c->ws + c->lay.mesh_r) + (size_t)n * n * n;
-    const int64_t nodes = (int64_t)n * n * n;
-    prof_begin(c);
-    fd4_gradient_kernel<T><<<(int)((nodes + kThreads - 1) / kThreads), kThreads, 0, c->stream>>>(
-        phi, reinterpret_cast<v4<T> *>(c->ws + c->lay.grad), n, log2n, (T)(1.0 / (12.0 * c->cell)));
-    prof_end(c, K_GRADIENT);
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -493,8 +577,8 @@ hipError_t launch_poisson(hrt_ctx *c) {
     return c->f64 ? poisson_impl<double>(c) : poisson_impl<float>(c);
 }
 
-hipError_t launch_ic(hrt_ctx *c, const void *noise, const IcParams &p, const hrt_matter *m) {
-    return c->f64 ? ic_impl<double>(c, noise, p, m) : ic_impl<float>(c, noise, p, m);
+hipError_t launch_ic(hrt_ctx *c, int r, const void *noise, const IcParams &p, const hrt_matter *m) {
+    return c->f64 ? ic_impl<double>(c, r, noise, p, m) : ic_impl<float>(c, r, noise, p, m);
 }
 
 hipError_t launch_gradient(hrt_ctx *c) {

@@ -43,16 +43,13 @@ struct PlaneEntry {
     int32_t pad;
 };
 
-// Workspace carve-up, identical in hrt_workspace_bytes and hrt_init.
+// Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
     size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, total;
     int64_t nbins;
 };
 Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
 
-}  // namespace hrt
-
-namespace hrt {
 // Kernel ids for the optional per-kernel HIP-event timing (hrt_profile_*).
 enum KernelId {
     K_BIN_COUNT = 0, K_BIN_SCAN, K_BIN_SCATTER, K_PAINT, K_FFT_X_R2C, K_FFT_Y_FWD, K_FFT_Z_POISSON,
@@ -62,21 +59,51 @@ struct ProfRecord {
     int id;
     hipEvent_t start, stop;
 };
+
+// Realisations per kernel launch: their pointers and scalars travel in the kernel's
+// by-value argument block (well under the 4 KB limit); larger batches launch in chunks.
+constexpr int kMaxBatch = 16;
+
+// One realisation of a (possibly batched) context.
+struct Real {
+    hrt_config cfg;
+    std::vector<double> sched;
+    int n = 0, np = 0, mx = 0, my = 0;
+    double cell = 0, box = 0;
+    StepTables tab;
+    Layout lay;
+    char *ws = nullptr;          // this realisation's part of the workspace
+    int fixed_bits = 0;          // paint fixed-point fraction bits
+};
+
+// Per-call state handed to the launchers: one entry per realisation.
+struct StepArgs {
+    const hrt_matter *m = nullptr;
+    const hrt_rays *r = nullptr;
+    int step = 0;
+    void *const *kappa = nullptr;
+    void *const *g1 = nullptr;
+    void *const *g2 = nullptr;
+    void *const *om = nullptr;
+};
+
+// Blocks of realisation r are [start[r], start[r+1]); start[R] is the grid size.
+struct BlockMap {
+    int R;
+    int start[kMaxBatch + 1];
+};
+
 }  // namespace hrt
 
 struct hrt_ctx {
-    hrt_config cfg;
-    std::vector<double> sched;
+    std::vector<hrt::Real> re;   // realisations (a plain run is a batch of one)
     hipStream_t stream = nullptr;
-    int n = 0, np = 0, mx = 0, my = 0, N = 0;
-    bool f64 = false, is_static = false;
-    double cell = 0, box = 0;
-    hrt::StepTables tab;
-    hrt::Layout lay;
-    char *ws = nullptr;
-    int fixed_bits = 0;          // paint fixed-point fraction bits
-    int force_step = -1;         // boundary of the G currently in the workspace
+    int N = 0;                   // shared number of steps
+    bool f64 = false, is_static = false, has_rays = false;
+    int force_step = -1;         // boundary of the G currently in the workspaces
     std::string err;
+    // captured step sequence (hrt_graph_capture / hrt_graph_launch)
+    hipGraphExec_t graph = nullptr;
     // per-kernel timing (off unless hrt_profile_enable)
     bool prof = false;
     std::vector<hrt::ProfRecord> prof_pending;
@@ -87,16 +114,18 @@ struct hrt_ctx {
     ~hrt_ctx();
 };
 
-// Kernel launchers (defined in the .hip files). Each returns hipSuccess or the error.
+// Kernel launchers (defined in the .hip files); each covers every realisation of the
+// context with one launch per kernel type (per mesh-size class for the FFT passes) and
+// returns hipSuccess or the error.
 namespace hrt {
 void prof_begin(hrt_ctx *c);           // record a start event when profiling is on
 void prof_end(hrt_ctx *c, int id);     // record the stop event of kernel `id`
-hipError_t launch_paint(hrt_ctx *c, const hrt_matter *m);
+hipError_t launch_paint(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_poisson(hrt_ctx *c);
 hipError_t launch_gradient(hrt_ctx *c);
-hipError_t launch_ic(hrt_ctx *c, const void *noise, const IcParams &p, const hrt_matter *m);
-hipError_t launch_matter_kd(hrt_ctx *c, const hrt_matter *m, double K, double D);
-hipError_t launch_ray_step(hrt_ctx *c, const hrt_rays *r, int begin, int count, double d);
-hipError_t launch_convergence(hrt_ctx *c, const hrt_rays *r, void *kappa, void *g1, void *g2,
-                              void *om);
+hipError_t launch_matter_kd(hrt_ctx *c, const StepArgs &a);
+hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
+hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a);
+hipError_t launch_ic(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
+                     const hrt_matter *m);
 }  // namespace hrt

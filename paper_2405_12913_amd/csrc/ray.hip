@@ -13,8 +13,8 @@
 // convergence_kernel (Eqs. A, obs_first_set, obs_second_set): finite differences of the
 // deflections over the pixel grid, central inside and second-order one-sided on the
 // edges; kappa, gamma1, gamma2, omega with omega kept to first order.
+// Both kernels cover all realisations of a context (uneven ray grids) in one launch.
 #include "device_common.h"
-#include "hrt_internal.h"
 
 namespace hrt {
 namespace {
@@ -22,27 +22,43 @@ namespace {
 constexpr int kThreads = 256;
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void ray_step_kernel(
-    T *__restrict__ dthx, T *__restrict__ dthy, T *__restrict__ px, T *__restrict__ py,
-    const PlaneEntry *__restrict__ planes, int begin, int count, const v4<T> *__restrict__ g,
-    int n, double inv_cell, double obsx, double obsy, int mx, int nrays, double mux, double muy,
-    double half_mx, double half_my, T d) {
-    const int i = xcd_block(gridDim.x) * kThreads + threadIdx.x;
-    if (i >= nrays) return;
-    const int ix = i % mx, iy = i / mx;
-    const double thx = ((ix + 0.5) - half_mx) * mux + (double)dthx[i];
-    const double thy = ((iy + 0.5) - half_my) * muy + (double)dthy[i];
-    const int m = n - 1;
+struct RayR {                  // one realisation, as the ray kernels see it
+    T *dthx, *dthy, *px, *py;
+    const PlaneEntry *planes;
+    const v4<T> *g;
+    T *kappa, *g1, *g2, *om;
+    int begin, count, n, mx, my, nrays;
+    double inv_cell, obsx, obsy, mux, muy, half_mx, half_my;
+    T d, inv2mux, inv2muy;
+};
+
+template <typename T>
+struct RayBatch {
+    BlockMap map;
+    RayR<T> r[kMaxBatch];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
+    const int blk = xcd_block(gridDim.x);
+    const int r = real_of(b.map, blk);
+    const RayR<T> &a = b.r[r];
+    const int i = (blk - b.map.start[r]) * kThreads + threadIdx.x;
+    if (i >= a.nrays) return;
+    const int ix = i % a.mx, iy = i / a.mx;
+    const double thx = ((ix + 0.5) - a.half_mx) * a.mux + (double)a.dthx[i];
+    const double thy = ((iy + 0.5) - a.half_my) * a.muy + (double)a.dthy[i];
+    const int n = a.n, m = n - 1;
     T ax = 0, ay = 0;
-    for (int e = begin; e < begin + count; ++e) {
-        const PlaneEntry pe = planes[e];
-        const double X = (obsx + pe.chi * thx) * inv_cell;
-        const double Y = (obsy + pe.chi * thy) * inv_cell;
+    for (int e = a.begin; e < a.begin + a.count; ++e) {
+        const PlaneEntry pe = a.planes[e];
+        const double X = (a.obsx + pe.chi * thx) * a.inv_cell;
+        const double Y = (a.obsy + pe.chi * thy) * a.inv_cell;
         const double flx = floor(X), fly = floor(Y);
         const T fx = (T)(X - flx), fy = (T)(Y - fly);
         const int x0 = (int)((int64_t)flx & m), y0 = (int)((int64_t)fly & m);
         const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
-        const v4<T> *plane = g + (size_t)pe.mesh * n * n;
+        const v4<T> *plane = a.g + (size_t)pe.mesh * n * n;
         const v4<T> g00 = plane[(size_t)y0 * n + x0], g01 = plane[(size_t)y0 * n + x1];
         const v4<T> g10 = plane[(size_t)y1 * n + x0], g11 = plane[(size_t)y1 * n + x1];
         const T w00 = (T(1) - fx) * (T(1) - fy), w01 = fx * (T(1) - fy);
@@ -53,11 +69,11 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(
         ax += w * gx;
         ay += w * gy;
     }
-    const T npx = px[i] + ax, npy = py[i] + ay;
-    px[i] = npx;
-    py[i] = npy;
-    dthx[i] += d * npx;
-    dthy[i] += d * npy;
+    const T npx = a.px[i] + ax, npy = a.py[i] + ay;
+    a.px[i] = npx;
+    a.py[i] = npy;
+    a.dthx[i] += a.d * npx;
+    a.dthy[i] += a.d * npy;
 }
 
 template <typename T>
@@ -68,64 +84,91 @@ __device__ __forceinline__ T fd(const T *f, int i, int k, int mk, int stride) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void convergence_kernel(
-    const T *__restrict__ dthx, const T *__restrict__ dthy, T *__restrict__ kappa,
-    T *__restrict__ g1, T *__restrict__ g2, T *__restrict__ om, int mx, int my, T inv2mux,
-    T inv2muy) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= mx * my) return;
-    const int ix = i % mx, iy = i / mx;
-    const T dxx = fd(dthx, i, ix, mx, 1) * inv2mux;    // d dth_x / d theta0_x = A11 - 1
-    const T dxy = fd(dthx, i, iy, my, mx) * inv2muy;   // A12
-    const T dyx = fd(dthy, i, ix, mx, 1) * inv2mux;    // A21
-    const T dyy = fd(dthy, i, iy, my, mx) * inv2muy;   // A22 - 1
-    const T k = T(-0.5) * (dxx + dyy);                 // kappa = 1 - (A11 + A22)/2
-    kappa[i] = k;
-    if (g1 || g2 || om) {
+__global__ __launch_bounds__(kThreads) void convergence_kernel(RayBatch<T> b) {
+    const int r = real_of(b.map, blockIdx.x);
+    const RayR<T> &a = b.r[r];
+    const int i = (blockIdx.x - b.map.start[r]) * kThreads + threadIdx.x;
+    if (i >= a.nrays) return;
+    const int mx = a.mx, my = a.my, ix = i % mx, iy = i / mx;
+    const T dxx = fd<T>(a.dthx, i, ix, mx, 1) * a.inv2mux;    // d dth_x / d theta0_x = A11 - 1
+    const T dxy = fd<T>(a.dthx, i, iy, my, mx) * a.inv2muy;   // A12
+    const T dyx = fd<T>(a.dthy, i, ix, mx, 1) * a.inv2mux;    // A21
+    const T dyy = fd<T>(a.dthy, i, iy, my, mx) * a.inv2muy;   // A22 - 1
+    const T k = T(-0.5) * (dxx + dyy);                        // kappa = 1 - (A11 + A22)/2
+    a.kappa[i] = k;
+    if (a.g1 || a.g2 || a.om) {
         const T c2v = T(0.5) * (dxy - dyx), c3 = T(0.5) * (dyy - dxx), c4 = T(0.5) * (dxy + dyx);
         const T w = c2v / (T(1) - k);
-        if (om) om[i] = w;
-        if (g1) g1[i] = c3 + c4 * w;
-        if (g2) g2[i] = -c4 + c3 * w;
+        if (a.om) a.om[i] = w;
+        if (a.g1) a.g1[i] = c3 + c4 * w;
+        if (a.g2) a.g2[i] = -c4 + c3 * w;
     }
 }
 
 template <typename T>
-hipError_t ray_impl(hrt_ctx *c, const hrt_rays *r, int begin, int count, double d) {
-    const int nrays = c->mx * c->my;
-    prof_begin(c);
-    ray_step_kernel<T><<<(nrays + kThreads - 1) / kThreads, kThreads, 0, c->stream>>>(
-        static_cast<T *>(r->dth[0]), static_cast<T *>(r->dth[1]), static_cast<T *>(r->p[0]),
-        static_cast<T *>(r->p[1]), reinterpret_cast<const PlaneEntry *>(c->ws + c->lay.planes), begin,
-        count, reinterpret_cast<const v4<T> *>(c->ws + c->lay.grad), c->n, 1.0 / c->cell,
-        c->cfg.observer[0], c->cfg.observer[1], c->mx, nrays, c->cfg.fov_x / c->mx,
-        c->cfg.fov_y / c->my, 0.5 * c->mx, 0.5 * c->my, (T)d);
-    prof_end(c, K_RAY_STEP);
-    return hipGetLastError();
+void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
+    const Real &re = c->re[r];
+    const hrt_rays &rays = s.r[r];
+    a = RayR<T>{};
+    a.dthx = static_cast<T *>(rays.dth[0]);
+    a.dthy = static_cast<T *>(rays.dth[1]);
+    a.px = static_cast<T *>(rays.p[0]);
+    a.py = static_cast<T *>(rays.p[1]);
+    a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
+    a.g = reinterpret_cast<const v4<T> *>(re.ws + re.lay.grad);
+    if (s.kappa) {
+        a.kappa = static_cast<T *>(s.kappa[r]);
+        a.g1 = s.g1 ? static_cast<T *>(s.g1[r]) : nullptr;
+        a.g2 = s.g2 ? static_cast<T *>(s.g2[r]) : nullptr;
+        a.om = s.om ? static_cast<T *>(s.om[r]) : nullptr;
+    }
+    a.begin = re.tab.plane_begin[s.step];
+    a.count = re.tab.plane_count[s.step];
+    a.n = re.n;
+    a.mx = re.mx;
+    a.my = re.my;
+    a.nrays = re.mx * re.my;
+    a.inv_cell = 1.0 / re.cell;
+    a.obsx = re.cfg.observer[0];
+    a.obsy = re.cfg.observer[1];
+    a.mux = re.cfg.fov_x / re.mx;
+    a.muy = re.cfg.fov_y / re.my;
+    a.half_mx = 0.5 * re.mx;
+    a.half_my = 0.5 * re.my;
+    a.d = (T)re.tab.d[s.step];
+    a.inv2mux = (T)(0.5 * re.mx / re.cfg.fov_x);
+    a.inv2muy = (T)(0.5 * re.my / re.cfg.fov_y);
+    (void)k;
 }
 
-template <typename T>
-hipError_t conv_impl(hrt_ctx *c, const hrt_rays *r, void *kappa, void *g1, void *g2, void *om) {
-    const int nrays = c->mx * c->my;
-    prof_begin(c);
-    convergence_kernel<T><<<(nrays + kThreads - 1) / kThreads, kThreads, 0, c->stream>>>(
-        static_cast<const T *>(r->dth[0]), static_cast<const T *>(r->dth[1]), static_cast<T *>(kappa),
-        static_cast<T *>(g1), static_cast<T *>(g2), static_cast<T *>(om), c->mx, c->my,
-        (T)(0.5 * c->mx / c->cfg.fov_x), (T)(0.5 * c->my / c->cfg.fov_y));
-    prof_end(c, K_CONVERGENCE);
+template <typename T, bool CONV>
+hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
+    const int nre = (int)c->re.size();
+    for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
+        const int R = std::min(kMaxBatch, nre - r0);
+        RayBatch<T> b{};
+        b.map.R = R;
+        b.map.start[0] = 0;
+        for (int k = 0; k < R; ++k) {
+            fill_rays<T>(c, r0 + k, s, k, b.r[k]);
+            b.map.start[k + 1] = b.map.start[k] + (b.r[k].nrays + kThreads - 1) / kThreads;
+        }
+        prof_begin(c);
+        if (CONV) convergence_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else ray_step_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        prof_end(c, CONV ? K_CONVERGENCE : K_RAY_STEP);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_ray_step(hrt_ctx *c, const hrt_rays *r, int begin, int count, double d) {
-    return c->f64 ? ray_impl<double>(c, r, begin, count, d) : ray_impl<float>(c, r, begin, count, d);
+hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &s) {
+    return c->f64 ? rays_impl<double, false>(c, s) : rays_impl<float, false>(c, s);
 }
 
-hipError_t launch_convergence(hrt_ctx *c, const hrt_rays *r, void *kappa, void *g1, void *g2,
-                              void *om) {
-    return c->f64 ? conv_impl<double>(c, r, kappa, g1, g2, om)
-                  : conv_impl<float>(c, r, kappa, g1, g2, om);
+hipError_t launch_convergence(hrt_ctx *c, const StepArgs &s) {
+    return c->f64 ? rays_impl<double, true>(c, s) : rays_impl<float, true>(c, s);
 }
 
 }  // namespace hrt

@@ -22,7 +22,7 @@ HRT_NUM_KERNELS = 13
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
             "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",
             "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
-            "hrt_ic_factors")
+            "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch")
 
 
 class HrtConfig(ctypes.Structure):
@@ -66,21 +66,24 @@ def lib():
                            "(run __graft_entry__.build() or python -m paper_2405_12913_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         P = POINTER
-        L.hrt_workspace_bytes.argtypes = [P(HrtConfig), P(c_size_t)]
-        L.hrt_init.argtypes = [P(HrtConfig), c_void_p, c_size_t, c_void_p, P(c_void_p)]
+        L.hrt_workspace_bytes.argtypes = [P(HrtConfig), c_int, P(c_size_t)]
+        L.hrt_init.argtypes = [P(HrtConfig), c_int, c_void_p, c_size_t, c_void_p, P(c_void_p)]
         L.hrt_destroy.argtypes = [c_void_p]
         L.hrt_last_error.argtypes = [c_void_p]
         L.hrt_last_error.restype = ctypes.c_char_p
         L.pm_force.argtypes = [c_void_p, P(HrtMatter), c_int]
         L.pm_step.argtypes = [c_void_p, P(HrtMatter), c_int]
         L.ray_step.argtypes = [c_void_p, P(HrtRays), c_int]
-        L.ray_convergence.argtypes = [c_void_p, P(HrtRays), c_void_p, c_void_p, c_void_p, c_void_p]
-        L.hrt_mesh_ptr.argtypes = [c_void_p, c_int, P(c_void_p)]
+        L.ray_convergence.argtypes = [c_void_p, P(HrtRays), P(c_void_p), P(c_void_p), P(c_void_p),
+                                      P(c_void_p)]
+        L.hrt_graph_capture.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int]
+        L.hrt_graph_launch.argtypes = [c_void_p]
+        L.hrt_mesh_ptr.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
         L.hrt_tables.argtypes = [P(HrtConfig)] + [P(c_double)] * 5 + [P(c_int32)] * 3 + \
             [P(c_double)] * 2 + [c_int32, P(c_int32)]
         L.hrt_profile_enable.argtypes = [c_void_p, c_int]
         L.hrt_profile_read.argtypes = [c_void_p, P(c_double), P(ctypes.c_int64), c_int]
-        L.hrt_ic_2lpt.argtypes = [c_void_p, c_void_p, P(HrtIcParams), P(HrtMatter)]
+        L.hrt_ic_2lpt.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter)]
         L.hrt_ic_factors.argtypes = [P(HrtConfig), P(HrtIcParams), P(c_double)]
         L.hrt_kernel_name.argtypes = [c_int]
         L.hrt_kernel_name.restype = ctypes.c_char_p
@@ -117,9 +120,11 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     return cfg, sched
 
 
-def hrt_workspace_bytes(cfg):
+def hrt_workspace_bytes(cfg, n_cfg=1):
+    """Workspace bytes for one config, or for an array of n_cfg configs."""
     out = c_size_t(0)
-    _check(lib().hrt_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+    arg = cfg if isinstance(cfg, ctypes.Array) else ctypes.pointer(cfg)
+    _check(lib().hrt_workspace_bytes(arg, n_cfg, ctypes.byref(out)))
     return out.value
 
 
@@ -164,26 +169,34 @@ def _ptr(t, dtype, numel, what):
 
 
 class Simulation:
-    """One HRT context: workspace, step tables and the C-ABI calls on the current stream."""
+    """One HRT context on the current stream: workspace, step tables and the C-ABI calls.
 
-    def __init__(self, *, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0,
-                 fov_y=0.0, observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False,
-                 static_mass=0.0, device="cuda"):
+    Single realisation: Simulation(mesh_n=..., box=..., ...); state arguments are lists of
+    device tensors (s = [sx, sy, sz], dth = [dx, dy]). Batch: Simulation(configs=[{...}, ...])
+    with one keyword dict per realisation; state arguments are then lists of such lists.
+    """
+
+    def __init__(self, *, configs=None, device="cuda", **single):
         import torch
-        self.cfg, self._sched = make_config(
-            mesh_n=mesh_n, box=box, ptcl_n=ptcl_n, n_steps=n_steps, sched=sched, ray_nx=ray_nx,
-            ray_ny=ray_ny, fov_x=fov_x, fov_y=fov_y, observer=observer, omega_m=omega_m,
-            dtype=dtype, static=static, static_mass=static_mass)
+        configs = [single] if configs is None else list(configs)
+        self.R = len(configs)
+        self.cfgs = (HrtConfig * self.R)()
+        self._scheds = []
+        for k, kw in enumerate(configs):
+            cfg, sched = make_config(**kw)
+            self.cfgs[k] = cfg
+            self._scheds.append(sched)
+        self.cfg = self.cfgs[0]
         self.dtype = torch.float64 if self.cfg.dtype == HRT_F64 else torch.float32
         self.device = torch.device(device)
-        self.n_particles = ptcl_n ** 3
-        self.n_rays = ray_nx * ray_ny
-        self.ws_bytes = hrt_workspace_bytes(self.cfg)
+        self.n_particles = [c.ptcl_n ** 3 for c in self.cfgs]
+        self.n_rays = [c.ray_nx * c.ray_ny for c in self.cfgs]
+        self.ws_bytes = hrt_workspace_bytes(self.cfgs, self.R)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = c_void_p(0)
-        _check(lib().hrt_init(ctypes.byref(self.cfg), c_void_p(self.workspace.data_ptr()),
-                              self.ws_bytes, c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        _check(lib().hrt_init(self.cfgs, self.R, c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                              c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
         self.ctx = ctx
 
     def close(self):
@@ -197,43 +210,75 @@ class Simulation:
         except Exception:
             pass
 
+    def _per(self, x):
+        """Normalise a single-realisation argument to a per-realisation list."""
+        import torch
+        if x is None:
+            return [None] * self.R
+        if self.R == 1 and len(x) > 0 and isinstance(x[0], torch.Tensor):
+            return [x]
+        if len(x) != self.R:
+            raise ValueError(f"expected {self.R} per-realisation entries, got {len(x)}")
+        return list(x)
+
     def _matter(self, s, p=None):
-        m = HrtMatter()
-        for d in range(3):
-            m.s[d] = _ptr(s[d], self.dtype, self.n_particles, "s")
-            m.p[d] = _ptr(p[d], self.dtype, self.n_particles, "p") if p is not None else None
+        m = (HrtMatter * self.R)()
+        for k, (sk, pk) in enumerate(zip(self._per(s), self._per(p))):
+            for d in range(3):
+                m[k].s[d] = _ptr(sk[d], self.dtype, self.n_particles[k], "s")
+                m[k].p[d] = _ptr(pk[d], self.dtype, self.n_particles[k], "p") if pk is not None else None
         return m
 
-    def _rays(self, dth, p):
-        r = HrtRays()
-        for d in range(2):
-            r.dth[d] = _ptr(dth[d], self.dtype, self.n_rays, "dth")
-            r.p[d] = _ptr(p[d], self.dtype, self.n_rays, "p")
+    def _rays(self, dth, p=None):
+        r = (HrtRays * self.R)()
+        for k, (dk, pk) in enumerate(zip(self._per(dth), self._per(p))):
+            for d in range(2):
+                r[k].dth[d] = _ptr(dk[d], self.dtype, self.n_rays[k], "dth")
+                r[k].p[d] = _ptr(pk[d], self.dtype, self.n_rays[k], "p") if pk is not None else None
         return r
 
     def pm_force(self, s, step):
-        _check(lib().pm_force(self.ctx, ctypes.byref(self._matter(s)), step), self.ctx)
+        _check(lib().pm_force(self.ctx, self._matter(s), step), self.ctx)
 
     def pm_step(self, s, p, step):
-        _check(lib().pm_step(self.ctx, ctypes.byref(self._matter(s, p)), step), self.ctx)
+        _check(lib().pm_step(self.ctx, self._matter(s, p), step), self.ctx)
 
     def ray_step(self, dth, p, step):
-        _check(lib().ray_step(self.ctx, ctypes.byref(self._rays(dth, p)), step), self.ctx)
+        _check(lib().ray_step(self.ctx, self._rays(dth, p), step), self.ctx)
 
     def ray_convergence(self, dth, kappa, gamma1=None, gamma2=None, omega=None):
-        r = HrtRays()
-        for d in range(2):
-            r.dth[d] = _ptr(dth[d], self.dtype, self.n_rays, "dth")
-            r.p[d] = None
-        outs = [None if t is None else c_void_p(_ptr(t, self.dtype, self.n_rays, "output"))
-                for t in (kappa, gamma1, gamma2, omega)]
-        _check(lib().ray_convergence(self.ctx, ctypes.byref(r), *outs), self.ctx)
+        import torch
 
-    def ic_2lpt(self, noise, s, p, ic):
+        def ptrs(ts):
+            if ts is None:
+                return None
+            ts = [ts] if isinstance(ts, torch.Tensor) else list(ts)
+            arr = (c_void_p * self.R)()
+            for k, t in enumerate(ts):
+                arr[k] = _ptr(t, self.dtype, self.n_rays[k], "output")
+            return arr
+        _check(lib().ray_convergence(self.ctx, self._rays(dth), ptrs(kappa), ptrs(gamma1),
+                                     ptrs(gamma2), ptrs(omega)), self.ctx)
+
+    def graph_capture(self, s, p, dth, pr, first_step, n_steps):
+        """Capture steps [first_step, first_step + n_steps) into one HIP graph."""
+        self._graph_args = (self._matter(s, p), self._rays(dth, pr) if dth is not None else None)
+        _check(lib().hrt_graph_capture(self.ctx, self._graph_args[0], self._graph_args[1],
+                                       first_step, n_steps), self.ctx)
+
+    def graph_launch(self):
+        _check(lib().hrt_graph_launch(self.ctx), self.ctx)
+
+    def ic_2lpt(self, noise, s, p, ic, realisation=0):
         """2LPT state at ic.a from unit white noise (device tensor, np^3, [z][y][x])."""
-        nz = _ptr(noise, self.dtype, self.n_particles, "noise")
-        _check(lib().hrt_ic_2lpt(self.ctx, c_void_p(nz), ctypes.byref(ic),
-                                 ctypes.byref(self._matter(s, p))), self.ctx)
+        k = realisation
+        nz = _ptr(noise, self.dtype, self.n_particles[k], "noise")
+        m = HrtMatter()
+        for d in range(3):
+            m.s[d] = _ptr(s[d], self.dtype, self.n_particles[k], "s")
+            m.p[d] = _ptr(p[d], self.dtype, self.n_particles[k], "p")
+        _check(lib().hrt_ic_2lpt(self.ctx, k, c_void_p(nz), ctypes.byref(ic), ctypes.byref(m)),
+               self.ctx)
 
     def profile_enable(self, on=True):
         _check(lib().hrt_profile_enable(self.ctx, 1 if on else 0), self.ctx)
@@ -245,13 +290,13 @@ class Simulation:
         _check(lib().hrt_profile_read(self.ctx, ms, cnt, HRT_NUM_KERNELS), self.ctx)
         return {lib().hrt_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(HRT_NUM_KERNELS)}
 
-    def mesh(self, which):
-        """View of an internal mesh in the workspace ([n, n, n], or [n, n, n, 4] for G)."""
+    def mesh(self, which, realisation=0):
+        """View of an internal mesh ([n, n, n], or [n, n, n, 4] for G) of one realisation."""
         ptr = c_void_p(0)
-        _check(lib().hrt_mesh_ptr(self.ctx, which, ctypes.byref(ptr)), self.ctx)
-        n = self.cfg.mesh_n
+        _check(lib().hrt_mesh_ptr(self.ctx, realisation, which, ctypes.byref(ptr)), self.ctx)
+        n = self.cfgs[realisation].mesh_n
         comps = 4 if which == HRT_MESH_GRAD else 1
-        esize = 8 if self.dtype.is_floating_point and self.cfg.dtype == HRT_F64 else 4
+        esize = 8 if self.cfg.dtype == HRT_F64 else 4
         off = ptr.value - self.workspace.data_ptr()
         nbytes = n ** 3 * comps * esize
         v = self.workspace[off:off + nbytes].view(self.dtype)
