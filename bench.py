@@ -59,6 +59,107 @@ def algorithmic_bytes(name, n, P, nrays):
     }[name]
 
 
+def evolved_ic(hrt, torch, cfg, dev, seed):
+    """State at a = 1 of one workload: 2LPT at a_init then forward PM + closing half-kick."""
+    import synth
+    np_, n, box = cfg["ptcl_n"], cfg["mesh_n"], cfg["box"]
+    P = np_ ** 3
+    noise = torch.tensor(synth.white_noise(seed, np_).astype(np.float32).ravel(), device=dev)
+    s = [torch.empty(P, device=dev) for _ in range(3)]
+    p = [torch.empty(P, device=dev) for _ in range(3)]
+    fwd = cfg["fwd_sched"]
+    sim_f = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(fwd) - 1, sched=fwd,
+                           omega_m=cfg["omega_m"], dtype="f32", device=dev)
+    sim_f.ic_2lpt(noise, s, p, hrt.ic_params(omega_b=cfg["omega_b"], h=cfg["h"], n_s=cfg["n_s"],
+                                             sigma8=cfg["sigma8"], a=fwd[0]))
+    for k in range(len(fwd)):          # steps 0..N-1 and the closing half-kick N
+        sim_f.pm_step(s, p, k)
+    torch.cuda.synchronize()
+    sim_f.close()
+    return s, p
+
+
+def sim_kwargs(cfg):
+    return dict(mesh_n=cfg["mesh_n"], box=cfg["box"], ptcl_n=cfg["ptcl_n"], n_steps=len(cfg["sched"]) - 1,
+                sched=cfg["sched"], ray_nx=cfg["ray_n"], ray_ny=cfg["ray_n"], fov_x=cfg["fov"],
+                fov_y=cfg["fov"], observer=cfg["observer"], omega_m=cfg["omega_m"], dtype="f32")
+
+
+def batched_bench(hrt, torch, dev):
+    """16 uneven realisations: one batched context replaying a captured 64-step graph vs
+    the same realisations run one after another, each from its own graph."""
+    import synth
+    cfgs = synth.batched16()
+    N = len(cfgs[0]["sched"]) - 1
+    print("[bench] batched: 16 realisations, initial conditions", file=sys.stderr, flush=True)
+    init = [evolved_ic(hrt, torch, c, dev, c["seed"]) for c in cfgs]
+    rays = [c["ray_n"] ** 2 for c in cfgs]
+
+    def fresh():
+        st = []
+        for (s0, p0), m in zip(init, rays):
+            st.append(([t.clone() for t in s0], [t.clone() for t in p0],
+                       [torch.zeros(m, device=dev) for _ in range(2)],
+                       [torch.zeros(m, device=dev) for _ in range(2)]))
+        return st
+
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        st = fresh()
+        sim = hrt.Simulation(configs=[sim_kwargs(c) for c in cfgs], device=dev)
+        sim.graph_capture([x[0] for x in st], [x[1] for x in st], [x[2] for x in st],
+                          [x[3] for x in st], 0, N)
+        sim.graph_launch()                                  # warm-up replay
+        torch.cuda.synchronize()
+        for x, (s0, p0) in zip(st, init):
+            for a, b in zip(x[0] + x[1], s0 + p0):
+                a.copy_(b)
+            for t in x[2] + x[3]:
+                t.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sim.graph_launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_batch = e0.elapsed_time(e1) * 1e-3
+        sim.close()
+        del sim, st
+        # plain: each realisation alone, one captured graph each, run back to back
+        st = fresh()
+        sims = []
+        for c, x in zip(cfgs, st):
+            s1 = hrt.Simulation(**sim_kwargs(c), device=dev)
+            s1.graph_capture(x[0], x[1], x[2], x[3], 0, N)
+            sims.append(s1)
+        for s1 in sims:
+            s1.graph_launch()                               # warm-up
+        torch.cuda.synchronize()
+        for x, (s0, p0) in zip(st, init):
+            for a, b in zip(x[0] + x[1], s0 + p0):
+                a.copy_(b)
+            for t in x[2] + x[3]:
+                t.zero_()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for s1 in sims:
+            s1.graph_launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_plain = e0.elapsed_time(e1) * 1e-3
+        for s1 in sims:
+            s1.close()
+    tot_rays = sum(rays)
+    return {"workload": "batched16: 8 x (128^3, box 200, 4 deg) + 8 x (256^3, box 400, 5 deg), "
+                        "ray grids 256^2..1024^2, (Omega_m, sigma_8) uniform in [0.2,0.4]x[0.6,1.0], "
+                        "64 co-evolution steps, captured as one HIP graph",
+            "realisation_steps_per_s": 16 * N / t_batch,
+            "ray_steps_per_s": tot_rays * N / t_batch,
+            "plain_sequential_realisation_steps_per_s": 16 * N / t_plain,
+            "plain_sequential_ray_steps_per_s": tot_rays * N / t_plain,
+            "speedup_vs_plain": t_plain / t_batch}
+
+
 def cpu_baseline():
     """Oracle (FP64 NumPy) time for one co-evolution step on a bounded sample."""
     import synth
@@ -99,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 16-realisation batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
@@ -120,28 +223,13 @@ def main():
     dev = torch.device("cuda:0")
     print(f"[bench] initial conditions: {np_}^3 2LPT at a=1/64, forward PM to a=1", file=sys.stderr,
           flush=True)
-    noise = torch.tensor(synth.white_noise(args.seed, np_).astype(np.float32).ravel(), device=dev)
-    s_init = [torch.empty(P, device=dev) for _ in range(3)]
-    p_init = [torch.empty(P, device=dev) for _ in range(3)]
-    fwd = cfg["fwd_sched"]
-    sim_f = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(fwd) - 1, sched=fwd,
-                           omega_m=cfg["omega_m"], dtype="f32", device="cuda:0")
-    sim_f.ic_2lpt(noise, s_init, p_init, hrt.ic_params(omega_b=cfg["omega_b"], h=cfg["h"],
-                                                       n_s=cfg["n_s"], sigma8=cfg["sigma8"],
-                                                       a=fwd[0]))
-    for k in range(len(fwd)):          # steps 0..N-1 and the closing half-kick N
-        sim_f.pm_step(s_init, p_init, k)
-    torch.cuda.synchronize()
-    sim_f.close()
-    del sim_f, noise
+    s_init, p_init = evolved_ic(hrt, torch, cfg, dev, args.seed)
     s = [t.clone() for t in s_init]
     p = [t.clone() for t in p_init]
     dth = [torch.zeros(nrays, device=dev) for _ in range(2)]
     pr = [torch.zeros(nrays, device=dev) for _ in range(2)]
     kappa = torch.empty(nrays, device=dev)
-    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=N, sched=cfg["sched"], ray_nx=nr,
-                         ray_ny=nr, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
-                         omega_m=cfg["omega_m"], dtype="f32", device="cuda:0")
+    sim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
 
     def step(k):
         m = k % N
@@ -234,6 +322,25 @@ def main():
                      "traffic": None},
         "kernels": kernels,
     }
+    # the same K steps replayed from one captured HIP graph (no host launches in the loop)
+    if args.steps <= N:
+        reset()
+        gstream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(gstream):
+            gsim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+            gsim.graph_capture(s, p, dth, pr, 0, args.steps)
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            g0.record(gstream)
+            gsim.graph_launch()
+            g1.record(gstream)
+            torch.cuda.synchronize()
+            gms = g0.elapsed_time(g1)
+            gsim.close()
+        out["graph_ray_steps_per_s"] = nrays * args.steps / (gms * 1e-3)
+        out["graph_ms_per_step"] = gms / args.steps
+    if not args.no_batched:
+        out["batched"] = batched_bench(hrt, torch, dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -66,6 +66,22 @@ def large1024():
                 a_end=1.0 / 3.0, name="large1024")
 
 
+def batched16(n_steps=64):
+    """16 uneven realisations: seed s has a 128^3 mesh and lattice in a 200 Mpc/h box with a
+    4 degree field when s is even, 256^3 in 400 Mpc/h with 5 degrees when odd; ray grid side
+    256 (1 + s mod 4); (Omega_m, sigma_8) = (0.2 + 0.2 u1, 0.6 + 0.4 u2) with (u1, u2) drawn
+    from default_rng(1000 + s); sources at z = 1."""
+    out = []
+    for s in range(16):
+        u1, u2 = np.random.default_rng(1000 + s).uniform(size=2)
+        big = s % 2 == 1
+        c = lcdm(mesh_n=256 if big else 128, ptcl_n=256 if big else 128, box=400.0 if big else 200.0,
+                 ray_n=256 * (1 + s % 4), fov_deg=5.0 if big else 4.0, n_steps=n_steps, seed=s,
+                 omega_m=0.2 + 0.2 * u1, sigma8=0.6 + 0.4 * u2, name=f"batched16[{s}]")
+        out.append(c)
+    return out
+
+
 def tiny(mesh_n=32, ptcl_n=32, box=50.0, ray_n=32, fov_deg=1.0, n_steps=8, seed=0):
     return lcdm(mesh_n=mesh_n, ptcl_n=ptcl_n, box=box, ray_n=ray_n, fov_deg=fov_deg,
                 n_steps=n_steps, seed=seed, name=f"tiny{mesh_n}")
