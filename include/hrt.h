@@ -59,8 +59,10 @@ enum { HRT_F32 = 0, HRT_F64 = 1 };
 
 /* flags */
 enum {
-    HRT_STATIC = 1          /* static point-lens run: a = 1, sched holds chi_n, the mesh
+    HRT_STATIC = 1,         /* static point-lens run: a = 1, sched holds chi_n, the mesh
                                source is unit-weight particles of mass static_mass each */
+    HRT_ADJOINT = 2         /* reserve the reverse-mode scratch (hrt_step_vjp) in the
+                               workspace: 24 n^3 + 256 more bytes                       */
 };
 
 typedef struct {
@@ -69,7 +71,7 @@ typedef struct {
     int32_t ray_nx, ray_ny; /* Mx, My >= 3 (0 = no rays)                                */
     int32_t n_steps;        /* N >= 1                                                    */
     int32_t dtype;          /* HRT_F32 or HRT_F64                                        */
-    int32_t flags;          /* HRT_STATIC or 0                                           */
+    int32_t flags;          /* HRT_STATIC and/or HRT_ADJOINT, or 0                      */
     int32_t reserved;       /* must be 0                                                 */
     double box;             /* periodic box side L [Mpc/h]                               */
     double fov_x, fov_y;    /* field of view [rad]                                       */
@@ -179,6 +181,37 @@ int hrt_ic_2lpt(hrt_ctx *ctx, int realisation, const void *noise, const hrt_ic_p
 /* Host-only: out[0..5] = amplitude A, D1(a), f1(a), D2(a), f2(a), D1(1) (growth factors
  * with D1 -> a deep in matter domination) for cfg and ic. */
 int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out);
+
+/* Reverse mode (vector-Jacobian products). The paper names gradients through the ray
+ * tracer as future work (Sec. 6, via the adjoint method of its ref. LiEtAl2024); these are
+ * the exact transposes of the forward discretisation above. A cotangent array has the
+ * shape, layout and dtype of the state array it belongs to; the functions update the
+ * cotangents in place (device, caller-owned).
+ *
+ * hrt_step_vjp: m (s; p may be NULL) and r (dth; p may be NULL) are the state BEFORE step
+ * `step`; on entry mc and rc hold the cotangents of the state AFTER the step, on return
+ * those of the state before it. It recomputes the force mesh of the step (pm_force), then
+ * runs the transposed ray kick-drift, the transposed matter kick-drift, and the transposed
+ * force (fourth-order difference, Poisson solve and CIC paint). The force-mesh cotangent is
+ * summed in 64-bit fixed point, so results are deterministic. r and rc are both NULL for
+ * matter only. Needs a context with one realisation (else HRT_EUNSUPPORTED) created with
+ * HRT_ADJOINT (else HRT_ESTATE); with HRT_STATIC the matter does not move, mc->p may be
+ * NULL and mc->s receives the lens-position cotangent. Overwrites the force mesh: the next
+ * ray_step needs a new pm_force/pm_step. */
+int hrt_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                 const hrt_rays *rc, int step);
+
+/* Adds the cotangent of the deflections from kappa_bar (n_cfg device pointers to Mx*My
+ * values: the cotangent of ray_convergence's kappa) to rc[k].dth (rc[k].p may be NULL). */
+int ray_convergence_vjp(hrt_ctx *ctx, void *const *kappa_bar, const hrt_rays *rc);
+
+/* Cotangent of the white noise of hrt_ic_2lpt: from the cotangents cot->s, cot->p of the
+ * 2LPT state (read only) writes noise_bar (np^3 values, layout of the noise; it must not
+ * alias noise or any cotangent array: it serves as scratch before the result is written;
+ * HRT_EINVAL if it is one of them). Uses the realisation's workspace as scratch (it
+ * overwrites the force mesh). */
+int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_ic_params *ic,
+                    const hrt_matter *cot, void *noise_bar);
 
 /* Optional per-kernel timing with HIP events recorded on the context's stream around
  * every kernel launch (for measurement; off by default). hrt_profile_enable(ctx, 1)

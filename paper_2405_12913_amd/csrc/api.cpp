@@ -36,6 +36,9 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     L.cursor = take((size_t)L.nbins * 4);
     L.sorted = take(P * 4 * T);
     L.planes = take((size_t)std::max<int64_t>(n_plane_entries, 1) * sizeof(PlaneEntry));
+    // reverse mode: 3 x n^3 64-bit fixed-point accumulators of the force-mesh cotangent and
+    // one 8-byte device scalar
+    L.adj = (cfg.flags & HRT_ADJOINT) ? take(3 * n3 * 8 + 256) : off;
     L.total = off;
     return L;
 }
@@ -439,6 +442,64 @@ extern "C" int hrt_ic_2lpt(hrt_ctx *c, int realisation, const void *noise, const
     if (int rc = check_hip(c, hrt::launch_ic(c, realisation, noise, p, out), "initial conditions"))
         return rc;
     c->force_step = -1;          // the force mesh was used as scratch
+    return HRT_OK;
+}
+
+extern "C" int hrt_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
+                            const hrt_matter *mc, const hrt_rays *rc, int step) {
+    if (!c) return HRT_EINVAL;
+    if (c->re.size() != 1) return fail(c, HRT_EUNSUPPORTED, "reverse mode needs a single realisation");
+    if (!(c->re[0].cfg.flags & HRT_ADJOINT))
+        return fail(c, HRT_ESTATE, "context was created without HRT_ADJOINT");
+    if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
+    if (int rc0 = check_matter(c, m, false)) return rc0;
+    if (int rc0 = check_matter(c, mc, !c->is_static)) return rc0;
+    if ((r == nullptr) != (rc == nullptr))
+        return fail(c, HRT_EINVAL, "ray state and ray cotangent must both be given or both be NULL");
+    if (r) {
+        if (int rc0 = check_rays(c, r, false)) return rc0;
+        if (int rc0 = check_rays(c, rc, true)) return rc0;
+    }
+    if (int rc0 = pm_force(c, m, step)) return rc0;
+    int rc0 = check_hip(c, hrt::launch_step_vjp(c, m, r, mc, rc, step, !c->is_static), "step vjp");
+    c->force_step = -1;          // the force mesh now holds the cotangent
+    return rc0;
+}
+
+extern "C" int ray_convergence_vjp(hrt_ctx *c, void *const *kappa_bar, const hrt_rays *rc) {
+    if (!c) return HRT_EINVAL;
+    if (int rc0 = check_rays(c, rc, false)) return rc0;
+    if (!kappa_bar) return fail(c, HRT_EINVAL, "NULL kappa_bar");
+    for (size_t k = 0; k < c->re.size(); ++k)
+        if (!kappa_bar[k]) return fail(c, HRT_EINVAL, "NULL kappa_bar array");
+    for (size_t k = 0; k < c->re.size(); ++k)
+        if (int rc0 = check_hip(c, hrt::launch_convergence_vjp(c, (int)k, kappa_bar[k], &rc[k]),
+                                "convergence vjp"))
+            return rc0;
+    return HRT_OK;
+}
+
+extern "C" int hrt_ic_2lpt_vjp(hrt_ctx *c, int realisation, const void *noise,
+                               const hrt_ic_params *ic, const hrt_matter *cot, void *noise_bar) {
+    if (!c) return HRT_EINVAL;
+    if (realisation < 0 || realisation >= (int)c->re.size())
+        return fail(c, HRT_EINVAL, "realisation index out of range");
+    if (!noise || !ic || !cot || !noise_bar) return fail(c, HRT_EINVAL, "NULL argument");
+    for (int d = 0; d < 3; ++d) {
+        if (!cot->s[d] || !cot->p[d]) return fail(c, HRT_EINVAL, "NULL cotangent array");
+        if (cot->s[d] == noise_bar || cot->p[d] == noise_bar)
+            return fail(c, HRT_EINVAL, "noise_bar aliases a cotangent array");
+    }
+    if (noise == noise_bar) return fail(c, HRT_EINVAL, "noise_bar aliases noise");
+    const hrt::Real &re = c->re[realisation];
+    if (re.np < 16) return fail(c, HRT_EUNSUPPORTED, "initial conditions need ptcl_n >= 16");
+    hrt::IcParams p;
+    std::string err;
+    if (int rc = hrt::ic_params(re.cfg, *ic, p, err)) return fail(c, rc, err);
+    if (int rc = check_hip(c, hrt::launch_ic_vjp(c, realisation, noise, p, cot, noise_bar),
+                           "initial conditions vjp"))
+        return rc;
+    c->force_step = -1;
     return HRT_OK;
 }
 

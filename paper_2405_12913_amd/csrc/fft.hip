@@ -424,7 +424,8 @@ __device__ __forceinline__ double eh_nowiggle(double k, const IcParams &p) {
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void spec_op_kernel(const c2<T> *__restrict__ in,
                                                            c2<T> *__restrict__ out, int op, int a,
-                                                           int b, double scale, IcParams p) {
+                                                           int b, double scale, IcParams p,
+                                                           int acc) {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (e >= (int64_t)(N / 2 + 1) * N * N) return;
     const int iky = (int)(e % N), ikz = (int)((e / N) % N), ikx = (int)(e / ((int64_t)N * N));
@@ -448,7 +449,13 @@ __global__ __launch_bounds__(kThreads) void spec_op_kernel(const c2<T> *__restri
             re = -scale / k2;
         }
     }
-    out[e] = c2<T>{(T)(re * v.x - im * v.y), (T)(re * v.y + im * v.x)};
+    c2<T> r{(T)(re * v.x - im * v.y), (T)(re * v.y + im * v.x)};
+    if (acc) {                        // accumulate (reverse mode)
+        const c2<T> o = out[e];
+        r.x += o.x;
+        r.y += o.y;
+    }
+    out[e] = r;
 }
 
 template <typename T>
@@ -527,33 +534,135 @@ hipError_t ic_n(hrt_ctx *c, int r, const T *noise, const IcParams &p, const hrt_
     const double inv_n3 = 1.0 / (double)P;
     hipStream_t st = c->stream;
     fwd3d<T, N>(c, r, noise, base, tws);
-    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_PHI1, 0, 0, 1.0, p);
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_PHI1, 0, 0, 1.0, p, 0);
     for (int d = 0; d < 3; ++d) {          // s1 = -grad phi1
-        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, -inv_n3, p);
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, -inv_n3, p, 0);
         inv3d<T, N>(c, r, work, s[d], tws);
     }
     T *diag[3] = {A, B, C};
     for (int d = 0; d < 3; ++d) {
-        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, d, d, inv_n3, p);
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, d, d, inv_n3, p, 0);
         inv3d<T, N>(c, r, work, diag[d], tws);
     }
     lpt_source_diag_kernel<T><<<pblocks, kThreads, 0, st>>>(A, B, C, src, P);
     const int off[3][2] = {{0, 1}, {0, 2}, {1, 2}};
     for (int k = 0; k < 3; ++k) {
         spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_HESS, off[k][0], off[k][1],
-                                                           inv_n3, p);
+                                                           inv_n3, p, 0);
         inv3d<T, N>(c, r, work, tmp, tws);
         lpt_source_off_kernel<T><<<pblocks, kThreads, 0, st>>>(tmp, src, P);
     }
     fwd3d<T, N>(c, r, src, base, tws);
-    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_INVLAP, 0, 0, 1.0, p);
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, base, OP_INVLAP, 0, 0, 1.0, p, 0);
     for (int d = 0; d < 3; ++d) {          // s2 = +grad phi2, parked in the momentum arrays
-        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, inv_n3, p);
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(base, work, OP_GRAD, d, 0, inv_n3, p, 0);
         inv3d<T, N>(c, r, work, q[d], tws);
     }
     for (int d = 0; d < 3; ++d)
         lpt_combine_kernel<T><<<pblocks, kThreads, 0, st>>>(s[d], q[d], P, p.g1, p.g2, p.m1, p.m2);
     return hipGetLastError();
+}
+
+// Reverse mode of the 2LPT state (linear in s1, s2; s2 quadratic in phi1):
+// tmp = g s_bar + m p_bar for one component.
+template <typename T>
+__global__ void lpt_cot_kernel(const T *__restrict__ sb, const T *__restrict__ pb, T *__restrict__ out,
+                               int64_t P, double g, double m) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < P) out[i] = (T)(g * (double)sb[i] + m * (double)pb[i]);
+}
+
+// Hessians H = (H00, H11, H22, H01, H02, H12) of phi1 -> their cotangents in place from the
+// cotangent u of the source sum_{i<j} (H_ii H_jj - H_ij^2).
+template <typename T>
+__global__ void lpt_hess_bar_kernel(T *__restrict__ h0, T *__restrict__ h1, T *__restrict__ h2,
+                                    T *__restrict__ h3, T *__restrict__ h4, T *__restrict__ h5,
+                                    const T *__restrict__ u, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= P) return;
+    const T a = h0[i], b = h1[i], cc = h2[i], ui = u[i];
+    h0[i] = ui * (b + cc);
+    h1[i] = ui * (a + cc);
+    h2[i] = ui * (a + b);
+    h3[i] = T(-2) * ui * h3[i];
+    h4[i] = T(-2) * ui * h4[i];
+    h5[i] = T(-2) * ui * h5[i];
+}
+
+// noise_bar from (s_bar, p_bar): recompute the six Hessians of phi1; src_bar =
+// L(-sum_d D_d s2_bar_d); Hessian cotangents; phi1_bar = sum_d D_d s1_bar_d +
+// sum_ij D_i D_j H_bar_ij; noise_bar = Phi phi1_bar (Phi: the real even multiplier of the
+// noise -> phi1 map). Spectra are accumulated in the second spectrum; the caller's
+// noise_bar array serves as the one real temporary until the last transform.
+template <typename T, int N>
+hipError_t ic_vjp_n(hrt_ctx *c, int r, const T *noise, const IcParams &p, const hrt_matter *cot,
+                    T *noise_bar) {
+    const Real &re = c->re[r];
+    const int tws = re.n / N;
+    const int64_t P = (int64_t)N * N * N;
+    const int64_t ns = (int64_t)(N / 2 + 1) * N * N;
+    const int sblocks = (int)((ns + kThreads - 1) / kThreads), pblocks = (int)((P + kThreads - 1) / kThreads);
+    c2<T> *acc = reinterpret_cast<c2<T> *>(re.ws + re.lay.spec2);
+    c2<T> *work = reinterpret_cast<c2<T> *>(re.ws + re.lay.spec);
+    T *g4 = reinterpret_cast<T *>(re.ws + re.lay.grad);        // 4 lattices of P values
+    T *m2 = reinterpret_cast<T *>(re.ws + re.lay.mesh_r);      // 2 lattices of P values
+    T *H[6] = {g4, g4 + P, g4 + 2 * P, g4 + 3 * P, m2, m2 + P};
+    const int hij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    const T *sb[3] = {static_cast<const T *>(cot->s[0]), static_cast<const T *>(cot->s[1]),
+                      static_cast<const T *>(cot->s[2])};
+    const T *pb[3] = {static_cast<const T *>(cot->p[0]), static_cast<const T *>(cot->p[1]),
+                      static_cast<const T *>(cot->p[2])};
+    T *tmp = noise_bar;
+    const double inv_n3 = 1.0 / (double)P;
+    hipStream_t st = c->stream;
+    // forward: phi1 spectrum, Hessians
+    fwd3d<T, N>(c, r, noise, acc, tws);
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(acc, acc, OP_PHI1, 0, 0, 1.0, p, 0);
+    for (int k = 0; k < 6; ++k) {
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(acc, work, OP_HESS, hij[k][0], hij[k][1],
+                                                           inv_n3, p, 0);
+        inv3d<T, N>(c, r, work, H[k], tws);
+    }
+    // src_bar = L(-sum_d D_d s2_bar_d), s2_bar = g2 s_bar + m2 p_bar
+    for (int d = 0; d < 3; ++d) {
+        lpt_cot_kernel<T><<<pblocks, kThreads, 0, st>>>(sb[d], pb[d], tmp, P, p.g2, p.m2);
+        fwd3d<T, N>(c, r, tmp, work, tws);
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(work, acc, OP_GRAD, d, 0, -1.0, p, d > 0);
+    }
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(acc, work, OP_INVLAP, 0, 0, inv_n3, p, 0);
+    inv3d<T, N>(c, r, work, tmp, tws);
+    lpt_hess_bar_kernel<T><<<pblocks, kThreads, 0, st>>>(H[0], H[1], H[2], H[3], H[4], H[5], tmp, P);
+    // phi1_bar spectrum: sum_d (i k_d) FFT(s1_bar_d) + sum_ij (-k_i k_j) FFT(H_bar_ij)
+    for (int d = 0; d < 3; ++d) {
+        lpt_cot_kernel<T><<<pblocks, kThreads, 0, st>>>(sb[d], pb[d], tmp, P, p.g1, p.m1);
+        fwd3d<T, N>(c, r, tmp, work, tws);
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(work, acc, OP_GRAD, d, 0, 1.0, p, d > 0);
+    }
+    for (int k = 0; k < 6; ++k) {
+        fwd3d<T, N>(c, r, H[k], work, tws);
+        spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(work, acc, OP_HESS, hij[k][0], hij[k][1],
+                                                           1.0, p, 1);
+    }
+    spec_op_kernel<T, N><<<sblocks, kThreads, 0, st>>>(acc, work, OP_PHI1, 0, 0, inv_n3, p, 0);
+    inv3d<T, N>(c, r, work, noise_bar, tws);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t ic_vjp_impl(hrt_ctx *c, int r, const void *noise, const IcParams &p, const hrt_matter *cot,
+                       void *noise_bar) {
+    const T *nz = static_cast<const T *>(noise);
+    T *nb = static_cast<T *>(noise_bar);
+    switch (c->re[r].np) {
+        case 16: return ic_vjp_n<T, 16>(c, r, nz, p, cot, nb);
+        case 32: return ic_vjp_n<T, 32>(c, r, nz, p, cot, nb);
+        case 64: return ic_vjp_n<T, 64>(c, r, nz, p, cot, nb);
+        case 128: return ic_vjp_n<T, 128>(c, r, nz, p, cot, nb);
+        case 256: return ic_vjp_n<T, 256>(c, r, nz, p, cot, nb);
+        case 512: return ic_vjp_n<T, 512>(c, r, nz, p, cot, nb);
+        case 1024: return ic_vjp_n<T, 1024>(c, r, nz, p, cot, nb);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -579,6 +688,12 @@ hipError_t launch_poisson(hrt_ctx *c) {
 
 hipError_t launch_ic(hrt_ctx *c, int r, const void *noise, const IcParams &p, const hrt_matter *m) {
     return c->f64 ? ic_impl<double>(c, r, noise, p, m) : ic_impl<float>(c, r, noise, p, m);
+}
+
+hipError_t launch_ic_vjp(hrt_ctx *c, int r, const void *noise, const IcParams &p, const hrt_matter *cot,
+                         void *noise_bar) {
+    return c->f64 ? ic_vjp_impl<double>(c, r, noise, p, cot, noise_bar)
+                  : ic_vjp_impl<float>(c, r, noise, p, cot, noise_bar);
 }
 
 hipError_t launch_gradient(hrt_ctx *c) {

@@ -45,7 +45,7 @@ struct PlaneEntry {
 
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
-    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, total;
+    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, total;
     int64_t nbins;
 };
 Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
@@ -128,4 +128,11 @@ hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ic(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
                      const hrt_matter *m);
+// Reverse mode (realisation 0 of a context created with HRT_ADJOINT, see adjoint.hip).
+hipError_t launch_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                           const hrt_rays *rc, int step, bool matter);
+hipError_t launch_convergence_vjp(hrt_ctx *c, int realisation, const void *kappa_bar,
+                                  const hrt_rays *rc);
+hipError_t launch_ic_vjp(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
+                         const hrt_matter *cot, void *noise_bar);
 }  // namespace hrt

@@ -247,7 +247,7 @@ int validate_config(const hrt_config &c, std::string &err) {
     if ((int64_t)c.ray_nx * c.ray_ny > (int64_t)1 << 26) return bad("too many rays");
     if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
     if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
-    if (c.flags & ~HRT_STATIC) return bad("unknown flag");
+    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT)) return bad("unknown flag");
     if (c.reserved != 0) return bad("reserved must be 0");
     if (!(c.box > 0) || !std::isfinite(c.box)) return bad("box must be positive");
     if (c.ray_nx > 0 && (!(c.fov_x > 0) || !(c.fov_y > 0) || c.fov_x > 1.0 || c.fov_y > 1.0))

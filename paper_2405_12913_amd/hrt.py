@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhrt.so")
 HRT_OK, HRT_EINVAL, HRT_ENOMEM, HRT_EDEVICE, HRT_ESTATE, HRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 HRT_F32, HRT_F64 = 0, 1
 HRT_STATIC = 1
+HRT_ADJOINT = 2
 HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
 HRT_NUM_KERNELS = 13
@@ -22,7 +23,8 @@ HRT_NUM_KERNELS = 13
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
             "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",
             "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
-            "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch")
+            "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
+            "ray_convergence_vjp", "hrt_ic_2lpt_vjp")
 
 
 class HrtConfig(ctypes.Structure):
@@ -85,6 +87,9 @@ def lib():
         L.hrt_profile_read.argtypes = [c_void_p, P(c_double), P(ctypes.c_int64), c_int]
         L.hrt_ic_2lpt.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter)]
         L.hrt_ic_factors.argtypes = [P(HrtConfig), P(HrtIcParams), P(c_double)]
+        L.hrt_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays), c_int]
+        L.ray_convergence_vjp.argtypes = [c_void_p, P(c_void_p), P(HrtRays)]
+        L.hrt_ic_2lpt_vjp.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter), c_void_p]
         L.hrt_kernel_name.argtypes = [c_int]
         L.hrt_kernel_name.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -101,7 +106,8 @@ def _check(rc, ctx=None):
 
 
 def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
-                observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0):
+                observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0,
+                adjoint=False):
     """hrt_config from keyword arguments; returns (config, schedule array kept alive)."""
     sched = np.ascontiguousarray(sched, dtype=np.float64)
     if len(sched) != n_steps + 1:
@@ -110,7 +116,7 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     cfg.mesh_n, cfg.ptcl_n, cfg.ray_nx, cfg.ray_ny = mesh_n, ptcl_n, ray_nx, ray_ny
     cfg.n_steps = n_steps
     cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
-    cfg.flags = HRT_STATIC if static else 0
+    cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0)
     cfg.reserved = 0
     cfg.box, cfg.fov_x, cfg.fov_y = box, fov_x, fov_y
     for i in range(3):
@@ -279,6 +285,43 @@ class Simulation:
             m.p[d] = _ptr(p[d], self.dtype, self.n_particles[k], "p")
         _check(lib().hrt_ic_2lpt(self.ctx, k, c_void_p(nz), ctypes.byref(ic), ctypes.byref(m)),
                self.ctx)
+
+    def step_vjp(self, s, dth, s_bar, p_bar, dth_bar, p_ray_bar, step):
+        """Reverse of step `step` (single realisation, created with adjoint=True).
+
+        s, dth: state before the step; the cotangents (lists of device tensors) hold those
+        of the state after the step and are overwritten with those before it. dth and the
+        ray cotangents are None for matter only; p_bar may be None for a static lens."""
+        m = self._matter(s)
+        mc = self._matter(s_bar, p_bar)
+        r = rc = None
+        if dth is not None:
+            r = self._rays(dth)
+            rc = self._rays(dth_bar, p_ray_bar)
+        _check(lib().hrt_step_vjp(self.ctx, m, r, mc, rc, step), self.ctx)
+
+    def convergence_vjp(self, kappa_bar, dth_bar):
+        """dth_bar += (d kappa / d dth)^T kappa_bar (per realisation lists for batches)."""
+        import torch
+        kb = [kappa_bar] if isinstance(kappa_bar, torch.Tensor) else list(kappa_bar)
+        arr = (c_void_p * self.R)()
+        for k, t in enumerate(kb):
+            arr[k] = _ptr(t, self.dtype, self.n_rays[k], "kappa_bar")
+        _check(lib().ray_convergence_vjp(self.ctx, arr, self._rays(dth_bar)), self.ctx)
+
+    def ic_2lpt_vjp(self, noise, s_bar, p_bar, ic, noise_bar, realisation=0):
+        """noise_bar = cotangent of the white noise from those of the 2LPT state."""
+        k = realisation
+        nz = _ptr(noise, self.dtype, self.n_particles[k], "noise")
+        nb = _ptr(noise_bar, self.dtype, self.n_particles[k], "noise_bar")
+        if nb == nz:
+            raise ValueError("noise_bar must not alias noise")
+        m = HrtMatter()
+        for d in range(3):
+            m.s[d] = _ptr(s_bar[d], self.dtype, self.n_particles[k], "s_bar")
+            m.p[d] = _ptr(p_bar[d], self.dtype, self.n_particles[k], "p_bar")
+        _check(lib().hrt_ic_2lpt_vjp(self.ctx, k, c_void_p(nz), ctypes.byref(ic), ctypes.byref(m),
+                                     c_void_p(nb)), self.ctx)
 
     def profile_enable(self, on=True):
         _check(lib().hrt_profile_enable(self.ctx, 1 if on else 0), self.ctx)

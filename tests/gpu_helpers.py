@@ -52,13 +52,13 @@ class Case:
             self.pr = pr.astype(npdt).astype(np.float64)
         self.dtype = dtype
 
-    def sim(self, sched=None):
+    def sim(self, sched=None, adjoint=False):
         from paper_2405_12913_amd import hrt
         sched = self.cfg["sched"] if sched is None else sched
         return hrt.Simulation(mesh_n=self.n, box=self.box, ptcl_n=self.np_, n_steps=len(sched) - 1,
                               sched=sched, ray_nx=self.mx, ray_ny=self.my, fov_x=self.cfg["fov"],
                               fov_y=self.cfg["fov"], observer=self.cfg["observer"],
-                              omega_m=self.cfg["omega_m"], dtype=self.dtype)
+                              omega_m=self.cfg["omega_m"], dtype=self.dtype, adjoint=adjoint)
 
     def oracle_tables(self, sched=None):
         sched = self.cfg["sched"] if sched is None else sched
