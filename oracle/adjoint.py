@@ -200,3 +200,53 @@ def lpt_vjp(noise, box, a, omega_m, omega_b, h, n_s, sigma8, s_bar, p_bar):
     amp = np.sqrt(pk(kk) / (box / n) ** 3)
     amp[0, 0, 0] = 0.0
     return _spectral(phi1_bar, lap_inv * amp, box)
+
+
+def pipeline_kappa(noise, box, n, cosmo_params, fwd_tab, co_tab, theta0, mx, my, fov, observer,
+                   keep=False):
+    """kappa of the differentiable pipeline, white noise -> convergence map.
+
+    2LPT state at a = fwd_tab.a[0] (``cosmo_params`` = (omega_m, omega_b, h, n_s, sigma8));
+    forward PM steps 0..N_f including the closing half-kick, which synchronises the momenta
+    at the last boundary; co-evolution steps 0..N_c - 1 from dth = p_ray = 0 (the closing
+    half-kick of the rays changes only their momenta, not the deflections at chi_N); then
+    the convergence map (M,). With ``keep`` also returns the states before every step."""
+    om, ob, h, ns, s8 = cosmo_params
+    n_p = noise.shape[0]
+    q = integrator.lattice(n_p, box)
+    s, p = ic.lpt_state(noise, box, fwd_tab.a[0], om, ob, h, ns, s8)
+    hist_f, hist_c = [], []
+    for k in range(fwd_tab.n_steps + 1):
+        hist_f.append(s)
+        grads, _ = integrator.pm_force(q + s, n, box)
+        s, p = integrator.matter_step(s, p, q, grads, fwd_tab.K[k], fwd_tab.D[k], box)
+    dth = np.zeros((mx * my, 2))
+    pr = np.zeros((mx * my, 2))
+    for k in range(co_tab.n_steps):
+        hist_c.append((s, p, dth, pr))
+        s, p, dth, pr = integrator.coevolve(s, p, q, dth, pr, theta0, co_tab, n, box, observer, steps=[k])
+    from . import observables
+    kappa = observables.convergence(dth, mx, my, fov / mx, fov / my).ravel()
+    return (kappa, hist_f, hist_c) if keep else kappa
+
+
+def pipeline_vjp(noise, box, n, cosmo_params, fwd_tab, co_tab, theta0, mx, my, fov, observer,
+                 kappa_bar):
+    """Cotangent of the white noise from the cotangent of ``pipeline_kappa``'s map."""
+    om, ob, h, ns, s8 = cosmo_params
+    q = integrator.lattice(noise.shape[0], box)
+    _, hist_f, hist_c = pipeline_kappa(noise, box, n, cosmo_params, fwd_tab, co_tab, theta0, mx, my,
+                                       fov, observer, keep=True)
+    db = convergence_vjp(kappa_bar, mx, my, fov / mx, fov / my)
+    pb = np.zeros((mx * my, 2))
+    sb = np.zeros_like(hist_f[0])
+    mb = np.zeros_like(hist_f[0])
+    for k in reversed(range(co_tab.n_steps)):
+        s, p, dth, pr = hist_c[k]
+        sb, mb, db, pb = coevolve_step_vjp(s, p, q, dth, pr, theta0, co_tab, k, n, box, observer,
+                                           (sb, mb, db, pb))
+    for k in reversed(range(fwd_tab.n_steps + 1)):
+        s = hist_f[k]
+        sb, mb, _, _ = coevolve_step_vjp(s, None, q, None, None, None, fwd_tab, k, n, box, observer,
+                                         (sb, mb, None, None))
+    return lpt_vjp(noise, box, fwd_tab.a[0], om, ob, h, ns, s8, sb, mb)

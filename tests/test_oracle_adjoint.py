@@ -98,3 +98,22 @@ def test_lpt_vjp_matches_finite_differences():
 
     got = np.sum(adjoint.lpt_vjp(noise, *args, sb, pb) * v)
     assert _fd(f, noise, v, 1e-3) == pytest.approx(got, rel=1e-7)
+
+
+def test_pipeline_vjp_matches_finite_differences():
+    """Whole chain noise -> 2LPT -> forward PM -> co-evolution -> kappa, FP64."""
+    from oracle import cosmo  # noqa: F401
+    n_p, n, box, m, fov = 8, 16, 24.0, 8, 3.0 * np.pi / 180.0
+    cp = (0.3, 0.045, 0.7, 0.96, 0.8)
+    fwd = tables.build_cosmo(np.linspace(0.2, 1.0, 3), 0.3, n, box, 0.0, with_rays=False)
+    co = tables.build_cosmo(np.linspace(1.0, 0.85, 3), 0.3, n, box, 0.0)
+    th0 = integrator.pixel_angles(m, m, fov, fov)
+    obs = np.array([box / 2, box / 2, 0.0])
+    r = _rng(7)
+    noise = r.normal(size=(n_p,) * 3)
+    kb = r.normal(size=m * m)
+    v = r.normal(size=noise.shape)
+    f = lambda x: float(np.sum(kb * adjoint.pipeline_kappa(x, box, n, cp, fwd, co, th0, m, m, fov, obs)))
+    fd = _fd(f, noise, v, 1e-6)
+    g = adjoint.pipeline_vjp(noise, box, n, cp, fwd, co, th0, m, m, fov, obs, kb)
+    assert fd == pytest.approx(float(np.sum(g * v)), rel=1e-6)
