@@ -160,6 +160,45 @@ def batched_bench(hrt, torch, dev):
             "speedup_vs_plain": t_plain / t_batch}
 
 
+def adjoint_bench(torch, dev):
+    """Gradient of a convergence map with respect to the white noise (reverse mode): 128^3
+    particles and mesh, box 200 Mpc/h, 256^2 rays over 4 deg, 32 forward PM + 32
+    co-evolution steps to a = 0.5, full state checkpointed every 4 steps."""
+    import synth
+    from paper_2405_12913_amd.autodiff import Pipeline
+    cfg = synth.adjoint128()
+    print("[bench] adjoint: 128^3, 32 + 32 steps, checkpoint every 4", file=sys.stderr, flush=True)
+    pipe = Pipeline(mesh_n=cfg["mesh_n"], box=cfg["box"], ptcl_n=cfg["ptcl_n"], fwd_sched=cfg["fwd_sched"],
+                    sched=cfg["sched"], ray_n=cfg["ray_n"], fov=cfg["fov"], observer=cfg["observer"],
+                    omega_m=cfg["omega_m"], omega_b=cfg["omega_b"], h=cfg["h"], n_s=cfg["n_s"],
+                    sigma8=cfg["sigma8"], dtype="f32", every=4, device=dev)
+    noise = torch.tensor(synth.white_noise(0, cfg["ptcl_n"]).astype(np.float32).ravel(), device=dev)
+    kb = torch.tensor(np.random.default_rng(1).normal(size=cfg["ray_n"] ** 2).astype(np.float32), device=dev)
+    st = pipe.co.stream
+    kappa, ck_f, ck_c = pipe.run(noise, keep=True)          # warm-up
+    pipe.vjp(noise, kb, ck_f, ck_c)
+    del ck_f, ck_c
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    kappa, ck_f, ck_c = pipe.run(noise, keep=True)
+    ev[1].record(st)
+    nb = pipe.vjp(noise, kb, ck_f, ck_c)
+    ev[2].record(st)
+    torch.cuda.synchronize()
+    assert torch.isfinite(nb).all()
+    f_ms, b_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    n_steps = pipe.n_fwd + pipe.n_co
+    return {"workload": "adjoint128: gradient of a 256^2 convergence map (4 deg) w.r.t. 128^3 white "
+                        "noise through 2LPT, 33 forward PM steps and 32 co-evolution steps "
+                        "(box 200 Mpc/h, a = 1 -> 0.5), checkpoint every 4 steps",
+            "gradients_per_s": 1e3 / (f_ms + b_ms),
+            "forward_ms": round(f_ms, 3), "backward_ms": round(b_ms, 3),
+            "backward_over_forward": round(b_ms / f_ms, 3),
+            "backward_ms_per_step": round(b_ms / n_steps, 4),
+            "checkpoints": len(ck_f) + len(ck_c)}
+
+
 def cpu_baseline():
     """Oracle (FP64 NumPy) time for one co-evolution step on a bounded sample."""
     import synth
@@ -202,6 +241,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-realisation batched workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
@@ -341,6 +381,8 @@ def main():
         out["graph_ms_per_step"] = gms / args.steps
     if not args.no_batched:
         out["batched"] = batched_bench(hrt, torch, dev)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench(torch, dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -62,7 +62,7 @@ enum {
     HRT_STATIC = 1,         /* static point-lens run: a = 1, sched holds chi_n, the mesh
                                source is unit-weight particles of mass static_mass each */
     HRT_ADJOINT = 2         /* reserve the reverse-mode scratch (hrt_step_vjp) in the
-                               workspace: 24 n^3 + 256 more bytes                       */
+                               workspace: 16 n^3 + 256 + 4 np^3 sizeof(dtype) bytes more */
 };
 
 typedef struct {

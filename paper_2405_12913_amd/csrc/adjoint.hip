@@ -6,21 +6,21 @@
 // Step n, forward: G = D L paint(q + s); p' = p + K readout(G, q + s); s' = s + D_n p';
 // p_r' = p_r + sum_j w_j B_j(G, X_obs + chi_j theta); dth' = dth + d_n p_r'.
 // Reverse, from the cotangents after the step (in place):
-//   1. recompute G for the state before the step (pm_force);
-//   2. p_bar += D s_bar, p_r_bar += d dth_bar                         (prep kernels)
-//   3. rays: dth_bar += sum_j w_j chi_j / cell (dB_j/du)^T p_r_bar; G_bar += bilinear
-//      scatter of w_j p_r_bar                                          (ray_vjp_kernel)
-//   4. matter: s_bar += K (d readout / dx)^T p_bar; G_bar += trilinear scatter of K p_bar
-//                                                                      (matter_vjp_kernel)
-//   5. phi_bar = -sum_d D_d G_bar_d (4th-order differences are antisymmetric), delta_bar =
+//   1. recompute G for the state before the step (pm_force, which also bins the particles);
+//   2. p_r_bar += d dth_bar                                           (ray_vjp_prep_kernel)
+//   3. matter: p_bar += D s_bar; s_bar += K (d readout / dx)^T p_bar; particles re-binned
+//      with their weights K p_bar                              (matter_vjp_kernel, pm.hip)
+//   4. rays: dth_bar += sum_j w_j chi_j / cell (dB_j/du)^T p_r_bar; the bilinear weights
+//      of w_j p_r_bar scattered into G_bar_x, G_bar_y                   (ray_vjp_kernel)
+//   5. G_bar = the particles' CIC-weighted K p_bar pulled per tile + the rays' part
+//                                                               (gbar_tiles_kernel, pm.hip)
+//   6. phi_bar = -sum_d D_d G_bar_d (4th-order differences are antisymmetric), delta_bar =
 //      L phi_bar (the Poisson operator is symmetric), s_bar += (d paint / dx)^T delta_bar
 //      / rho_bar                                                       (paint_vjp_kernel)
-// G_bar is accumulated in 64-bit fixed point with a scale set on the device from the
-// largest contribution: one unit is 2^-(62 - h) of it, h = log2 of the most contributions
-// a node can receive (particles plus ray-plane crossings), so no sum overflows. The sum is
-// exact and order-independent: reruns are bit-identical and no floating-point atomics are
-// used.
+// G_bar is summed in 64-bit fixed point (adj_fixed_scale), so the result is exact and
+// order-independent: reruns are bit-identical and no floating-point atomics are used.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "device_common.h"
@@ -29,173 +29,194 @@ namespace hrt {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWindow = 1024;      // nodes of a block's LDS window in the ray scatter
 
 template <typename T>
 struct AdjArgs {
-    // state before the step
-    const T *s[3];
+    const T *s[3];               // state before the step
     const T *dth[2];
-    // cotangents (in place)
-    T *sb[3], *pb[3], *db[2], *prb[2];
-    const v4<T> *grad;          // G of the step (forward), later reused for G_bar
+    T *sb[3], *db[2], *prb[2];   // cotangents (in place)
+    const v4<T> *grad;           // G of the step (forward), later the G_bar slot
     v4<T> *gout;
-    unsigned long long *gbar;   // 3 x n^3 fixed-point accumulators
-    unsigned long long *maxbits;// largest |contribution| (double bits)
-    const T *phi;               // delta_bar after the Poisson solve
-    T *div;                     // phi_bar
+    unsigned long long *gbar;    // 2 x n^3 fixed-point accumulators (rays' part)
+    unsigned long long *maxbits; // largest |contribution| (double bits)
+    const T *phi;                // delta_bar after the Poisson solve
+    T *div;                      // phi_bar
     const PlaneEntry *planes;
     int begin, count;
     int n, lnp, ratio, P, mx, my, nrays;
-    int hbits;                  // log2 bound of the contributions per node
-    double inv_cell, K, D, d, wmax, rho_bar;
+    int patch;                   // rays in 16 x 16 pixel patches per block
+    int hbits;                   // log2 bound of the contributions per node
+    double inv_cell, d, wmax, rho_bar;
     double obsx, obsy, mux, muy, half_mx, half_my;
 };
 
-__device__ __forceinline__ void atomic_max_abs(unsigned long long *slot, double v) {
-    atomicMax(slot, (unsigned long long)__double_as_longlong(fabs(v)));
-}
-
-__device__ __forceinline__ double fixed_scale(const unsigned long long *maxbits, int hbits) {
-    const double m = __longlong_as_double((long long)*maxbits);
-    if (!(m > 0.0)) return 1.0;
-    int e;
-    frexp(m, &e);                                   // m < 2^e
-    return ldexp(1.0, 62 - hbits - e);
-}
-
-__device__ __forceinline__ void add_fixed(unsigned long long *slot, double v, double scale) {
-    atomicAdd(slot, (unsigned long long)llrint(v * scale));
-}
-
 template <typename T>
-__global__ void adj_zero_kernel(AdjArgs<T> a) {
+__global__ void adj_zero_kernel(AdjArgs<T> a, int with_gbar) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t n3 = (int64_t)a.n * a.n * a.n;
-    if (i < 3 * n3) a.gbar[i] = 0ull;
+    if (with_gbar && i < 2 * n3) a.gbar[i] = 0ull;
     if (i == 0) *a.maxbits = 0ull;
 }
 
+// Ray handled by (block, thread): 16 x 16 pixel patches when both grid sides are multiples
+// of 16 (a patch lands on few mesh cells of every plane), else rows of the grid.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void matter_vjp_prep_kernel(AdjArgs<T> a) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= a.P) return;
-    double m = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const T pt = a.pb[d][i] + (T)a.D * a.sb[d][i];
-        a.pb[d][i] = pt;
-        m = fmax(m, fabs(a.K * (double)pt));
-    }
-    atomic_max_abs(a.maxbits, m);
+__device__ __forceinline__ int ray_of(const AdjArgs<T> &a) {
+    if (!a.patch) return blockIdx.x * kThreads + threadIdx.x;
+    const int pw = a.mx >> 4;
+    const int bx = blockIdx.x % pw, by = blockIdx.x / pw;
+    return ((by << 4) + (threadIdx.x >> 4)) * a.mx + (bx << 4) + (threadIdx.x & 15);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void ray_vjp_prep_kernel(AdjArgs<T> a) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= a.nrays) return;
     double m = 0.0;
-    for (int d = 0; d < 2; ++d) {
-        const T pt = a.prb[d][i] + (T)a.d * a.db[d][i];
-        a.prb[d][i] = pt;
-        m = fmax(m, fabs(a.wmax * (double)pt));
-    }
-    atomic_max_abs(a.maxbits, m);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= a.nrays) return;
-    const double scale = fixed_scale(a.maxbits, a.hbits);
-    const int ix = i % a.mx, iy = i / a.mx;
-    const double thx = ((ix + 0.5) - a.half_mx) * a.mux + (double)a.dth[0][i];
-    const double thy = ((iy + 0.5) - a.half_my) * a.muy + (double)a.dth[1][i];
-    const int n = a.n, m = n - 1;
-    const double ptx = a.prb[0][i], pty = a.prb[1][i];
-    double tbx = 0.0, tby = 0.0;
-    const size_t n3 = (size_t)n * n * n;
-    for (int e = a.begin; e < a.begin + a.count; ++e) {
-        const PlaneEntry pe = a.planes[e];
-        const double X = (a.obsx + pe.chi * thx) * a.inv_cell;
-        const double Y = (a.obsy + pe.chi * thy) * a.inv_cell;
-        const double flx = floor(X), fly = floor(Y);
-        const T fx = (T)(X - flx), fy = (T)(Y - fly);
-        const int x0 = (int)((int64_t)flx & m), y0 = (int)((int64_t)fly & m);
-        const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
-        const size_t base = (size_t)pe.mesh * n * n;
-        const size_t i00 = base + (size_t)y0 * n + x0, i01 = base + (size_t)y0 * n + x1;
-        const size_t i10 = base + (size_t)y1 * n + x0, i11 = base + (size_t)y1 * n + x1;
-        const v4<T> g00 = a.grad[i00], g01 = a.grad[i01], g10 = a.grad[i10], g11 = a.grad[i11];
-        // d bilinear / du (cell units) for the two components
-        const T dxa = (T(1) - fy) * (g01.x - g00.x) + fy * (g11.x - g10.x);
-        const T dya = (T(1) - fx) * (g10.x - g00.x) + fx * (g11.x - g01.x);
-        const T dxb = (T(1) - fy) * (g01.y - g00.y) + fy * (g11.y - g10.y);
-        const T dyb = (T(1) - fx) * (g10.y - g00.y) + fx * (g11.y - g01.y);
-        const double f = pe.w * pe.chi * a.inv_cell;
-        tbx += f * (ptx * (double)dxa + pty * (double)dxb);
-        tby += f * (ptx * (double)dya + pty * (double)dyb);
-        const double wx0 = 1.0 - (double)fx, wx1 = fx, wy0 = 1.0 - (double)fy, wy1 = fy;
-        const double cw[4] = {wx0 * wy0, wx1 * wy0, wx0 * wy1, wx1 * wy1};
-        const size_t id[4] = {i00, i01, i10, i11};
-        for (int c = 0; c < 4; ++c) {
-            add_fixed(a.gbar + id[c], pe.w * cw[c] * ptx, scale);
-            add_fixed(a.gbar + n3 + id[c], pe.w * cw[c] * pty, scale);
+    if (i < a.nrays) {
+        for (int d = 0; d < 2; ++d) {
+            const T pt = a.prb[d][i] + (T)a.d * a.db[d][i];
+            a.prb[d][i] = pt;
+            m = fmax(m, fabs(a.wmax * (double)pt));
         }
     }
-    a.db[0][i] += (T)tbx;
-    a.db[1][i] += (T)tby;
+    block_max_to(a.maxbits, m);
 }
 
+__device__ __forceinline__ int wave_min(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+// One lane per ray. Per plane: the transposed bilinear derivative gathers into dth_bar,
+// and the bilinear weights of w_j p_r_bar go into G_bar. The block's rays fall on a small
+// patch of the plane, so their contributions are first summed in an LDS window over the
+// block's bounding box (integer atomics, exact) and each touched node then receives one
+// global atomic per block; a box larger than the window falls back to direct atomics.
 template <typename T>
-__device__ __forceinline__ void cell_of(const AdjArgs<T> &a, int i, int c[3], double f[3]) {
-    const int pmk = (1 << a.lnp) - 1;
-    const int lat[3] = {i & pmk, (i >> a.lnp) & pmk, i >> (2 * a.lnp)};
-    for (int d = 0; d < 3; ++d) {
-        T fd;
-        axis_cell<T>(a.s[d][i], lat[d], a.ratio, (T)a.inv_cell, a.n - 1, c[d], fd);
-        f[d] = fd;
+__global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
+    __shared__ unsigned long long win[2][kWindow];
+    __shared__ int box[4][4];
+    const int i = ray_of(a);
+    const bool valid = i < a.nrays;
+    const double scale = adj_fixed_scale(a.maxbits, a.hbits);
+    const int n = a.n, m = n - 1;
+    const size_t n3 = (size_t)n * n * n;
+    double thx = 0.0, thy = 0.0, ptx = 0.0, pty = 0.0;
+    if (valid) {
+        const int ix = i % a.mx, iy = i / a.mx;
+        thx = ((ix + 0.5) - a.half_mx) * a.mux + (double)a.dth[0][i];
+        thy = ((iy + 0.5) - a.half_my) * a.muy + (double)a.dth[1][i];
+        ptx = a.prb[0][i];
+        pty = a.prb[1][i];
+    }
+    double tbx = 0.0, tby = 0.0;
+    const int wave = threadIdx.x >> 6;
+    for (int e = a.begin; e < a.begin + a.count; ++e) {
+        const PlaneEntry pe = a.planes[e];
+        int ux = 0, uy = 0;            // unwrapped cell of the ray on this plane
+        double q[4][2];                // fixed-point contributions of the 4 corners
+        if (valid) {
+            const double X = (a.obsx + pe.chi * thx) * a.inv_cell;
+            const double Y = (a.obsy + pe.chi * thy) * a.inv_cell;
+            const double flx = floor(X), fly = floor(Y);
+            ux = (int)flx;
+            uy = (int)fly;
+            const T fx = (T)(X - flx), fy = (T)(Y - fly);
+            const int x0 = ux & m, y0 = uy & m;
+            const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
+            const v4<T> *plane = a.grad + (size_t)pe.mesh * n * n;
+            const v4<T> g00 = plane[(size_t)y0 * n + x0], g01 = plane[(size_t)y0 * n + x1];
+            const v4<T> g10 = plane[(size_t)y1 * n + x0], g11 = plane[(size_t)y1 * n + x1];
+            const T dxa = (T(1) - fy) * (g01.x - g00.x) + fy * (g11.x - g10.x);
+            const T dya = (T(1) - fx) * (g10.x - g00.x) + fx * (g11.x - g01.x);
+            const T dxb = (T(1) - fy) * (g01.y - g00.y) + fy * (g11.y - g10.y);
+            const T dyb = (T(1) - fx) * (g10.y - g00.y) + fx * (g11.y - g01.y);
+            const double f = pe.w * pe.chi * a.inv_cell;
+            tbx += f * (ptx * (double)dxa + pty * (double)dxb);
+            tby += f * (ptx * (double)dya + pty * (double)dyb);
+            const double wx0 = 1.0 - (double)fx, wx1 = fx, wy0 = 1.0 - (double)fy, wy1 = fy;
+            const double cw[4] = {wx0 * wy0, wx1 * wy0, wx0 * wy1, wx1 * wy1};
+            for (int c = 0; c < 4; ++c) {
+                q[c][0] = pe.w * cw[c] * ptx * scale;
+                q[c][1] = pe.w * cw[c] * pty * scale;
+            }
+        }
+        // bounding box of the block's cells on this plane
+        const int lox = wave_min(valid ? ux : INT_MAX), loy = wave_min(valid ? uy : INT_MAX);
+        const int hix = wave_max(valid ? ux : INT_MIN), hiy = wave_max(valid ? uy : INT_MIN);
+        if (__lane_id() == 0) {
+            box[wave][0] = lox;
+            box[wave][1] = loy;
+            box[wave][2] = hix;
+            box[wave][3] = hiy;
+        }
+        __syncthreads();
+        const int bx0 = min(min(box[0][0], box[1][0]), min(box[2][0], box[3][0]));
+        const int by0 = min(min(box[0][1], box[1][1]), min(box[2][1], box[3][1]));
+        const int bx1 = max(max(box[0][2], box[1][2]), max(box[2][2], box[3][2]));
+        const int by1 = max(max(box[0][3], box[1][3]), max(box[2][3], box[3][3]));
+        const long long W = (long long)bx1 - bx0 + 2, H = (long long)by1 - by0 + 2;
+        if (bx1 >= bx0 && W * H <= kWindow) {
+            const int wn = (int)(W * H);
+            for (int k = threadIdx.x; k < wn; k += kThreads) {
+                win[0][k] = 0ull;
+                win[1][k] = 0ull;
+            }
+            __syncthreads();
+            if (valid) {
+                const int lx = ux - bx0, ly = uy - by0;
+                const int slot[4] = {ly * (int)W + lx, ly * (int)W + lx + 1, (ly + 1) * (int)W + lx,
+                                     (ly + 1) * (int)W + lx + 1};
+                for (int c = 0; c < 4; ++c) {
+                    atomicAdd(&win[0][slot[c]], (unsigned long long)llrint(q[c][0]));
+                    atomicAdd(&win[1][slot[c]], (unsigned long long)llrint(q[c][1]));
+                }
+            }
+            __syncthreads();
+            const size_t base = (size_t)pe.mesh * n * n;
+            for (int k = threadIdx.x; k < wn; k += kThreads) {
+                const unsigned long long vx = win[0][k], vy = win[1][k];
+                if (vx | vy) {
+                    const int gx = (bx0 + k % (int)W) & m, gy = (by0 + k / (int)W) & m;
+                    const size_t node = base + (size_t)gy * n + gx;
+                    if (vx) atomicAdd(a.gbar + node, vx);
+                    if (vy) atomicAdd(a.gbar + n3 + node, vy);
+                }
+            }
+        } else if (valid) {
+            const size_t base = (size_t)pe.mesh * n * n;
+            const int x0 = ux & m, y0 = uy & m, x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
+            const size_t id[4] = {base + (size_t)y0 * n + x0, base + (size_t)y0 * n + x1,
+                                  base + (size_t)y1 * n + x0, base + (size_t)y1 * n + x1};
+            for (int c = 0; c < 4; ++c) {
+                atomicAdd(a.gbar + id[c], (unsigned long long)llrint(q[c][0]));
+                atomicAdd(a.gbar + n3 + id[c], (unsigned long long)llrint(q[c][1]));
+            }
+        }
+        __syncthreads();                      // window and box reused by the next plane
+    }
+    if (valid) {
+        a.db[0][i] += (T)tbx;
+        a.db[1][i] += (T)tby;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void matter_vjp_kernel(AdjArgs<T> a) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= a.P) return;
-    const double scale = fixed_scale(a.maxbits, a.hbits);
-    int c[3];
-    double f[3];
-    cell_of(a, i, c, f);
-    const int n = a.n;
-    const size_t n3 = (size_t)n * n * n;
-    const double pt[3] = {a.pb[0][i], a.pb[1][i], a.pb[2][i]};
-    double xb[3] = {0.0, 0.0, 0.0};
-    for (int cz = 0; cz < 2; ++cz)
-        for (int cy = 0; cy < 2; ++cy)
-            for (int cx = 0; cx < 2; ++cx) {
-                const double w1[3] = {cx ? f[0] : 1.0 - f[0], cy ? f[1] : 1.0 - f[1], cz ? f[2] : 1.0 - f[2]};
-                const double s1[3] = {cx ? 1.0 : -1.0, cy ? 1.0 : -1.0, cz ? 1.0 : -1.0};
-                const size_t node = ((size_t)((c[2] + cz) & (n - 1)) * n + ((c[1] + cy) & (n - 1))) * n +
-                                    ((c[0] + cx) & (n - 1));
-                const v4<T> g = a.grad[node];
-                const double gp = pt[0] * (double)g.x + pt[1] * (double)g.y + pt[2] * (double)g.z;
-                xb[0] += gp * s1[0] * w1[1] * w1[2];
-                xb[1] += gp * w1[0] * s1[1] * w1[2];
-                xb[2] += gp * w1[0] * w1[1] * s1[2];
-                const double w = w1[0] * w1[1] * w1[2];
-                for (int d = 0; d < 3; ++d) add_fixed(a.gbar + d * n3 + node, a.K * w * pt[d], scale);
-            }
-    for (int d = 0; d < 3; ++d) a.sb[d][i] += (T)(a.K * a.inv_cell * xb[d]);
-}
-
+// Static lens (no matter VJP): G_bar from the rays' part only.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gbar_convert_kernel(AdjArgs<T> a) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t n3 = (int64_t)a.n * a.n * a.n;
     if (i >= n3) return;
-    const double inv = 1.0 / fixed_scale(a.maxbits, a.hbits);
+    const double inv = 1.0 / adj_fixed_scale(a.maxbits, a.hbits);
     v4<T> o;
     o.x = (T)((double)(long long)a.gbar[i] * inv);
     o.y = (T)((double)(long long)a.gbar[n3 + i] * inv);
-    o.z = (T)((double)(long long)a.gbar[2 * n3 + i] * inv);
+    o.z = T(0);
     o.w = T(0);
     a.gout[i] = o;
 }
@@ -217,8 +238,19 @@ __global__ __launch_bounds__(kThreads) void fd4_div_kernel(AdjArgs<T> a) {
 }
 
 template <typename T>
+__device__ __forceinline__ void cell_of(const AdjArgs<T> &a, int i, int c[3], double f[3]) {
+    const int pmk = (1 << a.lnp) - 1;
+    const int lat[3] = {i & pmk, (i >> a.lnp) & pmk, i >> (2 * a.lnp)};
+    for (int d = 0; d < 3; ++d) {
+        T fd;
+        axis_cell<T>(a.s[d][i], lat[d], a.ratio, (T)a.inv_cell, a.n - 1, c[d], fd);
+        f[d] = fd;
+    }
+}
+
+template <typename T>
 __global__ __launch_bounds__(kThreads) void paint_vjp_kernel(AdjArgs<T> a) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int i = particle_of(xcd_block(gridDim.x), threadIdx.x, a.lnp);
     if (i >= a.P) return;
     int c[3];
     double f[3];
@@ -271,13 +303,12 @@ __global__ __launch_bounds__(kThreads) void convergence_vjp_kernel(const T *__re
 
 template <typename T>
 AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
-                    const hrt_rays *rc, int step) {
+                    const hrt_rays *rc, int step, AdjScratch &sc) {
     const Real &re = c->re[0];
     AdjArgs<T> a{};
     for (int d = 0; d < 3; ++d) {
         a.s[d] = static_cast<const T *>(m->s[d]);
         a.sb[d] = static_cast<T *>(mc->s[d]);
-        a.pb[d] = static_cast<T *>(mc->p[d]);
     }
     if (r) {
         for (int d = 0; d < 2; ++d) {
@@ -287,10 +318,11 @@ AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
         }
     }
     const size_t n3 = (size_t)re.n * re.n * re.n;
+    const size_t P = (size_t)re.np * re.np * re.np;
     a.grad = reinterpret_cast<const v4<T> *>(re.ws + re.lay.grad);
     a.gout = reinterpret_cast<v4<T> *>(re.ws + re.lay.grad);
     a.gbar = reinterpret_cast<unsigned long long *>(re.ws + re.lay.adj);
-    a.maxbits = a.gbar + 3 * n3;
+    a.maxbits = a.gbar + 2 * n3;
     a.div = reinterpret_cast<T *>(re.ws + re.lay.mesh_r);
     a.phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + n3;
     a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
@@ -299,13 +331,12 @@ AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
     a.n = re.n;
     a.lnp = ilog2(re.np);
     a.ratio = re.n / re.np;
-    a.P = re.np * re.np * re.np;
+    a.P = (int)P;
     a.mx = re.mx;
     a.my = re.my;
     a.nrays = re.mx * re.my;
+    a.patch = (re.mx % 16 == 0 && re.my % 16 == 0) ? 1 : 0;
     a.inv_cell = 1.0 / re.cell;
-    a.K = re.tab.K[step];
-    a.D = re.tab.D[step];
     a.d = re.tab.d[step];
     double wmax = 0.0;
     for (int e = a.begin; e < a.begin + a.count; ++e) wmax = std::max(wmax, std::fabs(re.tab.plane_w[e]));
@@ -320,48 +351,46 @@ AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
     a.muy = re.cfg.fov_y / std::max(re.my, 1);
     a.half_mx = 0.5 * re.mx;
     a.half_my = 0.5 * re.my;
+    sc.gbar = a.gbar;
+    sc.maxbits = a.maxbits;
+    sc.wsorted = re.ws + re.lay.adj + 2 * n3 * 8 + 256;
+    sc.hbits = a.hbits;
     return a;
 }
 
 inline int nb(int64_t count) { return (int)((count + kThreads - 1) / kThreads); }
 
 template <typename T>
-hipError_t step_vjp_before_poisson(hrt_ctx *c, const AdjArgs<T> &a, bool matter, bool rays) {
+hipError_t step_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                         const hrt_rays *rc, int step, bool matter) {
+    AdjScratch sc{};
+    const AdjArgs<T> a = adj_args<T>(c, m, r, mc, rc, step, sc);
+    const bool rays = r != nullptr;
     hipStream_t st = c->stream;
     const int64_t n3 = (int64_t)a.n * a.n * a.n;
-    adj_zero_kernel<T><<<nb(3 * n3), kThreads, 0, st>>>(a);
-    if (matter) matter_vjp_prep_kernel<T><<<nb(a.P), kThreads, 0, st>>>(a);
+    const bool zero_gbar = rays || !matter;
+    adj_zero_kernel<T><<<zero_gbar ? nb(2 * n3) : 1, kThreads, 0, st>>>(a, zero_gbar ? 1 : 0);
     if (rays) ray_vjp_prep_kernel<T><<<nb(a.nrays), kThreads, 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && matter) e = launch_matter_vjp(c, m, mc, step, sc);
+    if (e != hipSuccess) return e;
     if (rays) ray_vjp_kernel<T><<<nb(a.nrays), kThreads, 0, st>>>(a);
-    if (matter) matter_vjp_kernel<T><<<nb(a.P), kThreads, 0, st>>>(a);
-    gbar_convert_kernel<T><<<nb(n3), kThreads, 0, st>>>(a);
+    if (matter) e = launch_gbar_tiles(c, rays, sc);
+    else gbar_convert_kernel<T><<<nb(n3), kThreads, 0, st>>>(a);
+    if (e != hipSuccess) return e;
     fd4_div_kernel<T><<<nb(n3), kThreads, 0, st>>>(a);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t step_vjp_after_poisson(hrt_ctx *c, const AdjArgs<T> &a) {
-    paint_vjp_kernel<T><<<nb(a.P), kThreads, 0, c->stream>>>(a);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_poisson(c);
+    if (e == hipSuccess) paint_vjp_kernel<T><<<nb(a.P), kThreads, 0, st>>>(a);
+    return e == hipSuccess ? hipGetLastError() : e;
 }
 
 }  // namespace
 
 hipError_t launch_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                            const hrt_rays *rc, int step, bool matter) {
-    hipError_t e;
-    if (c->f64) {
-        const AdjArgs<double> a = adj_args<double>(c, m, r, mc, rc, step);
-        e = step_vjp_before_poisson<double>(c, a, matter, r != nullptr);
-        if (e == hipSuccess) e = launch_poisson(c);
-        if (e == hipSuccess) e = step_vjp_after_poisson<double>(c, a);
-    } else {
-        const AdjArgs<float> a = adj_args<float>(c, m, r, mc, rc, step);
-        e = step_vjp_before_poisson<float>(c, a, matter, r != nullptr);
-        if (e == hipSuccess) e = launch_poisson(c);
-        if (e == hipSuccess) e = step_vjp_after_poisson<float>(c, a);
-    }
-    return e;
+    return c->f64 ? step_vjp_impl<double>(c, m, r, mc, rc, step, matter)
+                  : step_vjp_impl<float>(c, m, r, mc, rc, step, matter);
 }
 
 hipError_t launch_convergence_vjp(hrt_ctx *c, int realisation, const void *kappa_bar,

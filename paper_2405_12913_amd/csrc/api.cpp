@@ -36,9 +36,9 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     L.cursor = take((size_t)L.nbins * 4);
     L.sorted = take(P * 4 * T);
     L.planes = take((size_t)std::max<int64_t>(n_plane_entries, 1) * sizeof(PlaneEntry));
-    // reverse mode: 3 x n^3 64-bit fixed-point accumulators of the force-mesh cotangent and
-    // one 8-byte device scalar
-    L.adj = (cfg.flags & HRT_ADJOINT) ? take(3 * n3 * 8 + 256) : off;
+    // reverse mode: 2 x n^3 64-bit fixed-point accumulators (rays' part of the force-mesh
+    // cotangent), one 8-byte device scalar (256 bytes reserved) and P x 4 kick weights
+    L.adj = (cfg.flags & HRT_ADJOINT) ? take(2 * n3 * 8 + 256 + P * 4 * T) : off;
     L.total = off;
     return L;
 }

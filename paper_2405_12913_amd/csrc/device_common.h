@@ -102,6 +102,31 @@ __device__ __forceinline__ int xcd_block(int nblocks) {
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Reverse mode: the force-mesh cotangent is summed in 64-bit fixed point. With m the
+// largest single contribution (its double bits in *maxbits) and 2^h the most contributions
+// one node can receive, one unit is 2^-(62-h) of 2^ceil(log2 m): no partial sum reaches
+// 2^62, and integer sums are exact in any order.
+__device__ __forceinline__ double adj_fixed_scale(const unsigned long long *maxbits, int hbits) {
+    const double m = __longlong_as_double((long long)*maxbits);
+    if (!(m > 0.0)) return 1.0;
+    int e;
+    frexp(m, &e);                                   // m < 2^e
+    return ldexp(1.0, 62 - hbits - e);
+}
+
+// Block-wide maximum of v >= 0 (every thread of a 256-thread block calls), folded into
+// *slot with one integer atomicMax per block (non-negative doubles order as their bits).
+__device__ __forceinline__ void block_max_to(unsigned long long *slot, double v) {
+    __shared__ double wmax[4];
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if (__lane_id() == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        if (m > 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 // Realisation owning logical block blk (uniform over the block).
 __device__ __forceinline__ int real_of(const BlockMap &m, int blk) {
     int r = 0;

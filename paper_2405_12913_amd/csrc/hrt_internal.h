@@ -128,6 +128,22 @@ hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ic(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
                      const hrt_matter *m);
+// Reverse-mode scratch of realisation 0 (HRT_ADJOINT): fixed-point ray contributions to
+// the cotangent of G_x, G_y (2 n^3), the largest contribution (double bits), and the
+// particles' kick weights K p_bar in paint-bin order (P x 4 values of the dtype).
+struct AdjScratch {
+    unsigned long long *gbar;
+    unsigned long long *maxbits;
+    void *wsorted;
+    int hbits;
+};
+// Matter part of the step VJP: p_bar += D s_bar; s_bar += K (d readout/dx)^T p_bar; the
+// particles re-binned with their weights; the largest weight into *maxbits.
+hipError_t launch_matter_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+                             const AdjScratch &s);
+// Force-mesh cotangent: per tile, the particles' CIC-weighted K p_bar summed in LDS plus
+// the rays' part from s.gbar (if rays), converted into the G mesh slot.
+hipError_t launch_gbar_tiles(hrt_ctx *c, bool rays, const AdjScratch &s);
 // Reverse mode (realisation 0 of a context created with HRT_ADJOINT, see adjoint.hip).
 hipError_t launch_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                            const hrt_rays *rc, int step, bool matter);

@@ -177,6 +177,34 @@ __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
     if (i == 0) a.offs[a.nbins] = a.sums[a.nblk];
 }
 
+// The 27 bin ranges whose particles reach tile (tx, ty, tz): the tile's own 8 bins and
+// the upper-face bins of its 7 lower neighbours. Range r starts at sorted index rstart[r],
+// the ranges' prefix sizes are rpre[0..27], and rd[r] is the neighbour's tile offset.
+template <typename T>
+__device__ void tile_ranges(const Particles<T> &a, int tx, int ty, int tz, int *rstart, int *rpre,
+                            signed char (*rd)[3]) {
+    const int nt = a.n / kTile;
+    int r = 0;
+    rpre[0] = 0;
+    for (int dz = 0; dz >= -1; --dz)
+        for (int dy = 0; dy >= -1; --dy)
+            for (int dx = 0; dx >= -1; --dx) {
+                const int req = (dx ? 1 : 0) | (dy ? 2 : 0) | (dz ? 4 : 0);
+                const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt +
+                                ((tx + dx) & (nt - 1)));
+                for (int m = 0; m < 8; ++m) {
+                    if ((m & req) != req) continue;
+                    const int bb = tn * 8 + m;
+                    rstart[r] = (int)a.offs[bb];
+                    rpre[r + 1] = rpre[r] + (int)(a.offs[bb + 1] - a.offs[bb]);
+                    rd[r][0] = (signed char)dx;
+                    rd[r][1] = (signed char)dy;
+                    rd[r][2] = (signed char)dz;
+                    ++r;
+                }
+            }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     __shared__ unsigned long long acc[512];
@@ -189,27 +217,7 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     const int t = blk - b.map.start[rr];
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     for (int k = threadIdx.x; k < 512; k += kThreads) acc[k] = 0ull;
-    if (threadIdx.x == 0) {
-        int r = 0;
-        rpre[0] = 0;
-        for (int dz = 0; dz >= -1; --dz)
-            for (int dy = 0; dy >= -1; --dy)
-                for (int dx = 0; dx >= -1; --dx) {
-                    const int req = (dx ? 1 : 0) | (dy ? 2 : 0) | (dz ? 4 : 0);
-                    const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt +
-                                    ((tx + dx) & (nt - 1)));
-                    for (int m = 0; m < 8; ++m) {
-                        if ((m & req) != req) continue;
-                        const int bb = tn * 8 + m;
-                        rstart[r] = (int)a.offs[bb];
-                        rpre[r + 1] = rpre[r] + (int)(a.offs[bb + 1] - a.offs[bb]);
-                        rd[r][0] = (signed char)dx;
-                        rd[r][1] = (signed char)dy;
-                        rd[r][2] = (signed char)dz;
-                        ++r;
-                    }
-                }
-    }
+    if (threadIdx.x == 0) tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
     __syncthreads();
     const int total = rpre[27];
     const double scale = a.scale;
@@ -290,6 +298,170 @@ __global__ __launch_bounds__(kThreads) void matter_kd_kernel(PartBatch<T> b) {
         const T pn = ld_stream(a.p[d] + i) + a.K * g[d];
         st_stream(pn, a.p[d] + i);
         st_stream(sv[d] + a.D * pn, a.s[d] + i);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Reverse mode, matter side (one realisation). matter_vjp_kernel: per particle
+// p_bar' = p_bar + D s_bar, s_bar += K (d readout_G / dx)^T p_bar' (the CIC weight
+// derivatives against G at the 8 corners), p_bar = p_bar'; the particle is binned again
+// exactly as for the paint, and its weights K p_bar' are stored beside its cell fraction.
+// gbar_tiles_kernel then pulls, per tile, the weighted CIC contributions K p_bar'_a w_c
+// into LDS as 64-bit fixed point (the transpose of the readout, deterministic like the
+// paint), adds the rays' part and writes the cotangent of G into the G slot.
+
+template <typename T>
+struct MatterAdj {
+    Particles<T> a;
+    T *sb[3], *pb[3];
+    v4<T> *wsorted;
+    v4<T> *gout;
+    const unsigned long long *gbar;     // rays' part of G_bar_x, G_bar_y (or NULL)
+    unsigned long long *maxbits;
+    double K, D;
+    int hbits;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void matter_vjp_kernel(MatterAdj<T> m) {
+    const Particles<T> &a = m.a;
+    const int blk = xcd_block(gridDim.x);
+    const int i = particle_of(blk, threadIdx.x, a.lnp);
+    int key = -1;
+    int c[3] = {0, 0, 0};
+    T f[3] = {0, 0, 0}, sv[3];
+    T kp[3] = {0, 0, 0};
+    double big = 0.0;
+    if (i < a.P) {
+        particle_cell<T>(a, i, c, f, sv);
+        key = bin_key(c, a.n / kTile);
+        T pt[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pt[d] = m.pb[d][i] + (T)m.D * m.sb[d][i];
+        const int n = a.n;
+        double xb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz) {
+            const int z = (c[2] + cz) & (n - 1);
+            const double wz = cz ? (double)f[2] : 1.0 - (double)f[2], sz = cz ? 1.0 : -1.0;
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+                const int y = (c[1] + cy) & (n - 1);
+                const double wy = cy ? (double)f[1] : 1.0 - (double)f[1], sy = cy ? 1.0 : -1.0;
+#pragma unroll
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int x = (c[0] + cx) & (n - 1);
+                    const double wx = cx ? (double)f[0] : 1.0 - (double)f[0], sx = cx ? 1.0 : -1.0;
+                    const v4<T> g = a.grad[((size_t)z * n + y) * n + x];
+                    const double gp = (double)pt[0] * (double)g.x + (double)pt[1] * (double)g.y +
+                                      (double)pt[2] * (double)g.z;
+                    xb[0] += gp * sx * wy * wz;
+                    xb[1] += gp * wx * sy * wz;
+                    xb[2] += gp * wx * wy * sz;
+                }
+            }
+        }
+        const double kc = m.K * (double)a.inv_cell;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            m.sb[d][i] += (T)(kc * xb[d]);
+            m.pb[d][i] = pt[d];
+            kp[d] = (T)(m.K * (double)pt[d]);
+            big = fmax(big, fabs((double)kp[d]));
+        }
+    }
+    const int slot = wave_aggregated_increment<true>(a.cursor, key);
+    if (i < a.P) {
+        const int lcell = ((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7);
+        v4<T> e, w;
+        e.x = f[0];
+        e.y = f[1];
+        e.z = f[2];
+        if constexpr (sizeof(T) == 4) e.w = __int_as_float(lcell);
+        else e.w = (double)lcell;
+        w.x = kp[0];
+        w.y = kp[1];
+        w.z = kp[2];
+        w.w = T(0);
+        a.sorted[slot] = e;
+        m.wsorted[slot] = w;
+    }
+    block_max_to(m.maxbits, big);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cursor_reset_kernel(MatterAdj<T> m) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m.a.nbins) m.a.cursor[i] = m.a.offs[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gbar_tiles_kernel(MatterAdj<T> m) {
+    __shared__ unsigned long long acc[3][512];
+    __shared__ int rstart[27], rpre[28];
+    __shared__ signed char rd[27][3];
+    const Particles<T> &a = m.a;
+    const int t = xcd_block(gridDim.x);
+    const int n = a.n, nt = n / kTile;
+    const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+    for (int k = threadIdx.x; k < 3 * 512; k += kThreads) acc[k >> 9][k & 511] = 0ull;
+    if (threadIdx.x == 0) tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
+    __syncthreads();
+    const int total = rpre[27];
+    const double scale = adj_fixed_scale(m.maxbits, m.hbits);
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        int r = 0;
+        while (idx >= rpre[r + 1]) ++r;
+        const int at = rstart[r] + (idx - rpre[r]);
+        const v4<T> e = a.sorted[at];
+        const v4<T> wv = m.wsorted[at];
+        const double kw[3] = {(double)wv.x * scale, (double)wv.y * scale, (double)wv.z * scale};
+        int lcell;
+        if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
+        else lcell = (int)e.w;
+        const int bx = kTile * rd[r][0] + (lcell & 7);
+        const int by = kTile * rd[r][1] + ((lcell >> 3) & 7);
+        const int bz = kTile * rd[r][2] + (lcell >> 6);
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz) {
+            const int nz = bz + cz;
+            if (nz < 0 || nz >= kTile) continue;
+            const double wz = cz ? (double)e.z : 1.0 - (double)e.z;
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+                const int ny = by + cy;
+                if (ny < 0 || ny >= kTile) continue;
+                const double wyz = wz * (cy ? (double)e.y : 1.0 - (double)e.y);
+#pragma unroll
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int nx = bx + cx;
+                    if (nx < 0 || nx >= kTile) continue;
+                    const double w = wyz * (cx ? (double)e.x : 1.0 - (double)e.x);
+                    const int node = (nz * kTile + ny) * kTile + nx;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        atomicAdd(&acc[d][node], (unsigned long long)llrint(w * kw[d]));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const double inv = 1.0 / scale;
+    const size_t n3 = (size_t)n * n * n;
+    for (int k = threadIdx.x; k < 512; k += kThreads) {
+        const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
+        const size_t node = ((size_t)z * n + y) * n + x;
+        unsigned long long gx = acc[0][k], gy = acc[1][k];
+        if (m.gbar) {
+            gx += m.gbar[node];
+            gy += m.gbar[n3 + node];
+        }
+        v4<T> o;
+        o.x = (T)((double)(long long)gx * inv);
+        o.y = (T)((double)(long long)gy * inv);
+        o.z = (T)((double)(long long)acc[2][k] * inv);
+        o.w = T(0);
+        m.gout[node] = o;
     }
 }
 
@@ -382,7 +554,56 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
     return hipGetLastError();
 }
 
+template <typename T>
+MatterAdj<T> matter_adj(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+                        const AdjScratch &sc, bool rays) {
+    const Real &re = c->re[0];
+    MatterAdj<T> ma{};
+    fill_particles<T>(c, 0, *m, ma.a, 0.0, 0.0);
+    if (mc) {
+        for (int d = 0; d < 3; ++d) {
+            ma.sb[d] = static_cast<T *>(mc->s[d]);
+            ma.pb[d] = static_cast<T *>(mc->p[d]);
+        }
+    }
+    ma.wsorted = static_cast<v4<T> *>(sc.wsorted);
+    ma.gout = reinterpret_cast<v4<T> *>(re.ws + re.lay.grad);
+    ma.gbar = rays ? sc.gbar : nullptr;
+    ma.maxbits = sc.maxbits;
+    ma.K = re.tab.K[step];
+    ma.D = re.tab.D[step];
+    ma.hbits = sc.hbits;
+    return ma;
+}
+
+template <typename T>
+hipError_t matter_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+                           const AdjScratch &sc) {
+    const MatterAdj<T> ma = matter_adj<T>(c, m, mc, step, sc, false);
+    cursor_reset_kernel<T><<<(ma.a.nbins + 255) / 256, 256, 0, c->stream>>>(ma);
+    matter_vjp_kernel<T><<<particle_blocks(ma.a.P), kThreads, 0, c->stream>>>(ma);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gbar_tiles_impl(hrt_ctx *c, bool rays, const AdjScratch &sc) {
+    hrt_matter none{};
+    const MatterAdj<T> ma = matter_adj<T>(c, &none, nullptr, 0, sc, rays);
+    const int nt = ma.a.n / kTile;
+    gbar_tiles_kernel<T><<<nt * nt * nt, kThreads, 0, c->stream>>>(ma);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_matter_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+                             const AdjScratch &s) {
+    return c->f64 ? matter_vjp_impl<double>(c, m, mc, step, s) : matter_vjp_impl<float>(c, m, mc, step, s);
+}
+
+hipError_t launch_gbar_tiles(hrt_ctx *c, bool rays, const AdjScratch &s) {
+    return c->f64 ? gbar_tiles_impl<double>(c, rays, s) : gbar_tiles_impl<float>(c, rays, s);
+}
 
 hipError_t launch_paint(hrt_ctx *c, const StepArgs &a) {
     return c->f64 ? paint_impl<double>(c, a) : paint_impl<float>(c, a);

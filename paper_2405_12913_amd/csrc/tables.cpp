@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <functional>
+#include <vector>
 
 #include "hrt_internal.h"
 
@@ -53,35 +54,46 @@ double gk15(const std::function<double(double)> &f, double a, double b, double *
 }
 
 // Global adaptive quadrature: keep bisecting the sub-interval with the largest error
-// estimate until the summed error is below 1e-14 of the result (or 1e-300 absolute), with
-// at most 2000 sub-intervals, so the cost is bounded whatever the integrand.
-double integrate(const std::function<double(double)> &f, double a, double b) {
+// estimate (a heap) until the summed error is below 1e-14 of the result (or 1e-300
+// absolute) or the worst estimate is at rounding level, with at most 2000 bisections, so
+// the cost is bounded whatever the integrand. Pieces are summed in order of position.
+double integrate(const std::function<double(double)> &f, double a, double b, int n_init = 1) {
     if (a == b) return 0.0;
     struct Piece { double a, b, val, err; };
-    std::vector<Piece> pieces;
-    pieces.reserve(2048);
-    double err;
-    double val = gk15(f, a, b, &err);
-    pieces.push_back({a, b, val, err});
+    auto less = [](const Piece &x, const Piece &y) { return x.err < y.err; };
+    std::vector<Piece> heap;         // max-heap on the error estimate
+    heap.reserve(4096 + n_init);
+    double total = 0.0, total_err = 0.0;
+    for (int i = 0; i < n_init; ++i) {       // optional initial equal partition
+        const double lo = a + (b - a) * i / n_init, hi = a + (b - a) * (i + 1) / n_init;
+        double err;
+        const double val = gk15(f, lo, hi, &err);
+        heap.push_back({lo, hi, val, err});
+        total += val;
+        total_err += err;
+    }
+    std::make_heap(heap.begin(), heap.end(), less);
     for (int it = 0; it < 2000; ++it) {
-        double total = 0.0, total_err = 0.0;
-        size_t worst = 0;
-        for (size_t i = 0; i < pieces.size(); ++i) {
-            total += pieces[i].val;
-            total_err += pieces[i].err;
-            if (pieces[i].err > pieces[worst].err) worst = i;
-        }
         if (total_err <= std::max(1e-14 * std::fabs(total), 1e-300)) break;
-        const Piece p = pieces[worst];
+        const Piece p = heap.front();
+        // the worst piece's estimate is at rounding level: no bisection can improve it
+        if (p.err <= 1e-15 * std::fabs(p.val)) break;
+        std::pop_heap(heap.begin(), heap.end(), less);
+        heap.pop_back();
         const double m = 0.5 * (p.a + p.b);
         double e1, e2;
         const double v1 = gk15(f, p.a, m, &e1), v2 = gk15(f, m, p.b, &e2);
-        pieces[worst] = {p.a, m, v1, e1};
-        pieces.push_back({m, p.b, v2, e2});
+        heap.push_back({p.a, m, v1, e1});
+        std::push_heap(heap.begin(), heap.end(), less);
+        heap.push_back({m, p.b, v2, e2});
+        std::push_heap(heap.begin(), heap.end(), less);
+        total += v1 + v2 - p.val;
+        total_err += e1 + e2 - p.err;
     }
-    double total = 0.0;
-    for (const Piece &p : pieces) total += p.val;
-    return total;
+    std::sort(heap.begin(), heap.end(), [](const Piece &x, const Piece &y) { return x.a < y.a; });
+    double sum = 0.0;
+    for (const Piece &p : heap) sum += p.val;
+    return sum;
 }
 
 struct Cosmo {
@@ -210,12 +222,8 @@ int ic_params(const hrt_config &c, const hrt_ic_params &in, IcParams &p, std::st
         const double tk = transfer(k);
         return k * k * k * std::pow(k, in.n_s) * tk * tk * w * w;
     };
-    // split the range so the adaptive rule follows the top-hat's oscillations
-    double s2 = 0.0;
-    const double lo = std::log(1e-5), hi = std::log(1e3);
-    const int pieces = 64;
-    for (int i = 0; i < pieces; ++i)
-        s2 += integrate(integrand, lo + (hi - lo) * i / pieces, lo + (hi - lo) * (i + 1) / pieces);
+    // start from 64 pieces so the adaptive rule sees the top-hat's oscillations
+    double s2 = integrate(integrand, std::log(1e-5), std::log(1e3), 64);
     s2 /= 2.0 * kPi * kPi;
     p.amp = in.sigma8 * in.sigma8 / s2;
     const double box = c.box;
