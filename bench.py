@@ -85,7 +85,7 @@ def sim_kwargs(cfg):
                 fov_y=cfg["fov"], observer=cfg["observer"], omega_m=cfg["omega_m"], dtype="f32")
 
 
-def batched_bench(hrt, torch, dev):
+def batched_bench(hrt, torch, dev, tune=True):
     """16 uneven realisations: one batched context replaying a captured 64-step graph vs
     the same realisations run one after another, each from its own graph."""
     import synth
@@ -107,6 +107,8 @@ def batched_bench(hrt, torch, dev):
     with torch.cuda.stream(stream):
         st = fresh()
         sim = hrt.Simulation(configs=[sim_kwargs(c) for c in cfgs], device=dev)
+        if tune:
+            sim.autotune([x[0] for x in st], [x[1] for x in st], [x[2] for x in st], [x[3] for x in st])
         sim.graph_capture([x[0] for x in st], [x[1] for x in st], [x[2] for x in st],
                           [x[3] for x in st], 0, N)
         sim.graph_launch()                                  # warm-up replay
@@ -130,6 +132,8 @@ def batched_bench(hrt, torch, dev):
         sims = []
         for c, x in zip(cfgs, st):
             s1 = hrt.Simulation(**sim_kwargs(c), device=dev)
+            if tune:
+                s1.autotune(x[0], x[1], x[2], x[3])
             s1.graph_capture(x[0], x[1], x[2], x[3], 0, N)
             sims.append(s1)
         for s1 in sims:
@@ -242,6 +246,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-realisation batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode workload")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
@@ -270,6 +275,10 @@ def main():
     pr = [torch.zeros(nrays, device=dev) for _ in range(2)]
     kappa = torch.empty(nrays, device=dev)
     sim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+    tuned = {}
+    if not args.no_tune:
+        print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
+        tuned = sim.autotune(s, p, dth, pr, step=0)
 
     def step(k):
         m = k % N
@@ -357,6 +366,7 @@ def main():
         "ray_step_ms": round(ray_ms, 4),
         "ray_kernel_ray_steps_per_s": nrays / (ray_ms * 1e-3),
         "host_wall_s": round(wall, 4),
+        "launch_variants": tuned,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
@@ -368,6 +378,8 @@ def main():
         gstream = torch.cuda.Stream(device=dev)
         with torch.cuda.stream(gstream):
             gsim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+            for name, v in tuned.items():
+                gsim.set_variant(name, v)
             gsim.graph_capture(s, p, dth, pr, 0, args.steps)
             g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -380,7 +392,7 @@ def main():
         out["graph_ray_steps_per_s"] = nrays * args.steps / (gms * 1e-3)
         out["graph_ms_per_step"] = gms / args.steps
     if not args.no_batched:
-        out["batched"] = batched_bench(hrt, torch, dev)
+        out["batched"] = batched_bench(hrt, torch, dev, tune=not args.no_tune)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, dev)
     if not args.no_cpu_baseline:

@@ -213,6 +213,29 @@ int ray_convergence_vjp(hrt_ctx *ctx, void *const *kappa_bar, const hrt_rays *rc
 int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_ic_params *ic,
                     const hrt_matter *cot, void *noise_bar);
 
+/* Launch-shape variants. Some kernels can map particles or rays onto workgroups in several
+ * ways (Lagrangian patches of different shapes, linear order, pixel patches or rows) and
+ * group workgroups per XCD or not; every variant computes bit-identical results and they
+ * differ only in speed. Tunable kernel ids: bin_count, bin_scatter, matter_kd, ray_step
+ * (6 variants each), paint_tiles (2). hrt_num_variants(id) gives the count (1 = not
+ * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);
+ * hrt_get_variant reads it. A new context starts with variant 0 everywhere. */
+int hrt_num_variants(int kernel_id);
+int hrt_set_variant(hrt_ctx *ctx, int kernel_id, int variant);
+int hrt_get_variant(const hrt_ctx *ctx, int kernel_id, int *variant);
+
+/* Autotuner: runs pm_force(m, step), then times every variant of each tunable kernel on
+ * this context's sizes (a warm-up and 5 launches each, HIP events on the context's stream;
+ * synchronises the host) and keeps the fastest. With cache_path (may be NULL) the choices
+ * are kept in that JSON file under a key made of the device architecture, kernel name,
+ * dtype and every realisation's sizes: keys already in the file are applied without
+ * timing, new ones are added (the file is rewritten through a temporary and a rename).
+ * m (all six arrays) and r (may be NULL: the ray kernel is then not tuned) are scratch:
+ * the timed launches advance them, so pass copies of a representative state. Not valid
+ * with HRT_STATIC. Overwrites the force mesh. */
+int hrt_autotune(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int step,
+                 const char *cache_path);
+
 /* Optional per-kernel timing with HIP events recorded on the context's stream around
  * every kernel launch (for measurement; off by default). hrt_profile_enable(ctx, 1)
  * clears the totals and starts recording, 0 stops. hrt_profile_read synchronises the

@@ -86,8 +86,17 @@ __device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_sto
 // block covers a 16 x 16 patch of one Lagrangian plane and a wave a 16 x 4 strip, so a
 // wave's particles fall into few mesh tiles and read few mesh rows; smaller lattices use
 // plain linear order.
-__device__ __forceinline__ int particle_of(int b, int t, int lnp) {
-    if (lnp < 4) return b * 256 + t;
+// Launch-shape variants (chosen by the autotuner; every map covers each particle exactly
+// once and the per-particle arithmetic does not depend on it, so results are identical):
+// map 0 = the 16 x 16 patches above, 1 = linear order, 2 = 32 x 8 patches (wave 32 x 2,
+// needs np >= 32). A map a lattice is too small for falls back to linear order.
+__device__ __forceinline__ int particle_of(int b, int t, int lnp, int map = 0) {
+    if (map == 2 && lnp >= 5) {
+        const int pbx = 1 << (lnp - 5), pby = 1 << (lnp - 3);
+        const int bx = b & (pbx - 1), by = (b >> (lnp - 5)) & (pby - 1), z = b >> (2 * lnp - 8);
+        return (((z << lnp) + (by << 3) + (t >> 5)) << lnp) + (bx << 5) + (t & 31);
+    }
+    if (map == 1 || lnp < 4) return b * 256 + t;
     const int pb = 1 << (lnp - 4);
     const int bx = b & (pb - 1), by = (b >> (lnp - 4)) & (pb - 1), z = b >> (2 * (lnp - 4));
     return (((z << lnp) + (by << 4) + (t >> 4)) << lnp) + (bx << 4) + (t & 15);
@@ -125,6 +134,11 @@ __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v)
         const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
         if (m > 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
     }
+}
+
+// Logical block of this workgroup: XCD-grouped (xcd_block) or in dispatch order.
+__device__ __forceinline__ int logical_block(int xcd) {
+    return xcd ? xcd_block(gridDim.x) : (int)blockIdx.x;
 }
 
 // Realisation owning logical block blk (uniform over the block).

@@ -111,6 +111,8 @@ struct hrt_ctx {
     hipEvent_t prof_open = nullptr;
     double prof_ms[hrt::K_COUNT] = {};
     int64_t prof_n[hrt::K_COUNT] = {};
+    // launch-shape variant per kernel id (hrt_autotune / hrt_set_variant; 0 = default)
+    int variant[hrt::K_COUNT] = {};
     ~hrt_ctx();
 };
 

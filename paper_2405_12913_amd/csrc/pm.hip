@@ -37,6 +37,7 @@ template <typename T>
 struct PartBatch {
     BlockMap map;
     Particles<T> r[kMaxBatch];
+    int pmap, xcd;             // launch-shape variant: particle map, XCD block grouping
 };
 
 // np is a power of two (it divides the power-of-two mesh size): lattice indices by shifts.
@@ -67,9 +68,10 @@ __global__ __launch_bounds__(256) void fill_counts_kernel(PartBatch<T> b) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bin_count_kernel(PartBatch<T> b) {
-    const int r = real_of(b.map, blockIdx.x);
+    const int blk = logical_block(b.xcd);
+    const int r = real_of(b.map, blk);
     const Particles<T> &a = b.r[r];
-    const int i = particle_of(blockIdx.x - b.map.start[r], threadIdx.x, a.lnp);
+    const int i = particle_of(blk - b.map.start[r], threadIdx.x, a.lnp, b.pmap);
     int key = -1;
     if (i < a.P) {
         int c[3];
@@ -82,9 +84,10 @@ __global__ __launch_bounds__(kThreads) void bin_count_kernel(PartBatch<T> b) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(PartBatch<T> b) {
-    const int r = real_of(b.map, blockIdx.x);
+    const int blk = logical_block(b.xcd);
+    const int r = real_of(b.map, blk);
     const Particles<T> &a = b.r[r];
-    const int i = particle_of(blockIdx.x - b.map.start[r], threadIdx.x, a.lnp);
+    const int i = particle_of(blk - b.map.start[r], threadIdx.x, a.lnp, b.pmap);
     int key = -1;
     int c[3] = {0, 0, 0};
     T f[3] = {0, 0, 0}, sv[3];
@@ -178,31 +181,41 @@ __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
 }
 
 // The 27 bin ranges whose particles reach tile (tx, ty, tz): the tile's own 8 bins and
-// the upper-face bins of its 7 lower neighbours. Range r starts at sorted index rstart[r],
-// the ranges' prefix sizes are rpre[0..27], and rd[r] is the neighbour's tile offset.
+// the upper-face bins of its 7 lower neighbours (a neighbour displaced by -1 along some
+// axes contributes the bins whose face mask has those axes set). Computed in parallel by
+// threads 0..26 of the block, then prefix-summed: range r starts at sorted index
+// rstart[r], the ranges' prefix sizes are rpre[0..27], rd[r] is the neighbour's offset.
+// The order of the ranges only changes the order of the integer sums, not their value.
+__constant__ signed char kRangeTab[27][4] = {
+    {0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0, 0, 3}, {0, 0, 0, 4}, {0, 0, 0, 5},
+    {0, 0, 0, 6}, {0, 0, 0, 7},                                     // own tile, every mask
+    {-1, 0, 0, 1}, {-1, 0, 0, 3}, {-1, 0, 0, 5}, {-1, 0, 0, 7},     // x - 1: masks with x
+    {0, -1, 0, 2}, {0, -1, 0, 3}, {0, -1, 0, 6}, {0, -1, 0, 7},     // y - 1: masks with y
+    {0, 0, -1, 4}, {0, 0, -1, 5}, {0, 0, -1, 6}, {0, 0, -1, 7},     // z - 1: masks with z
+    {-1, -1, 0, 3}, {-1, -1, 0, 7}, {-1, 0, -1, 5}, {-1, 0, -1, 7}, // two axes
+    {0, -1, -1, 6}, {0, -1, -1, 7}, {-1, -1, -1, 7}};               // three axes
+
 template <typename T>
-__device__ void tile_ranges(const Particles<T> &a, int tx, int ty, int tz, int *rstart, int *rpre,
-                            signed char (*rd)[3]) {
+__device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int ty, int tz, int *rstart,
+                                            int *rpre, signed char (*rd)[3]) {
     const int nt = a.n / kTile;
-    int r = 0;
-    rpre[0] = 0;
-    for (int dz = 0; dz >= -1; --dz)
-        for (int dy = 0; dy >= -1; --dy)
-            for (int dx = 0; dx >= -1; --dx) {
-                const int req = (dx ? 1 : 0) | (dy ? 2 : 0) | (dz ? 4 : 0);
-                const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt +
-                                ((tx + dx) & (nt - 1)));
-                for (int m = 0; m < 8; ++m) {
-                    if ((m & req) != req) continue;
-                    const int bb = tn * 8 + m;
-                    rstart[r] = (int)a.offs[bb];
-                    rpre[r + 1] = rpre[r] + (int)(a.offs[bb + 1] - a.offs[bb]);
-                    rd[r][0] = (signed char)dx;
-                    rd[r][1] = (signed char)dy;
-                    rd[r][2] = (signed char)dz;
-                    ++r;
-                }
-            }
+    const int k = threadIdx.x;
+    if (k < 27) {
+        const int dx = kRangeTab[k][0], dy = kRangeTab[k][1], dz = kRangeTab[k][2];
+        const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt + ((tx + dx) & (nt - 1)));
+        const int bb = tn * 8 + kRangeTab[k][3];
+        const unsigned int o0 = a.offs[bb], o1 = a.offs[bb + 1];
+        rstart[k] = (int)o0;
+        rpre[k + 1] = (int)(o1 - o0);           // size; prefix-summed below
+        rd[k][0] = (signed char)dx;
+        rd[k][1] = (signed char)dy;
+        rd[k][2] = (signed char)dz;
+    }
+    __syncthreads();
+    if (k == 0) {
+        rpre[0] = 0;
+        for (int r = 1; r <= 27; ++r) rpre[r] += rpre[r - 1];
+    }
 }
 
 template <typename T>
@@ -210,19 +223,19 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     __shared__ unsigned long long acc[512];
     __shared__ int rstart[27], rpre[28];
     __shared__ signed char rd[27][3];
-    const int blk = xcd_block(gridDim.x);
+    const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
     const int n = a.n, nt = n / kTile;
     const int t = blk - b.map.start[rr];
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     for (int k = threadIdx.x; k < 512; k += kThreads) acc[k] = 0ull;
-    if (threadIdx.x == 0) tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
+    tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
     __syncthreads();
     const int total = rpre[27];
     const double scale = a.scale;
+    int r = 0;                                  // idx only grows: the range index too
     for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-        int r = 0;
         while (idx >= rpre[r + 1]) ++r;
         const v4<T> e = a.sorted[rstart[r] + (idx - rpre[r])];
         int lcell;
@@ -263,10 +276,10 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
 // neighbouring particle patches (which read the same mesh rows) share one L2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void matter_kd_kernel(PartBatch<T> b) {
-    const int blk = xcd_block(gridDim.x);
+    const int blk = logical_block(b.xcd);
     const int r = real_of(b.map, blk);
     const Particles<T> &a = b.r[r];
-    const int i = particle_of(blk - b.map.start[r], threadIdx.x, a.lnp);
+    const int i = particle_of(blk - b.map.start[r], threadIdx.x, a.lnp, b.pmap);
     if (i >= a.P) return;
     int c[3];
     T f[3], sv[3];
@@ -405,12 +418,12 @@ __global__ __launch_bounds__(kThreads) void gbar_tiles_kernel(MatterAdj<T> m) {
     const int n = a.n, nt = n / kTile;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     for (int k = threadIdx.x; k < 3 * 512; k += kThreads) acc[k >> 9][k & 511] = 0ull;
-    if (threadIdx.x == 0) tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
+    tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
     __syncthreads();
     const int total = rpre[27];
     const double scale = adj_fixed_scale(m.maxbits, m.hbits);
+    int r = 0;
     for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-        int r = 0;
         while (idx >= rpre[r + 1]) ++r;
         const int at = rstart[r] + (idx - rpre[r]);
         const v4<T> e = a.sorted[at];
@@ -502,6 +515,14 @@ void set_map(PartBatch<T> &b, int R, F blocks) {
 
 inline int particle_blocks(int P) { return (P + kThreads - 1) / kThreads; }
 
+// Particle-kernel variant v (0..5): particle map v % 3; v >= 3 flips the kernel's default
+// XCD block grouping.
+template <typename T>
+void set_variant(PartBatch<T> &b, int v, int default_xcd) {
+    b.pmap = v % 3;
+    b.xcd = (v >= 3) ? 1 - default_xcd : default_xcd;
+}
+
 template <typename T>
 hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
     hipStream_t st = c->stream;
@@ -514,6 +535,7 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
         fill_counts_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
         set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
+        set_variant(b, c->variant[K_BIN_COUNT], 0);
         bin_count_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
         prof_end(c, K_BIN_COUNT);
         prof_begin(c);
@@ -525,10 +547,13 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         prof_end(c, K_BIN_SCAN);
         prof_begin(c);
         set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
+        set_variant(b, c->variant[K_BIN_SCATTER], 0);
         bin_scatter_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
         prof_end(c, K_BIN_SCATTER);
         prof_begin(c);
         set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt; });
+        b.pmap = 0;
+        b.xcd = c->variant[K_PAINT] == 0 ? 1 : 0;
         paint_tiles_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
         prof_end(c, K_PAINT);
     }
@@ -547,6 +572,7 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
                               re.tab.D[args.step]);
         }
         set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
+        set_variant(b, c->variant[K_MATTER_KD], 1);
         prof_begin(c);
         matter_kd_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         prof_end(c, K_MATTER_KD);

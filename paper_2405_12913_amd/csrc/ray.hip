@@ -36,14 +36,30 @@ template <typename T>
 struct RayBatch {
     BlockMap map;
     RayR<T> r[kMaxBatch];
+    int rmap, xcd;             // launch-shape variant: ray map, XCD block grouping
 };
+
+// Ray of (logical block b, thread t). Variants (identical results, each ray is
+// independent): 0 = rows of the pixel grid, 1 = 16 x 16 pixel patches, 2 = 32 x 8 patches;
+// a patch map falls back to rows when the grid sides are not multiples of the patch.
+__device__ __forceinline__ int ray_of(int b, int t, int mx, int my, int map) {
+    if (map == 1 && (mx & 15) == 0 && (my & 15) == 0) {
+        const int pw = mx >> 4, bx = b % pw, by = b / pw;
+        return ((by << 4) + (t >> 4)) * mx + (bx << 4) + (t & 15);
+    }
+    if (map == 2 && (mx & 31) == 0 && (my & 7) == 0) {
+        const int pw = mx >> 5, bx = b % pw, by = b / pw;
+        return ((by << 3) + (t >> 5)) * mx + (bx << 5) + (t & 31);
+    }
+    return b * kThreads + t;
+}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
-    const int blk = xcd_block(gridDim.x);
+    const int blk = logical_block(b.xcd);
     const int r = real_of(b.map, blk);
     const RayR<T> &a = b.r[r];
-    const int i = (blk - b.map.start[r]) * kThreads + threadIdx.x;
+    const int i = ray_of(blk - b.map.start[r], threadIdx.x, a.mx, a.my, b.rmap);
     if (i >= a.nrays) return;
     const int ix = i % a.mx, iy = i / a.mx;
     const double thx = ((ix + 0.5) - a.half_mx) * a.mux + (double)a.dthx[i];
@@ -153,6 +169,9 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
             fill_rays<T>(c, r0 + k, s, k, b.r[k]);
             b.map.start[k + 1] = b.map.start[k] + (b.r[k].nrays + kThreads - 1) / kThreads;
         }
+        const int v = c->variant[K_RAY_STEP];
+        b.rmap = v % 3;
+        b.xcd = v >= 3 ? 0 : 1;
         prof_begin(c);
         if (CONV) convergence_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         else ray_step_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);

@@ -24,7 +24,8 @@ EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", 
             "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",
             "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
             "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
-            "ray_convergence_vjp", "hrt_ic_2lpt_vjp")
+            "ray_convergence_vjp", "hrt_ic_2lpt_vjp", "hrt_num_variants", "hrt_set_variant",
+            "hrt_get_variant", "hrt_autotune")
 
 
 class HrtConfig(ctypes.Structure):
@@ -90,6 +91,10 @@ def lib():
         L.hrt_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays), c_int]
         L.ray_convergence_vjp.argtypes = [c_void_p, P(c_void_p), P(HrtRays)]
         L.hrt_ic_2lpt_vjp.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter), c_void_p]
+        L.hrt_num_variants.argtypes = [c_int]
+        L.hrt_set_variant.argtypes = [c_void_p, c_int, c_int]
+        L.hrt_get_variant.argtypes = [c_void_p, c_int, P(c_int)]
+        L.hrt_autotune.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, ctypes.c_char_p]
         L.hrt_kernel_name.argtypes = [c_int]
         L.hrt_kernel_name.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -162,6 +167,20 @@ def hrt_ic_factors(cfg, ic):
     out = (c_double * 6)()
     _check(lib().hrt_ic_factors(ctypes.byref(cfg), ctypes.byref(ic), out))
     return tuple(out)
+
+
+def num_variants(kernel):
+    return lib().hrt_num_variants(kernel_id(kernel))
+
+
+def kernel_id(kernel):
+    """Kernel id from its name (as hrt_kernel_name gives it) or id."""
+    if isinstance(kernel, int):
+        return kernel
+    for k in range(HRT_NUM_KERNELS):
+        if lib().hrt_kernel_name(k).decode() == kernel:
+            return k
+    raise ValueError(f"unknown kernel {kernel!r}")
 
 
 def _ptr(t, dtype, numel, what):
@@ -322,6 +341,35 @@ class Simulation:
             m.p[d] = _ptr(p_bar[d], self.dtype, self.n_particles[k], "p_bar")
         _check(lib().hrt_ic_2lpt_vjp(self.ctx, k, c_void_p(nz), ctypes.byref(ic), ctypes.byref(m),
                                      c_void_p(nb)), self.ctx)
+
+    def set_variant(self, kernel, variant):
+        """Force launch-shape variant `variant` of kernel `kernel` (name or id)."""
+        _check(lib().hrt_set_variant(self.ctx, kernel_id(kernel), variant), self.ctx)
+
+    def variants(self):
+        """{kernel name: chosen variant} for the tunable kernels."""
+        out = {}
+        for k in range(HRT_NUM_KERNELS):
+            if lib().hrt_num_variants(k) > 1:
+                v = c_int(0)
+                _check(lib().hrt_get_variant(self.ctx, k, ctypes.byref(v)), self.ctx)
+                out[lib().hrt_kernel_name(k).decode()] = v.value
+        return out
+
+    def autotune(self, s, p, dth=None, pr=None, step=0, cache=None):
+        """Time every launch-shape variant on copies of the given state and keep the fastest
+        (choices cached in the JSON file `cache` if given). The state is not modified."""
+        s2 = [[t.clone() for t in x] for x in self._per(s)]
+        p2 = [[t.clone() for t in x] for x in self._per(p)]
+        m = self._matter(s2, p2)
+        r = None
+        if dth is not None:
+            d2 = [[t.clone() for t in x] for x in self._per(dth)]
+            r2 = [[t.clone() for t in x] for x in self._per(pr)]
+            r = self._rays(d2, r2)
+        path = cache.encode() if cache is not None else None
+        _check(lib().hrt_autotune(self.ctx, m, r, step, path), self.ctx)
+        return self.variants()
 
     def profile_enable(self, on=True):
         _check(lib().hrt_profile_enable(self.ctx, 1 if on else 0), self.ctx)

@@ -113,3 +113,12 @@ def test_ic_factors_match_oracle(om, a):
     assert d1 == pytest.approx(D1[0], rel=1e-9) and d1_today == pytest.approx(D1[1], rel=1e-9)
     assert f1 == pytest.approx(F1[0], rel=1e-9) and f2 == pytest.approx(F2[0], rel=1e-9)
     assert d2 == pytest.approx(D2[0], rel=1e-9)
+
+
+def test_variant_counts():
+    from paper_2405_12913_amd import hrt
+    counts = {hrt.lib().hrt_kernel_name(k).decode(): hrt.num_variants(k) for k in range(hrt.HRT_NUM_KERNELS)}
+    assert counts["matter_kd"] == 6 and counts["ray_step"] == 6 and counts["paint_tiles"] == 2
+    assert counts["bin_count"] == 6 and counts["bin_scatter"] == 6
+    assert counts["fft_x_r2c"] == 1
+    assert hrt.num_variants(hrt.HRT_NUM_KERNELS) == 0

@@ -1,0 +1,116 @@
+"""Launch-shape variants and the autotuner (GPU).
+
+Every variant of every tunable kernel must give results bit-identical to the default one
+(the variants only change how particles, rays and tiles map onto workgroups); the tuner
+must leave the caller's state untouched, write a JSON cache and apply it unchanged in a
+new context."""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import Case, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TUNABLE = ("bin_count", "bin_scatter", "paint_tiles", "matter_kd", "ray_step")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _case():
+    cfg = synth.tiny(mesh_n=64, ptcl_n=64, box=100.0, ray_n=64, fov_deg=2.0, n_steps=6, seed=21)
+    return Case(cfg, seed=21, dtype="f32", dth_rms=0.0, p_rms=0.0)
+
+
+def _run(c, sim, steps=3):
+    import torch
+    s, p = c.dev(c.s), c.dev(c.p)
+    d, pr = c.dev(np.zeros_like(c.dth)), c.dev(np.zeros_like(c.pr))
+    k = torch.empty(c.mx * c.my, device="cuda")
+    for step in range(steps):
+        sim.pm_step(s, p, step)
+        sim.ray_step(d, pr, step)
+    sim.ray_convergence(d, k)
+    torch.cuda.synchronize()
+    return s + p + d + pr + [k]
+
+
+def test_every_variant_is_bit_identical():
+    import torch
+    from paper_2405_12913_amd import hrt
+    c = _case()
+    base = _run(c, c.sim())
+    for name in TUNABLE:
+        nv = hrt.num_variants(name)
+        assert nv >= 2
+        for v in range(1, nv):
+            say(f"case variant {name}={v}")
+            sim = c.sim()
+            sim.set_variant(name, v)
+            out = _run(c, sim)
+            for a, b in zip(out, base):
+                assert torch.equal(a, b), (name, v)
+
+
+def test_autotune_keeps_state_and_cache_roundtrips(tmp_path):
+    import torch
+    say("case autotune and cache")
+    c = _case()
+    base = _run(c, c.sim())
+    sim = c.sim()
+    s, p = c.dev(c.s), c.dev(c.p)
+    d, pr = c.dev(c.dth), c.dev(c.pr)
+    before = [t.clone() for t in s + p + d + pr]
+    path = str(tmp_path / "tune.json")
+    chosen = sim.autotune(s, p, d, pr, step=0, cache=path)
+    torch.cuda.synchronize()
+    for a, b in zip(s + p + d + pr, before):
+        assert torch.equal(a, b)
+    with open(path) as f:
+        doc = json.load(f)
+    keys = [e["key"] for e in doc["entries"]]
+    assert len(keys) == len(TUNABLE) and all("|f32|64/64/64x64" in k for k in keys)
+    assert set(chosen) == set(TUNABLE)
+    mtime = (tmp_path / "tune.json").stat().st_mtime_ns
+    sim2 = c.sim()
+    assert sim2.autotune(s, p, d, pr, step=0, cache=path) == chosen
+    assert (tmp_path / "tune.json").stat().st_mtime_ns == mtime       # served from the cache
+    out = _run(c, sim)
+    for a, b in zip(out, base):
+        assert torch.equal(a, b)
+
+
+def test_batched_variants_with_uneven_grids():
+    import torch
+    from paper_2405_12913_amd import hrt
+    say("case batched variants, ray grids not multiples of 16")
+    specs = [(32, 32, 50.0, 24, 3.0, 11), (64, 32, 80.0, 64, 2.0, 12), (32, 16, 40.0, 40, 4.0, 13)]
+    cases, kws = [], []
+    for n, np_, box, nr, fov, seed in specs:
+        cfg = synth.tiny(mesh_n=n, ptcl_n=np_, box=box, ray_n=nr, fov_deg=fov, n_steps=4, seed=seed)
+        c = Case(cfg, seed=seed, dtype="f32", dth_rms=0.0, p_rms=0.0)
+        cases.append(c)
+        kws.append(dict(mesh_n=n, box=box, ptcl_n=np_, n_steps=4, sched=cfg["sched"], ray_nx=nr, ray_ny=nr,
+                        fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"], omega_m=0.3))
+
+    def run(variants):
+        sim = hrt.Simulation(configs=kws)
+        for k, v in variants.items():
+            sim.set_variant(k, v)
+        st = [(c.dev(c.s), c.dev(c.p), c.dev(np.zeros_like(c.dth)), c.dev(np.zeros_like(c.pr))) for c in cases]
+        for step in range(4):
+            sim.pm_step([x[0] for x in st], [x[1] for x in st], step)
+            sim.ray_step([x[2] for x in st], [x[3] for x in st], step)
+        torch.cuda.synchronize()
+        return [t for x in st for t in x[0] + x[1] + x[2] + x[3]]
+
+    base = run({})
+    for variants in ({"ray_step": 1, "matter_kd": 2}, {"ray_step": 5, "matter_kd": 4, "bin_count": 5,
+                                                        "bin_scatter": 2, "paint_tiles": 1}):
+        for a, b in zip(run(variants), base):
+            assert torch.equal(a, b), variants
