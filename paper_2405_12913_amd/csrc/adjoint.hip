@@ -121,12 +121,12 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
         int ux = 0, uy = 0;            // unwrapped cell of the ray on this plane
         double q[4][2];                // fixed-point contributions of the 4 corners
         if (valid) {
-            const double X = (a.obsx + pe.chi * thx) * a.inv_cell;
-            const double Y = (a.obsy + pe.chi * thy) * a.inv_cell;
-            const double flx = floor(X), fly = floor(Y);
+            double flx, fly, frx, fry;
+            plane_cell(a.obsx, pe.chi, thx, a.inv_cell, flx, frx);
+            plane_cell(a.obsy, pe.chi, thy, a.inv_cell, fly, fry);
             ux = (int)flx;
             uy = (int)fly;
-            const T fx = (T)(X - flx), fy = (T)(Y - fly);
+            const T fx = (T)frx, fy = (T)fry;
             const int x0 = ux & m, y0 = uy & m;
             const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
             const v4<T> *plane = a.grad + (size_t)pe.mesh * n * n;

@@ -28,10 +28,14 @@ __host__ __device__ inline int ilog2(int v) {
 
 // Cell index and fraction of particle i along one axis: u = i_lattice * ratio + s / cell.
 // The integer part of s / cell is split off first so the fraction keeps the precision
-// of the displacement rather than of the absolute coordinate.
+// of the displacement rather than of the absolute coordinate. Contraction is off: with
+// t = s * inv_cell fused into t - floor(t), the fraction could come out slightly negative
+// (the exact product just below the integer its rounded value hits), and a negative CIC
+// weight would break the paint's unsigned fixed-point sums.
 template <typename T>
 __device__ __forceinline__ void axis_cell(T s, int lattice, int ratio, T inv_cell, int nmask,
                                           int &c, T &f) {
+#pragma clang fp contract(off)
     T t = s * inv_cell;
     T fl = floor(t);
     f = t - fl;
@@ -40,6 +44,16 @@ __device__ __forceinline__ void axis_cell(T s, int lattice, int ratio, T inv_cel
         f = T(0);
         c = (c + 1) & nmask;
     }
+}
+
+// Cell and fraction of a ray on a lens plane along one axis: u = (obs + chi theta) / cell
+// in FP64, fraction u - floor(u) formed without contraction, so it lies in [0, 1).
+__device__ __forceinline__ void plane_cell(double obs, double chi, double th, double inv_cell,
+                                           double &fl, double &frac) {
+#pragma clang fp contract(off)
+    const double u = (obs + chi * th) * inv_cell;
+    fl = floor(u);
+    frac = u - fl;
 }
 
 // Wave-aggregated atomic increment of counter[key] for every lane with key >= 0.

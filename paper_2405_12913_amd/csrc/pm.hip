@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     __syncthreads();
     for (int k = threadIdx.x; k < 512; k += kThreads) {
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        st_stream((T)((double)acc[k] * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
+        st_stream((T)((double)(long long)acc[k] * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
 

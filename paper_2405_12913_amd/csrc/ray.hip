@@ -68,10 +68,10 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     T ax = 0, ay = 0;
     for (int e = a.begin; e < a.begin + a.count; ++e) {
         const PlaneEntry pe = a.planes[e];
-        const double X = (a.obsx + pe.chi * thx) * a.inv_cell;
-        const double Y = (a.obsy + pe.chi * thy) * a.inv_cell;
-        const double flx = floor(X), fly = floor(Y);
-        const T fx = (T)(X - flx), fy = (T)(Y - fly);
+        double flx, fly, frx, fry;
+        plane_cell(a.obsx, pe.chi, thx, a.inv_cell, flx, frx);
+        plane_cell(a.obsy, pe.chi, thy, a.inv_cell, fly, fry);
+        const T fx = (T)frx, fy = (T)fry;
         const int x0 = (int)((int64_t)flx & m), y0 = (int)((int64_t)fly & m);
         const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
         const v4<T> *plane = a.g + (size_t)pe.mesh * n * n;

@@ -1,0 +1,125 @@
+"""Parity at the benchmark's full size and at the largest configuration.
+
+lcdm256 (256^3 particles on a 256^3 mesh, box 400 Mpc/h, 512^2 rays over 5 deg), in the
+launch configuration bench.py times (autotuned variants, FP32): one co-evolution step
+against the FP64 oracle on the whole mesh (delta, G), on 8192 sampled particles (kick and
+drift) and on every ray (kick, drift and the convergence map). Tolerances as in
+test_gpu_parity: delta 2e-5 (max relative to 1 + |delta|), G 2e-5 rel-L2, matter and
+rays 1e-4 rel-L2 of the change, kappa 1e-3 relative rms.
+
+large (1024^3 mesh, 512^3 particles, 2048^2 rays): properties that hold at any size and
+need no full oracle solve: the paint of the unperturbed lattice is exact (delta = 7 on the
+even nodes, -1 elsewhere, G = 0 up to rounding), mass is conserved, and handing every
+particle the displacement of its lattice neighbour (the whole particle set moves by one
+lattice spacing, two cells) shifts delta exactly and G to rounding.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import Case, rel_l2, require_gpu, say
+from oracle import integrator, observables, tables
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_lcdm256_step_parity_full_size():
+    import torch
+    from paper_2405_12913_amd import hrt
+    cfg = synth.lcdm256()
+    n, np_, box, M = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
+    say("case lcdm256 full size: inputs")
+    s = synth.clustered_displacements(5, np_, box, n_halos=512).astype(np.float32).astype(np.float64)
+    p = synth.random_momenta(5, len(s), 3.0).astype(np.float32).astype(np.float64)
+    dth, pr = synth.random_rays(5, M * M, 1e-4, 0.3)
+    dth = dth.astype(np.float32).astype(np.float64)
+    pr = pr.astype(np.float32).astype(np.float64)
+    q = integrator.lattice(np_, box)
+    th0 = integrator.pixel_angles(M, M, cfg["fov"], cfg["fov"])
+    step = 10
+    dev = lambda a: [torch.tensor(np.ascontiguousarray(a[:, k]), dtype=torch.float32, device="cuda")
+                     for k in range(a.shape[1])]
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(cfg["sched"]) - 1, sched=cfg["sched"],
+                         ray_nx=M, ray_ny=M, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
+                         omega_m=cfg["omega_m"], dtype="f32")
+    gs, gp, gd, gr = dev(s), dev(p), dev(dth), dev(pr)
+    say("  autotune", sim.autotune(gs, gp, gd, gr, step=step))
+    sim.pm_step(gs, gp, step)
+    delta_g = sim.mesh(hrt.HRT_MESH_DELTA).double().cpu().numpy()
+    G_g = sim.mesh(hrt.HRT_MESH_GRAD).double().cpu().numpy()
+    sim.ray_step(gd, gr, step)
+    kap = torch.empty(M * M, device="cuda")
+    sim.ray_convergence(gd, kap)
+    torch.cuda.synchronize()
+    say("  oracle force")
+    grads, delta_o = integrator.pm_force(q + s, n, box)
+    err_d = np.max(np.abs(delta_g - delta_o) / (1.0 + np.abs(delta_o)))
+    err_g = max(rel_l2(G_g[..., d], grads[d]) for d in range(3))
+    say(f"  delta {err_d:.2e}  G {err_g:.2e}")
+    assert err_d < 2e-5 and err_g < 2e-5
+    tab = tables.build_cosmo(cfg["sched"], cfg["omega_m"], n, box, cfg["observer"][2])
+    idx = np.random.default_rng(6).choice(len(s), 8192, replace=False)
+    s_o, p_o = integrator.matter_step(s[idx], p[idx], q[idx], grads, tab.K[step], tab.D[step], box)
+    s_g, p_g = Case.host(gs)[idx], Case.host(gp)[idx]
+    say("  matter", rel_l2(p_g - p[idx], p_o - p[idx]), rel_l2(s_g - s[idx], s_o - s[idx]))
+    assert rel_l2(p_g - p[idx], p_o - p[idx]) < 1e-4
+    assert rel_l2(s_g - s[idx], s_o - s[idx]) < 1e-4
+    say("  oracle rays")
+    d_o, r_o = integrator.ray_step(dth, pr, th0, grads[0], grads[1], tab.planes[step], tab.d[step],
+                                   np.array(cfg["observer"][:2]), box)
+    d_g, r_g = Case.host(gd), Case.host(gr)
+    say("  rays", rel_l2(r_g - pr, r_o - pr), rel_l2(d_g - dth, d_o - dth), len(tab.planes[step]), "planes")
+    assert rel_l2(r_g - pr, r_o - pr) < 1e-4
+    assert rel_l2(d_g - dth, d_o - dth) < 1e-4
+    mu = cfg["fov"] / M
+    k_o = observables.convergence(d_o, M, M, mu, mu)
+    k_g = kap.double().cpu().numpy().reshape(M, M)
+    assert np.sqrt(np.mean((k_g - k_o) ** 2)) / np.sqrt(np.mean(k_o ** 2)) < 1e-3
+
+
+def test_large_config_properties():
+    import torch
+    from paper_2405_12913_amd import hrt
+    cfg = synth.large1024()
+    n, np_, box, M = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
+    say(f"case large: mesh {n}^3, {np_}^3 particles, {M}^2 rays")
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(cfg["sched"]) - 1, sched=cfg["sched"],
+                         ray_nx=M, ray_ny=M, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
+                         omega_m=cfg["omega_m"], dtype="f32")
+    P = np_ ** 3
+    zeros = [torch.zeros(P, device="cuda") for _ in range(3)]
+    sim.pm_force(zeros, 0)
+    delta = sim.mesh(hrt.HRT_MESH_DELTA)
+    even = delta[0::2, 0::2, 0::2]
+    assert bool((even == 7.0).all())
+    assert float(delta.double().sum()) == 7.0 * P - (n ** 3 - P)
+    assert float(sim.mesh(hrt.HRT_MESH_GRAD)[..., :3].abs().max()) < 1e-3
+    # smooth random displacements (rms 3 cells): mass conservation and shift covariance
+    say("  displaced lattice")
+    r = np.random.default_rng(3)
+    cell = box / n
+    s = []
+    for d in range(3):
+        k = r.integers(1, 4, size=3)
+        g = (np.arange(np_) * (2 * np.pi / np_))
+        w = (np.sin(k[0] * g)[None, None, :] + np.sin(k[1] * g + 1.0)[None, :, None]
+             + np.sin(k[2] * g + 2.0)[:, None, None]) * (3.0 * cell / np.sqrt(1.5))
+        s.append(torch.tensor(w.astype(np.float32).ravel(), device="cuda"))
+    sim.pm_force(s, 0)
+    d0 = delta.clone()
+    g0 = sim.mesh(hrt.HRT_MESH_GRAD)[..., :3].clone()
+    assert abs(float(d0.double().sum())) < 1e-6 * n ** 3
+    s_shift = [torch.roll(t.view(np_, np_, np_), 1, dims=2).reshape(-1).contiguous() for t in s]
+    sim.pm_force(s_shift, 0)
+    d1 = delta
+    g1 = sim.mesh(hrt.HRT_MESH_GRAD)[..., :3]
+    assert torch.equal(torch.roll(d0, 2, dims=2), d1)
+    # FP32 FFT round-off over log2(n^3) = 30 butterfly levels, forward and inverse, in both
+    # solves: ~6e-8 x 30 x 2 x sqrt(2) x a few ~ 3e-5
+    assert float((torch.roll(g0, 2, dims=2) - g1).norm() / g0.norm()) < 5e-5
+    torch.cuda.synchronize()
