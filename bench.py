@@ -34,6 +34,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lcdm256_hbm_traffic.md")
+
+
+def library_source_sha():
+    """sha256 of the HIP library's sources (any edit invalidates stored counter data)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2405_12913_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".cpp", ".h")))
+    for path in files + [os.path.join(ROOT, "include", "hrt.h")]:
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None when that summary
+    is missing or was taken from other library sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("<!-- traffic-json: "):
+                    doc = json.loads(line[len("<!-- traffic-json: "):].rsplit("-->", 1)[0])
+                    if doc.get("source_sha256") != library_source_sha():
+                        return None
+                    k = doc.get("kernels", {}).get(kernel)
+                    return None if k is None else k["traffic_bytes"]
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
 
 
 def algorithmic_bytes(name, n, P, nrays):
@@ -247,6 +279,11 @@ def main():
                     help="skip the 16-realisation batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode workload")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of launch-shape choices: read if present, written after tuning")
+    ap.add_argument("--workload", choices=["lcdm256", "batched16", "adjoint128"], default="lcdm256",
+                    help="lcdm256 (default) prints the benchmark line; batched16 / adjoint128 run only "
+                         "that section and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
@@ -260,6 +297,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     hrt.lib()                                   # fail loudly if the HIP library is missing
+    if args.workload == "batched16":
+        print(json.dumps(batched_bench(hrt, torch, torch.device("cuda:0"), tune=not args.no_tune)), flush=True)
+        return
+    if args.workload == "adjoint128":
+        print(json.dumps(adjoint_bench(torch, torch.device("cuda:0"))), flush=True)
+        return
 
     cfg = synth.lcdm256()
     n, np_, box, nr = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
@@ -278,7 +321,7 @@ def main():
     tuned = {}
     if not args.no_tune:
         print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
-        tuned = sim.autotune(s, p, dth, pr, step=0)
+        tuned = sim.autotune(s, p, dth, pr, step=0, cache=args.tune_cache)
 
     def step(k):
         m = k % N
@@ -369,7 +412,7 @@ def main():
         "launch_variants": tuned,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": pmc_traffic(dom)},
         "kernels": kernels,
     }
     # the same K steps replayed from one captured HIP graph (no host launches in the loop)
