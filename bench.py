@@ -7,9 +7,10 @@ Input (untimed set-up on the GPU): seeded unit white noise -> 2LPT at a = 1/64
 (Eisenstein-Hu no-wiggle spectrum, Omega_m = 0.3, sigma_8 = 0.8, h = 0.7, n_s = 0.96) ->
 64 forward PM steps to a = 1 and the closing half-kick, giving an evolved field.
 A step is one pm_step (paint, FFT Poisson solve, gradient, matter kick-drift) plus one
-ray_step (plane-sum kick over the lens shell, drift); the convergence map is taken
-at the source plane (every 64th step). Steps beyond 64 continue cyclically through the
-schedule from the current state.
+ray_step (plane-sum kick over the lens shell, drift), issued through hrt_run over runs of
+the schedule (bit-identical to step-by-step calls; each drift also counts the particles into
+the next paint's bins); the convergence map is taken at the source plane (every 64th step).
+Steps beyond 64 continue cyclically through the schedule from the current state.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
@@ -323,12 +324,17 @@ def main():
         print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
         tuned = sim.autotune(s, p, dth, pr, step=0, cache=args.tune_cache)
 
-    def step(k):
-        m = k % N
-        sim.pm_step(s, p, m)
-        sim.ray_step(dth, pr, m)
-        if m == N - 1:
-            sim.ray_convergence(dth, kappa)
+    def steps(K):
+        """K co-evolution steps from the start of the schedule (hrt_run over the schedule,
+        cyclically), with the convergence map at the source plane."""
+        k = 0
+        while k < K:
+            m = k % N
+            cnt = min(N - m, K - k)
+            sim.run(s, p, dth, pr, m, cnt)
+            if m + cnt == N:
+                sim.ray_convergence(dth, kappa)
+            k += cnt
 
     def reset():
         torch.cuda.synchronize()
@@ -339,16 +345,14 @@ def main():
         torch.cuda.synchronize()
 
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        step(k)
+    steps(args.warmup)
     reset()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     start.record(sim.stream)
-    for k in range(args.steps):
-        step(k)
+    steps(args.steps)
     stop.record(sim.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -366,8 +370,7 @@ def main():
     print(f"[bench] per-kernel pass, {args.steps} steps", file=sys.stderr, flush=True)
     reset()
     sim.profile_enable(True)
-    for k in range(args.steps):
-        step(k)
+    steps(args.steps)
     prof = sim.profile_read()
     sim.profile_enable(False)
 

@@ -129,9 +129,17 @@ int ray_step(hrt_ctx *ctx, const hrt_rays *r, int step);
 int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *const *gamma1,
                     void *const *gamma2, void *const *omega);
 
+/* Runs steps first_step .. first_step+n_steps-1: pm_step then ray_step for every
+ * realisation (r may be NULL for matter only); with HRT_STATIC one pm_force then the ray
+ * steps (r required). Results are bit-identical to calling pm_step / ray_step step by step;
+ * inside the sequence each matter drift also counts the drifted particles into the next
+ * step's paint bins, which saves the next paint one pass over the particles, so the state
+ * arrays must not be modified by anyone else while the call's work runs. */
+int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps);
+
 /* Captures steps first_step .. first_step+n_steps-1 (pm_step then ray_step for every
- * realisation; with HRT_STATIC one pm_force then ray_steps; r may be NULL for matter
- * only) into a HIP graph held by the context, replacing any previous one. Nothing runs
+ * realisation, as hrt_run does; with HRT_STATIC one pm_force then ray_steps; r may be NULL
+ * for matter only) into a HIP graph held by the context, replacing any previous one. Nothing runs
  * during capture; hrt_graph_launch replays the whole sequence with one launch on the
  * context's stream. The state arrays and workspace must stay the same between capture and
  * replays. Profiling must be off while capturing. */
@@ -216,8 +224,9 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
 /* Launch-shape variants. Some kernels can map particles or rays onto workgroups in several
  * ways (Lagrangian patches of different shapes, linear order, pixel patches or rows) and
  * group workgroups per XCD or not; every variant computes bit-identical results and they
- * differ only in speed. Tunable kernel ids: bin_count, bin_scatter, matter_kd, ray_step
- * (6 variants each), paint_tiles (2). hrt_num_variants(id) gives the count (1 = not
+ * differ only in speed (matter_kd also has shapes with two particles per lane). Tunable
+ * kernel ids: bin_count, bin_scatter, ray_step (6 variants each), matter_kd (12),
+ * paint_tiles (2). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);
  * hrt_get_variant reads it. A new context starts with variant 0 everywhere. */
 int hrt_num_variants(int kernel_id);

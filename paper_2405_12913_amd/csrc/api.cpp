@@ -370,6 +370,47 @@ extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *const *kappa
     return check_hip(c, hrt::launch_convergence(c, a), "convergence");
 }
 
+// Steps first..first+n-1 with the matter drift of each step counting the particles into
+// the next step's paint bins (the state is not touched by anyone else in between).
+static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int first, int n) {
+    if (c->is_static) {
+        if (int rc = pm_force(c, m, first)) return rc;
+        for (int k = first; k < first + n; ++k)
+            if (int rc = ray_step(c, r, k)) return rc;
+        return HRT_OK;
+    }
+    bool counted = false;
+    for (int k = first; k < first + n; ++k) {
+        hrt::StepArgs a;
+        a.m = m;
+        a.step = k;
+        a.counts_ready = counted;
+        if (int rc = check_hip(c, hrt::launch_paint(c, a), "paint")) return rc;
+        if (int rc = check_hip(c, hrt::launch_poisson(c), "poisson")) return rc;
+        if (int rc = check_hip(c, hrt::launch_gradient(c), "gradient")) return rc;
+        c->force_step = k;
+        a.counts_ready = false;
+        a.count_next = k + 1 < first + n;
+        if (int rc = check_hip(c, hrt::launch_matter_kd(c, a), "matter kick-drift")) return rc;
+        counted = a.count_next;
+        if (r)
+            if (int rc = ray_step(c, r, k)) return rc;
+    }
+    return HRT_OK;
+}
+
+extern "C" int hrt_run(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int first_step,
+                       int n_steps) {
+    if (!c) return HRT_EINVAL;
+    if (n_steps < 1 || first_step < 0 || first_step + n_steps > c->N + 1)
+        return fail(c, HRT_EINVAL, "steps out of range [0, n_steps]");
+    if (int rc = check_matter(c, m, !c->is_static)) return rc;
+    if (r)
+        if (int rc = check_rays(c, r, true)) return rc;
+    if (c->is_static && !r) return fail(c, HRT_EINVAL, "a static run needs rays");
+    return run_steps(c, m, r, first_step, n_steps);
+}
+
 extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
                                  int first_step, int n_steps) {
     if (!c) return HRT_EINVAL;
@@ -388,10 +429,8 @@ extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays
         return rc;
     c->stream = cap;
     int rc = check_hip(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    for (int k = first_step; rc == HRT_OK && k < first_step + n_steps; ++k) {
-        rc = c->is_static ? (k == first_step ? pm_force(c, m, k) : HRT_OK) : pm_step(c, m, k);
-        if (rc == HRT_OK && r) rc = ray_step(c, r, k);
-    }
+    if (rc == HRT_OK) rc = (c->is_static && !r) ? pm_force(c, m, first_step)
+                                                : run_steps(c, m, r, first_step, n_steps);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cap, &graph);
     c->stream = user;

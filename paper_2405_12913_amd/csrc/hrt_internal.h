@@ -85,6 +85,10 @@ struct StepArgs {
     void *const *g1 = nullptr;
     void *const *g2 = nullptr;
     void *const *om = nullptr;
+    // Fused bin histogram (hrt_run): the matter kick-drift also counts the drifted
+    // particles into the paint bins of the next step, whose paint then skips its own count.
+    bool count_next = false;     // launch_matter_kd: zero the counts, count the new positions
+    bool counts_ready = false;   // launch_paint: the counts already hold these positions
 };
 
 // Blocks of realisation r are [start[r], start[r+1]); start[R] is the grid size.

@@ -272,45 +272,77 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     }
 }
 
-// One lane per particle, particles in Lagrangian order; blocks are XCD-remapped so
-// neighbouring particle patches (which read the same mesh rows) share one L2.
-template <typename T>
+// One lane per ILP particles, particles in Lagrangian order (patch maps), optionally with
+// XCD-grouped blocks so neighbouring particle patches (which read the same mesh rows)
+// share one L2. With ILP = 2 a lane issues the loads and the 16 corner gathers of both
+// its particles before using any of them (more memory requests in flight per wave).
+// With COUNT the drifted particle is also counted into its paint bin for the next step
+// (the key comes from the very value stored, so the next paint's scatter recomputes it
+// bit for bit).
+template <typename T, int ILP, bool COUNT>
 __global__ __launch_bounds__(kThreads) void matter_kd_kernel(PartBatch<T> b) {
     const int blk = logical_block(b.xcd);
     const int r = real_of(b.map, blk);
     const Particles<T> &a = b.r[r];
-    const int i = particle_of(blk - b.map.start[r], threadIdx.x, a.lnp, b.pmap);
-    if (i >= a.P) return;
-    int c[3];
-    T f[3], sv[3];
-    particle_cell<T>(a, i, c, f, sv);
     const int n = a.n;
-    T gx = 0, gy = 0, gzz = 0;
+    int idx[ILP], c[ILP][3];
+    T f[ILP][3], sv[ILP][3], pv[ILP][3];
+    v4<T> g[ILP][8];
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz) {
-        const int z = (c[2] + cz) & (n - 1);
-        const T wz = cz ? f[2] : T(1) - f[2];
+    for (int j = 0; j < ILP; ++j) {
+        idx[j] = particle_of((blk - b.map.start[r]) * ILP + j, threadIdx.x, a.lnp, b.pmap);
+        if (idx[j] < a.P) particle_cell<T>(a, idx[j], c[j], f[j], sv[j]);
+    }
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy) {
-            const int y = (c[1] + cy) & (n - 1);
-            const T wyz = wz * (cy ? f[1] : T(1) - f[1]);
+    for (int j = 0; j < ILP; ++j) {
+        if (idx[j] >= a.P) continue;
 #pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const int x = (c[0] + cx) & (n - 1);
-                const T w = wyz * (cx ? f[0] : T(1) - f[0]);
-                const v4<T> gv = a.grad[((size_t)z * n + y) * n + x];
-                gx += w * gv.x;
-                gy += w * gv.y;
-                gzz += w * gv.z;
-            }
+        for (int k = 0; k < 8; ++k) {
+            const int z = (c[j][2] + (k >> 2)) & (n - 1);
+            const int y = (c[j][1] + ((k >> 1) & 1)) & (n - 1);
+            const int x = (c[j][0] + (k & 1)) & (n - 1);
+            g[j][k] = a.grad[((size_t)z * n + y) * n + x];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pv[j][d] = ld_stream(a.p[d] + idx[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) {
+        if (idx[j] >= a.P) continue;
+        T gx = 0, gy = 0, gzz = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const T wz = (k >> 2) ? f[j][2] : T(1) - f[j][2];
+            const T wyz = wz * (((k >> 1) & 1) ? f[j][1] : T(1) - f[j][1]);
+            const T w = wyz * ((k & 1) ? f[j][0] : T(1) - f[j][0]);
+            gx += w * g[j][k].x;
+            gy += w * g[j][k].y;
+            gzz += w * g[j][k].z;
+        }
+        const T gg[3] = {gx, gy, gzz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T pn = pv[j][d] + a.K * gg[d];
+            st_stream(pn, a.p[d] + idx[j]);
+            sv[j][d] = sv[j][d] + a.D * pn;
+            st_stream(sv[j][d], a.s[d] + idx[j]);
         }
     }
-    const T g[3] = {gx, gy, gzz};
+    if (COUNT) {
+        const int pm = (1 << a.lnp) - 1;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T pn = ld_stream(a.p[d] + i) + a.K * g[d];
-        st_stream(pn, a.p[d] + i);
-        st_stream(sv[d] + a.D * pn, a.s[d] + i);
+        for (int j = 0; j < ILP; ++j) {
+            int key = -1;
+            if (idx[j] < a.P) {
+                const int lat[3] = {idx[j] & pm, (idx[j] >> a.lnp) & pm, idx[j] >> (2 * a.lnp)};
+                int cn[3];
+                T fn;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) axis_cell<T>(sv[j][d], lat[d], a.ratio, a.inv_cell, a.n - 1, cn[d], fn);
+                key = bin_key(cn, a.n / kTile);
+            }
+            wave_aggregated_increment<false>(a.count, key);
+        }
     }
 }
 
@@ -531,13 +563,15 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         const int R = std::min(kMaxBatch, nre - r0);
         PartBatch<T> b{};
         for (int k = 0; k < R; ++k) fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
-        prof_begin(c);
-        set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
-        fill_counts_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
-        set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
-        set_variant(b, c->variant[K_BIN_COUNT], 0);
-        bin_count_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
-        prof_end(c, K_BIN_COUNT);
+        if (!args.counts_ready) {
+            prof_begin(c);
+            set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
+            fill_counts_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
+            set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
+            set_variant(b, c->variant[K_BIN_COUNT], 0);
+            bin_count_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
+            prof_end(c, K_BIN_COUNT);
+        }
         prof_begin(c);
         set_map(b, R, [](const Particles<T> &a) { return a.nblk; });
         scan_local_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
@@ -571,10 +605,22 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], re.tab.K[args.step],
                               re.tab.D[args.step]);
         }
-        set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
-        set_variant(b, c->variant[K_MATTER_KD], 1);
         prof_begin(c);
-        matter_kd_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        if (args.count_next) {
+            set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
+            fill_counts_kernel<T><<<b.map.start[R], 256, 0, c->stream>>>(b);
+        }
+        const int v = c->variant[K_MATTER_KD];
+        const int ilp = v >= 6 ? 2 : 1;
+        set_map(b, R, [ilp](const Particles<T> &a) { return (particle_blocks(a.P) + ilp - 1) / ilp; });
+        set_variant(b, v % 6, 1);
+        if (args.count_next) {
+            if (ilp == 2) matter_kd_kernel<T, 2, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+            else matter_kd_kernel<T, 1, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        } else {
+            if (ilp == 2) matter_kd_kernel<T, 2, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+            else matter_kd_kernel<T, 1, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        }
         prof_end(c, K_MATTER_KD);
     }
     return hipGetLastError();

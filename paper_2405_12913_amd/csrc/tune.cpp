@@ -1,8 +1,8 @@
 // Launch-shape variants and their autotuner (C ABI in include/hrt.h).
 //
-// A variant only changes how particles or rays are mapped onto workgroups and whether
-// workgroups are grouped per XCD; the arithmetic of every particle, ray and mesh node is
-// the same, so all variants give bit-identical results. The tuner times each variant on
+// A variant only changes how particles or rays are mapped onto workgroups and lanes (patch
+// shapes, particles per lane) and whether workgroups are grouped per XCD; the arithmetic of
+// every particle, ray and mesh node is the same, so all variants give bit-identical results. The tuner times each variant on
 // the context's own shapes and keeps the fastest; choices persist in a small JSON file
 // keyed by device architecture, kernel, dtype and sizes.
 #include <cstdio>
@@ -25,7 +25,8 @@ using hrt::K_RAY_STEP;
 
 int variants_of(int id) {
     switch (id) {
-        case K_BIN_COUNT: case K_BIN_SCATTER: case K_MATTER_KD: case K_RAY_STEP: return 6;
+        case K_MATTER_KD: return 12;
+        case K_BIN_COUNT: case K_BIN_SCATTER: case K_RAY_STEP: return 6;
         case K_PAINT: return 2;
         default: return (id >= 0 && id < K_COUNT) ? 1 : 0;
     }

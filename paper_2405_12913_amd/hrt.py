@@ -25,7 +25,7 @@ EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", 
             "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
             "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
             "ray_convergence_vjp", "hrt_ic_2lpt_vjp", "hrt_num_variants", "hrt_set_variant",
-            "hrt_get_variant", "hrt_autotune")
+            "hrt_get_variant", "hrt_autotune", "hrt_run")
 
 
 class HrtConfig(ctypes.Structure):
@@ -81,6 +81,7 @@ def lib():
                                       P(c_void_p)]
         L.hrt_graph_capture.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int]
         L.hrt_graph_launch.argtypes = [c_void_p]
+        L.hrt_run.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int]
         L.hrt_mesh_ptr.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
         L.hrt_tables.argtypes = [P(HrtConfig)] + [P(c_double)] * 5 + [P(c_int32)] * 3 + \
             [P(c_double)] * 2 + [c_int32, P(c_int32)]
@@ -284,6 +285,12 @@ class Simulation:
             return arr
         _check(lib().ray_convergence(self.ctx, self._rays(dth), ptrs(kappa), ptrs(gamma1),
                                      ptrs(gamma2), ptrs(omega)), self.ctx)
+
+    def run(self, s, p, dth, pr, first_step, n_steps):
+        """Steps [first_step, first_step + n_steps): pm_step + ray_step each (dth, pr may be
+        None for matter only); same results as calling them one by one, one pass less."""
+        r = self._rays(dth, pr) if dth is not None else None
+        _check(lib().hrt_run(self.ctx, self._matter(s, p), r, first_step, n_steps), self.ctx)
 
     def graph_capture(self, s, p, dth, pr, first_step, n_steps):
         """Capture steps [first_step, first_step + n_steps) into one HIP graph."""

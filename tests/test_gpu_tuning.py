@@ -114,3 +114,61 @@ def test_batched_variants_with_uneven_grids():
                                                         "bin_scatter": 2, "paint_tiles": 1}):
         for a, b in zip(run(variants), base):
             assert torch.equal(a, b), variants
+
+
+def test_run_equals_step_by_step():
+    """hrt_run (the drift counts the next paint's bins) is bit-identical to pm_step/ray_step
+    called one by one: single realisation with rays, matter only, an uneven batch, and the
+    two-particles-per-lane matter variant."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    say("case hrt_run vs step by step")
+    c = _case()
+    base = _run(c, c.sim(), steps=5)
+    for variant in (0, 8):
+        sim = c.sim()
+        sim.set_variant("matter_kd", variant)
+        s, p = c.dev(c.s), c.dev(c.p)
+        d, pr = c.dev(np.zeros_like(c.dth)), c.dev(np.zeros_like(c.pr))
+        k = torch.empty(c.mx * c.my, device="cuda")
+        sim.run(s, p, d, pr, 0, 2)
+        sim.run(s, p, d, pr, 2, 3)
+        sim.ray_convergence(d, k)
+        torch.cuda.synchronize()
+        for a, b in zip(s + p + d + pr + [k], base):
+            assert torch.equal(a, b), variant
+    # matter only
+    sim = c.sim()
+    s1, p1 = c.dev(c.s), c.dev(c.p)
+    for step in range(4):
+        sim.pm_step(s1, p1, step)
+    s2, p2 = c.dev(c.s), c.dev(c.p)
+    c.sim().run(s2, p2, None, None, 0, 4)
+    torch.cuda.synchronize()
+    for a, b in zip(s1 + p1, s2 + p2):
+        assert torch.equal(a, b)
+    # uneven batch
+    specs = [(32, 32, 50.0, 24, 3.0, 11), (64, 16, 80.0, 32, 2.0, 12)]
+    cases, kws = [], []
+    for n, np_, box, nr, fov, seed in specs:
+        cfg = synth.tiny(mesh_n=n, ptcl_n=np_, box=box, ray_n=nr, fov_deg=fov, n_steps=4, seed=seed)
+        cc = Case(cfg, seed=seed, dtype="f32", dth_rms=0.0, p_rms=0.0)
+        cases.append(cc)
+        kws.append(dict(mesh_n=n, box=box, ptcl_n=np_, n_steps=4, sched=cfg["sched"], ray_nx=nr, ray_ny=nr,
+                        fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"], omega_m=0.3))
+    outs = []
+    for use_run in (False, True):
+        sim = hrt.Simulation(configs=kws)
+        st = [(cc.dev(cc.s), cc.dev(cc.p), cc.dev(np.zeros_like(cc.dth)), cc.dev(np.zeros_like(cc.pr)))
+              for cc in cases]
+        S, Pm, D, R = ([x[i] for x in st] for i in range(4))
+        if use_run:
+            sim.run(S, Pm, D, R, 0, 5)
+        else:
+            for step in range(5):
+                sim.pm_step(S, Pm, step)
+                sim.ray_step(D, R, step)
+        torch.cuda.synchronize()
+        outs.append([t for x in st for t in x[0] + x[1] + x[2] + x[3]])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
