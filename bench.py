@@ -236,6 +236,36 @@ def adjoint_bench(torch, dev):
             "checkpoints": len(ck_f) + len(ck_c)}
 
 
+def large_bench(hrt, torch, dev, tune=True, steps=8):
+    """The largest configuration: 512^3 particles on a 1024^3 mesh, box 1000 Mpc/h, 2048^2
+    rays over 10 deg, 100 co-evolution steps to a = 1/3; `steps` steps from a = 1 timed."""
+    import synth
+    cfg = synth.large1024()
+    print("[bench] large: 1024^3 mesh, 512^3 particles, 2048^2 rays; initial conditions",
+          file=sys.stderr, flush=True)
+    s, p = evolved_ic(hrt, torch, cfg, dev, 0)
+    nr = cfg["ray_n"] ** 2
+    dth = [torch.zeros(nr, device=dev) for _ in range(2)]
+    pr = [torch.zeros(nr, device=dev) for _ in range(2)]
+    sim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+    tuned = sim.autotune(s, p, dth, pr, step=0) if tune else {}
+    sim.run(s, p, dth, pr, 0, 2)                                   # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    sim.run(s, p, dth, pr, 2, steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert torch.isfinite(dth[0]).all() and torch.isfinite(s[0]).all()
+    sim.close()
+    return {"workload": "large1024: 512^3 particles on a 1024^3 mesh, box 1000 Mpc/h, 2048^2 rays "
+                        "over 10 deg, 100-step schedule a = 1 -> 1/3 (steps 2..9 timed after 2 warm-up "
+                        "steps), evolved initial conditions as lcdm256",
+            "ray_steps_per_s": nr / (ms * 1e-3), "ms_per_step": round(ms, 3),
+            "launch_variants": tuned}
+
+
 def cpu_baseline():
     """Oracle (FP64 NumPy) time for one co-evolution step on a bounded sample."""
     import synth
@@ -265,7 +295,8 @@ def cpu_baseline():
                        f"256^2 rays over 5 deg (same cell and field): PM {t1 - t0:.1f} s, "
                        f"rays {t2 - t1:.2f} s; scaled x8 (PM) and x4 (rays) to the 256^3 / 512^2 "
                        f"workload; numpy single-threaded"),
-            "pm_step_ms": 8.0 * (t1 - t0) * 1e3}
+            "pm_step_ms": 8.0 * (t1 - t0) * 1e3, "ray_step_ms": 4.0 * (t2 - t1) * 1e3,
+            "host_nproc": os.cpu_count()}
 
 
 def main():
@@ -279,12 +310,14 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-realisation batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 workload")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of launch-shape choices: read if present, written after tuning")
-    ap.add_argument("--workload", choices=["lcdm256", "batched16", "adjoint128"], default="lcdm256",
-                    help="lcdm256 (default) prints the benchmark line; batched16 / adjoint128 run only "
-                         "that section and print its JSON (for profiling)")
+    ap.add_argument("--workload", choices=["lcdm256", "batched16", "adjoint128", "large1024"],
+                    default="lcdm256",
+                    help="lcdm256 (default) prints the benchmark line; the others run only that "
+                         "section and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on "
@@ -303,6 +336,9 @@ def main():
         return
     if args.workload == "adjoint128":
         print(json.dumps(adjoint_bench(torch, torch.device("cuda:0"))), flush=True)
+        return
+    if args.workload == "large1024":
+        print(json.dumps(large_bench(hrt, torch, torch.device("cuda:0"), tune=not args.no_tune)), flush=True)
         return
 
     cfg = synth.lcdm256()
@@ -359,13 +395,20 @@ def main():
     elapsed_ms = start.elapsed_time(stop)
     assert torch.isfinite(dth[0]).all() and torch.isfinite(s[0]).all()
 
-    if args.calibrate_copy:
-        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+    # copy ceiling: a plain 512 MiB device-to-device copy (read + write), best of 5; with
+    # --calibrate-copy these copies are also the reference dispatches of the counter runs
+    src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for _ in range(5 if args.calibrate_copy else 6):
+        c0.record()
+        dst.copy_(src)
+        c1.record()
         torch.cuda.synchronize()
-        del src, dst
+        copy_ms.append(c0.elapsed_time(c1))
+    copy_gbps = 2 * (512 << 20) / (min(copy_ms[1:]) * 1e-3) / 1e9
+    del src, dst
 
     print(f"[bench] per-kernel pass, {args.steps} steps", file=sys.stderr, flush=True)
     reset()
@@ -380,8 +423,14 @@ def main():
             continue
         avg_ms = ms / cnt
         b = algorithmic_bytes(name, n, P, nrays)
+        gbps = b / (avg_ms * 1e-3) / 1e9
         kernels[name] = {"launches": cnt, "avg_ms": round(avg_ms, 5), "total_ms": round(ms, 3),
-                         "alg_bytes": b, "alg_GBps": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+                         "alg_bytes": b, "alg_GBps": round(gbps, 1),
+                         "pct_hbm_peak": round(100 * gbps / HBM_PEAK_GBS, 1),
+                         "pct_copy_ceiling": round(100 * gbps / copy_gbps, 1)}
+        tb = pmc_traffic(name)
+        if tb is not None:
+            kernels[name]["traffic_GBps"] = round(tb / (avg_ms * 1e-3) / 1e9, 1)
     pm_names = ["bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
                 "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd"]
     pm_ms = sum(prof[k][0] for k in pm_names) / args.steps
@@ -416,8 +465,28 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": pmc_traffic(dom)},
+        "copy_ceiling_GBps": round(copy_gbps, 1),
         "kernels": kernels,
     }
+    # PM step alone: one captured pm_step replayed 23 times, HIP events around each replay,
+    # median of the last 20
+    reset()
+    pstream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(pstream):
+        psim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+        for name, v in tuned.items():
+            psim.set_variant(name, v)
+        psim.graph_capture(s, p, None, None, 10, 1)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(24)]
+        torch.cuda.synchronize()
+        for k in range(23):
+            evs[k].record(pstream)
+            psim.graph_launch()
+        evs[23].record(pstream)
+        torch.cuda.synchronize()
+        reps = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(3, 23))
+        psim.close()
+    out["pm_step_ms_graph_median"] = round(0.5 * (reps[9] + reps[10]), 4)
     # the same K steps replayed from one captured HIP graph (no host launches in the loop)
     if args.steps <= N:
         reset()
@@ -441,6 +510,8 @@ def main():
         out["batched"] = batched_bench(hrt, torch, dev, tune=not args.no_tune)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, dev)
+    if not args.no_large:
+        out["large"] = large_bench(hrt, torch, dev, tune=not args.no_tune)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

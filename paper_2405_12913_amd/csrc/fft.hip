@@ -46,7 +46,7 @@ __device__ __forceinline__ void dft(c2<T> *v) {
 }
 
 // One Stockham stage over LINES lines of length L in LDS (line stride LS), then the next.
-// tw holds W_n^m = exp(-2 pi i m / n); W_L^m = tw[m * twmul] with twmul = n / L.
+// tw (in LDS) holds W_n^m = exp(-2 pi i m / n); W_L^m = tw[m * twmul] with twmul = n / L.
 template <typename T, int L, int LINES, bool INV, int Ns>
 __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
                                           int twmul) {
@@ -92,11 +92,27 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__res
     }
 }
 
+// Stage the N twiddles W_N^m (every tws-th entry of the table) in LDS; the caller's next
+// __syncthreads makes them visible.
+template <typename T, int N>
+__device__ __forceinline__ void stage_twiddles(c2<T> *stw, const c2<T> *__restrict__ tw, int tws) {
+    for (int j = threadIdx.x; j < N; j += kThreads) stw[j] = tw[j * tws];
+}
+
+// Work per block (complex values staged in LDS). Small blocks keep many blocks resident per
+// CU, so one block's loads overlap other blocks' LDS stages (measured on gfx950 at 256^3:
+// 2048 values for the x passes, 1024 for y and 2048 for z were fastest). The x passes
+// write (read) the spectrum transposed and the z pass reads strided rows, so both keep at
+// least 16 (x) and 8 (z) lines per block at any N: 128- and 64-byte segments.
 template <typename T, int N>
 struct Cfg {
-    static constexpr int ELEMS = sizeof(T) == 4 ? 4096 : 2048;   // complex values per block
-    static constexpr int XROWS = (ELEMS / (N / 2)) < N * N ? ELEMS / (N / 2) : N * N;
-    static constexpr int LINES = ELEMS / N;                        // y and z passes
+    static constexpr int F = sizeof(T) == 4 ? 1 : 2;
+    static constexpr int EX = (2048 / F > 16 * N / (2 * F)) ? 2048 / F : 16 * N / (2 * F);
+    static constexpr int EY = (1024 / F > N) ? 1024 / F : N;
+    static constexpr int EZ = (2048 / F > 8 * N / F) ? 2048 / F : 8 * N / F;
+    static constexpr int XROWS = (EX / (N / 2)) < 1 ? 1 : ((EX / (N / 2)) < N * N ? EX / (N / 2) : N * N);
+    static constexpr int YLINES = EY / N < 1 ? 1 : EY / N;
+    static constexpr int ZLINES = EZ / N < 1 ? 1 : EZ / N;
 };
 
 // Per-launch arguments of the FFT passes: realisations of one mesh size N.
@@ -117,18 +133,18 @@ template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
+    __shared__ c2<T> tw[N];
     const int r = blockIdx.x / fb.bpr;
     const T *__restrict__ in = fb.rin[r];
     c2<T> *__restrict__ out = fb.spec[r];
-    const c2<T> *__restrict__ tw = fb.tw[r];
-    const int tws = fb.tws;
     const int row0 = (blockIdx.x % fb.bpr) * ROWS;
+    stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
         const int rr = e / L, m = e % L;
         buf[rr * LS + m] = reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + rr) * N)[m];
     }
     __syncthreads();
-    fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, tws * (N / L));
+    fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, N / L);
     // split step: X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) W_N^k (Z[k] - conj Z[L-k]),
     // each thread owns the pair (k, L-k); X[L] (Nyquist) comes from Z[0].
     for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
@@ -136,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
         c2<T> *line = buf + rr * LS;
         const c2<T> zk = line[k];
         const c2<T> zp = line[k == 0 ? 0 : L - k];
-        const c2<T> w = tw[k * tws];
+        const c2<T> w = tw[k];
         // A = zk + conj(zp), B = zk - conj(zp); X[k] = A/2 - (i/2) w B
         const c2<T> A{zk.x + zp.x, zk.y - zp.y}, B{zk.x - zp.x, zk.y + zp.y};
         const c2<T> wB = cmul<T>(w, B);
@@ -162,12 +178,12 @@ template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
+    __shared__ c2<T> tw[N];
     const int r = blockIdx.x / fb.bpr;
     const c2<T> *__restrict__ in = fb.spec[r];
     T *__restrict__ out = fb.rout[r];
-    const c2<T> *__restrict__ tw = fb.tw[r];
-    const int tws = fb.tws;
     const int row0 = (blockIdx.x % fb.bpr) * ROWS;
+    stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < ROWS * (L + 1); e += kThreads) {
         const int kx = e / ROWS, rr = e % ROWS;
         const int row = row0 + rr, z = row / N, y = row % N;
@@ -179,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
         const int rr = e / (L / 2 + 1), k = e % (L / 2 + 1);
         c2<T> *line = buf + rr * LS;
         const c2<T> xk = line[k], xp = line[L - k];
-        const c2<T> w = tw[k * tws];
+        const c2<T> w = tw[k];
         const c2<T> wc{w.x, -w.y};
         const c2<T> A{xk.x + xp.x, xk.y - xp.y}, B{xk.x - xp.x, xk.y + xp.y};
         const c2<T> wB = cmul<T>(wc, B);
@@ -192,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
         }
     }
     __syncthreads();
-    fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, tws * (N / L));
+    fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, N / L);
     for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
         const int rr = e / L, m = e % L;
         reinterpret_cast<c2<T> *>(out + (size_t)(row0 + rr) * N)[m] = buf[rr * LS + m];
@@ -202,18 +218,20 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
 // FFT along y of the transposed spectrum C[kx][z][y]: lines are contiguous.
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
-    constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
+    constexpr int LINES = Cfg<T, N>::YLINES, LS = N + 1;
     constexpr int TOTAL = (N / 2 + 1) * N;
     __shared__ c2<T> buf[LINES * LS];
+    __shared__ c2<T> tw[N];
     const int r = blockIdx.x / fb.bpr;
     c2<T> *__restrict__ data = fb.spec[r];
     const int l0 = (blockIdx.x % fb.bpr) * LINES;
+    stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int li = e / N, m = e % N;
         if (l0 + li < TOTAL) buf[li * LS + m] = data[(size_t)(l0 + li) * N + m];
     }
     __syncthreads();
-    fft_stage<T, N, LINES, INV, 1>(buf, LS, fb.tw[r], fb.tws);
+    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, 1);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int li = e / N, m = e % N;
         if (l0 + li < TOTAL) data[(size_t)(l0 + li) * N + m] = buf[li * LS + m];
@@ -224,19 +242,20 @@ __global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
 // -> 0), inverse. Line l = kx * N + y, element stride N.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
-    constexpr int LINES = Cfg<T, N>::LINES, LS = N + 1;
+    constexpr int LINES = Cfg<T, N>::ZLINES, LS = N + 1;
     constexpr int TOTAL = (N / 2 + 1) * N;
     __shared__ c2<T> buf[LINES * LS];
+    __shared__ c2<T> tw[N];
     const int r = blockIdx.x / fb.bpr;
     c2<T> *__restrict__ data = fb.spec[r];
-    const c2<T> *__restrict__ tw = fb.tw[r];
     const int l0 = (blockIdx.x % fb.bpr) * LINES;
+    stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int z = e / LINES, li = e % LINES, l = l0 + li;
         if (l < TOTAL) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
     }
     __syncthreads();
-    fft_stage<T, N, LINES, MODE == 1, 1>(buf, LS, tw, fb.tws);
+    fft_stage<T, N, LINES, MODE == 1, 1>(buf, LS, tw, 1);
     if constexpr (MODE == 2) {
         const double kf2 = fb.kf2[r], inv_n3 = 1.0 / ((double)N * N * N);
         for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
@@ -249,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
             buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
         }
         __syncthreads();
-        fft_stage<T, N, LINES, true, 1>(buf, LS, tw, fb.tws);
+        fft_stage<T, N, LINES, true, 1>(buf, LS, tw, 1);
     }
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int z = e / LINES, li = e % LINES, l = l0 + li;
@@ -320,22 +339,23 @@ FftBatch<T> fft_batch(hrt_ctx *c, const std::vector<int> &ids, int bpr, int tws)
 template <typename T, int N>
 hipError_t poisson_n(hrt_ctx *c, const std::vector<int> &ids) {
     hipStream_t st = c->stream;
-    constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
+    constexpr int XROWS = Cfg<T, N>::XROWS, YL = Cfg<T, N>::YLINES, ZL = Cfg<T, N>::ZLINES;
     const int xb = N * N / XROWS;
-    const int lb = ((N / 2 + 1) * N + LINES - 1) / LINES;
+    const int yb = ((N / 2 + 1) * N + YL - 1) / YL, zb = ((N / 2 + 1) * N + ZL - 1) / ZL;
     const int R = (int)ids.size();
-    FftBatch<T> fx = fft_batch<T, N>(c, ids, xb, 1), fl = fft_batch<T, N>(c, ids, lb, 1);
+    FftBatch<T> fx = fft_batch<T, N>(c, ids, xb, 1), fy = fft_batch<T, N>(c, ids, yb, 1),
+                fz = fft_batch<T, N>(c, ids, zb, 1);
     prof_begin(c);
     x_r2c_kernel<T, N><<<xb * R, kThreads, 0, st>>>(fx);
     prof_end(c, K_FFT_X_R2C);
     prof_begin(c);
-    y_lines_kernel<T, N, false><<<lb * R, kThreads, 0, st>>>(fl);
+    y_lines_kernel<T, N, false><<<yb * R, kThreads, 0, st>>>(fy);
     prof_end(c, K_FFT_Y_FWD);
     prof_begin(c);
-    z_lines_kernel<T, N, 2><<<lb * R, kThreads, 0, st>>>(fl);
+    z_lines_kernel<T, N, 2><<<zb * R, kThreads, 0, st>>>(fz);
     prof_end(c, K_FFT_Z_POISSON);
     prof_begin(c);
-    y_lines_kernel<T, N, true><<<lb * R, kThreads, 0, st>>>(fl);
+    y_lines_kernel<T, N, true><<<yb * R, kThreads, 0, st>>>(fy);
     prof_end(c, K_FFT_Y_INV);
     prof_begin(c);
     x_c2r_kernel<T, N><<<xb * R, kThreads, 0, st>>>(fx);
@@ -487,8 +507,9 @@ __global__ void lpt_combine_kernel(T *__restrict__ s, T *__restrict__ p, int64_t
 // workspace; tws = mesh size / N.
 template <typename T, int N>
 void fwd3d(hrt_ctx *c, int r, const T *real_in, c2<T> *spec, int tws) {
-    constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
-    const int xb = N * N / XROWS, lb = ((N / 2 + 1) * N + LINES - 1) / LINES;
+    constexpr int XROWS = Cfg<T, N>::XROWS, YL = Cfg<T, N>::YLINES, ZL = Cfg<T, N>::ZLINES;
+    const int xb = N * N / XROWS;
+    const int yb = ((N / 2 + 1) * N + YL - 1) / YL, zb = ((N / 2 + 1) * N + ZL - 1) / ZL;
     FftBatch<T> fb{};
     fb.tws = tws;
     fb.rin[0] = real_in;
@@ -496,23 +517,26 @@ void fwd3d(hrt_ctx *c, int r, const T *real_in, c2<T> *spec, int tws) {
     fb.tw[0] = reinterpret_cast<const c2<T> *>(c->re[r].ws + c->re[r].lay.twiddle);
     fb.bpr = xb;
     x_r2c_kernel<T, N><<<xb, kThreads, 0, c->stream>>>(fb);
-    fb.bpr = lb;
-    y_lines_kernel<T, N, false><<<lb, kThreads, 0, c->stream>>>(fb);
-    z_lines_kernel<T, N, 0><<<lb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = yb;
+    y_lines_kernel<T, N, false><<<yb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = zb;
+    z_lines_kernel<T, N, 0><<<zb, kThreads, 0, c->stream>>>(fb);
 }
 
 template <typename T, int N>
 void inv3d(hrt_ctx *c, int r, c2<T> *spec, T *real_out, int tws) {
-    constexpr int XROWS = Cfg<T, N>::XROWS, LINES = Cfg<T, N>::LINES;
-    const int xb = N * N / XROWS, lb = ((N / 2 + 1) * N + LINES - 1) / LINES;
+    constexpr int XROWS = Cfg<T, N>::XROWS, YL = Cfg<T, N>::YLINES, ZL = Cfg<T, N>::ZLINES;
+    const int xb = N * N / XROWS;
+    const int yb = ((N / 2 + 1) * N + YL - 1) / YL, zb = ((N / 2 + 1) * N + ZL - 1) / ZL;
     FftBatch<T> fb{};
     fb.tws = tws;
     fb.rout[0] = real_out;
     fb.spec[0] = spec;
     fb.tw[0] = reinterpret_cast<const c2<T> *>(c->re[r].ws + c->re[r].lay.twiddle);
-    fb.bpr = lb;
-    z_lines_kernel<T, N, 1><<<lb, kThreads, 0, c->stream>>>(fb);
-    y_lines_kernel<T, N, true><<<lb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = zb;
+    z_lines_kernel<T, N, 1><<<zb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = yb;
+    y_lines_kernel<T, N, true><<<yb, kThreads, 0, c->stream>>>(fb);
     fb.bpr = xb;
     x_c2r_kernel<T, N><<<xb, kThreads, 0, c->stream>>>(fb);
 }

@@ -31,7 +31,25 @@ struct Particles {             // one realisation, as the particle kernels see i
     int n, lnp, ratio, P, nbins, nblk;
     T inv_cell, K, D;
     double scale, inv_scale_rho;
+    int fixed_bits;            // scale = 2^fixed_bits
 };
+
+// CIC weight w in [0, 1] as a fixed-point integer round(w 2^F). For float the product is
+// formed from w's bits (mantissa shifted by its exponent): exact whenever w 2^F is an
+// integer (every w >= 2^(23-F)), rounded half up below that; for double by llrint.
+__device__ __forceinline__ unsigned long long to_fixed(float w, double, int F) {
+    const unsigned int bits = __float_as_uint(w);
+    const int e = (int)(bits >> 23);
+    if (e == 0) return 0ull;                                   // zero (and denormals)
+    const unsigned long long m = (bits & 0x7fffffu) | 0x800000u;
+    const int sh = e - 150 + F;                                // w 2^F = m 2^sh
+    if (sh >= 0) return m << sh;
+    if (sh < -24) return 0ull;
+    return (m + (1ull << (-sh - 1))) >> -sh;
+}
+__device__ __forceinline__ unsigned long long to_fixed(double w, double scale, int) {
+    return (unsigned long long)llrint(w * scale);
+}
 
 template <typename T>
 struct PartBatch {
@@ -197,9 +215,8 @@ __constant__ signed char kRangeTab[27][4] = {
 
 template <typename T>
 __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int ty, int tz, int *rstart,
-                                            int *rpre, signed char (*rd)[3]) {
+                                            int *rpre, signed char (*rd)[3], int k) {
     const int nt = a.n / kTile;
-    const int k = threadIdx.x;
     if (k < 27) {
         const int dx = kRangeTab[k][0], dy = kRangeTab[k][1], dz = kRangeTab[k][2];
         const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt + ((tx + dx) & (nt - 1)));
@@ -218,57 +235,70 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
     }
 }
 
+// Adds the CIC weights of one binned particle (range r) to the tile's LDS sums.
 template <typename T>
+__device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long long *acc, const v4<T> &e,
+                                          const signed char *d, double scale) {
+    int lcell;
+    if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
+    else lcell = (int)e.w;
+    const int bx = kTile * d[0] + (lcell & 7);
+    const int by = kTile * d[1] + ((lcell >> 3) & 7);
+    const int bz = kTile * d[2] + (lcell >> 6);
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz) {
+        const int nz = bz + cz;
+        if (nz < 0 || nz >= kTile) continue;
+        const T wz = cz ? e.z : T(1) - e.z;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+            const int ny = by + cy;
+            if (ny < 0 || ny >= kTile) continue;
+            const T wyz = wz * (cy ? e.y : T(1) - e.y);
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int nx = bx + cx;
+                if (nx < 0 || nx >= kTile) continue;
+                const T w = wyz * (cx ? e.x : T(1) - e.x);
+                atomicAdd(&acc[(nz * kTile + ny) * kTile + nx], to_fixed(w, scale, a.fixed_bits));
+            }
+        }
+    }
+}
+
+// U > 1: a lane first loads U binned particles (independent loads in flight), then adds
+// them; most tiles then need one round of loads.
+// TPB tiles per workgroup (256 / TPB lanes each): when particles are sparse relative to
+// nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
+// the bin-range round trip) are shared by several tiles.
+template <typename T, int TPB>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
-    __shared__ unsigned long long acc[512];
-    __shared__ int rstart[27], rpre[28];
-    __shared__ signed char rd[27][3];
+    constexpr int G = kThreads / TPB;           // lanes per tile
+    __shared__ unsigned long long acc[TPB][512];
+    __shared__ int rstart[TPB][27], rpre[TPB][28];
+    __shared__ signed char rd[TPB][27][3];
     const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
     const int n = a.n, nt = n / kTile;
-    const int t = blk - b.map.start[rr];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int t = (blk - b.map.start[rr]) * TPB + g;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
-    for (int k = threadIdx.x; k < 512; k += kThreads) acc[k] = 0ull;
-    tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
+    for (int k = lane; k < 512; k += G) acc[g][k] = 0ull;
+    tile_ranges<T>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane);
     __syncthreads();
-    const int total = rpre[27];
+    const int total = rpre[g][27];
     const double scale = a.scale;
     int r = 0;                                  // idx only grows: the range index too
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-        while (idx >= rpre[r + 1]) ++r;
-        const v4<T> e = a.sorted[rstart[r] + (idx - rpre[r])];
-        int lcell;
-        if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
-        else lcell = (int)e.w;
-        const int bx = kTile * rd[r][0] + (lcell & 7);
-        const int by = kTile * rd[r][1] + ((lcell >> 3) & 7);
-        const int bz = kTile * rd[r][2] + (lcell >> 6);
-#pragma unroll
-        for (int cz = 0; cz < 2; ++cz) {
-            const int nz = bz + cz;
-            if (nz < 0 || nz >= kTile) continue;
-            const T wz = cz ? e.z : T(1) - e.z;
-#pragma unroll
-            for (int cy = 0; cy < 2; ++cy) {
-                const int ny = by + cy;
-                if (ny < 0 || ny >= kTile) continue;
-                const T wyz = wz * (cy ? e.y : T(1) - e.y);
-#pragma unroll
-                for (int cx = 0; cx < 2; ++cx) {
-                    const int nx = bx + cx;
-                    if (nx < 0 || nx >= kTile) continue;
-                    const T w = wyz * (cx ? e.x : T(1) - e.x);
-                    const unsigned long long q = (unsigned long long)llrint((double)w * scale);
-                    atomicAdd(&acc[(nz * kTile + ny) * kTile + nx], q);
-                }
-            }
-        }
+    for (int idx = lane; idx < total; idx += G) {
+        while (idx >= rpre[g][r + 1]) ++r;
+        const v4<T> e = a.sorted[rstart[g][r] + (idx - rpre[g][r])];
+        paint_one<T>(a, acc[g], e, rd[g][r], scale);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < 512; k += kThreads) {
+    for (int k = lane; k < 512; k += G) {
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        st_stream((T)((double)(long long)acc[k] * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
+        st_stream((T)((double)(long long)acc[g][k] * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
 
@@ -450,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void gbar_tiles_kernel(MatterAdj<T> m) {
     const int n = a.n, nt = n / kTile;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     for (int k = threadIdx.x; k < 3 * 512; k += kThreads) acc[k >> 9][k & 511] = 0ull;
-    tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd);
+    tile_ranges<T>(a, tx, ty, tz, rstart, rpre, rd, threadIdx.x);
     __syncthreads();
     const int total = rpre[27];
     const double scale = adj_fixed_scale(m.maxbits, m.hbits);
@@ -535,6 +565,7 @@ void fill_particles(hrt_ctx *c, int r, const hrt_matter &m, Particles<T> &a, dou
     a.K = (T)K;
     a.D = (T)D;
     a.scale = std::ldexp(1.0, re.fixed_bits);
+    a.fixed_bits = re.fixed_bits;
     a.inv_scale_rho = 1.0 / (a.scale * ((double)a.P / ((double)n * n * n)));
 }
 
@@ -585,10 +616,14 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         bin_scatter_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
         prof_end(c, K_BIN_SCATTER);
         prof_begin(c);
-        set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt; });
+        // variant bits: 0 = no XCD grouping, 1 = four tiles per workgroup
+        const int pv = c->variant[K_PAINT];
+        const int tpb = (pv & 2) ? 4 : 1;
+        set_map(b, R, [tpb](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / tpb; });
         b.pmap = 0;
-        b.xcd = c->variant[K_PAINT] == 0 ? 1 : 0;
-        paint_tiles_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
+        b.xcd = (pv & 1) == 0 ? 1 : 0;
+        if (tpb == 4) paint_tiles_kernel<T, 4><<<b.map.start[R], kThreads, 0, st>>>(b);
+        else paint_tiles_kernel<T, 1><<<b.map.start[R], kThreads, 0, st>>>(b);
         prof_end(c, K_PAINT);
     }
     return hipGetLastError();

@@ -123,3 +123,41 @@ def test_large_config_properties():
     # solves: ~6e-8 x 30 x 2 x sqrt(2) x a few ~ 3e-5
     assert float((torch.roll(g0, 2, dims=2) - g1).norm() / g0.norm()) < 5e-5
     torch.cuda.synchronize()
+
+
+def test_lcdm256_every_variant_bit_identical():
+    """At the benchmark size, on a clustered state: every launch-shape variant of every tunable
+    kernel gives results bit-identical to the default shape, and reruns are identical."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    cfg = synth.lcdm256()
+    n, np_, box, M = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
+    say("case lcdm256 variants: inputs")
+    s = synth.clustered_displacements(6, np_, box, n_halos=512)
+    p = synth.random_momenta(6, len(s), 3.0)
+    dth, pr = synth.random_rays(6, M * M, 1e-4, 0.3)
+    dev = lambda a: [torch.tensor(np.ascontiguousarray(a[:, k]), dtype=torch.float32, device="cuda")
+                     for k in range(a.shape[1])]
+    base = [dev(x) for x in (s, p, dth, pr)]
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(cfg["sched"]) - 1, sched=cfg["sched"],
+                         ray_nx=M, ray_ny=M, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
+                         omega_m=cfg["omega_m"], dtype="f32")
+
+    def run():
+        st = [[t.clone() for t in x] for x in base]
+        sim.pm_step(st[0], st[1], 10)
+        delta = sim.mesh(hrt.HRT_MESH_DELTA).clone()
+        sim.ray_step(st[2], st[3], 10)
+        torch.cuda.synchronize()
+        return [delta] + sum(st, [])
+
+    ref = run()
+    for a, b in zip(run(), ref):
+        assert torch.equal(a, b)
+    for name in ("bin_count", "bin_scatter", "paint_tiles", "matter_kd", "ray_step"):
+        for v in range(1, hrt.num_variants(name)):
+            say(f"  {name} = {v}")
+            sim.set_variant(name, v)
+            for a, b in zip(run(), ref):
+                assert torch.equal(a, b), (name, v)
+        sim.set_variant(name, 0)

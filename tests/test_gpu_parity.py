@@ -252,3 +252,28 @@ def test_paint_fractions_at_cell_edges():
     d_o = integrator.density_contrast(integrator.lattice(np_, box) + s, n, box)
     assert d.min() >= -1.0 and abs(d.sum()) < 1e-3
     assert np.max(np.abs(d - d_o) / (1.0 + np.abs(d_o))) < 2e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gpu_time_reversibility(dtype):
+    """N co-evolution steps with the closing half-kick, then the reversed schedule, return the
+    initial matter and ray state (the integrator is symplectic and reversible; App. B).
+    FP32: rounding of the state over 2(N+1) steps, 1e-5 of each quantity's scale; FP64 1e-10."""
+    import torch
+    say(f"case time reversibility {dtype}")
+    cfg = synth.tiny(mesh_n=32, ptcl_n=16, box=40.0, ray_n=16, fov_deg=3.0, n_steps=6)
+    c = Case(cfg, seed=8, dtype=dtype, dth_rms=2e-4)
+    a = np.linspace(1.0, 0.7, 7)
+    s, p = c.dev(c.s), c.dev(c.p)
+    dth, pr = c.dev(c.dth), c.dev(c.pr)
+    init = [t.clone() for t in s + p + dth + pr]
+    fwd, rev = c.sim(sched=a), c.sim(sched=a[::-1].copy())
+    fwd.run(s, p, dth, pr, 0, 7)
+    torch.cuda.synchronize()
+    assert float((s[0] - init[0]).abs().max()) > 0.1
+    rev.run(s, p, dth, pr, 0, 7)
+    torch.cuda.synchronize()
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    for got, ref in zip(s + p + dth + pr, init):
+        scale = float(ref.abs().max())
+        assert float((got - ref).abs().max()) <= tol * scale, (dtype, float((got - ref).abs().max()), scale)

@@ -172,3 +172,36 @@ def test_run_equals_step_by_step():
         outs.append([t for x in st for t in x[0] + x[1] + x[2] + x[3]])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def test_paint_variants_with_dense_tiles():
+    """Tiles holding thousands of particles (several load rounds per lane in every paint
+    shape): all paint variants give the same delta, equal to the oracle's."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    from oracle import integrator
+    say("case paint variants, dense tiles")
+    n, np_, box = 32, 32, 32.0
+    r = np.random.default_rng(23)
+    q = integrator.lattice(np_, box)
+    s = synth.clustered_displacements(23, np_, box, n_halos=4)
+    dense = r.choice(len(q), 12000, replace=False)
+    target = np.array([10.3, 20.7, 5.2]) + r.normal(scale=0.8, size=(12000, 3))
+    s[dense] = target - q[dense]
+    s = s.astype(np.float32).astype(np.float64)
+    cfg = synth.tiny(mesh_n=n, ptcl_n=np_, box=box, ray_n=0, n_steps=4)
+    d_o = integrator.density_contrast(q + s, n, box)
+    dv = [torch.tensor(np.ascontiguousarray(s[:, k]), dtype=torch.float32, device="cuda") for k in range(3)]
+    ref = None
+    for v in range(hrt.num_variants("paint_tiles")):
+        sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=4, sched=cfg["sched"], omega_m=0.3)
+        sim.set_variant("paint_tiles", v)
+        sim.pm_force(dv, 0)
+        d = sim.mesh(hrt.HRT_MESH_DELTA).clone()
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = d
+            dd = d.double().cpu().numpy()
+            assert d_o.max() > 200
+            assert np.max(np.abs(dd - d_o) / (1.0 + np.abs(d_o))) < 2e-5
+        assert torch.equal(d, ref), v
