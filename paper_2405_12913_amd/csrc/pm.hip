@@ -38,14 +38,15 @@ struct Particles {             // one realisation, as the particle kernels see i
 // formed from w's bits (mantissa shifted by its exponent): exact whenever w 2^F is an
 // integer (every w >= 2^(23-F)), rounded half up below that; for double by llrint.
 __device__ __forceinline__ unsigned long long to_fixed(float w, double, int F) {
+    // branch-free: shift left by max(sh, 0), round and shift right by min(max(-sh, 0), 63)
     const unsigned int bits = __float_as_uint(w);
     const int e = (int)(bits >> 23);
-    if (e == 0) return 0ull;                                   // zero (and denormals)
     const unsigned long long m = (bits & 0x7fffffu) | 0x800000u;
     const int sh = e - 150 + F;                                // w 2^F = m 2^sh
-    if (sh >= 0) return m << sh;
-    if (sh < -24) return 0ull;
-    return (m + (1ull << (-sh - 1))) >> -sh;
+    const int ls = sh > 0 ? sh : 0;
+    const int rs = sh < 0 ? (-sh < 63 ? -sh : 63) : 0;
+    const unsigned long long r = ((m << ls) + ((1ull << rs) >> 1)) >> rs;
+    return e == 0 ? 0ull : r;                                  // zero (and denormals)
 }
 __device__ __forceinline__ unsigned long long to_fixed(double w, double scale, int) {
     return (unsigned long long)llrint(w * scale);
@@ -235,7 +236,8 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
     }
 }
 
-// Adds the CIC weights of one binned particle (range r) to the tile's LDS sums.
+// Adds the CIC weights of one binned particle (range r) to the tile's LDS sums; corners
+// outside the tile (the particle comes from a neighbour's face bin) are skipped.
 template <typename T>
 __device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long long *acc, const v4<T> &e,
                                           const signed char *d, double scale) {
@@ -266,8 +268,6 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long l
     }
 }
 
-// U > 1: a lane first loads U binned particles (independent loads in flight), then adds
-// them; most tiles then need one round of loads.
 // TPB tiles per workgroup (256 / TPB lanes each): when particles are sparse relative to
 // nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
 // the bin-range round trip) are shared by several tiles.
