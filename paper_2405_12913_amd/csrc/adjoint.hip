@@ -29,7 +29,7 @@ namespace hrt {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWindow = 1024;      // nodes of a block's LDS window in the ray scatter
+constexpr int kWaveWindow = 256;   // nodes of a wave's LDS window in the ray scatter
 
 template <typename T>
 struct AdjArgs {
@@ -93,19 +93,23 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // One lane per ray. Per plane: the transposed bilinear derivative gathers into dth_bar,
-// and the bilinear weights of w_j p_r_bar go into G_bar. The block's rays fall on a small
-// patch of the plane, so their contributions are first summed in an LDS window over the
-// block's bounding box (integer atomics, exact) and each touched node then receives one
-// global atomic per block; a box larger than the window falls back to direct atomics.
+// and the bilinear weights of w_j p_r_bar go into G_bar. A wave's rays fall on a small patch
+// of the plane, so their contributions are first summed in the wave's own LDS window over
+// the wave's bounding box (integer atomics, exact) and each touched node then receives one
+// global atomic per wave; a box larger than the window falls back to direct atomics. The
+// window is private to the wave, whose LDS operations execute in order, so no workgroup
+// barrier is needed between planes (wave_barrier only keeps the compiler from moving LDS
+// accesses across the phases).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
-    __shared__ unsigned long long win[2][kWindow];
-    __shared__ int box[4][4];
+    __shared__ unsigned long long win[kThreads / 64][2][kWaveWindow];
     const int i = ray_of(a);
     const bool valid = i < a.nrays;
     const double scale = adj_fixed_scale(a.maxbits, a.hbits);
     const int n = a.n, m = n - 1;
     const size_t n3 = (size_t)n * n * n;
+    const int lane = __lane_id();
+    unsigned long long *wx = win[threadIdx.x >> 6][0], *wy = win[threadIdx.x >> 6][1];
     double thx = 0.0, thy = 0.0, ptx = 0.0, pty = 0.0;
     if (valid) {
         const int ix = i % a.mx, iy = i / a.mx;
@@ -115,7 +119,6 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
         pty = a.prb[1][i];
     }
     double tbx = 0.0, tby = 0.0;
-    const int wave = threadIdx.x >> 6;
     for (int e = a.begin; e < a.begin + a.count; ++e) {
         const PlaneEntry pe = a.planes[e];
         int ux = 0, uy = 0;            // unwrapped cell of the ray on this plane
@@ -146,41 +149,31 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
                 q[c][1] = pe.w * cw[c] * pty * scale;
             }
         }
-        // bounding box of the block's cells on this plane
-        const int lox = wave_min(valid ? ux : INT_MAX), loy = wave_min(valid ? uy : INT_MAX);
-        const int hix = wave_max(valid ? ux : INT_MIN), hiy = wave_max(valid ? uy : INT_MIN);
-        if (__lane_id() == 0) {
-            box[wave][0] = lox;
-            box[wave][1] = loy;
-            box[wave][2] = hix;
-            box[wave][3] = hiy;
-        }
-        __syncthreads();
-        const int bx0 = min(min(box[0][0], box[1][0]), min(box[2][0], box[3][0]));
-        const int by0 = min(min(box[0][1], box[1][1]), min(box[2][1], box[3][1]));
-        const int bx1 = max(max(box[0][2], box[1][2]), max(box[2][2], box[3][2]));
-        const int by1 = max(max(box[0][3], box[1][3]), max(box[2][3], box[3][3]));
+        // bounding box of the wave's cells on this plane (uniform over the wave)
+        const int bx0 = wave_min(valid ? ux : INT_MAX), by0 = wave_min(valid ? uy : INT_MAX);
+        const int bx1 = wave_max(valid ? ux : INT_MIN), by1 = wave_max(valid ? uy : INT_MIN);
+        if (bx1 < bx0) continue;                   // no valid ray in this wave
         const long long W = (long long)bx1 - bx0 + 2, H = (long long)by1 - by0 + 2;
-        if (bx1 >= bx0 && W * H <= kWindow) {
+        const size_t base = (size_t)pe.mesh * n * n;
+        if (W * H <= kWaveWindow) {
             const int wn = (int)(W * H);
-            for (int k = threadIdx.x; k < wn; k += kThreads) {
-                win[0][k] = 0ull;
-                win[1][k] = 0ull;
+            for (int k = lane; k < wn; k += 64) {
+                wx[k] = 0ull;
+                wy[k] = 0ull;
             }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
             if (valid) {
                 const int lx = ux - bx0, ly = uy - by0;
                 const int slot[4] = {ly * (int)W + lx, ly * (int)W + lx + 1, (ly + 1) * (int)W + lx,
                                      (ly + 1) * (int)W + lx + 1};
                 for (int c = 0; c < 4; ++c) {
-                    atomicAdd(&win[0][slot[c]], (unsigned long long)llrint(q[c][0]));
-                    atomicAdd(&win[1][slot[c]], (unsigned long long)llrint(q[c][1]));
+                    atomicAdd(&wx[slot[c]], (unsigned long long)llrint(q[c][0]));
+                    atomicAdd(&wy[slot[c]], (unsigned long long)llrint(q[c][1]));
                 }
             }
-            __syncthreads();
-            const size_t base = (size_t)pe.mesh * n * n;
-            for (int k = threadIdx.x; k < wn; k += kThreads) {
-                const unsigned long long vx = win[0][k], vy = win[1][k];
+            __builtin_amdgcn_wave_barrier();
+            for (int k = lane; k < wn; k += 64) {
+                const unsigned long long vx = wx[k], vy = wy[k];
                 if (vx | vy) {
                     const int gx = (bx0 + k % (int)W) & m, gy = (by0 + k / (int)W) & m;
                     const size_t node = base + (size_t)gy * n + gx;
@@ -188,8 +181,8 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
                     if (vy) atomicAdd(a.gbar + n3 + node, vy);
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         } else if (valid) {
-            const size_t base = (size_t)pe.mesh * n * n;
             const int x0 = ux & m, y0 = uy & m, x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
             const size_t id[4] = {base + (size_t)y0 * n + x0, base + (size_t)y0 * n + x1,
                                   base + (size_t)y1 * n + x0, base + (size_t)y1 * n + x1};
@@ -198,7 +191,6 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
                 atomicAdd(a.gbar + n3 + id[c], (unsigned long long)llrint(q[c][1]));
             }
         }
-        __syncthreads();                      // window and box reused by the next plane
     }
     if (valid) {
         a.db[0][i] += (T)tbx;
