@@ -236,6 +236,12 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
     }
 }
 
+// LDS slot of tile node (x, y, z): rows padded to 9 entries and planes to 74, so that nodes
+// with equal (x, y) in different planes (or equal x four rows apart) fall in different
+// LDS banks; particles handled by one wave often sit at such nodes.
+constexpr int kAccPlane = 74, kAccRow = 9, kAccSize = kTile * kAccPlane;
+__device__ __forceinline__ int acc_slot(int x, int y, int z) { return z * kAccPlane + y * kAccRow + x; }
+
 // Adds the CIC weights of one binned particle (range r) to the tile's LDS sums; corners
 // outside the tile (the particle comes from a neighbour's face bin) are skipped.
 template <typename T>
@@ -262,7 +268,7 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long l
                 const int nx = bx + cx;
                 if (nx < 0 || nx >= kTile) continue;
                 const T w = wyz * (cx ? e.x : T(1) - e.x);
-                atomicAdd(&acc[(nz * kTile + ny) * kTile + nx], to_fixed(w, scale, a.fixed_bits));
+                atomicAdd(&acc[acc_slot(nx, ny, nz)], to_fixed(w, scale, a.fixed_bits));
             }
         }
     }
@@ -274,7 +280,7 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long l
 template <typename T, int TPB>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     constexpr int G = kThreads / TPB;           // lanes per tile
-    __shared__ unsigned long long acc[TPB][512];
+    __shared__ unsigned long long acc[TPB][kAccSize];
     __shared__ int rstart[TPB][27], rpre[TPB][28];
     __shared__ signed char rd[TPB][27][3];
     const int blk = logical_block(b.xcd);
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int t = (blk - b.map.start[rr]) * TPB + g;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
-    for (int k = lane; k < 512; k += G) acc[g][k] = 0ull;
+    for (int k = lane; k < kAccSize; k += G) acc[g][k] = 0ull;
     tile_ranges<T>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane);
     __syncthreads();
     const int total = rpre[g][27];
@@ -298,7 +304,8 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     __syncthreads();
     for (int k = lane; k < 512; k += G) {
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        st_stream((T)((double)(long long)acc[g][k] * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
+        const unsigned long long v = acc[g][acc_slot(k & 7, (k >> 3) & 7, k >> 6)];
+        st_stream((T)((double)(long long)v * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
 
