@@ -103,8 +103,15 @@ __device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_sto
 // Launch-shape variants (chosen by the autotuner; every map covers each particle exactly
 // once and the per-particle arithmetic does not depend on it, so results are identical):
 // map 0 = the 16 x 16 patches above, 1 = linear order, 2 = 32 x 8 patches (wave 32 x 2,
-// needs np >= 32). A map a lattice is too small for falls back to linear order.
+// needs np >= 32), 3 = 64 x 4 patches (a wave is one contiguous run of 64 particles, the
+// block's four waves four neighbouring rows; needs np >= 64). A map a lattice is too small
+// for falls back to linear order.
 __device__ __forceinline__ int particle_of(int b, int t, int lnp, int map = 0) {
+    if (map == 3 && lnp >= 6) {
+        const int pbx = 1 << (lnp - 6), pby = 1 << (lnp - 2);
+        const int bx = b & (pbx - 1), by = (b >> (lnp - 6)) & (pby - 1), z = b >> (2 * lnp - 8);
+        return (((z << lnp) + (by << 2) + (t >> 6)) << lnp) + (bx << 6) + (t & 63);
+    }
     if (map == 2 && lnp >= 5) {
         const int pbx = 1 << (lnp - 5), pby = 1 << (lnp - 3);
         const int bx = b & (pbx - 1), by = (b >> (lnp - 5)) & (pby - 1), z = b >> (2 * lnp - 8);

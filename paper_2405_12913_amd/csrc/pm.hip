@@ -585,12 +585,12 @@ void set_map(PartBatch<T> &b, int R, F blocks) {
 
 inline int particle_blocks(int P) { return (P + kThreads - 1) / kThreads; }
 
-// Particle-kernel variant v (0..5): particle map v % 3; v >= 3 flips the kernel's default
+// Particle-kernel variant v (0..7): particle map v % 4; v >= 4 flips the kernel's default
 // XCD block grouping.
 template <typename T>
 void set_variant(PartBatch<T> &b, int v, int default_xcd) {
-    b.pmap = v % 3;
-    b.xcd = (v >= 3) ? 1 - default_xcd : default_xcd;
+    b.pmap = v % 4;
+    b.xcd = (v >= 4) ? 1 - default_xcd : default_xcd;
 }
 
 template <typename T>
@@ -653,9 +653,9 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             fill_counts_kernel<T><<<b.map.start[R], 256, 0, c->stream>>>(b);
         }
         const int v = c->variant[K_MATTER_KD];
-        const int ilp = v >= 6 ? 2 : 1;
+        const int ilp = v >= 8 ? 2 : 1;
         set_map(b, R, [ilp](const Particles<T> &a) { return (particle_blocks(a.P) + ilp - 1) / ilp; });
-        set_variant(b, v % 6, 1);
+        set_variant(b, v % 8, 1);
         if (args.count_next) {
             if (ilp == 2) matter_kd_kernel<T, 2, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
             else matter_kd_kernel<T, 1, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);

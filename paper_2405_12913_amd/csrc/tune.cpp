@@ -25,8 +25,9 @@ using hrt::K_RAY_STEP;
 
 int variants_of(int id) {
     switch (id) {
-        case K_MATTER_KD: return 12;
-        case K_BIN_COUNT: case K_BIN_SCATTER: case K_RAY_STEP: return 6;
+        case K_MATTER_KD: return 16;
+        case K_BIN_COUNT: case K_BIN_SCATTER: return 8;
+        case K_RAY_STEP: return 6;
         case K_PAINT: return 4;
         default: return (id >= 0 && id < K_COUNT) ? 1 : 0;
     }
