@@ -243,10 +243,12 @@ constexpr int kAccPlane = 74, kAccRow = 9, kAccSize = kTile * kAccPlane;
 __device__ __forceinline__ int acc_slot(int x, int y, int z) { return z * kAccPlane + y * kAccRow + x; }
 
 // Adds the CIC weights of one binned particle (range r) to the tile's LDS sums; corners
-// outside the tile (the particle comes from a neighbour's face bin) are skipped.
-template <typename T>
-__device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long long *acc, const v4<T> &e,
-                                          const signed char *d, double scale) {
+// outside the tile (the particle comes from a neighbour's face bin) are skipped. FP32: 32-bit
+// sums with the tile's own scale 2^s (round(w 2^s), one multiply and one conversion);
+// FP64: 64-bit sums with the global scale.
+template <typename T, typename A>
+__device__ __forceinline__ void paint_one(const Particles<T> &a, A *acc, const v4<T> &e,
+                                          const signed char *d, double scale, float fscale) {
     int lcell;
     if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
     else lcell = (int)e.w;
@@ -268,7 +270,10 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long l
                 const int nx = bx + cx;
                 if (nx < 0 || nx >= kTile) continue;
                 const T w = wyz * (cx ? e.x : T(1) - e.x);
-                atomicAdd(&acc[acc_slot(nx, ny, nz)], to_fixed(w, scale, a.fixed_bits));
+                if constexpr (sizeof(A) == 4)
+                    atomicAdd(&acc[acc_slot(nx, ny, nz)], (unsigned int)rintf((float)w * fscale));
+                else
+                    atomicAdd(&acc[acc_slot(nx, ny, nz)], to_fixed(w, scale, a.fixed_bits));
             }
         }
     }
@@ -277,10 +282,16 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, unsigned long l
 // TPB tiles per workgroup (256 / TPB lanes each): when particles are sparse relative to
 // nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
 // the bin-range round trip) are shared by several tiles.
+// FP32 tiles that pull fewer than 1024 particles use 32-bit LDS sums: a node's sum is at
+// most the tile's particle count `total` (weights <= 1), so with 2^s <= 2^31 / (total + 1)
+// (here s = 21..24) no sum overflows, and each weight is rounded to 2^-(s+1) <= 2.4e-7,
+// the size of the FP32 rounding of the cell fractions themselves: half the LDS bytes per
+// atomic and a two-instruction conversion. Denser tiles, and FP64, keep the exact 64-bit
+// sums with the global scale.
 template <typename T, int TPB>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     constexpr int G = kThreads / TPB;           // lanes per tile
-    __shared__ unsigned long long acc[TPB][kAccSize];
+    __shared__ unsigned long long acc[TPB][kAccSize];   // 64-bit sums, or 32-bit in place
     __shared__ int rstart[TPB][27], rpre[TPB][28];
     __shared__ signed char rd[TPB][27][3];
     const int blk = logical_block(b.xcd);
@@ -295,17 +306,26 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     __syncthreads();
     const int total = rpre[g][27];
     const double scale = a.scale;
+    const bool narrow = sizeof(T) == 4 && total < 1024;          // uniform over the group
+    const int bits = total > 0 ? 32 - __clz(total) : 0;          // ceil(log2(total + 1))
+    const int ts = (31 - bits) < 24 ? 31 - bits : 24;            // narrow scale 2^ts
+    const float fscale = ldexpf(1.0f, ts);
+    unsigned int *acc32 = reinterpret_cast<unsigned int *>(acc[g]);
     int r = 0;                                  // idx only grows: the range index too
     for (int idx = lane; idx < total; idx += G) {
         while (idx >= rpre[g][r + 1]) ++r;
         const v4<T> e = a.sorted[rstart[g][r] + (idx - rpre[g][r])];
-        paint_one<T>(a, acc[g], e, rd[g][r], scale);
+        if (narrow) paint_one<T, unsigned int>(a, acc32, e, rd[g][r], scale, fscale);
+        else paint_one<T, unsigned long long>(a, acc[g], e, rd[g][r], scale, fscale);
     }
     __syncthreads();
+    // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
+    const double inv = narrow ? ldexp(a.inv_scale_rho * a.scale, -ts) : a.inv_scale_rho;
     for (int k = lane; k < 512; k += G) {
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        const unsigned long long v = acc[g][acc_slot(k & 7, (k >> 3) & 7, k >> 6)];
-        st_stream((T)((double)(long long)v * a.inv_scale_rho - 1.0), a.delta + ((size_t)z * n + y) * n + x);
+        const int sl = acc_slot(k & 7, (k >> 3) & 7, k >> 6);
+        const double sum = narrow ? (double)acc32[sl] : (double)(long long)acc[g][sl];
+        st_stream((T)(sum * inv - 1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
 
