@@ -69,9 +69,9 @@ def pmc_traffic(kernel):
     return None
 
 
-def algorithmic_bytes(name, n, P, nrays):
+def algorithmic_bytes(name, n, P, nrays, planes=0.0):
     """Compulsory HBM bytes of one launch of kernel `name` (each input read once,
-    each output written once)."""
+    each output written once); `planes`: lens planes per plane_gradient launch."""
     n3 = n ** 3
     spec = (n // 2 + 1) * n * n * 8          # complex64 half spectrum
     nbins = n3 // 64
@@ -89,6 +89,11 @@ def algorithmic_bytes(name, n, P, nrays):
         "matter_kd": 48 * P + 12 * n3,                 # read+write s, p; read G
         "ray_step": 32 * nrays,                        # read+write dth, p
         "convergence": 12 * nrays,                     # read dth, write kappa
+        # sorted-state run (hrt_run): records (s, lattice index) 16 B + momenta 12 B
+        "state_scatter": 28 * P + 28 * P,              # read the state, write it binned
+        "kd_tiles": 28 * P + 28 * P + 4 * n3,          # read+write the state in place; read phi
+        "plane_gradient": int(round((4 + 12) * n * n * planes)),   # phi plane, (G_x, G_y), G_z
+        "state_gather": 28 * P + 24 * P,               # read the state, write s, p
     }[name]
 
 
@@ -417,12 +422,15 @@ def main():
     prof = sim.profile_read()
     sim.profile_enable(False)
 
+    tab = hrt.hrt_tables(hrt.make_config(**sim_kwargs(cfg))[0])
+    plane_launches = int(sum(1 for k in range(N) if tab["plane_count"][k] > 0))
+    planes_per_launch = float(sum(tab["plane_count"][:N])) / max(plane_launches, 1)
     kernels = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        b = algorithmic_bytes(name, n, P, nrays)
+        b = algorithmic_bytes(name, n, P, nrays, planes_per_launch)
         gbps = b / (avg_ms * 1e-3) / 1e9
         kernels[name] = {"launches": cnt, "avg_ms": round(avg_ms, 5), "total_ms": round(ms, 3),
                          "alg_bytes": b, "alg_GBps": round(gbps, 1),
@@ -432,7 +440,8 @@ def main():
         if tb is not None:
             kernels[name]["traffic_GBps"] = round(tb / (avg_ms * 1e-3) / 1e9, 1)
     pm_names = ["bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
-                "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd"]
+                "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd",
+                "state_scatter", "kd_tiles", "plane_gradient", "state_gather"]
     pm_ms = sum(prof[k][0] for k in pm_names) / args.steps
     ray_ms = prof["ray_step"][0] / max(prof["ray_step"][1], 1)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])

@@ -131,10 +131,16 @@ int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *c
 
 /* Runs steps first_step .. first_step+n_steps-1: pm_step then ray_step for every
  * realisation (r may be NULL for matter only); with HRT_STATIC one pm_force then the ray
- * steps (r required). Results are bit-identical to calling pm_step / ray_step step by step;
- * inside the sequence each matter drift also counts the drifted particles into the next
- * step's paint bins, which saves the next paint one pass over the particles, so the state
- * arrays must not be modified by anyone else while the call's work runs. */
+ * steps (r required). Results are bit-identical to calling pm_step / ray_step step by step.
+ * Particle order (variant of kernel id kd_tiles): 2 keeps the particles in paint-bin order
+ * in the workspace from the call's first step to its last: the first step reads the state
+ * arrays, the last writes them back, and each drift counts the particles into the next
+ * step's bins. The force is then formed per 8^3 tile inside the kick-drift and, for the
+ * rays, on the lens planes only, so after such a call the G mesh is incomplete and
+ * ray_step needs a new pm_force / pm_step first. 1 runs pm_step's Lagrangian-order kernels
+ * (with the same fused counting). 0 (default) takes 2 for calls of 8 steps or more and 1
+ * otherwise. Either way the state arrays must not be modified by anyone else while the
+ * call's work runs. */
 int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps);
 
 /* Captures steps first_step .. first_step+n_steps-1 (pm_step then ray_step for every
@@ -226,7 +232,8 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
  * group workgroups per XCD or not; every variant computes bit-identical results and they
  * differ only in speed (matter_kd also has shapes with two particles per lane, paint_tiles
  * shapes that paint four tiles per workgroup). Tunable kernel ids: bin_count, bin_scatter
- * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (4). hrt_num_variants(id) gives the count (1 = not
+ * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (4), kd_tiles (3: the
+ * particle order of hrt_run, see there; not chosen by hrt_autotune). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);
  * hrt_get_variant reads it. A new context starts with variant 0 everywhere. */
 int hrt_num_variants(int kernel_id);
@@ -250,7 +257,7 @@ int hrt_autotune(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int step,
  * clears the totals and starts recording, 0 stops. hrt_profile_read synchronises the
  * stream and writes, for kernel ids 0..n-1, the summed milliseconds and launch counts.
  * hrt_kernel_name(id) names kernel id (NULL past the last id, HRT_NUM_KERNELS). */
-enum { HRT_NUM_KERNELS = 13 };
+enum { HRT_NUM_KERNELS = 17 };
 int hrt_profile_enable(hrt_ctx *ctx, int on);
 int hrt_profile_read(hrt_ctx *ctx, double *total_ms, int64_t *launches, int n);
 const char *hrt_kernel_name(int id);

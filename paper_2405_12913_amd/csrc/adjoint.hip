@@ -44,7 +44,7 @@ struct AdjArgs {
     T *div;                      // phi_bar
     const PlaneEntry *planes;
     int begin, count;
-    int n, lnp, ratio, P, mx, my, nrays;
+    int n, lnp, lratio, P, mx, my, nrays;
     int patch;                   // rays in 16 x 16 pixel patches per block
     int hbits;                   // log2 bound of the contributions per node
     double inv_cell, d, wmax, rho_bar;
@@ -235,7 +235,7 @@ __device__ __forceinline__ void cell_of(const AdjArgs<T> &a, int i, int c[3], do
     const int lat[3] = {i & pmk, (i >> a.lnp) & pmk, i >> (2 * a.lnp)};
     for (int d = 0; d < 3; ++d) {
         T fd;
-        axis_cell<T>(a.s[d][i], lat[d], a.ratio, (T)a.inv_cell, a.n - 1, c[d], fd);
+        axis_cell<T>(a.s[d][i], lat[d], a.lratio, (T)a.inv_cell, a.n - 1, c[d], fd);
         f[d] = fd;
     }
 }
@@ -322,7 +322,7 @@ AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
     a.count = re.tab.plane_count[step];
     a.n = re.n;
     a.lnp = ilog2(re.np);
-    a.ratio = re.n / re.np;
+    a.lratio = ilog2(re.n / re.np);
     a.P = (int)P;
     a.mx = re.mx;
     a.my = re.my;

@@ -39,6 +39,9 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     // reverse mode: 2 x n^3 64-bit fixed-point accumulators (rays' part of the force-mesh
     // cotangent), one 8-byte device scalar (256 bytes reserved) and P x 4 kick weights
     L.adj = (cfg.flags & HRT_ADJOINT) ? take(2 * n3 * 8 + 256 + P * 4 * T) : off;
+    // sorted-state run: the second record buffer (the first is `sorted`) and both momentum
+    // buffers, P x (4 + 3 + 3) values; a static run moves no particles
+    L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * 10 * T);
     L.total = off;
     return L;
 }
@@ -105,7 +108,7 @@ hrt_ctx::~hrt_ctx() {
 static const char *kKernelNames[hrt::K_COUNT] = {
     "bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
     "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd", "ray_step",
-    "convergence"};
+    "convergence", "state_scatter", "kd_tiles", "plane_gradient", "state_gather"};
 
 extern "C" const char *hrt_kernel_name(int id) {
     return (id >= 0 && id < hrt::K_COUNT) ? kKernelNames[id] : nullptr;
@@ -379,15 +382,32 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
             if (int rc = ray_step(c, r, k)) return rc;
         return HRT_OK;
     }
+    // Particle order of the sequence (kd_tiles variant): 1 = Lagrangian order (pm_step's
+    // kernels), 2 = paint-bin order (sorted-state kernels, G formed per tile and on the lens
+    // planes only), 0 = bin order for sequences of kSortedMinSteps steps or more, whose
+    // per-step saving outweighs the one-off cost of entering and leaving the sorted state.
+    // All give the same bits.
+    constexpr int kSortedMinSteps = 8;
+    const int order = c->variant[hrt::K_KD_TILES];
+    const bool sorted = order == 2 || (order == 0 && n >= kSortedMinSteps);
     bool counted = false;
+    int cur = 0;
     for (int k = first; k < first + n; ++k) {
         hrt::StepArgs a;
         a.m = m;
         a.step = k;
         a.counts_ready = counted;
+        if (sorted) {
+            a.state = k == first ? hrt::STATE_FROM_CALLER : hrt::STATE_SORTED;
+            a.cur = cur;
+        }
         if (int rc = check_hip(c, hrt::launch_paint(c, a), "paint")) return rc;
         if (int rc = check_hip(c, hrt::launch_poisson(c), "poisson")) return rc;
-        if (int rc = check_hip(c, hrt::launch_gradient(c), "gradient")) return rc;
+        if (!sorted) {
+            if (int rc = check_hip(c, hrt::launch_gradient(c), "gradient")) return rc;
+        } else if (r) {
+            if (int rc = check_hip(c, hrt::launch_plane_gradient(c, k), "plane gradient")) return rc;
+        }
         c->force_step = k;
         a.counts_ready = false;
         a.count_next = k + 1 < first + n;
@@ -395,6 +415,14 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         counted = a.count_next;
         if (r)
             if (int rc = ray_step(c, r, k)) return rc;
+        cur ^= 1;                        // sorted: the next paint bins into the other buffer
+    }
+    if (sorted) {
+        hrt::StepArgs a;
+        a.m = m;
+        a.cur = cur ^ 1;                 // the buffer the last step moved
+        if (int rc = check_hip(c, hrt::launch_state_gather(c, a), "state gather")) return rc;
+        c->force_step = -1;              // G was formed only on the lens planes
     }
     return HRT_OK;
 }

@@ -26,23 +26,62 @@ __host__ __device__ inline int ilog2(int v) {
     return l;
 }
 
-// Cell index and fraction of particle i along one axis: u = i_lattice * ratio + s / cell.
-// The integer part of s / cell is split off first so the fraction keeps the precision
-// of the displacement rather than of the absolute coordinate. Contraction is off: with
-// t = s * inv_cell fused into t - floor(t), the fraction could come out slightly negative
-// (the exact product just below the integer its rounded value hits), and a negative CIC
-// weight would break the paint's unsigned fixed-point sums.
+// Cell index and fraction of particle i along one axis: u = i_lattice * 2^lratio + s / cell
+// (2^lratio mesh cells per lattice spacing). The integer part of t = s / cell is split off
+// first so the fraction keeps the precision of the displacement rather than of the absolute
+// coordinate. The fraction is the hardware fract of t: t - floor(t), exact, except where t
+// lies so little below an integer that t - floor(t) rounds to 1, and there the largest value
+// below 1 (the particle keeps its cell floor(t) and puts all but 2^-24 (FP32) of its weight
+// on the upper node, where it lies to that precision). So the fraction is always in [0, 1)
+// and the CIC weights f and 1 - f are never negative (the paint's unsigned fixed-point sums
+// rely on it). Contraction is off: t is the rounded product, as in every other use.
+__device__ __forceinline__ float fract_of(float t) { return __builtin_amdgcn_fractf(t); }
+__device__ __forceinline__ double fract_of(double t) { return __builtin_amdgcn_fract(t); }
+
 template <typename T>
-__device__ __forceinline__ void axis_cell(T s, int lattice, int ratio, T inv_cell, int nmask,
+__device__ __forceinline__ void axis_cell(T s, int lattice, int lratio, T inv_cell, int nmask,
                                           int &c, T &f) {
 #pragma clang fp contract(off)
-    T t = s * inv_cell;
-    T fl = floor(t);
-    f = t - fl;
-    c = (lattice * ratio + (int)fl) & nmask;
-    if (f >= T(1)) {          // t just below an integer rounds up: same point, next cell
-        f = T(0);
-        c = (c + 1) & nmask;
+    const T t = s * inv_cell;
+    f = fract_of(t);
+    c = ((lattice << lratio) + (int)floor(t)) & nmask;
+}
+
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Fourth-order central difference of phi along one axis from its values at -2, -1, +1, +2
+// nodes, divided by the cell (inv12cell = 1 / (12 cell)). No contraction: every kernel
+// that forms G (whole mesh, lens planes only, or one tile in LDS) gets the same bits.
+template <typename T>
+__device__ __forceinline__ T fd4(T m2, T m1, T p1, T p2, T inv12cell) {
+#pragma clang fp contract(off)
+    return (T(8) * (p1 - m1) - (p2 - m2)) * inv12cell;
+}
+
+// One particle's CIC readout of G from the 8 corner values g[k] (corner k is offset
+// (k & 1, (k >> 1) & 1, k >> 2) from the particle's cell, f its fractions), then the kick
+// p += K G and the drift s += D p. Explicit FMAs in a fixed order, so the kick-drift
+// kernels of both particle orders move a particle to the same bits.
+template <typename T>
+__device__ __forceinline__ void cic_kick_drift(const T f[3], const v4<T> g[8], T K, T D, T s[3],
+                                               T p[3]) {
+#pragma clang fp contract(off)
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const T wz = (k >> 2) ? f[2] : T(1) - f[2];
+        const T wyz = wz * (((k >> 1) & 1) ? f[1] : T(1) - f[1]);
+        const T w = wyz * ((k & 1) ? f[0] : T(1) - f[0]);
+        gx = fmadd(w, g[k].x, gx);
+        gy = fmadd(w, g[k].y, gy);
+        gz = fmadd(w, g[k].z, gz);
+    }
+    const T gg[3] = {gx, gy, gz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        p[d] = fmadd(K, gg[d], p[d]);
+        s[d] = fmadd(D, p[d], s[d]);
     }
 }
 
@@ -69,8 +108,8 @@ __device__ __forceinline__ int wave_aggregated_increment(unsigned int *counter, 
     int leader_of_mine = lane, rank = 0;
     unsigned int count = 0;
     while (remaining) {
-        const int leader = __ffsll((long long)remaining) - 1;
-        const int lkey = __shfl(key, leader);
+        const int leader = __ffsll((long long)remaining) - 1;             // wave-uniform
+        const int lkey = __builtin_amdgcn_readlane(key, leader);         // no LDS round trip
         const unsigned long long grp = __ballot(key == lkey);
         if (key == lkey) {
             leader_of_mine = leader;

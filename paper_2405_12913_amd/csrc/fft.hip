@@ -306,16 +306,53 @@ __global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(GradBatch<T> b) 
     auto at = [&](int xx, int yy, int zz) {
         return phi[(((size_t)(zz & m) * n + (yy & m)) * n) + (xx & m)];
     };
-    const T dx = T(8) * (phi[row + ((x + 1) & m)] - phi[row + ((x - 1) & m)]) -
-                 (phi[row + ((x + 2) & m)] - phi[row + ((x - 2) & m)]);
-    const T dy = T(8) * (at(x, y + 1, z) - at(x, y - 1, z)) - (at(x, y + 2, z) - at(x, y - 2, z));
-    const T dz = T(8) * (at(x, y, z + 1) - at(x, y, z - 1)) - (at(x, y, z + 2) - at(x, y, z - 2));
     v4<T> out;
-    out.x = dx * a.inv12cell;
-    out.y = dy * a.inv12cell;
-    out.z = dz * a.inv12cell;
+    out.x = fd4<T>(phi[row + ((x - 2) & m)], phi[row + ((x - 1) & m)], phi[row + ((x + 1) & m)],
+                   phi[row + ((x + 2) & m)], a.inv12cell);
+    out.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), a.inv12cell);
+    out.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), a.inv12cell);
     out.w = T(0);
     a.g[idx] = out;
+}
+
+// G on the lens planes of one step only (the sorted-state run forms G tile by tile inside
+// the kick-drift and keeps no G mesh): entry e of the step's plane list, one lane per node
+// of mesh plane z = planes[e].mesh, with the same differences as fd4_gradient_kernel.
+// Entries that share a mesh plane write the same values.
+template <typename T>
+struct PlaneGradR {
+    const T *phi;
+    v4<T> *g;
+    const PlaneEntry *planes;
+    int n, log2n, begin, count;
+    T inv12cell;
+};
+template <typename T>
+struct PlaneGradBatch {
+    BlockMap map;
+    PlaneGradR<T> r[kMaxBatch];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void plane_gradient_kernel(PlaneGradBatch<T> b) {
+    const int r = real_of(b.map, blockIdx.x);
+    const PlaneGradR<T> &a = b.r[r];
+    const int n = a.n, log2n = a.log2n, m = n - 1;
+    const int64_t idx = (int64_t)(blockIdx.x - b.map.start[r]) * kThreads + threadIdx.x;
+    const int e = (int)(idx >> (2 * log2n));
+    if (e >= a.count) return;
+    const int z = a.planes[a.begin + e].mesh;
+    const int x = (int)(idx & m), y = (int)((idx >> log2n) & m);
+    const T *__restrict__ phi = a.phi;
+    auto at = [&](int xx, int yy, int zz) {
+        return phi[(((size_t)(zz & m) * n + (yy & m)) * n) + (xx & m)];
+    };
+    v4<T> out;
+    out.x = fd4<T>(at(x - 2, y, z), at(x - 1, y, z), at(x + 1, y, z), at(x + 2, y, z), a.inv12cell);
+    out.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), a.inv12cell);
+    out.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), a.inv12cell);
+    out.w = T(0);
+    a.g[((size_t)z * n + y) * n + x] = out;
 }
 
 template <typename T, int N>
@@ -420,6 +457,37 @@ hipError_t gradient_impl(hrt_ctx *c) {
         prof_begin(c);
         fd4_gradient_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         prof_end(c, K_GRADIENT);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t plane_gradient_impl(hrt_ctx *c, int step) {
+    const int nre = (int)c->re.size();
+    for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
+        const int R = std::min(kMaxBatch, nre - r0);
+        PlaneGradBatch<T> b{};
+        b.map.R = R;
+        b.map.start[0] = 0;
+        for (int k = 0; k < R; ++k) {
+            const Real &re = c->re[r0 + k];
+            const size_t n3 = (size_t)re.n * re.n * re.n;
+            PlaneGradR<T> &a = b.r[k];
+            a.phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + n3;
+            a.g = reinterpret_cast<v4<T> *>(re.ws + re.lay.grad);
+            a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
+            a.n = re.n;
+            a.log2n = ilog2(re.n);
+            a.begin = re.tab.plane_begin[step];
+            a.count = re.tab.plane_count[step];
+            a.inv12cell = (T)(1.0 / (12.0 * re.cell));
+            const int64_t nodes = (int64_t)a.count * re.n * re.n;
+            b.map.start[k + 1] = b.map.start[k] + (int)((nodes + kThreads - 1) / kThreads);
+        }
+        if (b.map.start[R] == 0) continue;
+        prof_begin(c);
+        plane_gradient_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        prof_end(c, K_PLANE_GRADIENT);
     }
     return hipGetLastError();
 }
@@ -722,6 +790,10 @@ hipError_t launch_ic_vjp(hrt_ctx *c, int r, const void *noise, const IcParams &p
 
 hipError_t launch_gradient(hrt_ctx *c) {
     return c->f64 ? gradient_impl<double>(c) : gradient_impl<float>(c);
+}
+
+hipError_t launch_plane_gradient(hrt_ctx *c, int step) {
+    return c->f64 ? plane_gradient_impl<double>(c, step) : plane_gradient_impl<float>(c, step);
 }
 
 }  // namespace hrt

@@ -45,7 +45,7 @@ struct PlaneEntry {
 
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
-    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, total;
+    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, total;
     int64_t nbins;
 };
 Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
@@ -53,7 +53,8 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
 // Kernel ids for the optional per-kernel HIP-event timing (hrt_profile_*).
 enum KernelId {
     K_BIN_COUNT = 0, K_BIN_SCAN, K_BIN_SCATTER, K_PAINT, K_FFT_X_R2C, K_FFT_Y_FWD, K_FFT_Z_POISSON,
-    K_FFT_Y_INV, K_FFT_X_C2R, K_GRADIENT, K_MATTER_KD, K_RAY_STEP, K_CONVERGENCE, K_COUNT
+    K_FFT_Y_INV, K_FFT_X_C2R, K_GRADIENT, K_MATTER_KD, K_RAY_STEP, K_CONVERGENCE,
+    K_STATE_SCATTER, K_KD_TILES, K_PLANE_GRADIENT, K_STATE_GATHER, K_COUNT
 };
 struct ProfRecord {
     int id;
@@ -89,7 +90,14 @@ struct StepArgs {
     // particles into the paint bins of the next step, whose paint then skips its own count.
     bool count_next = false;     // launch_matter_kd: zero the counts, count the new positions
     bool counts_ready = false;   // launch_paint: the counts already hold these positions
+    // Where the particle kernels find the state (hrt_run keeps it in paint-bin order between
+    // its first and last step). The paint bins it into sorted-state buffer `cur` from the
+    // caller's arrays (STATE_FROM_CALLER) or from buffer 1 - cur (STATE_SORTED); the
+    // kick-drift then works on buffer cur in place.
+    int state = 0;               // STATE_LAGRANGIAN, STATE_FROM_CALLER or STATE_SORTED
+    int cur = 0;
 };
+enum { STATE_LAGRANGIAN = 0, STATE_FROM_CALLER = 1, STATE_SORTED = 2 };
 
 // Blocks of realisation r are [start[r], start[r+1]); start[R] is the grid size.
 struct BlockMap {
@@ -129,6 +137,8 @@ void prof_end(hrt_ctx *c, int id);     // record the stop event of kernel `id`
 hipError_t launch_paint(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_poisson(hrt_ctx *c);
 hipError_t launch_gradient(hrt_ctx *c);
+hipError_t launch_plane_gradient(hrt_ctx *c, int step);      // G on the step's lens planes
+hipError_t launch_state_gather(hrt_ctx *c, const StepArgs &a);   // sorted state -> caller
 hipError_t launch_matter_kd(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a);

@@ -28,8 +28,11 @@ struct Particles {             // one realisation, as the particle kernels see i
     v4<T> *sorted;
     const v4<T> *grad;
     T *delta;
-    int n, lnp, ratio, P, nbins, nblk;
-    T inv_cell, K, D;
+    v4<T> *rec[2];             // sorted-state run: records (s_x, s_y, s_z, lattice index)
+    T *mom[2];                 //   and momenta (3 x P, axis-major), two buffers in turn
+    const T *phi;
+    int n, lnp, lratio, lnt, P, nbins, nblk;   // lnt = log2(n / 8)
+    T inv_cell, K, D, inv12cell;
     double scale, inv_scale_rho;
     int fixed_bits;            // scale = 2^fixed_bits
 };
@@ -40,7 +43,7 @@ struct Particles {             // one realisation, as the particle kernels see i
 __device__ __forceinline__ unsigned long long to_fixed(float w, double, int F) {
     // branch-free: shift left by max(sh, 0), round and shift right by min(max(-sh, 0), 63)
     const unsigned int bits = __float_as_uint(w);
-    const int e = (int)(bits >> 23);
+    const int e = (int)((bits >> 23) & 0xffu);                 // sign dropped: -0 gives 0
     const unsigned long long m = (bits & 0x7fffffu) | 0x800000u;
     const int sh = e - 150 + F;                                // w 2^F = m 2^sh
     const int ls = sh > 0 ? sh : 0;
@@ -58,6 +61,7 @@ struct PartBatch {
     Particles<T> r[kMaxBatch];
     int pmap, xcd;             // launch-shape variant: particle map, XCD block grouping
 };
+static_assert(sizeof(PartBatch<double>) <= 4096, "kernel argument block over 4 KB");
 
 // np is a power of two (it divides the power-of-two mesh size): lattice indices by shifts.
 template <typename T>
@@ -68,13 +72,51 @@ __device__ __forceinline__ void particle_cell(const Particles<T> &a, int i, int 
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         sv[d] = ld_stream(a.s[d] + i);
-        axis_cell<T>(sv[d], lat[d], a.ratio, a.inv_cell, a.n - 1, c[d], f[d]);
+        axis_cell<T>(sv[d], lat[d], a.lratio, a.inv_cell, a.n - 1, c[d], f[d]);
     }
 }
 
-__device__ __forceinline__ int bin_key(const int c[3], int nt) {
+// Sorted-state records (hrt_run): (s_x, s_y, s_z, lattice index), the index stored as the
+// float's bits (FP32) or as an exact double (FP64).
+template <typename T>
+__device__ __forceinline__ int rec_index(const v4<T> &r) {
+    if constexpr (sizeof(T) == 4) return __float_as_int(r.w);
+    else return (int)r.w;
+}
+
+template <typename T>
+__device__ __forceinline__ T index_field(int i) {
+    if constexpr (sizeof(T) == 4) return __int_as_float(i);
+    else return (T)i;
+}
+
+// What a particle's cell needs, copied out of the kernel arguments once so that loops keep
+// it in registers (the compiler reloads argument fields after every global store).
+template <typename T>
+struct CellGeom {
+    int lnp, lratio, nmask;
+    T inv_cell;
+};
+template <typename T>
+__device__ __forceinline__ CellGeom<T> geom_of(const Particles<T> &a) {
+    return CellGeom<T>{a.lnp, a.lratio, a.n - 1, a.inv_cell};
+}
+
+// Cell and fraction of a record, exactly as particle_cell forms them from s and i.
+template <typename T>
+__device__ __forceinline__ void record_cell(const CellGeom<T> &g, const v4<T> &rec, int c[3], T f[3]) {
+    const int i = rec_index<T>(rec), pm = (1 << g.lnp) - 1;
+    const int lat[3] = {i & pm, (i >> g.lnp) & pm, i >> (2 * g.lnp)};
+    axis_cell<T>(rec.x, lat[0], g.lratio, g.inv_cell, g.nmask, c[0], f[0]);
+    axis_cell<T>(rec.y, lat[1], g.lratio, g.inv_cell, g.nmask, c[1], f[1]);
+    axis_cell<T>(rec.z, lat[2], g.lratio, g.inv_cell, g.nmask, c[2], f[2]);
+}
+
+// Bin of a particle in cell c: its 8^3 tile ((n/8)^3 = 2^(3 lnt) tiles, x fastest) times 8
+// plus the mask of the tile's upper faces that its cell touches.
+__device__ __forceinline__ int bin_key(const int c[3], int lnt) {
     const int mask = ((c[0] & 7) == 7) | (((c[1] & 7) == 7) << 1) | (((c[2] & 7) == 7) << 2);
-    return (((c[2] >> 3) * nt + (c[1] >> 3)) * nt + (c[0] >> 3)) * 8 + mask;
+    return (((((c[2] >> 3) << lnt) + (c[1] >> 3)) << lnt) + (c[0] >> 3)) * 8 + mask;
 }
 
 template <typename T>
@@ -96,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void bin_count_kernel(PartBatch<T> b) {
         int c[3];
         T f[3], sv[3];
         particle_cell<T>(a, i, c, f, sv);
-        key = bin_key(c, a.n / kTile);
+        key = bin_key(c, a.lnt);
     }
     wave_aggregated_increment<false>(a.count, key);
 }
@@ -112,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(PartBatch<T> b) {
     T f[3] = {0, 0, 0}, sv[3];
     if (i < a.P) {
         particle_cell<T>(a, i, c, f, sv);
-        key = bin_key(c, a.n / kTile);
+        key = bin_key(c, a.lnt);
     }
     const int slot = wave_aggregated_increment<true>(a.cursor, key);
     if (i < a.P) {
@@ -202,8 +244,10 @@ __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
 // The 27 bin ranges whose particles reach tile (tx, ty, tz): the tile's own 8 bins and
 // the upper-face bins of its 7 lower neighbours (a neighbour displaced by -1 along some
 // axes contributes the bins whose face mask has those axes set). Computed in parallel by
-// threads 0..26 of the block, then prefix-summed: range r starts at sorted index
-// rstart[r], the ranges' prefix sizes are rpre[0..27], rd[r] is the neighbour's offset.
+// lanes 0..26 of the group's first wave and prefix-summed across the wave (visible after
+// the caller's barrier): range r starts at sorted index rstart[r], the ranges' prefix sizes
+// are rpre[0..27], rd[r] is the neighbour's offset. Each group's arrays are padded to 32
+// entries and 16-byte aligned, so no access to one group's entries touches another's.
 // The order of the ranges only changes the order of the integer sums, not their value.
 __constant__ signed char kRangeTab[27][4] = {
     {0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0, 0, 3}, {0, 0, 0, 4}, {0, 0, 0, 5},
@@ -217,23 +261,28 @@ __constant__ signed char kRangeTab[27][4] = {
 template <typename T>
 __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int ty, int tz, int *rstart,
                                             int *rpre, signed char (*rd)[3], int k) {
+    if (k >= 64) return;                        // the group's first wave does it all
     const int nt = a.n / kTile;
+    int size = 0;
     if (k < 27) {
         const int dx = kRangeTab[k][0], dy = kRangeTab[k][1], dz = kRangeTab[k][2];
         const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt + ((tx + dx) & (nt - 1)));
         const int bb = tn * 8 + kRangeTab[k][3];
         const unsigned int o0 = a.offs[bb], o1 = a.offs[bb + 1];
         rstart[k] = (int)o0;
-        rpre[k + 1] = (int)(o1 - o0);           // size; prefix-summed below
+        size = (int)(o1 - o0);
         rd[k][0] = (signed char)dx;
         rd[k][1] = (signed char)dy;
         rd[k][2] = (signed char)dz;
     }
-    __syncthreads();
-    if (k == 0) {
-        rpre[0] = 0;
-        for (int r = 1; r <= 27; ++r) rpre[r] += rpre[r - 1];
+    int incl = size;                            // inclusive prefix over the wave's lanes
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (k >= off) incl += v;
     }
+    if (k < 27) rpre[k + 1] = incl;
+    if (k == 0) rpre[0] = 0;
 }
 
 // LDS slot of tile node (x, y, z): rows padded to 9 entries and planes to 74, so that nodes
@@ -245,10 +294,12 @@ __device__ __forceinline__ int acc_slot(int x, int y, int z) { return z * kAccPl
 // Adds the CIC weights of one binned particle (range r) to the tile's LDS sums; corners
 // outside the tile (the particle comes from a neighbour's face bin) are skipped. FP32: 32-bit
 // sums with the tile's own scale 2^s (round(w 2^s), one multiply and one conversion);
-// FP64: 64-bit sums with the global scale.
+// FP64: 64-bit sums with the global scale. No contraction, so every instantiation of the
+// paint kernel forms the same weights.
 template <typename T, typename A>
-__device__ __forceinline__ void paint_one(const Particles<T> &a, A *acc, const v4<T> &e,
+__device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e,
                                           const signed char *d, double scale, float fscale) {
+#pragma clang fp contract(off)
     int lcell;
     if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
     else lcell = (int)e.w;
@@ -273,7 +324,7 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, A *acc, const v
                 if constexpr (sizeof(A) == 4)
                     atomicAdd(&acc[acc_slot(nx, ny, nz)], (unsigned int)rintf((float)w * fscale));
                 else
-                    atomicAdd(&acc[acc_slot(nx, ny, nz)], to_fixed(w, scale, a.fixed_bits));
+                    atomicAdd(&acc[acc_slot(nx, ny, nz)], to_fixed(w, scale, fixed_bits));
             }
         }
     }
@@ -288,12 +339,15 @@ __device__ __forceinline__ void paint_one(const Particles<T> &a, A *acc, const v
 // the size of the FP32 rounding of the cell fractions themselves: half the LDS bytes per
 // atomic and a two-instruction conversion. Denser tiles, and FP64, keep the exact 64-bit
 // sums with the global scale.
-template <typename T, int TPB>
-__global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
+// SORTED: the particles are sorted-state records (buffer cur) rather than the binned
+// (fraction, local cell) entries of the Lagrangian-order scatter.
+template <typename T, int TPB, bool SORTED>
+__global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, int cur) {
     constexpr int G = kThreads / TPB;           // lanes per tile
     __shared__ unsigned long long acc[TPB][kAccSize];   // 64-bit sums, or 32-bit in place
-    __shared__ int rstart[TPB][27], rpre[TPB][28];
-    __shared__ signed char rd[TPB][27][3];
+    __shared__ __align__(16) int rstart[TPB][32];
+    __shared__ __align__(16) int rpre[TPB][32];
+    __shared__ __align__(16) signed char rd[TPB][32][3];
     const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
@@ -311,12 +365,24 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
     const int ts = (31 - bits) < 24 ? 31 - bits : 24;            // narrow scale 2^ts
     const float fscale = ldexpf(1.0f, ts);
     unsigned int *acc32 = reinterpret_cast<unsigned int *>(acc[g]);
+    const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
+    const CellGeom<T> cg = geom_of(a);
+    const int fixed_bits = a.fixed_bits;
     int r = 0;                                  // idx only grows: the range index too
     for (int idx = lane; idx < total; idx += G) {
         while (idx >= rpre[g][r + 1]) ++r;
-        const v4<T> e = a.sorted[rstart[g][r] + (idx - rpre[g][r])];
-        if (narrow) paint_one<T, unsigned int>(a, acc32, e, rd[g][r], scale, fscale);
-        else paint_one<T, unsigned long long>(a, acc[g], e, rd[g][r], scale, fscale);
+        v4<T> e = src[rstart[g][r] + (idx - rpre[g][r])];
+        if constexpr (SORTED) {                 // record -> (fractions, local cell)
+            int c[3];
+            T f[3];
+            record_cell<T>(cg, e, c, f);
+            e.x = f[0];
+            e.y = f[1];
+            e.z = f[2];
+            e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
+        }
+        if (narrow) paint_one<T, unsigned int>(fixed_bits, acc32, e, rd[g][r], scale, fscale);
+        else paint_one<T, unsigned long long>(fixed_bits, acc[g], e, rd[g][r], scale, fscale);
     }
     __syncthreads();
     // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
@@ -325,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b) {
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
         const int sl = acc_slot(k & 7, (k >> 3) & 7, k >> 6);
         const double sum = narrow ? (double)acc32[sl] : (double)(long long)acc[g][sl];
-        st_stream((T)(sum * inv - 1.0), a.delta + ((size_t)z * n + y) * n + x);
+        st_stream((T)fmadd(sum, inv, -1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
 
@@ -366,22 +432,10 @@ __global__ __launch_bounds__(kThreads) void matter_kd_kernel(PartBatch<T> b) {
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
         if (idx[j] >= a.P) continue;
-        T gx = 0, gy = 0, gzz = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const T wz = (k >> 2) ? f[j][2] : T(1) - f[j][2];
-            const T wyz = wz * (((k >> 1) & 1) ? f[j][1] : T(1) - f[j][1]);
-            const T w = wyz * ((k & 1) ? f[j][0] : T(1) - f[j][0]);
-            gx += w * g[j][k].x;
-            gy += w * g[j][k].y;
-            gzz += w * g[j][k].z;
-        }
-        const T gg[3] = {gx, gy, gzz};
+        cic_kick_drift<T>(f[j], g[j], a.K, a.D, sv[j], pv[j]);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const T pn = pv[j][d] + a.K * gg[d];
-            st_stream(pn, a.p[d] + idx[j]);
-            sv[j][d] = sv[j][d] + a.D * pn;
+            st_stream(pv[j][d], a.p[d] + idx[j]);
             st_stream(sv[j][d], a.s[d] + idx[j]);
         }
     }
@@ -395,12 +449,187 @@ __global__ __launch_bounds__(kThreads) void matter_kd_kernel(PartBatch<T> b) {
                 int cn[3];
                 T fn;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) axis_cell<T>(sv[j][d], lat[d], a.ratio, a.inv_cell, a.n - 1, cn[d], fn);
-                key = bin_key(cn, a.n / kTile);
+                for (int d = 0; d < 3; ++d) axis_cell<T>(sv[j][d], lat[d], a.lratio, a.inv_cell, a.n - 1, cn[d], fn);
+                key = bin_key(cn, a.lnt);
             }
             wave_aggregated_increment<false>(a.count, key);
         }
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Sorted-state run (hrt_run). From the first to the last step of a call the particles are
+// kept in paint-bin order, as records (s_x, s_y, s_z, lattice index) plus momenta (3 x P,
+// axis-major) in two buffers used in turn:
+//   state_scatter  moves the state from the caller's arrays (first step) or from the other
+//                  buffer into the bins of its current positions (counts and scan as for
+//                  the paint; the order inside a bin is that of the atomics, and no result
+//                  depends on it)
+//   paint_tiles    reads the records directly (cell and fraction recomputed per particle)
+//   kd_tiles       one workgroup per 8^3 tile forms G at the tile's 9^3 corner nodes from a
+//                  block of phi in LDS (the differences of the mesh pass) and moves the
+//                  tile's particles in place, reading G from LDS; it also counts the moved
+//                  particles into the next step's bins
+//   state_gather   writes the state back into the caller's arrays at the end.
+// A particle's arithmetic (cell, fraction, readout, kick, drift) is the one of the
+// Lagrangian-order kernels, so both orders give the same bits. The gain: every particle
+// access streams, and G never goes through HBM (only phi, read once per tile with halos).
+// (Moving each particle straight into its next bin from the kick-drift, after a counting
+// pass, was measured slower at 256^3: the counting pass costs most of a kick-drift.)
+
+// FROM_CALLER: thread (block, lane) takes particle particle_of(...) of the caller's arrays;
+// otherwise sorted slot j of buffer 1 - dst. Writes into buffer dst at the bin cursor.
+template <typename T, bool FROM_CALLER>
+__global__ __launch_bounds__(kThreads) void state_scatter_kernel(PartBatch<T> b, int dst) {
+    const int blk = FROM_CALLER ? logical_block(b.xcd) : (int)blockIdx.x;
+    const int r = real_of(b.map, blk);
+    const Particles<T> &a = b.r[r];
+    const size_t P = (size_t)a.P;
+    const int i = FROM_CALLER ? particle_of(blk - b.map.start[r], threadIdx.x, a.lnp, b.pmap)
+                              : (blk - b.map.start[r]) * kThreads + (int)threadIdx.x;
+    int key = -1;
+    v4<T> rec;
+    T pv[3];
+    if (i < a.P) {
+        if (FROM_CALLER) {
+            rec.x = ld_stream(a.s[0] + i);
+            rec.y = ld_stream(a.s[1] + i);
+            rec.z = ld_stream(a.s[2] + i);
+            rec.w = index_field<T>(i);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pv[d] = ld_stream(a.p[d] + i);
+        } else {
+            rec = a.rec[1 - dst][i];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pv[d] = ld_stream(a.mom[1 - dst] + d * P + i);
+        }
+        int c[3];
+        T f[3];
+        record_cell<T>(geom_of(a), rec, c, f);
+        key = bin_key(c, a.lnt);
+    }
+    const int slot = wave_aggregated_increment<true>(a.cursor, key);
+    if (i < a.P) {
+        a.rec[dst][slot] = rec;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.mom[dst][d * P + slot] = pv[d];
+    }
+}
+
+// phi block of one tile in LDS: x from x0 - 4 (16 values: four aligned quadruples), y and z
+// from y0 - 2 and z0 - 2 (13 values), periodic. G is needed at the 9^3 nodes x0..x0+8 (a
+// cell's upper corners reach the next tile's first node), fd4 reaches 2 nodes further.
+constexpr int kPhiX = 16, kPhiYZ = 13, kGN = 9;
+
+// With COUNT the moved particle is also counted into its bin for the next step.
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int cur) {
+    __shared__ v4<T> ph4[kPhiYZ * kPhiYZ * (kPhiX / 4)];
+    __shared__ v4<T> gl[kGN * kGN * kGN];
+    const int blk = logical_block(b.xcd);
+    const int rr = real_of(b.map, blk);
+    const Particles<T> &a = b.r[rr];
+    const int n = a.n, nt = n / kTile, m = n - 1;
+    const size_t P = (size_t)a.P;
+    const int t = blk - b.map.start[rr];
+    const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+    const int j0 = (int)a.offs[t * 8], j1 = (int)a.offs[t * 8 + 8];
+    if (j0 == j1) return;                       // empty tile (uniform over the block)
+    v4<T> *const recs = a.rec[cur];
+    T *const mom = a.mom[cur];
+    // A lane handles two particles per trip (j and j + 256). The first trip's state is
+    // requested before the phi block, so those loads overlap the G set-up; every later trip
+    // requests the next one's before working on its own.
+    struct Item {
+        v4<T> rec;
+        T p[3];
+    };
+    auto fetch = [&](int j, Item &it) {
+        if (j < j1) {
+            it.rec = recs[j];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) it.p[d] = ld_stream(mom + d * P + j);
+        }
+    };
+    Item cur0, cur1;
+    fetch(j0 + (int)threadIdx.x, cur0);
+    fetch(j0 + kThreads + (int)threadIdx.x, cur1);
+    for (int e = threadIdx.x; e < kPhiYZ * kPhiYZ * (kPhiX / 4); e += kThreads) {
+        const int q = e & 3, row = e >> 2, ly = row % kPhiYZ, lz = row / kPhiYZ;
+        const int gx = (tx * kTile - 4 + 4 * q) & m;
+        const int gy = (ty * kTile - 2 + ly) & m, gz = (tz * kTile - 2 + lz) & m;
+        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + ((size_t)gz * n + gy) * n + gx);
+    }
+    __syncthreads();
+    const T *ph = reinterpret_cast<const T *>(ph4);
+    auto at = [&](int x, int y, int z) { return ph[(z * kPhiYZ + y) * kPhiX + x]; };
+    for (int e = threadIdx.x; e < kGN * kGN * kGN; e += kThreads) {
+        const int x = e % kGN + 4, y = (e / kGN) % kGN + 2, z = e / (kGN * kGN) + 2;
+        v4<T> o;
+        o.x = fd4<T>(at(x - 2, y, z), at(x - 1, y, z), at(x + 1, y, z), at(x + 2, y, z), a.inv12cell);
+        o.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), a.inv12cell);
+        o.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), a.inv12cell);
+        o.w = T(0);
+        gl[e] = o;
+    }
+    __syncthreads();
+    unsigned int *const count = a.count;
+    const T K = a.K, D = a.D;
+    const CellGeom<T> cg = geom_of(a);
+    const int lnt = a.lnt;
+    auto move = [&](int j, Item &it) {
+        int key = -1;
+        if (j < j1) {
+            v4<T> rec = it.rec;
+            int c[3];
+            T f[3];
+            record_cell<T>(cg, rec, c, f);
+            const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGN + (c[0] & 7);
+            v4<T> g[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGN + (k & 1)];
+            T sv[3] = {rec.x, rec.y, rec.z};
+            cic_kick_drift<T>(f, g, K, D, sv, it.p);
+            rec.x = sv[0];
+            rec.y = sv[1];
+            rec.z = sv[2];
+            asm volatile("" : "+v"(rec.w));     // store the whole record: no partial lines
+            recs[j] = rec;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom + d * P + j);
+            if (COUNT) {
+                record_cell<T>(cg, rec, c, f);
+                key = bin_key(c, lnt);
+            }
+        }
+        if (COUNT) wave_aggregated_increment<false>(count, key);
+    };
+    for (int base = j0; base < j1; base += 2 * kThreads) {   // same trip count for every lane
+        Item nxt0, nxt1;
+        fetch(base + 2 * kThreads + (int)threadIdx.x, nxt0);
+        fetch(base + 3 * kThreads + (int)threadIdx.x, nxt1);
+        move(base + (int)threadIdx.x, cur0);
+        move(base + kThreads + (int)threadIdx.x, cur1);
+        cur0 = nxt0;
+        cur1 = nxt1;
+    }
+}
+
+// Sorted slot j of buffer cur back to the caller's arrays at the record's lattice index.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void state_gather_kernel(PartBatch<T> b, int cur) {
+    const int r = real_of(b.map, blockIdx.x);
+    const Particles<T> &a = b.r[r];
+    const size_t P = (size_t)a.P;
+    const int j = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
+    if (j >= a.P) return;
+    const v4<T> rec = a.rec[cur][j];
+    const int i = rec_index<T>(rec);
+    a.s[0][i] = rec.x;
+    a.s[1][i] = rec.y;
+    a.s[2][i] = rec.z;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.p[d][i] = ld_stream(a.mom[cur] + d * P + j);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -436,7 +665,7 @@ __global__ __launch_bounds__(kThreads) void matter_vjp_kernel(MatterAdj<T> m) {
     double big = 0.0;
     if (i < a.P) {
         particle_cell<T>(a, i, c, f, sv);
-        key = bin_key(c, a.n / kTile);
+        key = bin_key(c, a.lnt);
         T pt[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) pt[d] = m.pb[d][i] + (T)m.D * m.sb[d][i];
@@ -500,8 +729,9 @@ __global__ __launch_bounds__(256) void cursor_reset_kernel(MatterAdj<T> m) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gbar_tiles_kernel(MatterAdj<T> m) {
     __shared__ unsigned long long acc[3][512];
-    __shared__ int rstart[27], rpre[28];
-    __shared__ signed char rd[27][3];
+    __shared__ __align__(16) int rstart[32];
+    __shared__ __align__(16) int rpre[32];
+    __shared__ __align__(16) signed char rd[32][3];
     const Particles<T> &a = m.a;
     const int t = xcd_block(gridDim.x);
     const int n = a.n, nt = n / kTile;
@@ -584,7 +814,8 @@ void fill_particles(hrt_ctx *c, int r, const hrt_matter &m, Particles<T> &a, dou
     a.delta = reinterpret_cast<T *>(re.ws + re.lay.mesh_r);
     a.n = n;
     a.lnp = ilog2(np);
-    a.ratio = n / np;
+    a.lratio = ilog2(n / np);
+    a.lnt = ilog2(n / kTile);
     a.P = np * np * np;
     a.nbins = (int)re.lay.nbins;
     a.nblk = (int)((re.lay.nbins + 1023) / 1024);
@@ -594,6 +825,12 @@ void fill_particles(hrt_ctx *c, int r, const hrt_matter &m, Particles<T> &a, dou
     a.scale = std::ldexp(1.0, re.fixed_bits);
     a.fixed_bits = re.fixed_bits;
     a.inv_scale_rho = 1.0 / (a.scale * ((double)a.P / ((double)n * n * n)));
+    a.inv12cell = (T)(1.0 / (12.0 * re.cell));
+    a.phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + (size_t)n * n * n;
+    a.rec[0] = a.sorted;
+    a.rec[1] = re.lay.state ? reinterpret_cast<v4<T> *>(re.ws + re.lay.state) : nullptr;
+    a.mom[0] = re.lay.state ? reinterpret_cast<T *>(a.rec[1] + a.P) : nullptr;
+    a.mom[1] = re.lay.state ? a.mom[0] + (size_t)3 * a.P : nullptr;
 }
 
 template <typename T, typename F>
@@ -613,14 +850,30 @@ void set_variant(PartBatch<T> &b, int v, int default_xcd) {
     b.xcd = (v >= 4) ? 1 - default_xcd : default_xcd;
 }
 
+// Exclusive scan of the bin counts into offsets and cursors, every realisation of b.
+template <typename T>
+void launch_scan(hrt_ctx *c, PartBatch<T> &b, int R) {
+    hipStream_t st = c->stream;
+    prof_begin(c);
+    set_map(b, R, [](const Particles<T> &a) { return a.nblk; });
+    scan_local_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
+    scan_sums_kernel<T><<<R, 1024, 0, st>>>(b);
+    set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
+    scan_add_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
+    prof_end(c, K_BIN_SCAN);
+}
+
 template <typename T>
 hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
+    // the sorted state is only ever counted by the previous step's kick-drift
+    if (args.state == STATE_SORTED && !args.counts_ready) return hipErrorInvalidValue;
     hipStream_t st = c->stream;
     const int nre = (int)c->re.size();
     for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
         const int R = std::min(kMaxBatch, nre - r0);
         PartBatch<T> b{};
         for (int k = 0; k < R; ++k) fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
+        const int cur = args.cur;
         if (!args.counts_ready) {
             prof_begin(c);
             set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
@@ -630,18 +883,20 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
             bin_count_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
             prof_end(c, K_BIN_COUNT);
         }
-        prof_begin(c);
-        set_map(b, R, [](const Particles<T> &a) { return a.nblk; });
-        scan_local_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
-        scan_sums_kernel<T><<<R, 1024, 0, st>>>(b);
-        set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
-        scan_add_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
-        prof_end(c, K_BIN_SCAN);
+        launch_scan<T>(c, b, R);
         prof_begin(c);
         set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
         set_variant(b, c->variant[K_BIN_SCATTER], 0);
-        bin_scatter_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
-        prof_end(c, K_BIN_SCATTER);
+        if (args.state == STATE_LAGRANGIAN) {
+            bin_scatter_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
+            prof_end(c, K_BIN_SCATTER);
+        } else if (args.state == STATE_FROM_CALLER) {
+            state_scatter_kernel<T, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+            prof_end(c, K_STATE_SCATTER);
+        } else {
+            state_scatter_kernel<T, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+            prof_end(c, K_STATE_SCATTER);
+        }
         prof_begin(c);
         // variant bits: 0 = no XCD grouping, 1 = four tiles per workgroup
         const int pv = c->variant[K_PAINT];
@@ -649,8 +904,14 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         set_map(b, R, [tpb](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / tpb; });
         b.pmap = 0;
         b.xcd = (pv & 1) == 0 ? 1 : 0;
-        if (tpb == 4) paint_tiles_kernel<T, 4><<<b.map.start[R], kThreads, 0, st>>>(b);
-        else paint_tiles_kernel<T, 1><<<b.map.start[R], kThreads, 0, st>>>(b);
+        const bool sorted = args.state != STATE_LAGRANGIAN;
+        if (tpb == 4) {
+            if (sorted) paint_tiles_kernel<T, 4, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+            else paint_tiles_kernel<T, 4, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+        } else {
+            if (sorted) paint_tiles_kernel<T, 1, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+            else paint_tiles_kernel<T, 1, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+        }
         prof_end(c, K_PAINT);
     }
     return hipGetLastError();
@@ -671,6 +932,16 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
         if (args.count_next) {
             set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
             fill_counts_kernel<T><<<b.map.start[R], 256, 0, c->stream>>>(b);
+        }
+        if (args.state != STATE_LAGRANGIAN) {
+            auto tiles = [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt; };
+            set_map(b, R, tiles);
+            b.pmap = 0;
+            b.xcd = 1;
+            if (args.count_next) kd_tiles_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            else kd_tiles_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            prof_end(c, K_KD_TILES);
+            continue;
         }
         const int v = c->variant[K_MATTER_KD];
         const int ilp = v >= 8 ? 2 : 1;
@@ -745,6 +1016,25 @@ hipError_t launch_paint(hrt_ctx *c, const StepArgs &a) {
 
 hipError_t launch_matter_kd(hrt_ctx *c, const StepArgs &a) {
     return c->f64 ? matter_impl<double>(c, a) : matter_impl<float>(c, a);
+}
+
+template <typename T>
+hipError_t state_gather_impl(hrt_ctx *c, const StepArgs &args) {
+    const int nre = (int)c->re.size();
+    for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
+        const int R = std::min(kMaxBatch, nre - r0);
+        PartBatch<T> b{};
+        for (int k = 0; k < R; ++k) fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
+        set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
+        prof_begin(c);
+        state_gather_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+        prof_end(c, K_STATE_GATHER);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_state_gather(hrt_ctx *c, const StepArgs &a) {
+    return c->f64 ? state_gather_impl<double>(c, a) : state_gather_impl<float>(c, a);
 }
 
 }  // namespace hrt

@@ -29,6 +29,7 @@ int variants_of(int id) {
         case K_BIN_COUNT: case K_BIN_SCATTER: return 8;
         case K_RAY_STEP: return 6;
         case K_PAINT: return 4;
+        case hrt::K_KD_TILES: return 3;      // run order: 0 automatic, 1 Lagrangian, 2 sorted state
         default: return (id >= 0 && id < K_COUNT) ? 1 : 0;
     }
 }

@@ -18,7 +18,7 @@ HRT_STATIC = 1
 HRT_ADJOINT = 2
 HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
-HRT_NUM_KERNELS = 13
+HRT_NUM_KERNELS = 17
 
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
             "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",

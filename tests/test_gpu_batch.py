@@ -90,10 +90,13 @@ def test_batched_equals_plain_and_oracle():
     assert rel_l2(Case.host(states[1][2]), d_o) < 1e-3
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("order", [1, 2])
+def test_graph_replay_matches_eager(order):
+    """Replays of a captured batched sequence (Lagrangian or sorted-state particle order)
+    match eager step-by-step calls bit for bit, with eager work between the replays."""
     import torch
     from paper_2405_12913_amd import hrt
-    say("case graph capture and replay, batched")
+    say(f"case graph capture and replay, batched, order {order}")
     cases = _cases()[:3]
     eager = hrt.Simulation(configs=[_kwargs(c) for c in cases])
     st_e = [_state(c) for c in cases]
@@ -103,6 +106,7 @@ def test_graph_replay_matches_eager():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         g = hrt.Simulation(configs=[_kwargs(c) for c in cases])
+        g.set_variant("kd_tiles", order)
         st = [_state(c) for c in cases]
         init = [[t.clone() for t in sum(x, [])] for x in st]
         g.graph_capture([x[0] for x in st], [x[1] for x in st], [x[2] for x in st], [x[3] for x in st],

@@ -161,3 +161,46 @@ def test_lcdm256_every_variant_bit_identical():
             for a, b in zip(run(), ref):
                 assert torch.equal(a, b), (name, v)
         sim.set_variant(name, 0)
+
+
+def test_lcdm256_sorted_run_bit_identical():
+    """At the benchmark size, on a clustered state (dense tiles): hrt_run keeping the
+    particles in paint-bin order (the default for long runs) gives the bits of pm_step / ray_step called
+    step by step, for every paint_tiles variant, and so does the Lagrangian-order run.
+    Afterwards the G mesh is incomplete, so ray_step refuses to run before a new pm_force."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    cfg = synth.lcdm256()
+    n, np_, box, M = cfg["mesh_n"], cfg["ptcl_n"], cfg["box"], cfg["ray_n"]
+    say("case lcdm256 sorted run: inputs")
+    s = synth.clustered_displacements(7, np_, box, n_halos=512)
+    p = synth.random_momenta(7, len(s), 3.0)
+    dth, pr = synth.random_rays(7, M * M, 1e-4, 0.3)
+    dev = lambda a: [torch.tensor(np.ascontiguousarray(a[:, k]), dtype=torch.float32, device="cuda")
+                     for k in range(a.shape[1])]
+    base = [dev(x) for x in (s, p, dth, pr)]
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(cfg["sched"]) - 1, sched=cfg["sched"],
+                         ray_nx=M, ray_ny=M, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
+                         omega_m=cfg["omega_m"], dtype="f32")
+    steps = (20, 21, 22)
+    st = [[t.clone() for t in x] for x in base]
+    for k in steps:
+        sim.pm_step(st[0], st[1], k)
+        sim.ray_step(st[2], st[3], k)
+    torch.cuda.synchronize()
+    ref = sum(st, [])
+    for kd, paints in ((2, range(hrt.num_variants("paint_tiles"))), (1, (0,))):
+        sim.set_variant("kd_tiles", kd)
+        for pv in paints:
+            say(f"  kd_tiles = {kd}, paint_tiles = {pv}")
+            sim.set_variant("paint_tiles", pv)
+            st = [[t.clone() for t in x] for x in base]
+            sim.run(st[0], st[1], st[2], st[3], steps[0], len(steps))
+            torch.cuda.synchronize()
+            for a, b in zip(sum(st, []), ref):
+                assert torch.equal(a, b), (kd, pv)
+    sim.set_variant("kd_tiles", 2)
+    sim.set_variant("paint_tiles", 0)
+    sim.run(st[0], st[1], None, None, 23, 1)
+    with pytest.raises(hrt.HRTError, match="no force mesh"):
+        sim.ray_step(st[2], st[3], 23)

@@ -75,7 +75,7 @@ def test_autotune_keeps_state_and_cache_roundtrips(tmp_path):
         doc = json.load(f)
     keys = [e["key"] for e in doc["entries"]]
     assert len(keys) == len(TUNABLE) and all("|f32|64/64/64x64" in k for k in keys)
-    assert set(chosen) == set(TUNABLE)
+    assert set(chosen) == set(TUNABLE) | {"kd_tiles"} and chosen["kd_tiles"] == 0   # run order: not tuned
     mtime = (tmp_path / "tune.json").stat().st_mtime_ns
     sim2 = c.sim()
     assert sim2.autotune(s, p, d, pr, step=0, cache=path) == chosen
@@ -118,15 +118,17 @@ def test_batched_variants_with_uneven_grids():
 
 def test_run_equals_step_by_step():
     """hrt_run (the drift counts the next paint's bins) is bit-identical to pm_step/ray_step
-    called one by one: single realisation with rays, matter only, an uneven batch, and the
-    two-particles-per-lane matter variant."""
+    called one by one: in both particle orders of the run (sorted state, the default, and
+    Lagrangian order with one and two particles per lane), single realisation with rays,
+    matter only, and an uneven batch (one realisation with 8 mesh nodes per particle)."""
     import torch
     from paper_2405_12913_amd import hrt
     say("case hrt_run vs step by step")
     c = _case()
     base = _run(c, c.sim(), steps=5)
-    for variant in (0, 8):
+    for kd, variant in ((2, 0), (1, 0), (1, 8)):
         sim = c.sim()
+        sim.set_variant("kd_tiles", kd)
         sim.set_variant("matter_kd", variant)
         s, p = c.dev(c.s), c.dev(c.p)
         d, pr = c.dev(np.zeros_like(c.dth)), c.dev(np.zeros_like(c.pr))
@@ -136,14 +138,16 @@ def test_run_equals_step_by_step():
         sim.ray_convergence(d, k)
         torch.cuda.synchronize()
         for a, b in zip(s + p + d + pr + [k], base):
-            assert torch.equal(a, b), variant
+            assert torch.equal(a, b), (kd, variant)
     # matter only
     sim = c.sim()
     s1, p1 = c.dev(c.s), c.dev(c.p)
     for step in range(4):
         sim.pm_step(s1, p1, step)
     s2, p2 = c.dev(c.s), c.dev(c.p)
-    c.sim().run(s2, p2, None, None, 0, 4)
+    sim = c.sim()
+    sim.set_variant("kd_tiles", 2)
+    sim.run(s2, p2, None, None, 0, 4)
     torch.cuda.synchronize()
     for a, b in zip(s1 + p1, s2 + p2):
         assert torch.equal(a, b)
@@ -163,6 +167,7 @@ def test_run_equals_step_by_step():
               for cc in cases]
         S, Pm, D, R = ([x[i] for x in st] for i in range(4))
         if use_run:
+            sim.set_variant("kd_tiles", 2)
             sim.run(S, Pm, D, R, 0, 5)
         else:
             for step in range(5):
