@@ -246,9 +246,13 @@ __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
     constexpr int TOTAL = (N / 2 + 1) * N;
     __shared__ c2<T> buf[LINES * LS];
     __shared__ c2<T> tw[N];
-    const int r = blockIdx.x / fb.bpr;
+    // A block's rows are LINES consecutive y (LINES x 8 bytes of a 128-byte line in FP32):
+    // XCD-grouped block order puts the blocks that share those lines on one XCD, so each line
+    // comes from HBM once rather than once per XCD.
+    const int blk = xcd_block(gridDim.x);
+    const int r = blk / fb.bpr;
     c2<T> *__restrict__ data = fb.spec[r];
-    const int l0 = (blockIdx.x % fb.bpr) * LINES;
+    const int l0 = (blk % fb.bpr) * LINES;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
         const int z = e / LINES, li = e % LINES, l = l0 + li;
