@@ -256,13 +256,15 @@ def test_paint_fractions_at_cell_edges():
     assert np.max(np.abs(d - d_o) / (1.0 + np.abs(d_o))) < 2e-5
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_gpu_time_reversibility(dtype):
+def test_gpu_time_reversibility(dtype, order):
     """N co-evolution steps with the closing half-kick, then the reversed schedule, return the
-    initial matter and ray state (the integrator is symplectic and reversible; App. B).
+    initial matter and ray state (the integrator is symplectic and reversible; App. B), in both
+    particle orders of hrt_run.
     FP32: rounding of the state over 2(N+1) steps, 1e-5 of each quantity's scale; FP64 1e-10."""
     import torch
-    say(f"case time reversibility {dtype}")
+    say(f"case time reversibility {dtype}, order {order}")
     cfg = synth.tiny(mesh_n=32, ptcl_n=16, box=40.0, ray_n=16, fov_deg=3.0, n_steps=6)
     c = Case(cfg, seed=8, dtype=dtype, dth_rms=2e-4)
     a = np.linspace(1.0, 0.7, 7)
@@ -270,6 +272,8 @@ def test_gpu_time_reversibility(dtype):
     dth, pr = c.dev(c.dth), c.dev(c.pr)
     init = [t.clone() for t in s + p + dth + pr]
     fwd, rev = c.sim(sched=a), c.sim(sched=a[::-1].copy())
+    for sim in (fwd, rev):
+        sim.set_variant("kd_tiles", order)     # Lagrangian or paint-bin particle order
     fwd.run(s, p, dth, pr, 0, 7)
     torch.cuda.synchronize()
     assert float((s[0] - init[0]).abs().max()) > 0.1

@@ -210,3 +210,27 @@ def test_paint_variants_with_dense_tiles():
             assert d_o.max() > 200
             assert np.max(np.abs(dd - d_o) / (1.0 + np.abs(d_o))) < 2e-5
         assert torch.equal(d, ref), v
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sorted_run_default_threshold_and_dtypes(dtype):
+    """The automatic particle order of hrt_run (paint-bin order from 8 steps on) gives the
+    bits of step-by-step pm_step / ray_step calls in FP32 and FP64, over a 9-step call that
+    starts mid-schedule (np = n/2: the sorted kick-drift with 64 particles per tile)."""
+    import torch
+    say(f"case sorted run {dtype}")
+    cfg = synth.tiny(mesh_n=64, ptcl_n=32, box=100.0, ray_n=32, fov_deg=2.0, n_steps=12, seed=23)
+    c = Case(cfg, seed=23, dtype=dtype, dth_rms=1e-4, p_rms=0.1)
+    first, count = 2, 9
+    ref = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
+    sim = c.sim()
+    for step in range(first, first + count):
+        sim.pm_step(ref[0], ref[1], step)
+        sim.ray_step(ref[2], ref[3], step)
+    got = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
+    sim2 = c.sim()
+    assert sim2.variants()["kd_tiles"] == 0
+    sim2.run(got[0], got[1], got[2], got[3], first, count)
+    torch.cuda.synchronize()
+    for a, b in zip(sum(got, []), sum(ref, [])):
+        assert torch.equal(a, b)
