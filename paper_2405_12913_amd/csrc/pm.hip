@@ -297,15 +297,15 @@ __device__ __forceinline__ int acc_slot(int x, int y, int z) { return z * kAccPl
 // FP64: 64-bit sums with the global scale. No contraction, so every instantiation of the
 // paint kernel forms the same weights.
 template <typename T, typename A>
-__device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e,
-                                          const signed char *d, double scale, float fscale) {
+__device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e, int dx, int dy,
+                                          int dz, double scale, float fscale) {
 #pragma clang fp contract(off)
     int lcell;
     if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
     else lcell = (int)e.w;
-    const int bx = kTile * d[0] + (lcell & 7);
-    const int by = kTile * d[1] + ((lcell >> 3) & 7);
-    const int bz = kTile * d[2] + (lcell >> 6);
+    const int bx = kTile * dx + (lcell & 7);
+    const int by = kTile * dy + ((lcell >> 3) & 7);
+    const int bz = kTile * dz + (lcell >> 6);
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz) {
         const int nz = bz + cz;
@@ -368,10 +368,21 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, i
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
-    int r = 0;                                  // idx only grows: the range index too
+    // idx only grows, so the range index r does too; its bounds, start and neighbour offset
+    // stay in registers until idx leaves the range
+    int r = -1, hi = 0, base = 0, dx = 0, dy = 0, dz = 0;
     for (int idx = lane; idx < total; idx += G) {
-        while (idx >= rpre[g][r + 1]) ++r;
-        v4<T> e = src[rstart[g][r] + (idx - rpre[g][r])];
+        if (idx >= hi) {
+            do {
+                ++r;
+            } while (idx >= rpre[g][r + 1]);
+            hi = rpre[g][r + 1];
+            base = rstart[g][r] - rpre[g][r];
+            dx = rd[g][r][0];
+            dy = rd[g][r][1];
+            dz = rd[g][r][2];
+        }
+        v4<T> e = src[base + idx];
         if constexpr (SORTED) {                 // record -> (fractions, local cell)
             int c[3];
             T f[3];
@@ -381,8 +392,8 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, i
             e.z = f[2];
             e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
         }
-        if (narrow) paint_one<T, unsigned int>(fixed_bits, acc32, e, rd[g][r], scale, fscale);
-        else paint_one<T, unsigned long long>(fixed_bits, acc[g], e, rd[g][r], scale, fscale);
+        if (narrow) paint_one<T, unsigned int>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
+        else paint_one<T, unsigned long long>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
     }
     __syncthreads();
     // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
