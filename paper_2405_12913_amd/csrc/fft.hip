@@ -102,14 +102,21 @@ __device__ __forceinline__ void stage_twiddles(c2<T> *stw, const c2<T> *__restri
 // Work per block (complex values staged in LDS). Small blocks keep many blocks resident per
 // CU, so one block's loads overlap other blocks' LDS stages (measured on gfx950 at 256^3:
 // 2048 values for the x passes, 1024 for y and 2048 for z were fastest). The x passes
-// write (read) the spectrum transposed and the z pass reads strided rows, so both keep at
-// least 16 (x) and 8 (z) lines per block at any N: 128- and 64-byte segments.
+// write (read) the spectrum transposed and the z pass reads strided rows, so both keep 16
+// (x) and 8 (z) lines per block, 128- and 64-byte segments, while that fits in 32 KB of LDS
+// (4096 FP32 complex values); larger meshes take fewer lines rather than fewer resident
+// blocks (at 1024^3: 8 and 4 lines), and the XCD-grouped block order of these passes
+// puts the blocks that share a segment's line on one L2.
 template <typename T, int N>
 struct Cfg {
     static constexpr int F = sizeof(T) == 4 ? 1 : 2;
-    static constexpr int EX = (2048 / F > 16 * N / (2 * F)) ? 2048 / F : 16 * N / (2 * F);
+    static constexpr int EXW = (2048 / F > 16 * N / (2 * F)) ? 2048 / F : 16 * N / (2 * F);
+    static constexpr int EXC = (4096 / F > N / 2) ? 4096 / F : N / 2;
+    static constexpr int EX = EXW < EXC ? EXW : EXC;
     static constexpr int EY = (1024 / F > N) ? 1024 / F : N;
-    static constexpr int EZ = (2048 / F > 8 * N / F) ? 2048 / F : 8 * N / F;
+    static constexpr int EZW = (2048 / F > 8 * N / F) ? 2048 / F : 8 * N / F;
+    static constexpr int EZC = (4096 / F > N) ? 4096 / F : N;
+    static constexpr int EZ = EZW < EZC ? EZW : EZC;
     static constexpr int XROWS = (EX / (N / 2)) < 1 ? 1 : ((EX / (N / 2)) < N * N ? EX / (N / 2) : N * N);
     static constexpr int YLINES = EY / N < 1 ? 1 : EY / N;
     static constexpr int ZLINES = EZ / N < 1 ? 1 : EZ / N;
@@ -134,10 +141,12 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
     __shared__ c2<T> tw[N];
-    const int r = blockIdx.x / fb.bpr;
+    // XCD-grouped block order only when a block's transposed segments are under 128 bytes
+    const int blk = ROWS * (int)sizeof(c2<T>) < 128 ? xcd_block(gridDim.x) : (int)blockIdx.x;
+    const int r = blk / fb.bpr;
     const T *__restrict__ in = fb.rin[r];
     c2<T> *__restrict__ out = fb.spec[r];
-    const int row0 = (blockIdx.x % fb.bpr) * ROWS;
+    const int row0 = (blk % fb.bpr) * ROWS;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
         const int rr = e / L, m = e % L;
@@ -179,10 +188,12 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
     constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
     __shared__ c2<T> tw[N];
-    const int r = blockIdx.x / fb.bpr;
+    // XCD-grouped block order only when a block's transposed segments are under 128 bytes
+    const int blk = ROWS * (int)sizeof(c2<T>) < 128 ? xcd_block(gridDim.x) : (int)blockIdx.x;
+    const int r = blk / fb.bpr;
     const c2<T> *__restrict__ in = fb.spec[r];
     T *__restrict__ out = fb.rout[r];
-    const int row0 = (blockIdx.x % fb.bpr) * ROWS;
+    const int row0 = (blk % fb.bpr) * ROWS;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     for (int e = threadIdx.x; e < ROWS * (L + 1); e += kThreads) {
         const int kx = e / ROWS, rr = e % ROWS;
