@@ -44,6 +44,8 @@ struct AdjArgs {
     T *div;                      // phi_bar
     const PlaneEntry *planes;
     int begin, count;
+    double *tbpart;              // ray VJP: per plane group, per ray (dth_bar x, y) partial sums
+    int parts, chunk;            //   plane groups and plane entries per group
     int n, lnp, lratio, P, mx, my, nrays;
     int patch;                   // rays in 16 x 16 pixel patches per block
     int hbits;                   // log2 bound of the contributions per node
@@ -92,7 +94,9 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// One lane per ray. Per plane: the transposed bilinear derivative gathers into dth_bar,
+// One lane per ray, the step's lens planes split over gridDim.y groups (blockIdx.y takes
+// `chunk` consecutive entries; its partial dth_bar goes to tbpart). Per plane: the
+// transposed bilinear derivative gathers into dth_bar,
 // and the bilinear weights of w_j p_r_bar go into G_bar. A wave's rays fall on a small patch
 // of the plane, so their contributions are first summed in the wave's own LDS window over
 // the wave's bounding box (integer atomics, exact) and each touched node then receives one
@@ -119,7 +123,9 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
         pty = a.prb[1][i];
     }
     double tbx = 0.0, tby = 0.0;
-    for (int e = a.begin; e < a.begin + a.count; ++e) {
+    const int e0 = a.begin + (int)blockIdx.y * a.chunk;
+    const int e1 = min(e0 + a.chunk, a.begin + a.count);
+    for (int e = e0; e < e1; ++e) {
         const PlaneEntry pe = a.planes[e];
         int ux = 0, uy = 0;            // unwrapped cell of the ray on this plane
         double q[4][2];                // fixed-point contributions of the 4 corners
@@ -193,9 +199,25 @@ __global__ __launch_bounds__(kThreads) void ray_vjp_kernel(AdjArgs<T> a) {
         }
     }
     if (valid) {
-        a.db[0][i] += (T)tbx;
-        a.db[1][i] += (T)tby;
+        double *tp = a.tbpart + ((size_t)blockIdx.y * a.nrays + i) * 2;
+        tp[0] = tbx;
+        tp[1] = tby;
     }
+}
+
+// dth_bar += the plane groups' partial sums, added in group order (deterministic).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ray_vjp_sum_kernel(AdjArgs<T> a) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= a.nrays) return;
+    double sx = 0.0, sy = 0.0;
+    for (int g = 0; g < a.parts; ++g) {
+        const double *tp = a.tbpart + ((size_t)g * a.nrays + i) * 2;
+        sx += tp[0];
+        sy += tp[1];
+    }
+    a.db[0][i] += (T)sx;
+    a.db[1][i] += (T)sy;
 }
 
 // Static lens (no matter VJP): G_bar from the rays' part only.
@@ -346,6 +368,9 @@ AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
     sc.gbar = a.gbar;
     sc.maxbits = a.maxbits;
     sc.wsorted = re.ws + re.lay.adj + 2 * n3 * 8 + 256;
+    a.tbpart = reinterpret_cast<double *>(re.ws + re.lay.adj + 2 * n3 * 8 + 256 + P * 4 * sizeof(T));
+    a.parts = std::max(1, std::min(kRayVjpParts, a.count));
+    a.chunk = (a.count + a.parts - 1) / a.parts;
     sc.hbits = a.hbits;
     return a;
 }
@@ -366,7 +391,10 @@ hipError_t step_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, con
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && matter) e = launch_matter_vjp(c, m, mc, step, sc);
     if (e != hipSuccess) return e;
-    if (rays) ray_vjp_kernel<T><<<nb(a.nrays), kThreads, 0, st>>>(a);
+    if (rays) {
+        ray_vjp_kernel<T><<<dim3(nb(a.nrays), a.parts), kThreads, 0, st>>>(a);
+        ray_vjp_sum_kernel<T><<<nb(a.nrays), kThreads, 0, st>>>(a);
+    }
     if (matter) e = launch_gbar_tiles(c, rays, sc);
     else gbar_convert_kernel<T><<<nb(n3), kThreads, 0, st>>>(a);
     if (e != hipSuccess) return e;

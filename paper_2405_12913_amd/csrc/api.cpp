@@ -37,8 +37,10 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     L.sorted = take(P * 4 * T);
     L.planes = take((size_t)std::max<int64_t>(n_plane_entries, 1) * sizeof(PlaneEntry));
     // reverse mode: 2 x n^3 64-bit fixed-point accumulators (rays' part of the force-mesh
-    // cotangent), one 8-byte device scalar (256 bytes reserved) and P x 4 kick weights
-    L.adj = (cfg.flags & HRT_ADJOINT) ? take(2 * n3 * 8 + 256 + P * 4 * T) : off;
+    // cotangent), one 8-byte device scalar (256 bytes reserved), P x 4 kick weights and the
+    // ray VJP's per-group partial sums (kRayVjpParts x rays x 2 doubles)
+    const size_t M = (size_t)cfg.ray_nx * cfg.ray_ny;
+    L.adj = (cfg.flags & HRT_ADJOINT) ? take(2 * n3 * 8 + 256 + P * 4 * T + kRayVjpParts * M * 16) : off;
     // sorted-state run: the second record buffer (the first is `sorted`) and both momentum
     // buffers, P x (4 + 3 + 3) values; a static run moves no particles
     L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * 10 * T);

@@ -65,6 +65,11 @@ struct ProfRecord {
 // by-value argument block (well under the 4 KB limit); larger batches launch in chunks.
 constexpr int kMaxBatch = 16;
 
+// The ray part of the step VJP splits a step's lens planes over this many groups of
+// workgroups (more waves than one per 64 rays); each group's per-ray partial sums of the
+// deflection cotangent are added in group order afterwards (reverse-mode scratch).
+constexpr int kRayVjpParts = 8;
+
 // One realisation of a (possibly batched) context.
 struct Real {
     hrt_config cfg;
