@@ -184,7 +184,10 @@ __device__ __forceinline__ double adj_fixed_scale(const unsigned long long *maxb
 }
 
 // Block-wide maximum of v >= 0 (every thread of a 256-thread block calls), folded into
-// *slot with one integer atomicMax per block (non-negative doubles order as their bits).
+// *slot with an integer atomicMax (non-negative doubles order as their bits), issued only when
+// the block's maximum exceeds the value already there: the slot only grows, so a stale read
+// skips nothing that matters, and most blocks of a launch skip their atomic (same-address
+// atomics serialise in L2, a few ns each).
 __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v) {
     __shared__ double wmax[4];
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
@@ -192,7 +195,8 @@ __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v)
     __syncthreads();
     if (threadIdx.x == 0) {
         const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
-        if (m > 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+        if (m > 0.0 && mb > __atomic_load_n(slot, __ATOMIC_RELAXED)) atomicMax(slot, mb);
     }
 }
 

@@ -341,14 +341,15 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 // sums with the global scale.
 // SORTED: the particles are sorted-state records (buffer cur) rather than the binned
 // (fraction, local cell) entries of the Lagrangian-order scatter.
+// The work of logical block blk (TPB tiles); the paint kernels call it once (one block per
+// tile group) or in a loop over a work queue.
 template <typename T, int TPB, bool SORTED>
-__global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, int cur) {
+__device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur, int blk) {
     constexpr int G = kThreads / TPB;           // lanes per tile
     __shared__ unsigned long long acc[TPB][kAccSize];   // 64-bit sums, or 32-bit in place
     __shared__ __align__(16) int rstart[TPB][32];
     __shared__ __align__(16) int rpre[TPB][32];
     __shared__ __align__(16) signed char rd[TPB][32][3];
-    const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
     const int n = a.n, nt = n / kTile;
@@ -405,6 +406,37 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, i
         st_stream((T)fmadd(sum, inv, -1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
+
+template <typename T, int TPB, bool SORTED>
+__global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, int cur) {
+    paint_tiles_body<T, TPB, SORTED>(b, cur, logical_block(b.xcd));
+}
+
+// Persistent form: a grid of about one wave of resident workgroups takes chunks of
+// kQueueChunk logical blocks from a counter (*queue, zeroed before the launch) until all
+// nblocks are done (one atomic per chunk: same-address atomics serialise in L2). Every tile
+// is still painted whole by one workgroup, so the result is the same bits.
+constexpr int kQueueChunk = 16;
+__device__ __forceinline__ int next_chunk(unsigned int *queue, int *slot) {
+    if (threadIdx.x == 0) *slot = (int)atomicAdd(queue, (unsigned int)kQueueChunk);
+    __syncthreads();
+    const int base = *slot;
+    __syncthreads();                            // all lanes hold base before the slot is reused
+    return base;
+}
+
+template <typename T, bool SORTED>
+__global__ __launch_bounds__(kThreads) void paint_tiles_queue_kernel(PartBatch<T> b, int cur,
+                                                                     unsigned int *queue, int nblocks) {
+    __shared__ int slot;
+    for (int base = next_chunk(queue, &slot); base < nblocks; base = next_chunk(queue, &slot))
+        for (int blk = base; blk < base + kQueueChunk && blk < nblocks; ++blk) {
+            paint_tiles_body<T, 1, SORTED>(b, cur, blk);
+            __syncthreads();                    // LDS of this tile read out before the next clears it
+        }
+}
+
+__global__ void queue_reset_kernel(unsigned int *queue) { *queue = 0u; }
 
 // One lane per ILP particles, particles in Lagrangian order (patch maps), optionally with
 // XCD-grouped blocks so neighbouring particle patches (which read the same mesh rows)
@@ -532,12 +564,12 @@ __global__ __launch_bounds__(kThreads) void state_scatter_kernel(PartBatch<T> b,
 // cell's upper corners reach the next tile's first node), fd4 reaches 2 nodes further.
 constexpr int kPhiX = 16, kPhiYZ = 13, kGN = 9;
 
-// With COUNT the moved particle is also counted into its bin for the next step.
+// With COUNT the moved particle is also counted into its bin for the next step. The work
+// of logical block blk (one tile).
 template <typename T, bool COUNT>
-__global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int cur) {
+__device__ __forceinline__ void kd_tiles_body(const PartBatch<T> &b, int cur, int blk) {
     __shared__ v4<T> ph4[kPhiYZ * kPhiYZ * (kPhiX / 4)];
     __shared__ v4<T> gl[kGN * kGN * kGN];
-    const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
     const int n = a.n, nt = n / kTile, m = n - 1;
@@ -624,6 +656,22 @@ __global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int 
         cur0 = nxt0;
         cur1 = nxt1;
     }
+}
+
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int cur) {
+    kd_tiles_body<T, COUNT>(b, cur, logical_block(b.xcd));
+}
+
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(kThreads) void kd_tiles_queue_kernel(PartBatch<T> b, int cur,
+                                                                  unsigned int *queue, int nblocks) {
+    __shared__ int slot;
+    for (int base = next_chunk(queue, &slot); base < nblocks; base = next_chunk(queue, &slot))
+        for (int blk = base; blk < base + kQueueChunk && blk < nblocks; ++blk) {
+            kd_tiles_body<T, COUNT>(b, cur, blk);
+            __syncthreads();                    // LDS of this tile used up before the next fills it
+        }
 }
 
 // Sorted slot j of buffer cur back to the caller's arrays at the record's lattice index.
@@ -874,6 +922,15 @@ void launch_scan(hrt_ctx *c, PartBatch<T> &b, int R) {
     prof_end(c, K_BIN_SCAN);
 }
 
+// Workgroups of a persistent tile kernel: per_cu resident per compute unit.
+inline int resident_blocks(int per_cu) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus * per_cu;
+}
+
 template <typename T>
 hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
     // the sorted state is only ever counted by the previous step's kick-drift
@@ -909,13 +966,25 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
             prof_end(c, K_STATE_SCATTER);
         }
         prof_begin(c);
-        // variant bits: 0 = no XCD grouping, 1 = four tiles per workgroup
+        // variants 0-3, bits: 0 = no XCD grouping, 1 = four tiles per workgroup; 4 = one tile
+        // per workgroup from a work queue (persistent grid)
         const int pv = c->variant[K_PAINT];
+        const bool sorted = args.state != STATE_LAGRANGIAN;
+        if (pv == 4) {
+            set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt; });
+            unsigned int *queue = reinterpret_cast<unsigned int *>(c->re[r0].ws + c->re[r0].lay.queue);
+            const int nblk = b.map.start[R];
+            const int grid = std::min(nblk, resident_blocks(8));
+            queue_reset_kernel<<<1, 1, 0, st>>>(queue);
+            if (sorted) paint_tiles_queue_kernel<T, true><<<grid, kThreads, 0, st>>>(b, cur, queue, nblk);
+            else paint_tiles_queue_kernel<T, false><<<grid, kThreads, 0, st>>>(b, cur, queue, nblk);
+            prof_end(c, K_PAINT);
+            continue;
+        }
         const int tpb = (pv & 2) ? 4 : 1;
         set_map(b, R, [tpb](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / tpb; });
         b.pmap = 0;
         b.xcd = (pv & 1) == 0 ? 1 : 0;
-        const bool sorted = args.state != STATE_LAGRANGIAN;
         if (tpb == 4) {
             if (sorted) paint_tiles_kernel<T, 4, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
             else paint_tiles_kernel<T, 4, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
@@ -949,8 +1018,18 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             set_map(b, R, tiles);
             b.pmap = 0;
             b.xcd = 1;
-            if (args.count_next) kd_tiles_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
-            else kd_tiles_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            if (c->variant[K_KD_TILES] == 3) {          // persistent work-queue form
+                unsigned int *queue = reinterpret_cast<unsigned int *>(c->re[r0].ws + c->re[r0].lay.queue);
+                const int nblk = b.map.start[R];
+                const int grid = std::min(nblk, resident_blocks(7));
+                queue_reset_kernel<<<1, 1, 0, c->stream>>>(queue);
+                if (args.count_next) kd_tiles_queue_kernel<T, true><<<grid, kThreads, 0, c->stream>>>(b, args.cur, queue, nblk);
+                else kd_tiles_queue_kernel<T, false><<<grid, kThreads, 0, c->stream>>>(b, args.cur, queue, nblk);
+            } else if (args.count_next) {
+                kd_tiles_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            } else {
+                kd_tiles_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            }
             prof_end(c, K_KD_TILES);
             continue;
         }

@@ -126,7 +126,7 @@ def test_run_equals_step_by_step():
     say("case hrt_run vs step by step")
     c = _case()
     base = _run(c, c.sim(), steps=5)
-    for kd, variant in ((2, 0), (1, 0), (1, 8)):
+    for kd, variant in ((2, 0), (3, 0), (1, 0), (1, 8)):
         sim = c.sim()
         sim.set_variant("kd_tiles", kd)
         sim.set_variant("matter_kd", variant)
