@@ -237,6 +237,7 @@ __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
         const unsigned int v = a.offs[i] + a.sums[i / 1024];
         a.offs[i] = v;
         a.cursor[i] = v;
+        a.count[i] = 0u;       // consumed by scan_local: zero for the next count (kick-drift)
     }
     if (i == 0) a.offs[a.nbins] = a.sums[a.nblk];
 }
@@ -1009,10 +1010,7 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
                               re.tab.D[args.step]);
         }
         prof_begin(c);
-        if (args.count_next) {
-            set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
-            fill_counts_kernel<T><<<b.map.start[R], 256, 0, c->stream>>>(b);
-        }
+        // with count_next the counts start from zero: the scan of this step's paint cleared them
         if (args.state != STATE_LAGRANGIAN) {
             auto tiles = [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt; };
             set_map(b, R, tiles);
