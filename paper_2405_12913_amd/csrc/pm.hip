@@ -730,28 +730,30 @@ __global__ __launch_bounds__(kThreads) void matter_vjp_kernel(MatterAdj<T> m) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) pt[d] = m.pb[d][i] + (T)m.D * m.sb[d][i];
         const int n = a.n;
+        // gp[k] = p_bar' . G at corner k (FP64); the derivative of the trilinear weights along
+        // axis d pairs corners that differ in d: xb_d = sum over the other two axes of their
+        // weights times (gp[upper] - gp[lower])
+        double gp[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int z = (c[2] + (k >> 2)) & (n - 1);
+            const int y = (c[1] + ((k >> 1) & 1)) & (n - 1);
+            const int x = (c[0] + (k & 1)) & (n - 1);
+            const v4<T> g = a.grad[((size_t)z * n + y) * n + x];
+            gp[k] = (double)pt[0] * (double)g.x + (double)pt[1] * (double)g.y + (double)pt[2] * (double)g.z;
+        }
+        const double w[3][2] = {{1.0 - (double)f[0], (double)f[0]},
+                                {1.0 - (double)f[1], (double)f[1]},
+                                {1.0 - (double)f[2], (double)f[2]}};
         double xb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int cz = 0; cz < 2; ++cz) {
-            const int z = (c[2] + cz) & (n - 1);
-            const double wz = cz ? (double)f[2] : 1.0 - (double)f[2], sz = cz ? 1.0 : -1.0;
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int cy = 0; cy < 2; ++cy) {
-                const int y = (c[1] + cy) & (n - 1);
-                const double wy = cy ? (double)f[1] : 1.0 - (double)f[1], sy = cy ? 1.0 : -1.0;
-#pragma unroll
-                for (int cx = 0; cx < 2; ++cx) {
-                    const int x = (c[0] + cx) & (n - 1);
-                    const double wx = cx ? (double)f[0] : 1.0 - (double)f[0], sx = cx ? 1.0 : -1.0;
-                    const v4<T> g = a.grad[((size_t)z * n + y) * n + x];
-                    const double gp = (double)pt[0] * (double)g.x + (double)pt[1] * (double)g.y +
-                                      (double)pt[2] * (double)g.z;
-                    xb[0] += gp * sx * wy * wz;
-                    xb[1] += gp * wx * sy * wz;
-                    xb[2] += gp * wx * wy * sz;
-                }
+            for (int v = 0; v < 2; ++v) {
+                xb[0] += w[1][u] * w[2][v] * (gp[(v << 2) | (u << 1) | 1] - gp[(v << 2) | (u << 1)]);
+                xb[1] += w[0][u] * w[2][v] * (gp[(v << 2) | 2 | u] - gp[(v << 2) | u]);
+                xb[2] += w[0][u] * w[1][v] * (gp[4 | (v << 1) | u] - gp[(v << 1) | u]);
             }
-        }
         const double kc = m.K * (double)a.inv_cell;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
