@@ -1,8 +1,9 @@
 // FFT Poisson solve and gradient of the PM step (paper Sec. 2 Poisson equation; Sec. 4.1:
 // the potential gradient is obtained with FFTs once per step).
 //
-// Hand-written LDS-staged Stockham FFTs (radix 4, one radix-2 stage when log2 L is
-// odd), one workgroup of 256 threads per batch of lines:
+// Hand-written LDS-staged Stockham FFTs (radix 8 where every thread still gets a
+// butterfly, else radix 4; one radix-2 stage when needed), one workgroup of 256 threads per
+// batch of lines:
 //   x_r2c      real rows -> half spectrum, written transposed as C[kx][z][y]
 //              (length-N/2 complex FFT of packed even/odd samples + split step)
 //   yz_lines   forward FFT along y (contiguous lines in the transposed layout)
@@ -25,9 +26,27 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// In-register DFT of R points in natural order (X[m] = sum_r v[r] W_R^{rm}, W_R = e^{-2 pi i/R},
+// conjugate for INV). Radix 8 as 4 x 2: DFT4 over the even and the odd samples, twiddles
+// W_8^{m0} on the odd ones (from the LDS table: W_8^q = tw[q * twq]), DFT2 across.
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void dft(c2<T> *v) {
-    if constexpr (R == 2) {
+__device__ __forceinline__ void dft(c2<T> *v, const c2<T> *__restrict__ tw = nullptr, int twq = 0) {
+    if constexpr (R == 8) {
+        c2<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft<T, 4, INV>(e);
+        dft<T, 4, INV>(o);
+#pragma unroll
+        for (int m0 = 0; m0 < 4; ++m0) {
+            c2<T> b = o[m0];
+            if (m0 > 0) {
+                c2<T> w = tw[m0 * twq];
+                if (INV) w.y = -w.y;
+                b = cmul<T>(b, w);
+            }
+            v[m0] = c2<T>{e[m0].x + b.x, e[m0].y + b.y};
+            v[m0 + 4] = c2<T>{e[m0].x - b.x, e[m0].y - b.y};
+        }
+    } else if constexpr (R == 2) {
         const c2<T> a = v[0], b = v[1];
         v[0] = c2<T>{a.x + b.x, a.y + b.y};
         v[1] = c2<T>{a.x - b.x, a.y - b.y};
@@ -51,7 +70,8 @@ template <typename T, int L, int LINES, bool INV, int Ns>
 __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
                                           int twmul) {
     if constexpr (Ns < L) {
-        constexpr int R = (Ns * 4 <= L) ? 4 : 2;
+        // radix 8 where it keeps every thread busy (LINES x L/8 butterflies), else 4, last 2
+        constexpr int R = (Ns * 8 <= L && LINES * (L / 8) >= kThreads) ? 8 : (Ns * 4 <= L) ? 4 : 2;
         constexpr int NB = LINES * (L / R);
         constexpr int BF = (NB + kThreads - 1) / kThreads;
         c2<T> v[BF][R];
@@ -72,7 +92,7 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__res
                     }
                     v[k][r] = x;
                 }
-                dft<T, R, INV>(v[k]);
+                dft<T, R, INV>(v[k], tw, twmul * (L / 8));
             }
         }
         __syncthreads();
