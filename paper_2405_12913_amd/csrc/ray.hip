@@ -66,24 +66,52 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     const double thy = ((iy + 0.5) - a.half_my) * a.muy + (double)a.dthy[i];
     const int n = a.n, m = n - 1;
     T ax = 0, ay = 0;
-    for (int e = a.begin; e < a.begin + a.count; ++e) {
+    // The kick reads every plane at the step's starting angles, so the planes are
+    // independent: kChunk of them have their gathers in flight together, then are added in
+    // plane order (the same sums as one plane at a time).
+    constexpr int kChunk = 4;
+    struct Sample {
+        v4<T> g00, g01, g10, g11;
+        T fx, fy, w;
+    };
+    auto fetch = [&](int e, Sample &q) {
         const PlaneEntry pe = a.planes[e];
         double flx, fly, frx, fry;
         plane_cell(a.obsx, pe.chi, thx, a.inv_cell, flx, frx);
         plane_cell(a.obsy, pe.chi, thy, a.inv_cell, fly, fry);
-        const T fx = (T)frx, fy = (T)fry;
+        q.fx = (T)frx;
+        q.fy = (T)fry;
+        q.w = (T)pe.w;
         const int x0 = (int)((int64_t)flx & m), y0 = (int)((int64_t)fly & m);
         const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
         const v4<T> *plane = a.g + (size_t)pe.mesh * n * n;
-        const v4<T> g00 = plane[(size_t)y0 * n + x0], g01 = plane[(size_t)y0 * n + x1];
-        const v4<T> g10 = plane[(size_t)y1 * n + x0], g11 = plane[(size_t)y1 * n + x1];
+        q.g00 = plane[(size_t)y0 * n + x0];
+        q.g01 = plane[(size_t)y0 * n + x1];
+        q.g10 = plane[(size_t)y1 * n + x0];
+        q.g11 = plane[(size_t)y1 * n + x1];
+    };
+    auto add = [&](const Sample &q) {
+        const T fx = q.fx, fy = q.fy;
         const T w00 = (T(1) - fx) * (T(1) - fy), w01 = fx * (T(1) - fy);
         const T w10 = (T(1) - fx) * fy, w11 = fx * fy;
-        const T gx = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
-        const T gy = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
-        const T w = (T)pe.w;
-        ax += w * gx;
-        ay += w * gy;
+        const T gx = w00 * q.g00.x + w01 * q.g01.x + w10 * q.g10.x + w11 * q.g11.x;
+        const T gy = w00 * q.g00.y + w01 * q.g01.y + w10 * q.g10.y + w11 * q.g11.y;
+        ax += q.w * gx;
+        ay += q.w * gy;
+    };
+    const int e_end = a.begin + a.count;
+    int e = a.begin;
+    for (; e + kChunk <= e_end; e += kChunk) {
+        Sample q[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) fetch(e + k, q[k]);
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) add(q[k]);
+    }
+    for (; e < e_end; ++e) {
+        Sample q;
+        fetch(e, q);
+        add(q);
     }
     const T npx = a.px[i] + ax, npy = a.py[i] + ay;
     a.px[i] = npx;
