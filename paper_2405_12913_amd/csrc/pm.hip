@@ -295,35 +295,36 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
 constexpr int kAccPlane = 74, kAccRow = 9, kAccSize = kTile * kAccPlane;
 __device__ __forceinline__ int acc_slot(int x, int y, int z) { return z * kAccPlane + y * kAccRow + x; }
 
-// Adds the CIC weights of one binned particle (range r) to the tile's LDS sums; corners
-// outside the tile (the particle comes from a neighbour's face bin) are skipped. FP32: 32-bit
-// sums with the tile's own scale 2^s (round(w 2^s), one multiply and one conversion);
-// FP64: 64-bit sums with the global scale. No contraction, so every instantiation of the
-// paint kernel forms the same weights.
-template <typename T, typename A>
+// Adds the CIC weights of one binned particle to the tile's LDS sums. INSIDE: the particle
+// is in the tile's own bin that touches no upper face (range 0), so its 8 corners are all
+// tile nodes and need no checks; otherwise corners outside the tile (a neighbour's face-bin
+// particle, or an upper face) are skipped. FP32: 32-bit sums with the tile's own scale 2^s
+// (round(w 2^s)); FP64 and dense tiles: 64-bit sums with the global scale. No contraction,
+// so every instantiation of the paint kernel forms the same weights.
+template <typename T, typename A, bool INSIDE>
 __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e, int dx, int dy,
                                           int dz, double scale, float fscale) {
 #pragma clang fp contract(off)
     int lcell;
     if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
     else lcell = (int)e.w;
-    const int bx = kTile * dx + (lcell & 7);
-    const int by = kTile * dy + ((lcell >> 3) & 7);
-    const int bz = kTile * dz + (lcell >> 6);
+    const int bx = (INSIDE ? 0 : kTile * dx) + (lcell & 7);
+    const int by = (INSIDE ? 0 : kTile * dy) + ((lcell >> 3) & 7);
+    const int bz = (INSIDE ? 0 : kTile * dz) + (lcell >> 6);
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz) {
         const int nz = bz + cz;
-        if (nz < 0 || nz >= kTile) continue;
+        if (!INSIDE && (nz < 0 || nz >= kTile)) continue;
         const T wz = cz ? e.z : T(1) - e.z;
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
             const int ny = by + cy;
-            if (ny < 0 || ny >= kTile) continue;
+            if (!INSIDE && (ny < 0 || ny >= kTile)) continue;
             const T wyz = wz * (cy ? e.y : T(1) - e.y);
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
                 const int nx = bx + cx;
-                if (nx < 0 || nx >= kTile) continue;
+                if (!INSIDE && (nx < 0 || nx >= kTile)) continue;
                 const T w = wyz * (cx ? e.x : T(1) - e.x);
                 if constexpr (sizeof(A) == 4)
                     atomicAdd(&acc[acc_slot(nx, ny, nz)], (unsigned int)rintf((float)w * fscale));
@@ -350,7 +351,8 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 template <typename T, int TPB, bool SORTED>
 __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur, int blk) {
     constexpr int G = kThreads / TPB;           // lanes per tile
-    __shared__ unsigned long long acc[TPB][kAccSize];   // 64-bit sums, or 32-bit in place
+    __shared__ unsigned long long acc[TPB][kAccSize];   // 64-bit sums
+    __shared__ unsigned int acc32s[TPB][kAccSize];      // 32-bit sums (separate: no type punning)
     __shared__ __align__(16) int rstart[TPB][32];
     __shared__ __align__(16) int rpre[TPB][32];
     __shared__ __align__(16) signed char rd[TPB][32][3];
@@ -360,7 +362,10 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int t = (blk - b.map.start[rr]) * TPB + g;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
-    for (int k = lane; k < kAccSize; k += G) acc[g][k] = 0ull;
+    for (int k = lane; k < kAccSize; k += G) {
+        acc[g][k] = 0ull;
+        acc32s[g][k] = 0u;
+    }
     tile_ranges<T>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane);
     __syncthreads();
     const int total = rpre[g][27];
@@ -369,7 +374,7 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     const int bits = total > 0 ? 32 - __clz(total) : 0;          // ceil(log2(total + 1))
     const int ts = (31 - bits) < 24 ? 31 - bits : 24;            // narrow scale 2^ts
     const float fscale = ldexpf(1.0f, ts);
-    unsigned int *acc32 = reinterpret_cast<unsigned int *>(acc[g]);
+    unsigned int *acc32 = acc32s[g];
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
@@ -397,8 +402,13 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
             e.z = f[2];
             e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
         }
-        if (narrow) paint_one<T, unsigned int>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
-        else paint_one<T, unsigned long long>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+        if (r == 0) {                           // own tile, no upper face: 8 inside corners
+            if (narrow) paint_one<T, unsigned int, true>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
+            else paint_one<T, unsigned long long, true>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+        } else {
+            if (narrow) paint_one<T, unsigned int, false>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
+            else paint_one<T, unsigned long long, false>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+        }
     }
     __syncthreads();
     // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
