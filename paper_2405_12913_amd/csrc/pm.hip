@@ -379,20 +379,36 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
     // idx only grows, so the range index r does too; its bounds, start and neighbour offset
-    // stay in registers until idx leaves the range
-    int r = -1, hi = 0, base = 0, dx = 0, dy = 0, dz = 0;
-    for (int idx = lane; idx < total; idx += G) {
-        if (idx >= hi) {
+    // stay in registers until idx leaves the range. The next particle's entry is requested
+    // before the current one is added (one load in flight per lane while it works).
+    struct Slot {
+        int r, hi, base, dx, dy, dz;
+    };
+    auto advance = [&](int idx, Slot &q) {
+        if (idx >= q.hi) {
             do {
-                ++r;
-            } while (idx >= rpre[g][r + 1]);
-            hi = rpre[g][r + 1];
-            base = rstart[g][r] - rpre[g][r];
-            dx = rd[g][r][0];
-            dy = rd[g][r][1];
-            dz = rd[g][r][2];
+                ++q.r;
+            } while (idx >= rpre[g][q.r + 1]);
+            q.hi = rpre[g][q.r + 1];
+            q.base = rstart[g][q.r] - rpre[g][q.r];
+            q.dx = rd[g][q.r][0];
+            q.dy = rd[g][q.r][1];
+            q.dz = rd[g][q.r][2];
         }
-        v4<T> e = src[base + idx];
+    };
+    Slot cs{-1, 0, 0, 0, 0, 0};
+    v4<T> e{};
+    if (lane < total) {
+        advance(lane, cs);
+        e = src[cs.base + lane];
+    }
+    for (int idx = lane; idx < total; idx += G) {
+        Slot ns = cs;
+        v4<T> ne{};
+        if (idx + G < total) {
+            advance(idx + G, ns);
+            ne = src[ns.base + idx + G];
+        }
         if constexpr (SORTED) {                 // record -> (fractions, local cell)
             int c[3];
             T f[3];
@@ -402,13 +418,15 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
             e.z = f[2];
             e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
         }
-        if (r == 0) {                           // own tile, no upper face: 8 inside corners
-            if (narrow) paint_one<T, unsigned int, true>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
-            else paint_one<T, unsigned long long, true>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+        if (cs.r == 0) {                        // own tile, no upper face: 8 inside corners
+            if (narrow) paint_one<T, unsigned int, true>(fixed_bits, acc32, e, cs.dx, cs.dy, cs.dz, scale, fscale);
+            else paint_one<T, unsigned long long, true>(fixed_bits, acc[g], e, cs.dx, cs.dy, cs.dz, scale, fscale);
         } else {
-            if (narrow) paint_one<T, unsigned int, false>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
-            else paint_one<T, unsigned long long, false>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+            if (narrow) paint_one<T, unsigned int, false>(fixed_bits, acc32, e, cs.dx, cs.dy, cs.dz, scale, fscale);
+            else paint_one<T, unsigned long long, false>(fixed_bits, acc[g], e, cs.dx, cs.dy, cs.dz, scale, fscale);
         }
+        cs = ns;
+        e = ne;
     }
     __syncthreads();
     // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
@@ -426,10 +444,11 @@ __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, i
     paint_tiles_body<T, TPB, SORTED>(b, cur, logical_block(b.xcd));
 }
 
-// Persistent form: a grid of about one wave of resident workgroups takes chunks of
-// kQueueChunk logical blocks from a counter (*queue, zeroed before the launch) until all
-// nblocks are done (one atomic per chunk: same-address atomics serialise in L2). Every tile
-// is still painted whole by one workgroup, so the result is the same bits.
+// Persistent form (used by the tile kick-drift): a grid of about one wave of resident
+// workgroups takes chunks of kQueueChunk logical blocks from a counter (*queue, zeroed before
+// the launch) until all nblocks are done (one atomic per chunk: same-address atomics
+// serialise in L2). Every tile is still done whole by one workgroup, so the result is the
+// same bits.
 constexpr int kQueueChunk = 16;
 __device__ __forceinline__ int next_chunk(unsigned int *queue, int *slot) {
     if (threadIdx.x == 0) *slot = (int)atomicAdd(queue, (unsigned int)kQueueChunk);
@@ -437,17 +456,6 @@ __device__ __forceinline__ int next_chunk(unsigned int *queue, int *slot) {
     const int base = *slot;
     __syncthreads();                            // all lanes hold base before the slot is reused
     return base;
-}
-
-template <typename T, bool SORTED>
-__global__ __launch_bounds__(kThreads) void paint_tiles_queue_kernel(PartBatch<T> b, int cur,
-                                                                     unsigned int *queue, int nblocks) {
-    __shared__ int slot;
-    for (int base = next_chunk(queue, &slot); base < nblocks; base = next_chunk(queue, &slot))
-        for (int blk = base; blk < base + kQueueChunk && blk < nblocks; ++blk) {
-            paint_tiles_body<T, 1, SORTED>(b, cur, blk);
-            __syncthreads();                    // LDS of this tile read out before the next clears it
-        }
 }
 
 __global__ void queue_reset_kernel(unsigned int *queue) { *queue = 0u; }
@@ -982,21 +990,9 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
             prof_end(c, K_STATE_SCATTER);
         }
         prof_begin(c);
-        // variants 0-3, bits: 0 = no XCD grouping, 1 = four tiles per workgroup; 4 = one tile
-        // per workgroup from a work queue (persistent grid)
+        // variant bits: 0 = no XCD grouping, 1 = four tiles per workgroup
         const int pv = c->variant[K_PAINT];
         const bool sorted = args.state != STATE_LAGRANGIAN;
-        if (pv == 4) {
-            set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt; });
-            unsigned int *queue = reinterpret_cast<unsigned int *>(c->re[r0].ws + c->re[r0].lay.queue);
-            const int nblk = b.map.start[R];
-            const int grid = std::min(nblk, resident_blocks(8));
-            queue_reset_kernel<<<1, 1, 0, st>>>(queue);
-            if (sorted) paint_tiles_queue_kernel<T, true><<<grid, kThreads, 0, st>>>(b, cur, queue, nblk);
-            else paint_tiles_queue_kernel<T, false><<<grid, kThreads, 0, st>>>(b, cur, queue, nblk);
-            prof_end(c, K_PAINT);
-            continue;
-        }
         const int tpb = (pv & 2) ? 4 : 1;
         set_map(b, R, [tpb](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / tpb; });
         b.pmap = 0;
