@@ -824,12 +824,27 @@ __global__ __launch_bounds__(kThreads) void gbar_tiles_kernel(MatterAdj<T> m) {
     __syncthreads();
     const int total = rpre[27];
     const double scale = adj_fixed_scale(m.maxbits, m.hbits);
-    int r = 0;
+    // range index per entry (idx only grows); the next entry is requested before the current
+    // one is added, as in the paint
+    int r = 0, nr = 0;
+    auto entry = [&](int idx, int &rr) {
+        while (idx >= rpre[rr + 1]) ++rr;
+        return rstart[rr] + (idx - rpre[rr]);
+    };
+    v4<T> ne{}, nw{};
+    if ((int)threadIdx.x < total) {
+        const int at = entry(threadIdx.x, nr);
+        ne = a.sorted[at];
+        nw = m.wsorted[at];
+    }
     for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-        while (idx >= rpre[r + 1]) ++r;
-        const int at = rstart[r] + (idx - rpre[r]);
-        const v4<T> e = a.sorted[at];
-        const v4<T> wv = m.wsorted[at];
+        r = nr;
+        const v4<T> e = ne, wv = nw;
+        if (idx + kThreads < total) {
+            const int at = entry(idx + kThreads, nr);
+            ne = a.sorted[at];
+            nw = m.wsorted[at];
+        }
         const double kw[3] = {(double)wv.x * scale, (double)wv.y * scale, (double)wv.z * scale};
         int lcell;
         if constexpr (sizeof(T) == 4) lcell = __float_as_int(e.w);
