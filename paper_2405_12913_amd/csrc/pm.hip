@@ -348,6 +348,8 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 // (fraction, local cell) entries of the Lagrangian-order scatter.
 // The work of logical block blk (TPB tiles); the paint kernels call it once (one block per
 // tile group) or in a loop over a work queue.
+constexpr int kPaintDepth = 4;              // entries in flight per lane
+
 template <typename T, int TPB, bool SORTED>
 __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur, int blk) {
     constexpr int G = kThreads / TPB;           // lanes per tile
@@ -378,55 +380,56 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
-    // idx only grows, so the range index r does too; its bounds, start and neighbour offset
-    // stay in registers until idx leaves the range. The next particle's entry is requested
-    // before the current one is added (one load in flight per lane while it works).
-    struct Slot {
-        int r, hi, base, dx, dy, dz;
-    };
-    auto advance = [&](int idx, Slot &q) {
-        if (idx >= q.hi) {
+    // idx only grows, so the range index does too: (fr, fhi, fbase) belong to the furthest
+    // entry requested and stay in registers until idx leaves that range. Each lane keeps
+    // kPaintDepth entries in flight: entry idx + kPaintDepth G is requested before entry idx
+    // is added (a tile's entries are then mostly all requested before the first returns).
+    int fr = -1, fhi = 0, fbase = 0;
+    auto request = [&](int idx, v4<T> &e, int &r) {
+        if (idx >= fhi) {
             do {
-                ++q.r;
-            } while (idx >= rpre[g][q.r + 1]);
-            q.hi = rpre[g][q.r + 1];
-            q.base = rstart[g][q.r] - rpre[g][q.r];
-            q.dx = rd[g][q.r][0];
-            q.dy = rd[g][q.r][1];
-            q.dz = rd[g][q.r][2];
+                ++fr;
+            } while (idx >= rpre[g][fr + 1]);
+            fhi = rpre[g][fr + 1];
+            fbase = rstart[g][fr] - rpre[g][fr];
         }
+        e = src[fbase + idx];
+        r = fr;
     };
-    Slot cs{-1, 0, 0, 0, 0, 0};
-    v4<T> e{};
-    if (lane < total) {
-        advance(lane, cs);
-        e = src[cs.base + lane];
+    v4<T> ev[kPaintDepth];
+    int rv[kPaintDepth];
+#pragma unroll
+    for (int k = 0; k < kPaintDepth; ++k) {
+        ev[k] = v4<T>{};
+        rv[k] = 0;
+        if (lane + k * G < total) request(lane + k * G, ev[k], rv[k]);
     }
-    for (int idx = lane; idx < total; idx += G) {
-        Slot ns = cs;
-        v4<T> ne{};
-        if (idx + G < total) {
-            advance(idx + G, ns);
-            ne = src[ns.base + idx + G];
+    for (int base = lane; base < total; base += kPaintDepth * G) {
+#pragma unroll
+        for (int k = 0; k < kPaintDepth; ++k) {
+            const int idx = base + k * G;
+            if (idx >= total) break;
+            v4<T> e = ev[k];
+            const int r = rv[k];
+            if (idx + kPaintDepth * G < total) request(idx + kPaintDepth * G, ev[k], rv[k]);
+            if constexpr (SORTED) {             // record -> (fractions, local cell)
+                int c[3];
+                T f[3];
+                record_cell<T>(cg, e, c, f);
+                e.x = f[0];
+                e.y = f[1];
+                e.z = f[2];
+                e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
+            }
+            if (r == 0) {                       // own tile, no upper face: 8 inside corners
+                if (narrow) paint_one<T, unsigned int, true>(fixed_bits, acc32, e, 0, 0, 0, scale, fscale);
+                else paint_one<T, unsigned long long, true>(fixed_bits, acc[g], e, 0, 0, 0, scale, fscale);
+            } else {
+                const int dx = rd[g][r][0], dy = rd[g][r][1], dz = rd[g][r][2];
+                if (narrow) paint_one<T, unsigned int, false>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
+                else paint_one<T, unsigned long long, false>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+            }
         }
-        if constexpr (SORTED) {                 // record -> (fractions, local cell)
-            int c[3];
-            T f[3];
-            record_cell<T>(cg, e, c, f);
-            e.x = f[0];
-            e.y = f[1];
-            e.z = f[2];
-            e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
-        }
-        if (cs.r == 0) {                        // own tile, no upper face: 8 inside corners
-            if (narrow) paint_one<T, unsigned int, true>(fixed_bits, acc32, e, cs.dx, cs.dy, cs.dz, scale, fscale);
-            else paint_one<T, unsigned long long, true>(fixed_bits, acc[g], e, cs.dx, cs.dy, cs.dz, scale, fscale);
-        } else {
-            if (narrow) paint_one<T, unsigned int, false>(fixed_bits, acc32, e, cs.dx, cs.dy, cs.dz, scale, fscale);
-            else paint_one<T, unsigned long long, false>(fixed_bits, acc[g], e, cs.dx, cs.dy, cs.dz, scale, fscale);
-        }
-        cs = ns;
-        e = ne;
     }
     __syncthreads();
     // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
