@@ -337,7 +337,8 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 
 // TPB tiles per workgroup (256 / TPB lanes each): when particles are sparse relative to
 // nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
-// the bin-range round trip) are shared by several tiles.
+// the bin-range round trip) are shared by several tiles; at one particle per node two tiles
+// per workgroup keep twice as many tiles resident per CU (wave slots, not LDS, limit it).
 // FP32 tiles that pull fewer than 1024 particles use 32-bit LDS sums: a node's sum is at
 // most the tile's particle count `total` (weights <= 1), so with 2^s <= 2^31 / (total + 1)
 // (here s = 21..24) no sum overflows, and each weight is rounded to 2^-(s+1) <= 2.4e-7,
@@ -1008,16 +1009,20 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
             prof_end(c, K_STATE_SCATTER);
         }
         prof_begin(c);
-        // variant bits: 0 = no XCD grouping, 1 = four tiles per workgroup
+        // variant: bit 0 = no XCD grouping; pv >> 1 = tiles per workgroup (0: one, 1: four,
+        // 2: two)
         const int pv = c->variant[K_PAINT];
         const bool sorted = args.state != STATE_LAGRANGIAN;
-        const int tpb = (pv & 2) ? 4 : 1;
+        const int tpb = (pv >> 1) == 1 ? 4 : (pv >> 1) == 2 ? 2 : 1;
         set_map(b, R, [tpb](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / tpb; });
         b.pmap = 0;
         b.xcd = (pv & 1) == 0 ? 1 : 0;
         if (tpb == 4) {
             if (sorted) paint_tiles_kernel<T, 4, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
             else paint_tiles_kernel<T, 4, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+        } else if (tpb == 2) {
+            if (sorted) paint_tiles_kernel<T, 2, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+            else paint_tiles_kernel<T, 2, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
         } else {
             if (sorted) paint_tiles_kernel<T, 1, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
             else paint_tiles_kernel<T, 1, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
