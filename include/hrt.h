@@ -138,7 +138,8 @@ int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *c
  * step's bins. The force is then formed per 8^3 tile inside the kick-drift and, for the
  * rays, on the lens planes only, so after such a call the G mesh is incomplete and
  * ray_step needs a new pm_force / pm_step first. 3 is 2 with the tile kick-drift run as a
- * persistent grid that takes tiles from a work queue. 1 runs pm_step's Lagrangian-order
+ * persistent, software-pipelined grid (each workgroup loads its next tile while it moves
+ * the current one). 1 runs pm_step's Lagrangian-order
  * kernels (with the same fused counting). 0 (default) takes 2 for calls of 8 steps or more
  * and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
  * call's work runs. */
@@ -234,7 +235,7 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
  * differ only in speed (matter_kd also has shapes with two particles per lane, paint_tiles
  * shapes that paint two or four tiles per workgroup). Tunable kernel ids: bin_count, bin_scatter
  * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (6), kd_tiles (4: the particle order of hrt_run, see
- * there, 3 being the paint-bin order with a persistent work-queue kick-drift; not chosen by
+ * there, 3 being the paint-bin order with a persistent pipelined kick-drift; not chosen by
  * hrt_autotune). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);
  * hrt_get_variant reads it. A new context starts with variant 0 everywhere. */

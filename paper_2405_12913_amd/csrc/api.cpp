@@ -44,7 +44,6 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     // sorted-state run: the second record buffer (the first is `sorted`) and both momentum
     // buffers, P x (4 + 3 + 3) values; a static run moves no particles
     L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * 10 * T);
-    L.queue = take(256);                                // work-queue counter of the persistent tile kernels
     L.total = off;
     return L;
 }
@@ -387,7 +386,7 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
     }
     // Particle order of the sequence (kd_tiles variant): 1 = Lagrangian order (pm_step's
     // kernels), 2 = paint-bin order (sorted-state kernels, G formed per tile and on the lens
-    // planes only), 3 = the same with the tile kick-drift as a persistent work-queue kernel,
+    // planes only), 3 = the same with the tile kick-drift as a persistent pipelined kernel,
     // 0 = bin order for sequences of kSortedMinSteps steps or more, whose
     // per-step saving outweighs the one-off cost of entering and leaving the sorted state.
     // All give the same bits.

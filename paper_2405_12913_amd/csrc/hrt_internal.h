@@ -45,7 +45,7 @@ struct PlaneEntry {
 
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
-    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, queue, total;
+    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, total;
     int64_t nbins;
 };
 Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);

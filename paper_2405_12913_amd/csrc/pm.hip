@@ -347,8 +347,7 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 // sums with the global scale.
 // SORTED: the particles are sorted-state records (buffer cur) rather than the binned
 // (fraction, local cell) entries of the Lagrangian-order scatter.
-// The work of logical block blk (TPB tiles); the paint kernels call it once (one block per
-// tile group) or in a loop over a work queue.
+// The work of logical block blk (TPB tiles).
 constexpr int kPaintDepth = 4;              // entries in flight per lane
 
 template <typename T, int TPB, bool SORTED>
@@ -447,22 +446,6 @@ template <typename T, int TPB, bool SORTED>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, int cur) {
     paint_tiles_body<T, TPB, SORTED>(b, cur, logical_block(b.xcd));
 }
-
-// Persistent form (used by the tile kick-drift): a grid of about one wave of resident
-// workgroups takes chunks of kQueueChunk logical blocks from a counter (*queue, zeroed before
-// the launch) until all nblocks are done (one atomic per chunk: same-address atomics
-// serialise in L2). Every tile is still done whole by one workgroup, so the result is the
-// same bits.
-constexpr int kQueueChunk = 16;
-__device__ __forceinline__ int next_chunk(unsigned int *queue, int *slot) {
-    if (threadIdx.x == 0) *slot = (int)atomicAdd(queue, (unsigned int)kQueueChunk);
-    __syncthreads();
-    const int base = *slot;
-    __syncthreads();                            // all lanes hold base before the slot is reused
-    return base;
-}
-
-__global__ void queue_reset_kernel(unsigned int *queue) { *queue = 0u; }
 
 // One lane per ILP particles, particles in Lagrangian order (patch maps), optionally with
 // XCD-grouped blocks so neighbouring particle patches (which read the same mesh rows)
@@ -589,115 +572,215 @@ __global__ __launch_bounds__(kThreads) void state_scatter_kernel(PartBatch<T> b,
 // from y0 - 2 and z0 - 2 (13 values), periodic. G is needed at the 9^3 nodes x0..x0+8 (a
 // cell's upper corners reach the next tile's first node), fd4 reaches 2 nodes further.
 constexpr int kPhiX = 16, kPhiYZ = 13, kGN = 9;
+constexpr int kPhiQuads = kPhiYZ * kPhiYZ * (kPhiX / 4);        // 676 aligned quadruples
+static_assert(kPhiQuads > 2 * kThreads && kPhiQuads <= 3 * kThreads, "three phi quadruples per lane");
 
-// With COUNT the moved particle is also counted into its bin for the next step. The work
-// of logical block blk (one tile).
+// Mesh offset of quadruple e of tile (tx, ty, tz)'s phi block.
+__device__ __forceinline__ size_t phi_quad_offset(int e, int tx, int ty, int tz, int n) {
+    const int m = n - 1, q = e & 3, row = e >> 2, ly = row % kPhiYZ, lz = row / kPhiYZ;
+    const int gx = (tx * kTile - 4 + 4 * q) & m;
+    const int gy = (ty * kTile - 2 + ly) & m, gz = (tz * kTile - 2 + lz) & m;
+    return ((size_t)gz * n + gy) * n + gx;
+}
+
+// G at the tile's 9^3 nodes from the phi block (every thread of the workgroup calls).
+template <typename T>
+__device__ __forceinline__ void tile_gradient(const v4<T> *ph4, v4<T> *gl, T inv12cell) {
+    const T *ph = reinterpret_cast<const T *>(ph4);
+    auto at = [&](int x, int y, int z) { return ph[(z * kPhiYZ + y) * kPhiX + x]; };
+    for (int e = threadIdx.x; e < kGN * kGN * kGN; e += kThreads) {
+        const int x = e % kGN + 4, y = (e / kGN) % kGN + 2, z = e / (kGN * kGN) + 2;
+        v4<T> o;
+        o.x = fd4<T>(at(x - 2, y, z), at(x - 1, y, z), at(x + 1, y, z), at(x + 2, y, z), inv12cell);
+        o.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), inv12cell);
+        o.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), inv12cell);
+        o.w = T(0);
+        gl[e] = o;
+    }
+}
+
+// One particle's state (sorted record and momenta) held in registers between its load and
+// its move.
+template <typename T>
+struct KdItem {
+    v4<T> rec;
+    T p[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void kd_fetch(const v4<T> *recs, const T *mom, size_t P, int j, int j1,
+                                         KdItem<T> &it) {
+    if (j < j1) {
+        it.rec = recs[j];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) it.p[d] = ld_stream(mom + d * P + j);
+    }
+}
+
+// Readout of G (from LDS) at particle j, kick, drift, store in place; with COUNT the moved
+// particle is also counted into its next bin. All 64 lanes of a wave call (j >= j1: none).
 template <typename T, bool COUNT>
-__device__ __forceinline__ void kd_tiles_body(const PartBatch<T> &b, int cur, int blk) {
-    __shared__ v4<T> ph4[kPhiYZ * kPhiYZ * (kPhiX / 4)];
+__device__ __forceinline__ void kd_move(v4<T> *recs, T *mom, size_t P, int j, int j1, KdItem<T> &it,
+                                        const v4<T> *gl, T K, T D, const CellGeom<T> &cg, int lnt,
+                                        unsigned int *count) {
+    int key = -1;
+    if (j < j1) {
+        v4<T> rec = it.rec;
+        int c[3];
+        T f[3];
+        record_cell<T>(cg, rec, c, f);
+        const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGN + (c[0] & 7);
+        v4<T> g[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGN + (k & 1)];
+        T sv[3] = {rec.x, rec.y, rec.z};
+        cic_kick_drift<T>(f, g, K, D, sv, it.p);
+        rec.x = sv[0];
+        rec.y = sv[1];
+        rec.z = sv[2];
+        asm volatile("" : "+v"(rec.w));         // store the whole record: no partial lines
+        recs[j] = rec;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom + d * P + j);
+        if (COUNT) {
+            record_cell<T>(cg, rec, c, f);
+            key = bin_key(c, lnt);
+        }
+    }
+    if (COUNT) wave_aggregated_increment<false>(count, key);
+}
+
+// Load of a value that is the same for the whole wave and that no kernel running alongside
+// writes (the bin offsets, written by an earlier launch), through the constant address space,
+// so it is a scalar load: it is not counted with the vector memory operations, and waiting
+// for it does not wait for the stores the wave has issued.
+__device__ __forceinline__ unsigned int uniform_load(const unsigned int *p) {
+    return *(const __attribute__((address_space(4))) unsigned int *)p;
+}
+
+// One workgroup per tile (logical block blk).
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int cur) {
+    __shared__ v4<T> ph4[kPhiQuads];
     __shared__ v4<T> gl[kGN * kGN * kGN];
+    const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
-    const int n = a.n, nt = n / kTile, m = n - 1;
+    const int n = a.n, nt = n / kTile;
     const size_t P = (size_t)a.P;
     const int t = blk - b.map.start[rr];
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
-    const int j0 = (int)a.offs[t * 8], j1 = (int)a.offs[t * 8 + 8];
+    const int j0 = (int)uniform_load(a.offs + t * 8), j1 = (int)uniform_load(a.offs + t * 8 + 8);
     if (j0 == j1) return;                       // empty tile (uniform over the block)
     v4<T> *const recs = a.rec[cur];
     T *const mom = a.mom[cur];
     // A lane handles two particles per trip (j and j + 256). The first trip's state is
     // requested before the phi block, so those loads overlap the G set-up; every later trip
     // requests the next one's before working on its own.
-    struct Item {
-        v4<T> rec;
-        T p[3];
-    };
-    auto fetch = [&](int j, Item &it) {
-        if (j < j1) {
-            it.rec = recs[j];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) it.p[d] = ld_stream(mom + d * P + j);
-        }
-    };
-    Item cur0, cur1;
-    fetch(j0 + (int)threadIdx.x, cur0);
-    fetch(j0 + kThreads + (int)threadIdx.x, cur1);
-    for (int e = threadIdx.x; e < kPhiYZ * kPhiYZ * (kPhiX / 4); e += kThreads) {
-        const int q = e & 3, row = e >> 2, ly = row % kPhiYZ, lz = row / kPhiYZ;
-        const int gx = (tx * kTile - 4 + 4 * q) & m;
-        const int gy = (ty * kTile - 2 + ly) & m, gz = (tz * kTile - 2 + lz) & m;
-        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + ((size_t)gz * n + gy) * n + gx);
-    }
+    KdItem<T> cur0, cur1;
+    kd_fetch<T>(recs, mom, P, j0 + (int)threadIdx.x, j1, cur0);
+    kd_fetch<T>(recs, mom, P, j0 + kThreads + (int)threadIdx.x, j1, cur1);
+    for (int e = threadIdx.x; e < kPhiQuads; e += kThreads)
+        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset(e, tx, ty, tz, n));
     __syncthreads();
-    const T *ph = reinterpret_cast<const T *>(ph4);
-    auto at = [&](int x, int y, int z) { return ph[(z * kPhiYZ + y) * kPhiX + x]; };
-    for (int e = threadIdx.x; e < kGN * kGN * kGN; e += kThreads) {
-        const int x = e % kGN + 4, y = (e / kGN) % kGN + 2, z = e / (kGN * kGN) + 2;
-        v4<T> o;
-        o.x = fd4<T>(at(x - 2, y, z), at(x - 1, y, z), at(x + 1, y, z), at(x + 2, y, z), a.inv12cell);
-        o.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), a.inv12cell);
-        o.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), a.inv12cell);
-        o.w = T(0);
-        gl[e] = o;
-    }
+    tile_gradient<T>(ph4, gl, a.inv12cell);
     __syncthreads();
-    unsigned int *const count = a.count;
     const T K = a.K, D = a.D;
     const CellGeom<T> cg = geom_of(a);
     const int lnt = a.lnt;
-    auto move = [&](int j, Item &it) {
-        int key = -1;
-        if (j < j1) {
-            v4<T> rec = it.rec;
-            int c[3];
-            T f[3];
-            record_cell<T>(cg, rec, c, f);
-            const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGN + (c[0] & 7);
-            v4<T> g[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGN + (k & 1)];
-            T sv[3] = {rec.x, rec.y, rec.z};
-            cic_kick_drift<T>(f, g, K, D, sv, it.p);
-            rec.x = sv[0];
-            rec.y = sv[1];
-            rec.z = sv[2];
-            asm volatile("" : "+v"(rec.w));     // store the whole record: no partial lines
-            recs[j] = rec;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom + d * P + j);
-            if (COUNT) {
-                record_cell<T>(cg, rec, c, f);
-                key = bin_key(c, lnt);
-            }
-        }
-        if (COUNT) wave_aggregated_increment<false>(count, key);
-    };
     for (int base = j0; base < j1; base += 2 * kThreads) {   // same trip count for every lane
-        Item nxt0, nxt1;
-        fetch(base + 2 * kThreads + (int)threadIdx.x, nxt0);
-        fetch(base + 3 * kThreads + (int)threadIdx.x, nxt1);
-        move(base + (int)threadIdx.x, cur0);
-        move(base + kThreads + (int)threadIdx.x, cur1);
+        KdItem<T> nxt0, nxt1;
+        kd_fetch<T>(recs, mom, P, base + 2 * kThreads + (int)threadIdx.x, j1, nxt0);
+        kd_fetch<T>(recs, mom, P, base + 3 * kThreads + (int)threadIdx.x, j1, nxt1);
+        kd_move<T, COUNT>(recs, mom, P, base + (int)threadIdx.x, j1, cur0, gl, K, D, cg, lnt, a.count);
+        kd_move<T, COUNT>(recs, mom, P, base + kThreads + (int)threadIdx.x, j1, cur1, gl, K, D, cg, lnt, a.count);
         cur0 = nxt0;
         cur1 = nxt1;
     }
 }
 
-template <typename T, bool COUNT>
-__global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int cur) {
-    kd_tiles_body<T, COUNT>(b, cur, logical_block(b.xcd));
+// Requests tile t (realisation rr, sorted slots j0..j1)'s phi block and first 512 particles
+// into registers (nothing for an empty tile).
+template <typename T>
+__device__ __forceinline__ void kd_request(const PartBatch<T> &b, int cur, int rr, int t, int j0, int j1,
+                                           v4<T> &f0, v4<T> &f1, v4<T> &f2, KdItem<T> &i0, KdItem<T> &i1) {
+    if (j0 == j1) return;                       // uniform
+    const Particles<T> &a = b.r[rr];
+    const int nt = a.n / kTile;
+    const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+    kd_fetch<T>(a.rec[cur], a.mom[cur], (size_t)a.P, j0 + (int)threadIdx.x, j1, i0);
+    kd_fetch<T>(a.rec[cur], a.mom[cur], (size_t)a.P, j0 + kThreads + (int)threadIdx.x, j1, i1);
+    const int e = (int)threadIdx.x;
+    f0 = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset(e, tx, ty, tz, a.n));
+    f1 = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset(e + kThreads, tx, ty, tz, a.n));
+    if (e + 2 * kThreads < kPhiQuads)
+        f2 = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset(e + 2 * kThreads, tx, ty, tz, a.n));
 }
 
+// Persistent, software-pipelined form: a grid of W resident workgroups, workgroup w taking
+// tiles w, w + W, w + 2W, ... (logical numbering, XCD-grouped). While one tile's particles
+// are moved, the phi block and first 512 particles of the workgroup's next tile are already
+// requested into registers, so a tile's loads wait behind the previous tile's work rather
+// than in front of its own. Particles past a tile's first 512 are loaded and moved in trips
+// of 256 afterwards. Every tile is still done whole by one workgroup with the same
+// arithmetic, so the result is the same bits.
 template <typename T, bool COUNT>
-__global__ __launch_bounds__(kThreads) void kd_tiles_queue_kernel(PartBatch<T> b, int cur,
-                                                                  unsigned int *queue, int nblocks) {
-    __shared__ int slot;
-    for (int base = next_chunk(queue, &slot); base < nblocks; base = next_chunk(queue, &slot))
-        for (int blk = base; blk < base + kQueueChunk && blk < nblocks; ++blk) {
-            kd_tiles_body<T, COUNT>(b, cur, blk);
-            __syncthreads();                    // LDS of this tile used up before the next fills it
+__global__ __launch_bounds__(kThreads) void kd_tiles_stream_kernel(PartBatch<T> b, int cur, int nblocks) {
+    __shared__ v4<T> ph4[kPhiQuads];
+    __shared__ v4<T> gl[kGN * kGN * kGN];
+    struct TileRef {
+        int rr, t, j0, j1;
+    };
+    auto tile_at = [&](int L) {
+        TileRef q{0, 0, 0, 0};
+        if (L < nblocks) {
+            q.rr = real_of(b.map, L);
+            q.t = L - b.map.start[q.rr];
+            q.j0 = (int)uniform_load(b.r[q.rr].offs + q.t * 8);
+            q.j1 = (int)uniform_load(b.r[q.rr].offs + q.t * 8 + 8);
         }
+        return q;
+    };
+    v4<T> f0{}, f1{}, f2{};                     // phi quadruples e, e + 256, e + 512 of lane e
+    KdItem<T> nx0, nx1;
+    const int W = (int)gridDim.x;
+    int L = logical_block(b.xcd);
+    TileRef cq = tile_at(L);
+    kd_request<T>(b, cur, cq.rr, cq.t, cq.j0, cq.j1, f0, f1, f2, nx0, nx1);
+    for (; L < nblocks; L += W) {
+        const TileRef nq = tile_at(L + W);
+        __syncthreads();                        // the previous tile's LDS reads are done
+        const bool work = cq.j0 != cq.j1;       // uniform
+        if (work) {
+            const int e = (int)threadIdx.x;
+            ph4[e] = f0;
+            ph4[e + kThreads] = f1;
+            if (e + 2 * kThreads < kPhiQuads) ph4[e + 2 * kThreads] = f2;
+        }
+        KdItem<T> c0 = nx0, c1 = nx1;
+        kd_request<T>(b, cur, nq.rr, nq.t, nq.j0, nq.j1, f0, f1, f2, nx0, nx1);
+        if (work) {
+            const Particles<T> &a = b.r[cq.rr];
+            const size_t P = (size_t)a.P;
+            v4<T> *const recs = a.rec[cur];
+            T *const mom = a.mom[cur];
+            const T K = a.K, D = a.D;
+            const CellGeom<T> cg = geom_of(a);
+            const int lnt = a.lnt;
+            __syncthreads();
+            tile_gradient<T>(ph4, gl, a.inv12cell);
+            __syncthreads();
+            kd_move<T, COUNT>(recs, mom, P, cq.j0 + (int)threadIdx.x, cq.j1, c0, gl, K, D, cg, lnt, a.count);
+            kd_move<T, COUNT>(recs, mom, P, cq.j0 + kThreads + (int)threadIdx.x, cq.j1, c1, gl, K, D, cg, lnt,
+                              a.count);
+            for (int base = cq.j0 + 2 * kThreads; base < cq.j1; base += kThreads) {
+                KdItem<T> it;
+                kd_fetch<T>(recs, mom, P, base + (int)threadIdx.x, cq.j1, it);
+                kd_move<T, COUNT>(recs, mom, P, base + (int)threadIdx.x, cq.j1, it, gl, K, D, cg, lnt, a.count);
+            }
+        }
+        cq = nq;
+    }
 }
 
 // Sorted slot j of buffer cur back to the caller's arrays at the record's lattice index.
@@ -966,6 +1049,22 @@ void launch_scan(hrt_ctx *c, PartBatch<T> &b, int R) {
 }
 
 // Workgroups of a persistent tile kernel: per_cu resident per compute unit.
+// Workgroups of the pipelined tile kick-drift that fit on one CU at once (its grid is one
+// such wave over all CUs), from the runtime's occupancy calculator (4 if that fails).
+template <typename T>
+int kd_stream_per_cu(bool count) {
+    static int cached[2] = {0, 0};
+    int &v = cached[count ? 1 : 0];
+    if (v == 0) {
+        int nb = 0;
+        const hipError_t e =
+            count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kd_tiles_stream_kernel<T, true>, kThreads, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kd_tiles_stream_kernel<T, false>, kThreads, 0);
+        v = (e == hipSuccess && nb > 0) ? nb : 4;
+    }
+    return v;
+}
+
 inline int resident_blocks(int per_cu) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1050,13 +1149,11 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             set_map(b, R, tiles);
             b.pmap = 0;
             b.xcd = 1;
-            if (c->variant[K_KD_TILES] == 3) {          // persistent work-queue form
-                unsigned int *queue = reinterpret_cast<unsigned int *>(c->re[r0].ws + c->re[r0].lay.queue);
+            if (c->variant[K_KD_TILES] == 3) {          // persistent, software-pipelined form
                 const int nblk = b.map.start[R];
-                const int grid = std::min(nblk, resident_blocks(7));
-                queue_reset_kernel<<<1, 1, 0, c->stream>>>(queue);
-                if (args.count_next) kd_tiles_queue_kernel<T, true><<<grid, kThreads, 0, c->stream>>>(b, args.cur, queue, nblk);
-                else kd_tiles_queue_kernel<T, false><<<grid, kThreads, 0, c->stream>>>(b, args.cur, queue, nblk);
+                const int grid = std::min(nblk, resident_blocks(kd_stream_per_cu<T>(args.count_next)));
+                if (args.count_next) kd_tiles_stream_kernel<T, true><<<grid, kThreads, 0, c->stream>>>(b, args.cur, nblk);
+                else kd_tiles_stream_kernel<T, false><<<grid, kThreads, 0, c->stream>>>(b, args.cur, nblk);
             } else if (args.count_next) {
                 kd_tiles_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
             } else {

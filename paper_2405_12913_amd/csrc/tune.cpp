@@ -30,7 +30,7 @@ int variants_of(int id) {
         case K_RAY_STEP: return 6;
         case K_PAINT: return 6;
         case hrt::K_KD_TILES: return 4;      // run order: 0 automatic, 1 Lagrangian, 2 sorted state,
-                                             // 3 sorted state with a work-queue kick-drift
+                                             // 3 sorted state with a pipelined persistent kick-drift
         default: return (id >= 0 && id < K_COUNT) ? 1 : 0;
     }
 }
