@@ -64,14 +64,42 @@ __device__ __forceinline__ void dft(c2<T> *v, const c2<T> *__restrict__ tw = nul
     }
 }
 
-// One Stockham stage over LINES lines of length L in LDS (line stride LS), then the next.
-// tw (in LDS) holds W_n^m = exp(-2 pi i m / n); W_L^m = tw[m * twmul] with twmul = n / L.
-template <typename T, int L, int LINES, bool INV, int Ns>
+// Radix of the Stockham stage that starts at span Ns: 8 where it keeps every thread busy
+// (LINES x L/8 butterflies), else 4, a last 2 when needed.
+template <int L, int LINES>
+__host__ __device__ constexpr int radix_at(int Ns) {
+    return (Ns * 8 <= L && LINES * (L / 8) >= kThreads) ? 8 : (Ns * 4 <= L) ? 4 : 2;
+}
+// Span of the last stage (the one whose outputs are in natural order).
+template <int L, int LINES>
+__host__ __device__ constexpr int last_span() {
+    int Ns = 1;
+    while (Ns * radix_at<L, LINES>(Ns) < L) Ns *= radix_at<L, LINES>(Ns);
+    return Ns;
+}
+
+// Butterfly j of the stage at span Ns: v[r] = x[j + r L/R] on entry; twiddles W_{Ns R}^{kk r}
+// (kk = j mod Ns; tw in LDS holds W_n^m, W_L^m = tw[m twmul]) on the inputs, then the R-point
+// DFT. Its outputs belong at (j / Ns) Ns R + kk + r Ns.
+template <typename T, int L, int R, bool INV, int Ns>
+__device__ __forceinline__ void butterfly(c2<T> *v, int j, const c2<T> *__restrict__ tw, int twmul) {
+    const int kk = j % Ns;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        c2<T> w = tw[(kk * r * (L / (Ns * R))) * twmul];
+        if (INV) w.y = -w.y;
+        v[r] = cmul<T>(v[r], w);
+    }
+    dft<T, R, INV>(v, tw, twmul * (L / 8));
+}
+
+// One Stockham stage over LINES lines of length L in LDS (line stride LS), then the next
+// (up to the last stage, or up to but not including it when STOP_BEFORE_LAST).
+template <typename T, int L, int LINES, bool INV, int Ns, bool STOP_BEFORE_LAST = false>
 __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
                                           int twmul) {
-    if constexpr (Ns < L) {
-        // radix 8 where it keeps every thread busy (LINES x L/8 butterflies), else 4, last 2
-        constexpr int R = (Ns * 8 <= L && LINES * (L / 8) >= kThreads) ? 8 : (Ns * 4 <= L) ? 4 : 2;
+    if constexpr (Ns < L && !(STOP_BEFORE_LAST && Ns == last_span<L, LINES>())) {
+        constexpr int R = radix_at<L, LINES>(Ns);
         constexpr int NB = LINES * (L / R);
         constexpr int BF = (NB + kThreads - 1) / kThreads;
         c2<T> v[BF][R];
@@ -80,19 +108,10 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__res
             const int b = threadIdx.x + k * kThreads;
             if (b < NB) {
                 const int line = b / (L / R), j = b % (L / R);
-                const int kk = j % Ns;
                 const c2<T> *src = buf + line * LS;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    c2<T> x = src[j + r * (L / R)];
-                    if (r > 0) {
-                        c2<T> w = tw[(kk * r * (L / (Ns * R))) * twmul];
-                        if (INV) w.y = -w.y;
-                        x = cmul<T>(x, w);
-                    }
-                    v[k][r] = x;
-                }
-                dft<T, R, INV>(v[k], tw, twmul * (L / 8));
+                for (int r = 0; r < R; ++r) v[k][r] = src[j + r * (L / R)];
+                butterfly<T, L, R, INV, Ns>(v[k], j, tw, twmul);
             }
         }
         __syncthreads();
@@ -108,7 +127,96 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__res
             }
         }
         __syncthreads();
-        fft_stage<T, L, LINES, INV, Ns * R>(buf, LS, tw, twmul);
+        fft_stage<T, L, LINES, INV, Ns * R, STOP_BEFORE_LAST>(buf, LS, tw, twmul);
+    }
+}
+
+// Butterfly b of a stage that reads or writes global memory directly: LINE_FAST puts
+// consecutive butterflies on consecutive lines (for lines that are strided in memory, so a
+// wave's accesses to one element index form contiguous segments), else on consecutive j
+// (contiguous lines).
+template <int L, int LINES, int R, bool LINE_FAST>
+__device__ __forceinline__ void global_bfly(int b, int &line, int &j) {
+    if (LINE_FAST) {
+        line = b % LINES;
+        j = b / LINES;
+    } else {
+        line = b / (L / R);
+        j = b % (L / R);
+    }
+}
+
+// First stage with its inputs read from global memory: ld(line, m) is element m of the
+// block's line `line` (never called for lines with !valid(line)); the outputs go to LDS.
+// The loads are issued first, then the block synchronises (which also makes the twiddles
+// the caller staged visible), then the butterflies run.
+template <typename T, int L, int LINES, bool INV, bool LINE_FAST, class Ld, class Valid>
+__device__ __forceinline__ void first_stage_global(c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
+                                                   int twmul, Ld ld, Valid valid) {
+    constexpr int R = radix_at<L, LINES>(1);
+    constexpr int NB = LINES * (L / R);
+    constexpr int BF = (NB + kThreads - 1) / kThreads;
+    c2<T> v[BF][R];
+#pragma unroll
+    for (int k = 0; k < BF; ++k) {
+        const int b = threadIdx.x + k * kThreads;
+        int line, j;
+        global_bfly<L, LINES, R, LINE_FAST>(b, line, j);
+        if (b < NB && valid(line)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[k][r] = ld(line, j + r * (L / R));
+        }
+    }
+    __syncthreads();                            // twiddles staged by the caller
+#pragma unroll
+    for (int k = 0; k < BF; ++k) {
+        const int b = threadIdx.x + k * kThreads;
+        int line, j;
+        global_bfly<L, LINES, R, LINE_FAST>(b, line, j);
+        if (b < NB && valid(line)) {
+            butterfly<T, L, R, INV, 1>(v[k], j, tw, twmul);
+            c2<T> *dst = buf + line * LS + j * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r] = v[k][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Last stage, inputs from LDS, outputs handed to st(line, m, value) in natural order m
+// (never for lines with !valid(line)). With SYNC the block synchronises between reading
+// and handing out (for a st that writes the same LDS buffer).
+template <typename T, int L, int LINES, bool INV, bool LINE_FAST, bool SYNC, class St, class Valid>
+__device__ __forceinline__ void last_stage_out(const c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
+                                               int twmul, St st, Valid valid) {
+    constexpr int Ns = last_span<L, LINES>();
+    constexpr int R = radix_at<L, LINES>(Ns);
+    static_assert(Ns * R == L, "last stage spans the line");
+    constexpr int NB = LINES * (L / R);
+    constexpr int BF = (NB + kThreads - 1) / kThreads;
+    c2<T> v[BF][R];
+#pragma unroll
+    for (int k = 0; k < BF; ++k) {
+        const int b = threadIdx.x + k * kThreads;
+        int line, j;
+        global_bfly<L, LINES, R, LINE_FAST>(b, line, j);
+        if (b < NB && valid(line)) {
+            const c2<T> *src = buf + line * LS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[k][r] = src[j + r * (L / R)];
+            butterfly<T, L, R, INV, Ns>(v[k], j, tw, twmul);
+        }
+    }
+    if (SYNC) __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BF; ++k) {
+        const int b = threadIdx.x + k * kThreads;
+        int line, j;
+        global_bfly<L, LINES, R, LINE_FAST>(b, line, j);
+        if (b < NB && valid(line)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) st(line, j + r * Ns, v[k][r]);
+        }
     }
 }
 
@@ -168,12 +276,16 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
     c2<T> *__restrict__ out = fb.spec[r];
     const int row0 = (blk % fb.bpr) * ROWS;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
-    for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
-        const int rr = e / L, m = e % L;
-        buf[rr * LS + m] = reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + rr) * N)[m];
+    auto ld = [&](int rr, int m) { return reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + rr) * N)[m]; };
+    if constexpr (last_span<L, ROWS>() > 1) {
+        // the first stage reads the packed rows from HBM directly, the rest run in LDS
+        first_stage_global<T, L, ROWS, false, false>(buf, LS, tw, N / L, ld, [](int) { return true; });
+        fft_stage<T, L, ROWS, false, radix_at<L, ROWS>(1)>(buf, LS, tw, N / L);
+    } else {                                    // one stage (N = 16): staged through LDS
+        for (int e = threadIdx.x; e < ROWS * L; e += kThreads) buf[(e / L) * LS + e % L] = ld(e / L, e % L);
+        __syncthreads();
+        fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, N / L);
     }
-    __syncthreads();
-    fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, N / L);
     // split step: X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) W_N^k (Z[k] - conj Z[L-k]),
     // each thread owns the pair (k, L-k); X[L] (Nyquist) comes from Z[0].
     for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
@@ -239,42 +351,51 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
         }
     }
     __syncthreads();
-    fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, N / L);
-    for (int e = threadIdx.x; e < ROWS * L; e += kThreads) {
-        const int rr = e / L, m = e % L;
-        reinterpret_cast<c2<T> *>(out + (size_t)(row0 + rr) * N)[m] = buf[rr * LS + m];
+    auto st = [&](int rr, int m, const c2<T> &v) { reinterpret_cast<c2<T> *>(out + (size_t)(row0 + rr) * N)[m] = v; };
+    if constexpr (last_span<L, ROWS>() > 1) {
+        // all stages but the last in LDS; the last writes the rows of phi to HBM directly
+        fft_stage<T, L, ROWS, true, 1, true>(buf, LS, tw, N / L);
+        last_stage_out<T, L, ROWS, true, false, false>(buf, LS, tw, N / L, st, [](int) { return true; });
+    } else {                                    // one stage (N = 16): staged through LDS
+        fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, N / L);
+        for (int e = threadIdx.x; e < ROWS * L; e += kThreads) st(e / L, e % L, buf[(e / L) * LS + e % L]);
     }
 }
 
-// FFT along y of the transposed spectrum C[kx][z][y]: lines are contiguous.
+// FFT along y of the transposed spectrum C[kx][z][y]: lines are contiguous. The first
+// stage reads the lines from HBM and the last writes them back (no staging pass through
+// LDS); the stages in between work in LDS.
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
     constexpr int LINES = Cfg<T, N>::YLINES, LS = N + 1;
     constexpr int TOTAL = (N / 2 + 1) * N;
+    static_assert(last_span<N, LINES>() > 1, "at least two stages");
     __shared__ c2<T> buf[LINES * LS];
     __shared__ c2<T> tw[N];
     const int r = blockIdx.x / fb.bpr;
     c2<T> *__restrict__ data = fb.spec[r];
     const int l0 = (blockIdx.x % fb.bpr) * LINES;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int li = e / N, m = e % N;
-        if (l0 + li < TOTAL) buf[li * LS + m] = data[(size_t)(l0 + li) * N + m];
-    }
-    __syncthreads();
-    fft_stage<T, N, LINES, INV, 1>(buf, LS, tw, 1);
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int li = e / N, m = e % N;
-        if (l0 + li < TOTAL) data[(size_t)(l0 + li) * N + m] = buf[li * LS + m];
-    }
+    auto valid = [&](int li) { return l0 + li < TOTAL; };
+    first_stage_global<T, N, LINES, INV, false>(
+        buf, LS, tw, 1, [&](int li, int m) { return data[(size_t)(l0 + li) * N + m]; }, valid);
+    fft_stage<T, N, LINES, INV, radix_at<N, LINES>(1), true>(buf, LS, tw, 1);
+    last_stage_out<T, N, LINES, INV, false, false>(
+        buf, LS, tw, 1, [&](int li, int m, const c2<T> &v) { data[(size_t)(l0 + li) * N + m] = v; },
+        valid);
 }
 
 // FFT along z; MODE 0: forward, 1: inverse, 2: forward, multiply by -1/(k^2 n^3) (k = 0
-// -> 0), inverse. Line l = kx * N + y, element stride N.
+// -> 0), inverse. Line l = kx * N + y, element stride N. The first stage reads HBM and the
+// last writes it (consecutive lanes on consecutive lines: LINES consecutive y form one
+// contiguous segment per z); MODE 2 applies the multiply to the forward transform's last
+// stage as it writes LDS. Line stride N + 9 (complex) spreads the line-strided and the
+// Stockham accesses over the LDS banks.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
-    constexpr int LINES = Cfg<T, N>::ZLINES, LS = N + 1;
+    constexpr int LINES = Cfg<T, N>::ZLINES, LS = N + 9;
     constexpr int TOTAL = (N / 2 + 1) * N;
+    static_assert(last_span<N, LINES>() > 1, "at least two stages");
     __shared__ c2<T> buf[LINES * LS];
     __shared__ c2<T> tw[N];
     // A block's rows are LINES consecutive y (LINES x 8 bytes of a 128-byte line in FP32):
@@ -285,29 +406,32 @@ __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
     c2<T> *__restrict__ data = fb.spec[r];
     const int l0 = (blk % fb.bpr) * LINES;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int z = e / LINES, li = e % LINES, l = l0 + li;
-        if (l < TOTAL) buf[li * LS + z] = data[((size_t)(l / N) * N + z) * N + (l % N)];
-    }
-    __syncthreads();
-    fft_stage<T, N, LINES, MODE == 1, 1>(buf, LS, tw, 1);
+    auto at = [&](int li, int z) {
+        const int l = l0 + li;
+        return ((size_t)(l / N) * N + z) * N + (l % N);
+    };
+    auto valid = [&](int li) { return l0 + li < TOTAL; };
+    auto store = [&](int li, int z, const c2<T> &v) { data[at(li, z)] = v; };
+    first_stage_global<T, N, LINES, MODE == 1, true>(
+        buf, LS, tw, 1, [&](int li, int z) { return data[at(li, z)]; }, valid);
+    fft_stage<T, N, LINES, MODE == 1, radix_at<N, LINES>(1), true>(buf, LS, tw, 1);
     if constexpr (MODE == 2) {
         const double kf2 = fb.kf2[r], inv_n3 = 1.0 / ((double)N * N * N);
-        for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-            const int li = e / N, kz = e % N, l = l0 + li;
-            const int kx = l / N, ky = l % N;
-            const int fy = ky <= N / 2 ? ky : ky - N, fz = kz <= N / 2 ? kz : kz - N;
-            const double k2 = kf2 * (double)(kx * kx + fy * fy + fz * fz);
-            const T g = k2 > 0.0 ? (T)(-inv_n3 / k2) : T(0);
-            c2<T> v = buf[li * LS + kz];
-            buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
-        }
+        last_stage_out<T, N, LINES, false, false, true>(
+            buf, LS, tw, 1,
+            [&](int li, int kz, const c2<T> &v) {
+                const int l = l0 + li, kx = l / N, ky = l % N;
+                const int fy = ky <= N / 2 ? ky : ky - N, fz = kz <= N / 2 ? kz : kz - N;
+                const double k2 = kf2 * (double)(kx * kx + fy * fy + fz * fz);
+                const T g = k2 > 0.0 ? (T)(-inv_n3 / k2) : T(0);
+                buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
+            },
+            valid);
         __syncthreads();
-        fft_stage<T, N, LINES, true, 1>(buf, LS, tw, 1);
-    }
-    for (int e = threadIdx.x; e < LINES * N; e += kThreads) {
-        const int z = e / LINES, li = e % LINES, l = l0 + li;
-        if (l < TOTAL) data[((size_t)(l / N) * N + z) * N + (l % N)] = buf[li * LS + z];
+        fft_stage<T, N, LINES, true, 1, true>(buf, LS, tw, 1);
+        last_stage_out<T, N, LINES, true, true, false>(buf, LS, tw, 1, store, valid);
+    } else {
+        last_stage_out<T, N, LINES, MODE == 1, true, false>(buf, LS, tw, 1, store, valid);
     }
 }
 
