@@ -327,27 +327,43 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
     T *__restrict__ out = fb.rout[r];
     const int row0 = (blk % fb.bpr) * ROWS;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
-    for (int e = threadIdx.x; e < ROWS * (L + 1); e += kThreads) {
-        const int kx = e / ROWS, rr = e % ROWS;
+    // Z[k] = (X[k] + conj X[L-k]) + i W_N^{-k} (X[k] - conj X[L-k]), pairs (k, L-k), read
+    // straight from the transposed spectrum (consecutive lanes on consecutive rows of one k,
+    // so a wave's loads form segments of ROWS values); the loads go out before the barrier
+    // that makes the twiddles visible.
+    constexpr int NP = ROWS * (L / 2 + 1), PI = (NP + kThreads - 1) / kThreads;
+    auto get = [&](int rr, int kx) {
         const int row = row0 + rr, z = row / N, y = row % N;
-        buf[rr * LS + kx] = in[((size_t)kx * N + z) * N + y];
+        return in[((size_t)kx * N + z) * N + y];
+    };
+    c2<T> xk[PI], xp[PI];
+#pragma unroll
+    for (int q = 0; q < PI; ++q) {
+        const int e = (int)threadIdx.x + q * kThreads;
+        if (e < NP) {
+            const int rr = e % ROWS, k = e / ROWS;
+            xk[q] = get(rr, k);
+            xp[q] = get(rr, L - k);
+        }
     }
     __syncthreads();
-    // Z[k] = (X[k] + conj X[L-k]) + i W_N^{-k} (X[k] - conj X[L-k]), pairs (k, L-k)
-    for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
-        const int rr = e / (L / 2 + 1), k = e % (L / 2 + 1);
-        c2<T> *line = buf + rr * LS;
-        const c2<T> xk = line[k], xp = line[L - k];
-        const c2<T> w = tw[k];
-        const c2<T> wc{w.x, -w.y};
-        const c2<T> A{xk.x + xp.x, xk.y - xp.y}, B{xk.x - xp.x, xk.y + xp.y};
-        const c2<T> wB = cmul<T>(wc, B);
-        line[k] = c2<T>{A.x - wB.y, A.y + wB.x};
-        if (k != 0 && k != L - k) {
-            // Z[L-k] = conj(A) + i (-w) (-conj(B))
-            const c2<T> Ap{A.x, -A.y}, Bp{-B.x, B.y}, wp{-w.x, -w.y};
-            const c2<T> wBp = cmul<T>(wp, Bp);
-            line[L - k] = c2<T>{Ap.x - wBp.y, Ap.y + wBp.x};
+#pragma unroll
+    for (int q = 0; q < PI; ++q) {
+        const int e = (int)threadIdx.x + q * kThreads;
+        if (e < NP) {
+            const int rr = e % ROWS, k = e / ROWS;
+            c2<T> *line = buf + rr * LS;
+            const c2<T> w = tw[k];
+            const c2<T> wc{w.x, -w.y};
+            const c2<T> A{xk[q].x + xp[q].x, xk[q].y - xp[q].y}, B{xk[q].x - xp[q].x, xk[q].y + xp[q].y};
+            const c2<T> wB = cmul<T>(wc, B);
+            line[k] = c2<T>{A.x - wB.y, A.y + wB.x};
+            if (k != 0 && k != L - k) {
+                // Z[L-k] = conj(A) + i (-w) (-conj(B))
+                const c2<T> Ap{A.x, -A.y}, Bp{-B.x, B.y}, wp{-w.x, -w.y};
+                const c2<T> wBp = cmul<T>(wp, Bp);
+                line[L - k] = c2<T>{Ap.x - wBp.y, Ap.y + wBp.x};
+            }
         }
     }
     __syncthreads();
