@@ -586,16 +586,33 @@ __device__ __forceinline__ size_t phi_quad_offset(int e, int tx, int ty, int tz,
 // G at the tile's 9^3 nodes from the phi block (every thread of the workgroup calls).
 template <typename T>
 __device__ __forceinline__ void tile_gradient(const v4<T> *ph4, v4<T> *gl, T inv12cell) {
-    const T *ph = reinterpret_cast<const T *>(ph4);
-    auto at = [&](int x, int y, int z) { return ph[(z * kPhiYZ + y) * kPhiX + x]; };
-    for (int e = threadIdx.x; e < kGN * kGN * kGN; e += kThreads) {
-        const int x = e % kGN + 4, y = (e / kGN) % kGN + 2, z = e / (kGN * kGN) + 2;
+    // A lane takes four nodes along x (one aligned phi quadruple q = 1..3 of a row (y, z);
+    // q = 3 holds only the last node, x = 12) and reads whole quadruples: the row's q - 1,
+    // q and q + 1 for the x differences, quadruple q of the rows y +- 1, 2 and z +- 1, 2 for
+    // the others. 81 rows x 3 quadruples = 243 lanes, one pass.
+    constexpr int kTasks = kGN * kGN * 3;
+    const int e = threadIdx.x;
+    if (e >= kTasks) return;
+    const int q = e % 3 + 1, row = e / 3, gy = row % kGN, gz = row / kGN;
+    const int y = gy + 2, z = gz + 2;
+    auto quad = [&](int yy, int zz, int qq) { return ph4[(zz * kPhiYZ + yy) * (kPhiX / 4) + qq]; };
+    auto el = [](const v4<T> &v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; };
+    const v4<T> xm = quad(y, z, q - 1), x0 = quad(y, z, q);
+    const v4<T> xp = q < 3 ? quad(y, z, q + 1) : x0;          // q = 3 needs only x <= 14
+    const v4<T> ym2 = quad(y - 2, z, q), ym1 = quad(y - 1, z, q), yp1 = quad(y + 1, z, q), yp2 = quad(y + 2, z, q);
+    const v4<T> zm2 = quad(y, z - 2, q), zm1 = quad(y, z - 1, q), zp1 = quad(y, z + 1, q), zp2 = quad(y, z + 2, q);
+    // phi along the row from x = 4q - 4 to 4q + 7
+    const T r[12] = {xm.x, xm.y, xm.z, xm.w, x0.x, x0.y, x0.z, x0.w, xp.x, xp.y, xp.z, xp.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int gx = 4 * q + k - 4;                           // node x = 4q + k
+        if (gx >= kGN) break;
         v4<T> o;
-        o.x = fd4<T>(at(x - 2, y, z), at(x - 1, y, z), at(x + 1, y, z), at(x + 2, y, z), inv12cell);
-        o.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), inv12cell);
-        o.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), inv12cell);
+        o.x = fd4<T>(r[k + 2], r[k + 3], r[k + 5], r[k + 6], inv12cell);
+        o.y = fd4<T>(el(ym2, k), el(ym1, k), el(yp1, k), el(yp2, k), inv12cell);
+        o.z = fd4<T>(el(zm2, k), el(zm1, k), el(zp1, k), el(zp2, k), inv12cell);
         o.w = T(0);
-        gl[e] = o;
+        gl[(gz * kGN + gy) * kGN + gx] = o;
     }
 }
 
