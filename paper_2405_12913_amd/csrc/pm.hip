@@ -800,21 +800,38 @@ __global__ __launch_bounds__(kThreads) void kd_tiles_stream_kernel(PartBatch<T> 
     }
 }
 
-// Sorted slot j of buffer cur back to the caller's arrays at the record's lattice index.
+// The sorted state (buffer cur) goes back to the caller's arrays in two passes. First the
+// slot of every particle by lattice index, perm[i] = j (one scattered 4-byte store per
+// particle, into the idle record buffer 1 - cur); then in lattice order each lane gathers its
+// particle's record and momenta and writes s and p with contiguous stores. Writing s and p
+// straight from sorted order would scatter six 4-byte stores per particle over partly
+// written lines. Indices outside [0, P) (none in a consistent state) are skipped.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void state_perm_kernel(PartBatch<T> b, int cur) {
+    const int r = real_of(b.map, blockIdx.x);
+    const Particles<T> &a = b.r[r];
+    const int j = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
+    if (j >= a.P) return;
+    unsigned int *perm = reinterpret_cast<unsigned int *>(a.rec[1 - cur]);
+    const int i = rec_index<T>(a.rec[cur][j]);
+    if ((unsigned int)i < (unsigned int)a.P) perm[i] = (unsigned int)j;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void state_gather_kernel(PartBatch<T> b, int cur) {
     const int r = real_of(b.map, blockIdx.x);
     const Particles<T> &a = b.r[r];
     const size_t P = (size_t)a.P;
-    const int j = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
-    if (j >= a.P) return;
+    const int i = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
+    if (i >= a.P) return;
+    const unsigned int j = reinterpret_cast<const unsigned int *>(a.rec[1 - cur])[i];
+    if (j >= (unsigned int)a.P) return;
     const v4<T> rec = a.rec[cur][j];
-    const int i = rec_index<T>(rec);
-    a.s[0][i] = rec.x;
-    a.s[1][i] = rec.y;
-    a.s[2][i] = rec.z;
+    st_stream(rec.x, a.s[0] + i);
+    st_stream(rec.y, a.s[1] + i);
+    st_stream(rec.z, a.s[2] + i);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) a.p[d][i] = ld_stream(a.mom[cur] + d * P + j);
+    for (int d = 0; d < 3; ++d) st_stream(a.mom[cur][d * P + j], a.p[d] + i);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1263,6 +1280,7 @@ hipError_t state_gather_impl(hrt_ctx *c, const StepArgs &args) {
         for (int k = 0; k < R; ++k) fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
         set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
         prof_begin(c);
+        state_perm_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
         state_gather_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
         prof_end(c, K_STATE_GATHER);
     }
