@@ -231,18 +231,47 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(PartBatch<T> b) {
     if (threadIdx.x == 1023) a.sums[nb] = sh[1023];
 }
 
-template <typename T>
+// FUSED (every realisation has at most 1024 blocks of 1024 bins): the block totals are not
+// scanned by a kernel of their own; each workgroup sums the totals of the blocks before its
+// own (and all of them, for the end offset) from the unscanned array, integer sums in any
+// order. Otherwise scan_sums_kernel has scanned them in place.
+template <typename T, bool FUSED>
 __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
     const int r = real_of(b.map, blockIdx.x);
     const Particles<T> &a = b.r[r];
-    const int i = (blockIdx.x - b.map.start[r]) * 256 + threadIdx.x;
+    const int i0 = (blockIdx.x - b.map.start[r]) * 256, i = i0 + threadIdx.x;
+    unsigned int pre, total;
+    if constexpr (FUSED) {
+        __shared__ unsigned int part[2][4];
+        const int grp = i0 / 1024;              // uniform: 1024 is a multiple of 256
+        unsigned int v = 0, vt = 0;
+        for (int k = threadIdx.x; k < a.nblk; k += 256) {
+            const unsigned int x = a.sums[k];
+            v += k < grp ? x : 0u;
+            vt += x;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            v += __shfl_xor(v, off);
+            vt += __shfl_xor(vt, off);
+        }
+        if (__lane_id() == 0) {
+            part[0][threadIdx.x >> 6] = v;
+            part[1][threadIdx.x >> 6] = vt;
+        }
+        __syncthreads();
+        pre = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        total = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    } else {
+        pre = i < a.nbins ? a.sums[i / 1024] : 0u;
+        total = a.sums[a.nblk];
+    }
     if (i < a.nbins) {
-        const unsigned int v = a.offs[i] + a.sums[i / 1024];
+        const unsigned int v = a.offs[i] + pre;
         a.offs[i] = v;
         a.cursor[i] = v;
         a.count[i] = 0u;       // consumed by scan_local: zero for the next count (kick-drift)
     }
-    if (i == 0) a.offs[a.nbins] = a.sums[a.nblk];
+    if (i == 0) a.offs[a.nbins] = total;
 }
 
 // The 27 bin ranges whose particles reach tile (tx, ty, tz): the tile's own 8 bins and
@@ -1076,13 +1105,16 @@ void launch_scan(hrt_ctx *c, PartBatch<T> &b, int R) {
     prof_begin(c);
     set_map(b, R, [](const Particles<T> &a) { return a.nblk; });
     scan_local_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
-    scan_sums_kernel<T><<<R, 1024, 0, st>>>(b);
+    int max_nblk = 0;
+    for (int k = 0; k < R; ++k) max_nblk = std::max(max_nblk, b.r[k].nblk);
+    const bool fused = max_nblk <= 1024;
+    if (!fused) scan_sums_kernel<T><<<R, 1024, 0, st>>>(b);
     set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
-    scan_add_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
+    if (fused) scan_add_kernel<T, true><<<b.map.start[R], 256, 0, st>>>(b);
+    else scan_add_kernel<T, false><<<b.map.start[R], 256, 0, st>>>(b);
     prof_end(c, K_BIN_SCAN);
 }
 
-// Workgroups of a persistent tile kernel: per_cu resident per compute unit.
 // Workgroups of the pipelined tile kick-drift that fit on one CU at once (its grid is one
 // such wave over all CUs), from the runtime's occupancy calculator (4 if that fails).
 template <typename T>
@@ -1099,6 +1131,7 @@ int kd_stream_per_cu(bool count) {
     return v;
 }
 
+// Workgroups of a persistent tile kernel: per_cu resident per compute unit.
 inline int resident_blocks(int per_cu) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
