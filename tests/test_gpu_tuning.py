@@ -240,7 +240,8 @@ def test_sorted_run_with_empty_and_dense_tiles():
     """hrt_run in paint-bin order on a state where most 8^3 tiles are empty and a few hold
     thousands of particles (tiles skipped by the kick-drift, several trips per lane, 64-bit
     paint sums): every particle order (sorted per tile, sorted with the persistent pipelined
-    kick-drift, Lagrangian) gives the bits of step-by-step pm_step / ray_step calls."""
+    kick-drift, Lagrangian) and every paint shape gives the bits of step-by-step pm_step /
+    ray_step calls."""
     import torch
     from oracle import integrator
     say("case sorted run, empty and dense tiles")
@@ -263,11 +264,14 @@ def test_sorted_run_with_empty_and_dense_tiles():
         sim.pm_step(ref[0], ref[1], step)
         sim.ray_step(ref[2], ref[3], step)
     torch.cuda.synchronize()
-    for kd in (0, 2, 3, 1):
+    from paper_2405_12913_amd import hrt
+    cases = [(kd, 0) for kd in (0, 3, 1)] + [(2, pv) for pv in range(hrt.num_variants("paint_tiles"))]
+    for kd, pv in cases:
         got = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
         sim2 = c.sim()
         sim2.set_variant("kd_tiles", kd)
+        sim2.set_variant("paint_tiles", pv)
         sim2.run(got[0], got[1], got[2], got[3], first, count)
         torch.cuda.synchronize()
         for a, b in zip(sum(got, []), sum(ref, [])):
-            assert torch.equal(a, b), kd
+            assert torch.equal(a, b), (kd, pv)
