@@ -213,12 +213,14 @@ def test_paint_variants_with_dense_tiles():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_sorted_run_default_threshold_and_dtypes(dtype):
-    """The automatic particle order of hrt_run (paint-bin order from 8 steps on) gives the
-    bits of step-by-step pm_step / ray_step calls in FP32 and FP64, over a 9-step call that
-    starts mid-schedule (np = n/2: the sorted kick-drift with 64 particles per tile)."""
+@pytest.mark.parametrize("kd", [0, 3])
+def test_sorted_run_default_threshold_and_dtypes(dtype, kd):
+    """The automatic particle order of hrt_run (paint-bin order from 8 steps on), and the
+    paint-bin order with the persistent pipelined kick-drift, give the bits of step-by-step
+    pm_step / ray_step calls in FP32 and FP64, over a 9-step call that starts mid-schedule
+    (np = n/2: the sorted kick-drift with 64 particles per tile)."""
     import torch
-    say(f"case sorted run {dtype}")
+    say(f"case sorted run {dtype} kd_tiles {kd}")
     cfg = synth.tiny(mesh_n=64, ptcl_n=32, box=100.0, ray_n=32, fov_deg=2.0, n_steps=12, seed=23)
     c = Case(cfg, seed=23, dtype=dtype, dth_rms=1e-4, p_rms=0.1)
     first, count = 2, 9
@@ -230,6 +232,7 @@ def test_sorted_run_default_threshold_and_dtypes(dtype):
     got = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
     sim2 = c.sim()
     assert sim2.variants()["kd_tiles"] == 0
+    sim2.set_variant("kd_tiles", kd)
     sim2.run(got[0], got[1], got[2], got[3], first, count)
     torch.cuda.synchronize()
     for a, b in zip(sum(got, []), sum(ref, [])):
