@@ -1,9 +1,10 @@
 // FFT Poisson solve and gradient of the PM step (paper Sec. 2 Poisson equation; Sec. 4.1:
 // the potential gradient is obtained with FFTs once per step).
 //
-// Hand-written LDS-staged Stockham FFTs (radix 8 where every thread still gets a
-// butterfly, else radix 4; one radix-2 stage when needed), one workgroup of 256 threads per
-// batch of lines:
+// Hand-written Stockham FFTs (radix 8 where every thread still gets a butterfly, else
+// radix 4; one radix-2 stage when needed), one workgroup of 256 threads per batch of lines;
+// a pass's first stage reads HBM straight into registers and its last stage writes HBM
+// (except where a split step needs whole lines), the stages between work in LDS:
 //   x_r2c      real rows -> half spectrum, written transposed as C[kx][z][y]
 //              (length-N/2 complex FFT of packed even/odd samples + split step)
 //   yz_lines   forward FFT along y (contiguous lines in the transposed layout)

@@ -7,10 +7,10 @@
 //                  faces the particle's cell touches), wave-aggregated integer counts
 //   2. scan        exclusive prefix sum of the counts (bin offsets, scatter cursors)
 //   3. bin_scatter write (cell fraction, local cell) of every particle into its bin
-//   4. paint_tiles one workgroup per tile pulls the particles of its own bins and of the
-//                  upper-face bins of its 7 lower neighbours, and sums their CIC weights
-//                  into the tile's 8^3 nodes in LDS as fixed point (32-bit at a per-tile
-//                  scale for FP32 tiles under 1024 particles, else 64-bit).
+//   4. paint_tiles each tile (one, two or four per workgroup) pulls the particles of its
+//                  own bins and of the upper-face bins of its 7 lower neighbours, and sums
+//                  their CIC weights into the tile's 8^3 nodes in LDS as fixed point (32-bit
+//                  at a per-tile scale for FP32 tiles under 1024 particles, else 64-bit).
 // Integer sums are exact and order-independent, so the mesh is bit-identical across
 // runs whatever the atomics' interleaving; each node is written by exactly one
 // workgroup with a plain store. The result is delta = rho / rho_bar - 1.
