@@ -4,7 +4,7 @@
  * One particle-mesh (PM) gravity step co-evolved with light rays, following
  * Zhou et al., "A Hamiltonian, post-Born, three-dimensional, on-the-fly ray
  * tracing algorithm for gravitational lensing" (arXiv:2405.12913):
- *   pm_force        CIC paint + FFT Poisson solve + gradient   (Sec. 2 Poisson eq.; Sec. 4.1-4.2)
+ *   pm_force        CIC paint + FFT Poisson solve + gradient   (Sec. 2 Poisson eq.; Sec. 5.1-5.2)
  *   pm_step         pm_force + matter kick and drift           (Alg. 1, nbody_reverse_step)
  *   ray_step        ray kick over one lens shell + ray drift   (Eqs. symp_1-3, kick, drift)
  *   ray_convergence kappa (gamma1, gamma2, omega) from finite  (Eqs. A, obs_first_set,
@@ -171,7 +171,7 @@ int hrt_tables(const hrt_config *cfg, double *a, double *chi, double *K, double 
                double *plane_chi, double *plane_w, int32_t max_planes, int32_t *n_planes);
 
 /* Initial conditions (support for the cosmological runs; the paper starts from 2LPT at
- * a = 1/64, Sec. 5.2, without giving the recipe). Linear spectrum at a = 1:
+ * a = 1/64, Sec. 6.2, without giving the recipe). Linear spectrum at a = 1:
  * P(k) = A k^n_s T(k)^2 with the Eisenstein & Hu (1998) no-wiggle transfer function and A
  * fixed by sigma8 (top-hat of 8 Mpc/h); field on the particle lattice
  * delta_k = FFT(noise)_k sqrt(P(k) / (box/np)^3) (k = 0 removed); second-order Lagrangian
@@ -199,7 +199,7 @@ int hrt_ic_2lpt(hrt_ctx *ctx, int realisation, const void *noise, const hrt_ic_p
 int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out);
 
 /* Reverse mode (vector-Jacobian products). The paper names gradients through the ray
- * tracer as future work (Sec. 6, via the adjoint method of its ref. LiEtAl2024); these are
+ * tracer as future work (Sec. 7, via the adjoint method of its ref. LiEtAl2024); these are
  * the exact transposes of the forward discretisation above. A cotangent array has the
  * shape, layout and dtype of the state array it belongs to; the functions update the
  * cotangents in place (device, caller-owned).

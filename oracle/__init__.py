@@ -10,11 +10,11 @@ paper (Zhou et al., "A Hamiltonian, post-Born, three-dimensional, on-the-fly ray
 tracing algorithm for gravitational lensing", arXiv:2405.12913):
 
 * ``cosmo``        background expansion, comoving distance, linear growth (Sec. 2, Sec. 3.2)
-* ``mesh``         cloud-in-cell paint / readout, FFT Poisson gradient (Sec. 2, Sec. 4.2)
+* ``mesh``         cloud-in-cell paint / readout, FFT Poisson gradient (Sec. 2, Sec. 5.2)
 * ``tables``       step schedule, lens shells and kick/drift factors (Sec. 3.1-3.2)
 * ``integrator``   matter and ray kick-drift-kick steps (Eqs. symp_1-3, kick, drift; Alg. 1)
 * ``observables``  distortion matrix and kappa/gamma/omega (Eqs. A, obs_first_set, obs_second_set)
-* ``ic``           Gaussian initial conditions and 2LPT (Sec. 5.2; not part of the paper's method)
+* ``ic``           Gaussian initial conditions and 2LPT (Sec. 6.2; not part of the paper's method)
 * ``pointmass``    point-lens deflection targets (Eqs. pointmass_analytic, pointmass_periodic)
 
 Arrays are float64. Meshes are indexed ``[z, y, x]`` with the line of sight

@@ -1,7 +1,7 @@
 """Reverse-mode derivatives (vector-Jacobian products) of the HRT step, FP64.
 
 Test infrastructure only. The paper leaves memory-efficient gradients through HRT to
-future work (Sec. 6, the adjoint method of its ref. LiEtAl2024); these are hand-written
+future work (Sec. 7, the adjoint method of its ref. LiEtAl2024); these are hand-written
 VJPs of the oracle's own discretisation (``oracle.integrator``, ``oracle.mesh``,
 ``oracle.observables``, ``oracle.ic``), pinned by dot-product and finite-difference tests.
 

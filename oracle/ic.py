@@ -1,7 +1,7 @@
 """Gaussian initial conditions and second-order Lagrangian perturbation theory, FP64.
 
 Test infrastructure only. The paper starts its cosmological runs from 2LPT at
-a = 1/64 (Sec. 5.2) but does not give the IC recipe; this module follows the
+a = 1/64 (Sec. 6.2) but does not give the IC recipe; this module follows the
 standard one:
 
 * Linear power spectrum at a = 1: P(k) = A k^{n_s} T(k)^2 with the Eisenstein & Hu

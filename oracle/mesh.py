@@ -2,10 +2,10 @@
 
 * Cloud-in-cell (trilinear) paint and readout with periodic wrap. The paper uses CIC
   both to move mass onto the 3D particle mesh and to move mesh values back to
-  points (Sec. 4.2, "cloud-in-cell (CIC), or trilinear, interpolation").
+  points (Sec. 5.2, "cloud-in-cell (CIC), or trilinear, interpolation").
 * Poisson solve by FFT, grad^2 phi = delta (the paper's Poisson equation of Sec. 2 with
   its prefactor applied by the caller), followed by a gradient. The paper only says the
-  gradient is obtained "via the Fast Fourier Transform" (Sec. 4.1); the reading used
+  gradient is obtained "via the Fast Fourier Transform" (Sec. 5.1); the reading used
   here is: continuous Green's function -1/k^2 with the k = 0 mode set to zero, no CIC
   deconvolution, and the fourth-order central finite difference
       G_d(i) = [8 (phi(i+1) - phi(i-1)) - (phi(i+2) - phi(i-2))] / (12 cell)

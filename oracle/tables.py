@@ -21,7 +21,7 @@ Conventions (paper Sec. 3.1, Eqs. symp_1-3, kick_notimecor, drift; Sec. 3.2, Eq.
   radius, d_n = (chi_{n+1} - chi_n) / r(chi_{n+1/2})^2 (Eq. drift).
 * The kick's line-of-sight integral (Eq. kick) is a sum over the mesh's z-planes
   lying in the shell, plane j at line-of-sight coordinate z_j = j * cell and
-  chi_j = z_j - z_obs, each evaluated at the ray's current angle (Sec. 4.2, "mesh
+  chi_j = z_j - z_obs, each evaluated at the ray's current angle (Sec. 5.2, "mesh
   points within the lens plane"). Plane j belongs to shell n iff
   lo_n <= chi_j < hi_n, lo/hi being the two half points sorted, so a schedule run
   backwards reuses exactly the same planes. Plane j reads mesh plane j mod n.

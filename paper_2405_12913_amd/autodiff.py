@@ -1,6 +1,6 @@
 """Differentiable convergence maps: white noise -> 2LPT -> forward PM -> co-evolution -> kappa.
 
-The paper leaves gradients through the ray tracer to future work (Sec. 6, by the adjoint
+The paper leaves gradients through the ray tracer to future work (Sec. 7, by the adjoint
 method of its ref. LiEtAl2024). ``Pipeline.kappa`` is a ``torch.autograd.Function`` whose
 forward and backward passes issue only C-ABI calls of libhrt.so (hrt_ic_2lpt, pm_step,
 ray_step, ray_convergence and their VJPs hrt_step_vjp, ray_convergence_vjp,

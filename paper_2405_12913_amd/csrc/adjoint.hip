@@ -1,5 +1,5 @@
 // Reverse mode of the co-evolution step and of the convergence map (vector-Jacobian
-// products). The paper leaves gradients through HRT to future work (Sec. 6: the adjoint
+// products). The paper leaves gradients through HRT to future work (Sec. 7: the adjoint
 // method of its ref. LiEtAl2024); this is the hand-written adjoint of the discretisation
 // the forward kernels compute.
 //

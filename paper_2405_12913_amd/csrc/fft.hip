@@ -1,4 +1,4 @@
-// FFT Poisson solve and gradient of the PM step (paper Sec. 2 Poisson equation; Sec. 4.1:
+// FFT Poisson solve and gradient of the PM step (paper Sec. 2 Poisson equation; Sec. 5.1:
 // the potential gradient is obtained with FFTs once per step).
 //
 // Hand-written Stockham FFTs (radix 8 where every thread still gets a butterfly, else
@@ -670,7 +670,7 @@ hipError_t plane_gradient_impl(hrt_ctx *c, int step) {
 
 // ---------------------------------------------------------------------------------------
 // Initial conditions: Gaussian field with the Eisenstein-Hu no-wiggle spectrum and its
-// 2LPT displacements (standard recipe; the paper starts from 2LPT at a = 1/64, Sec. 5.2).
+// 2LPT displacements (standard recipe; the paper starts from 2LPT at a = 1/64, Sec. 6.2).
 // Spectra use the transposed layout [kx][kz][ky] left by the forward passes. Derivatives
 // use i k_d with the Nyquist wavenumber zeroed; second derivatives apply it twice.
 

@@ -2,7 +2,7 @@
 // CIC readout + matter kick + drift. Every kernel covers all realisations of a context
 // in one launch; realisation r owns the blocks [map.start[r], map.start[r+1]).
 //
-// Paint (paper Sec. 4.2, CIC onto the 3D particle mesh), in four kernels:
+// Paint (paper Sec. 5.2, CIC onto the 3D particle mesh), in four kernels:
 //   1. bin_count   particles -> bin key (8^3-cell tile, and which of the tile's upper
 //                  faces the particle's cell touches), wave-aggregated integer counts
 //   2. scan        exclusive prefix sum of the counts (bin offsets, scatter cursors)

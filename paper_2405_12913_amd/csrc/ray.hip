@@ -1,13 +1,13 @@
 // Ray side of the co-evolution step.
 //
-// ray_step_kernel (paper Eqs. symp_1-3, kick, drift; Sec. 4.2): one lane per ray. The
+// ray_step_kernel (paper Eqs. symp_1-3, kick, drift; Sec. 5.2): one lane per ray. The
 // kick over lens shell n sums, for every mesh z-plane j in the shell,
 //     w_j * bilinear(G_x, G_y on mesh plane j mod n)(X_obs + chi_j * theta),
 // where theta = theta0 + dth is the ray's current angle and w_j carries the line-of-sight
 // element, r_j, the Poisson prefactor and the growth correction of Eq. kick. Then
 // p += dp and dth += d_n p (drift with the midpoint radius, Eq. drift). Positions on a
 // plane are formed in FP64 (chi_j * theta reaches hundreds of Mpc/h) and the fractions
-// handed to the FP32 bilinear weights. Rays are independent (Sec. 4.1), so neighbouring
+// handed to the FP32 bilinear weights. Rays are independent (Sec. 5.1), so neighbouring
 // lanes are neighbouring pixels and read neighbouring mesh nodes of the same plane.
 //
 // convergence_kernel (Eqs. A, obs_first_set, obs_second_set): finite differences of the

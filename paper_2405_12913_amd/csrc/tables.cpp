@@ -5,7 +5,7 @@
 // r = chi (Sec. 2); KDK ray integrator with kick and drift operators (Sec. 3.1,
 // Eqs. symp_1-3, kick_notimecor, drift); growth correction of the potential inside a
 // shell (Sec. 3.2, Eq. kick); mesh points of the 3D mesh inside the lens shell
-// chi_a <= chi < chi_b carry the kick (Sec. 4.2).
+// chi_a <= chi < chi_b carry the kick (Sec. 5.2).
 //
 // Readings (fused leapfrog, half points, shell membership) are stated next to each
 // function. Integrals use adaptive Gauss-Kronrod (7/15) on substituted integrands

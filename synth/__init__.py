@@ -5,7 +5,7 @@ and seeded random inputs only. It contains none of the method's arithmetic: no
 painting, no Poisson solve, no growth factors, no integrator. Both the oracle side
 and the GPU side receive what it produces as plain arrays.
 
-Workloads (sizes follow the paper's tests, Secs. 5.1-5.2, scaled to one GPU):
+Workloads (sizes follow the paper's tests, Secs. 6.1-6.2, scaled to one GPU):
 
 * ``pointlens``: static point lens, M = 1e15 Msun/h at the centre of a 512 Mpc/h
   periodic box, 128^3 mesh (float64), observer on the z = 0 face, lens at 256 Mpc/h,

@@ -2,8 +2,8 @@
 
 Born deflections through the periodic, neutralised point-mass potential (the
 potential the FFT Poisson solver represents) for a sample of the static point-lens
-rays above the resolution threshold theta_thresh = 4 cell / chi_l (paper Sec. 5.1,
-Fig. 1 caption and text; Appendix C, Eq. pointmass_periodic for the periodic images).
+rays above the resolution threshold theta_thresh = 4 cell / chi_l (paper Sec. 6.1,
+Fig. 1 caption and text; Appendix D, Eq. pointmass_periodic for the periodic images).
 Run from the repository root:  python tests/golden/make_pointlens_golden.py
 """
 import json
@@ -29,7 +29,7 @@ def main():
     be = pointmass.born_ewald(th0[idx], cfg["lens"], cfg["observer"], cfg["chi_s"], cfg["mass"], cfg["box"])
     thin = pointmass.thin_lens(th0[idx], chi_l, cfg["chi_s"], cfg["mass"])
     out = dict(
-        source="oracle.pointmass.born_ewald; paper Sec. 5.1 and Appendix C (Eq. pointmass_periodic)",
+        source="oracle.pointmass.born_ewald; paper Sec. 6.1 and Appendix D (Eq. pointmass_periodic)",
         workload="static point lens: M=1e15 Msun/h, box 512 Mpc/h, 128^3 mesh, 64x64 rays over 10 deg",
         theta_thresh=thresh, ray_index=idx.tolist(), born_ewald=be.tolist(), thin_lens=thin.tolist())
     path = os.path.join(ROOT, "tests", "golden", "pointlens_born_ewald.json")

@@ -1,6 +1,6 @@
 """Pins of the oracle's initial-condition generator (no GPU).
 
-The paper starts from 2LPT at a = 1/64 (Sec. 5.2) without giving the recipe; the
+The paper starts from 2LPT at a = 1/64 (Sec. 6.2) without giving the recipe; the
 oracle follows the standard one (see oracle.ic). Pins:
 * the white-noise field has the requested power spectrum (normalisation convention);
 * 2LPT: a single plane wave has zero second-order displacement, two orthogonal waves

@@ -2,10 +2,10 @@
 
 * CIC against its geometric definition (volume overlap of a cell-sized cube with each
   node's cell), brute force on a tiny mesh.
-* Mass conservation, node-centred particles, the uniform lattice (paper Sec. 4.2: CIC).
+* Mass conservation, node-centred particles, the uniform lattice (paper Sec. 5.2: CIC).
 * Paint/readout adjointness and exact reproduction of affine fields.
 * A single lattice mode through the Poisson solve: phi = -delta / k^2 exactly at the
-  nodes, and the 4th-order difference gradient's transfer function (Sec. 2, Sec. 4.1)."""
+  nodes, and the 4th-order difference gradient's transfer function (Sec. 2, Sec. 5.1)."""
 import itertools
 import math
 

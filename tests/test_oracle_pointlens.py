@@ -1,8 +1,8 @@
 """Point-lens pins of the whole static path of the oracle (no GPU).
 
-Paper Sec. 5.1: a point lens traced with HRT reproduces the deflection above the
+Paper Sec. 6.1: a point lens traced with HRT reproduces the deflection above the
 resolution threshold theta_thresh = 4 cell / chi_l to sub-percent accuracy, with the
-periodic images of the FFT solver accounted for (Appendix C, Eq. pointmass_periodic).
+periodic images of the FFT solver accounted for (Appendix D, Eq. pointmass_periodic).
 The target here is the exact Born deflection through the periodic, neutralised
 point-mass potential (tests/golden/pointlens_born_ewald.json, written by
 make_pointlens_golden.py from oracle.pointmass only). For the 10 degree field the 3D
