@@ -98,6 +98,22 @@ int hrt_workspace_bytes(const hrt_config *cfg, int n_cfg, size_t *bytes);
 int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes, void *stream,
              hrt_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hrt_init without a caller workspace.
+ * The workspace is a static device array of the library, HRT_NOALLOC_MAX_BYTES bytes on
+ * every device the library runs on (held until the process ends); the context is laid
+ * out in the array of the device current at the call, which must also be the device of
+ * `stream` and of every state array. The call allocates no device memory (it uploads the
+ * step tables into the array and synchronises the stream, as hrt_init does). Returns
+ * HRT_ENOMEM, with the size needed in hrt_last_error(NULL), if hrt_workspace_bytes(cfg,
+ * n_cfg) exceeds HRT_NOALLOC_MAX_BYTES. All contexts created this way on one device share
+ * that one array: a context stays valid until the next hrt_init_noalloc on its device
+ * (after which its GPU entry points return HRT_ESTATE; hrt_destroy is still required),
+ * and work of two such contexts that overlaps in time on one device races. Everything
+ * else (entry points, results, bits) is as for a context from hrt_init. */
+#define HRT_NOALLOC_MAX_BYTES 67108864
+int hrt_init_noalloc(const hrt_config *cfg, int n_cfg, void *stream, hrt_ctx **out);
+
 /* Frees the host-side context (does not touch the caller's device memory). */
 int hrt_destroy(hrt_ctx *ctx);
 

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhrt.so")
 
-SOURCES = ["tables.cpp", "api.cpp", "tune.cpp", "pm.hip", "fft.hip", "ray.hip", "adjoint.hip"]
+SOURCES = ["tables.cpp", "api.cpp", "tune.cpp", "pm.hip", "fft.hip", "ray.hip", "adjoint.hip",
+           "noalloc.hip"]
 
 
 def _hipcc():

@@ -213,8 +213,8 @@ extern "C" int hrt_tables(const hrt_config *cfg, double *a, double *chi, double 
     return HRT_OK;
 }
 
-extern "C" int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes,
-                        void *stream, hrt_ctx **out) {
+int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes,
+                      void *stream, hrt_ctx **out) {
     if (!cfg || !out) return fail(nullptr, HRT_EINVAL, "NULL argument");
     *out = nullptr;
     std::vector<hrt::StepTables> tabs;
@@ -225,7 +225,9 @@ extern "C" int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_
     size_t total = 0;
     for (const hrt::Layout &L : lays) total += L.total;
     if (!workspace || ws_bytes < total)
-        return fail(nullptr, HRT_ENOMEM, "workspace missing or smaller than hrt_workspace_bytes()");
+        return fail(nullptr, HRT_ENOMEM,
+                    "workspace missing or smaller than hrt_workspace_bytes() (" + std::to_string(total) +
+                        " bytes needed, " + std::to_string(ws_bytes) + " given)");
     if (reinterpret_cast<uintptr_t>(workspace) % 256)
         return fail(nullptr, HRT_EINVAL, "workspace must be 256-byte aligned");
     hrt_ctx *c = new (std::nothrow) hrt_ctx();
@@ -291,6 +293,22 @@ extern "C" int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_
     return HRT_OK;
 }
 
+extern "C" int hrt_init(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes,
+                        void *stream, hrt_ctx **out) {
+    return hrt::init_context(cfg, n_cfg, workspace, ws_bytes, stream, out);
+}
+
+int hrt::set_init_error(int code, const std::string &msg) { return fail(nullptr, code, msg); }
+
+// A context whose workspace is the static no-allocation array stays valid only until the
+// next hrt_init_noalloc on the same device re-lays that array out for another context.
+static int guard(hrt_ctx *c) {
+    if (hrt::noalloc_superseded(c))
+        return fail(c, HRT_ESTATE, "context superseded: a later hrt_init_noalloc on this device "
+                                   "re-used the static workspace");
+    return HRT_OK;
+}
+
 extern "C" int hrt_destroy(hrt_ctx *ctx) {
     delete ctx;
     return HRT_OK;
@@ -323,6 +341,7 @@ static int check_rays(hrt_ctx *c, const hrt_rays *r, bool need_p) {
 
 extern "C" int pm_force(hrt_ctx *c, const hrt_matter *m, int step) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
     if (int rc = check_matter(c, m, false)) return rc;
     hrt::StepArgs a;
@@ -348,6 +367,7 @@ extern "C" int pm_step(hrt_ctx *c, const hrt_matter *m, int step) {
 
 extern "C" int ray_step(hrt_ctx *c, const hrt_rays *r, int step) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
     if (int rc = check_rays(c, r, true)) return rc;
     if (c->force_step < 0) return fail(c, HRT_ESTATE, "no force mesh yet: call pm_force or pm_step first");
@@ -362,6 +382,7 @@ extern "C" int ray_step(hrt_ctx *c, const hrt_rays *r, int step) {
 extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *const *kappa,
                                void *const *gamma1, void *const *gamma2, void *const *omega) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (int rc = check_rays(c, r, false)) return rc;
     if (!kappa) return fail(c, HRT_EINVAL, "NULL kappa");
     for (size_t k = 0; k < c->re.size(); ++k)
@@ -433,6 +454,7 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
 extern "C" int hrt_run(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int first_step,
                        int n_steps) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (n_steps < 1 || first_step < 0 || first_step + n_steps > c->N + 1)
         return fail(c, HRT_EINVAL, "steps out of range [0, n_steps]");
     if (int rc = check_matter(c, m, !c->is_static)) return rc;
@@ -445,6 +467,7 @@ extern "C" int hrt_run(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int f
 extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
                                  int first_step, int n_steps) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (c->prof) return fail(c, HRT_ESTATE, "switch profiling off before capturing a graph");
     if (n_steps < 1 || first_step < 0 || first_step + n_steps > c->N + 1)
         return fail(c, HRT_EINVAL, "captured steps out of range [0, n_steps]");
@@ -475,6 +498,7 @@ extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays
 
 extern "C" int hrt_graph_launch(hrt_ctx *c) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (!c->graph) return fail(c, HRT_ESTATE, "no captured graph");
     return check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
 }
@@ -499,6 +523,7 @@ extern "C" int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, do
 extern "C" int hrt_ic_2lpt(hrt_ctx *c, int realisation, const void *noise, const hrt_ic_params *ic,
                            const hrt_matter *out) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (realisation < 0 || realisation >= (int)c->re.size())
         return fail(c, HRT_EINVAL, "realisation index out of range");
     if (!noise || !ic || !out) return fail(c, HRT_EINVAL, "NULL argument");
@@ -518,6 +543,7 @@ extern "C" int hrt_ic_2lpt(hrt_ctx *c, int realisation, const void *noise, const
 extern "C" int hrt_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
                             const hrt_matter *mc, const hrt_rays *rc, int step) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (c->re.size() != 1) return fail(c, HRT_EUNSUPPORTED, "reverse mode needs a single realisation");
     if (!(c->re[0].cfg.flags & HRT_ADJOINT))
         return fail(c, HRT_ESTATE, "context was created without HRT_ADJOINT");
@@ -538,6 +564,7 @@ extern "C" int hrt_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
 
 extern "C" int ray_convergence_vjp(hrt_ctx *c, void *const *kappa_bar, const hrt_rays *rc) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (int rc0 = check_rays(c, rc, false)) return rc0;
     if (!kappa_bar) return fail(c, HRT_EINVAL, "NULL kappa_bar");
     for (size_t k = 0; k < c->re.size(); ++k)
@@ -552,6 +579,7 @@ extern "C" int ray_convergence_vjp(hrt_ctx *c, void *const *kappa_bar, const hrt
 extern "C" int hrt_ic_2lpt_vjp(hrt_ctx *c, int realisation, const void *noise,
                                const hrt_ic_params *ic, const hrt_matter *cot, void *noise_bar) {
     if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
     if (realisation < 0 || realisation >= (int)c->re.size())
         return fail(c, HRT_EINVAL, "realisation index out of range");
     if (!noise || !ic || !cot || !noise_bar) return fail(c, HRT_EINVAL, "NULL argument");

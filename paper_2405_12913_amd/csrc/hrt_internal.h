@@ -130,8 +130,23 @@ struct hrt_ctx {
     int64_t prof_n[hrt::K_COUNT] = {};
     // launch-shape variant per kernel id (hrt_autotune / hrt_set_variant; 0 = default)
     int variant[hrt::K_COUNT] = {};
+    // workspace in the static no-allocation array (hrt_init_noalloc): its device and the
+    // generation of that device's array this context was laid out in (-1: caller workspace)
+    int noalloc_dev = -1;
+    uint64_t noalloc_gen = 0;
     ~hrt_ctx();
 };
+
+namespace hrt {
+// hrt_init on an explicit workspace (shared by hrt_init and hrt_init_noalloc).
+int init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t ws_bytes, void *stream,
+                 hrt_ctx **out);
+// Records the message returned by hrt_last_error(NULL) and returns code.
+int set_init_error(int code, const std::string &msg);
+// True if c lives in the static no-allocation array of its device and a later
+// hrt_init_noalloc on that device has laid the array out for another context.
+bool noalloc_superseded(const hrt_ctx *c);
+}  // namespace hrt
 
 // Kernel launchers (defined in the .hip files); each covers every realisation of the
 // context with one launch per kernel type (per mesh-size class for the FFT passes) and

@@ -19,13 +19,14 @@ HRT_ADJOINT = 2
 HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
 HRT_NUM_KERNELS = 17
+HRT_NOALLOC_MAX_BYTES = 67108864
 
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
             "pm_step", "ray_step", "ray_convergence", "hrt_mesh_ptr", "hrt_tables",
             "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
             "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
             "ray_convergence_vjp", "hrt_ic_2lpt_vjp", "hrt_num_variants", "hrt_set_variant",
-            "hrt_get_variant", "hrt_autotune", "hrt_run")
+            "hrt_get_variant", "hrt_autotune", "hrt_run", "hrt_init_noalloc")
 
 
 class HrtConfig(ctypes.Structure):
@@ -71,6 +72,7 @@ def lib():
         P = POINTER
         L.hrt_workspace_bytes.argtypes = [P(HrtConfig), c_int, P(c_size_t)]
         L.hrt_init.argtypes = [P(HrtConfig), c_int, c_void_p, c_size_t, c_void_p, P(c_void_p)]
+        L.hrt_init_noalloc.argtypes = [P(HrtConfig), c_int, c_void_p, P(c_void_p)]
         L.hrt_destroy.argtypes = [c_void_p]
         L.hrt_last_error.argtypes = [c_void_p]
         L.hrt_last_error.restype = ctypes.c_char_p
@@ -202,7 +204,9 @@ class Simulation:
     with one keyword dict per realisation; state arguments are then lists of such lists.
     """
 
-    def __init__(self, *, configs=None, device="cuda", **single):
+    def __init__(self, *, configs=None, device="cuda", static_workspace=False, **single):
+        """static_workspace=True lays the context out in the library's static device array
+        (hrt_init_noalloc) instead of a workspace tensor: no device allocation."""
         import torch
         configs = [single] if configs is None else list(configs)
         self.R = len(configs)
@@ -218,11 +222,17 @@ class Simulation:
         self.n_particles = [c.ptcl_n ** 3 for c in self.cfgs]
         self.n_rays = [c.ray_nx * c.ray_ny for c in self.cfgs]
         self.ws_bytes = hrt_workspace_bytes(self.cfgs, self.R)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = c_void_p(0)
-        _check(lib().hrt_init(self.cfgs, self.R, c_void_p(self.workspace.data_ptr()), self.ws_bytes,
-                              c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib().hrt_init_noalloc(self.cfgs, self.R, c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(ctx)))
+        else:
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            _check(lib().hrt_init(self.cfgs, self.R, c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                  c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
         self.ctx = ctx
 
     def close(self):
@@ -390,6 +400,8 @@ class Simulation:
 
     def mesh(self, which, realisation=0):
         """View of an internal mesh ([n, n, n], or [n, n, n, 4] for G) of one realisation."""
+        if self.workspace is None:
+            raise HRTError("mesh views need a workspace tensor (not available with static_workspace)")
         ptr = c_void_p(0)
         _check(lib().hrt_mesh_ptr(self.ctx, realisation, which, ctypes.byref(ptr)), self.ctx)
         n = self.cfgs[realisation].mesh_n

@@ -122,3 +122,17 @@ def test_variant_counts():
     assert counts["bin_count"] == 8 and counts["bin_scatter"] == 8
     assert counts["fft_x_r2c"] == 1 and counts["kd_tiles"] == 4 and counts["state_scatter"] == 1
     assert hrt.num_variants(hrt.HRT_NUM_KERNELS) == 0
+
+
+def test_noalloc_init_rejects_configurations_beyond_the_static_workspace():
+    # 128^3 FP32 needs ~190 MiB of workspace, more than the static array holds; the check
+    # happens on the host before any device call
+    a = np.linspace(1.0, 0.5, 9)
+    cfg, keep = _cosmo_cfg(a, mesh_n=128, box=200.0)
+    need = hrt.hrt_workspace_bytes(cfg)
+    assert need > hrt.HRT_NOALLOC_MAX_BYTES
+    ctx = ctypes.c_void_p(0)
+    rc = hrt.lib().hrt_init_noalloc(ctypes.byref(cfg), 1, None, ctypes.byref(ctx))
+    assert rc == hrt.HRT_ENOMEM and not ctx.value
+    msg = hrt.lib().hrt_last_error(None).decode()
+    assert str(need) in msg and str(hrt.HRT_NOALLOC_MAX_BYTES) in msg
