@@ -9,7 +9,8 @@ Input (untimed set-up on the GPU): seeded unit white noise -> 2LPT at a = 1/64
 A step is one pm_step (paint, FFT Poisson solve, gradient, matter kick-drift) plus one
 ray_step (plane-sum kick over the lens shell, drift), issued through hrt_run over runs of
 the schedule (bit-identical to step-by-step calls; each drift also counts the particles into
-the next paint's bins); the convergence map is taken at the source plane (every 64th step).
+the next paint's bins); hrt_run writes the convergence map at the source plane z = 1 (the
+schedule's last boundary, every 64th step).
 Steps beyond 64 continue cyclically through the schedule from the current state.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
@@ -117,10 +118,17 @@ def evolved_ic(hrt, torch, cfg, dev, seed):
     return s, p
 
 
-def sim_kwargs(cfg):
+def sim_kwargs(cfg, src=None):
+    """Simulation arguments of a workload; src: source-plane redshifts (step boundaries)."""
     return dict(mesh_n=cfg["mesh_n"], box=cfg["box"], ptcl_n=cfg["ptcl_n"], n_steps=len(cfg["sched"]) - 1,
                 sched=cfg["sched"], ray_nx=cfg["ray_n"], ray_ny=cfg["ray_n"], fov_x=cfg["fov"],
-                fov_y=cfg["fov"], observer=cfg["observer"], omega_m=cfg["omega_m"], dtype="f32")
+                fov_y=cfg["fov"], observer=cfg["observer"], omega_m=cfg["omega_m"], dtype="f32",
+                src=src)
+
+
+def last_boundary_z(cfg):
+    """Redshift of the schedule's last boundary (the source plane of the workload)."""
+    return 1.0 / cfg["sched"][-1] - 1.0
 
 
 def batched_bench(hrt, torch, dev, tune=True):
@@ -164,7 +172,8 @@ def batched_bench(hrt, torch, dev, tune=True):
         torch.cuda.synchronize()
         t_batch = e0.elapsed_time(e1) * 1e-3
         sim.close()
-        del sim, st
+        batched_final = st
+        del sim
         # plain: each realisation alone, one captured graph each, run back to back
         st = fresh()
         sims = []
@@ -191,6 +200,11 @@ def batched_bench(hrt, torch, dev, tune=True):
         t_plain = e0.elapsed_time(e1) * 1e-3
         for s1 in sims:
             s1.close()
+        # batched and one-by-one runs of the same realisations must agree bit for bit
+        identical = all(torch.equal(a, b) for xb, xp in zip(batched_final, st)
+                        for a, b in zip(xb[0] + xb[1] + xb[2] + xb[3], xp[0] + xp[1] + xp[2] + xp[3]))
+        del batched_final
+    assert identical, "batched and sequential realisations differ"
     tot_rays = sum(rays)
     return {"workload": "batched16: 8 x (128^3, box 200, 4 deg) + 8 x (256^3, box 400, 5 deg), "
                         "ray grids 256^2..1024^2, (Omega_m, sigma_8) uniform in [0.2,0.4]x[0.6,1.0], "
@@ -199,7 +213,8 @@ def batched_bench(hrt, torch, dev, tune=True):
             "ray_steps_per_s": tot_rays * N / t_batch,
             "plain_sequential_realisation_steps_per_s": 16 * N / t_plain,
             "plain_sequential_ray_steps_per_s": tot_rays * N / t_plain,
-            "speedup_vs_plain": t_plain / t_batch}
+            "speedup_vs_plain": t_plain / t_batch,
+            "batched_equals_sequential_bitwise": identical}
 
 
 def adjoint_bench(torch, dev):
@@ -241,66 +256,122 @@ def adjoint_bench(torch, dev):
             "checkpoints": len(ck_f) + len(ck_c)}
 
 
-def large_bench(hrt, torch, dev, tune=True, steps=8):
+def large_bench(hrt, torch, dev, tune=True):
     """The largest configuration: 512^3 particles on a 1024^3 mesh, box 1000 Mpc/h, 2048^2
-    rays over 10 deg, 100 co-evolution steps to a = 1/3; `steps` steps from a = 1 timed."""
+    rays over 10 deg, the whole 100-step co-evolution schedule a = 1 -> 1/3 timed, with
+    the convergence map written at the source planes z = 1 (step boundary 75) and z = 2
+    (boundary 100) by hrt_run."""
     import synth
     cfg = synth.large1024()
+    N = len(cfg["sched"]) - 1
     print("[bench] large: 1024^3 mesh, 512^3 particles, 2048^2 rays; initial conditions",
           file=sys.stderr, flush=True)
-    s, p = evolved_ic(hrt, torch, cfg, dev, 0)
+    s0, p0 = evolved_ic(hrt, torch, cfg, dev, 0)
+    s = [t.clone() for t in s0]
+    p = [t.clone() for t in p0]
     nr = cfg["ray_n"] ** 2
     dth = [torch.zeros(nr, device=dev) for _ in range(2)]
     pr = [torch.zeros(nr, device=dev) for _ in range(2)]
-    sim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+    src = [1.0, 2.0]
+    sim = hrt.Simulation(**sim_kwargs(cfg, src=src), device=dev)
     tuned = sim.autotune(s, p, dth, pr, step=0) if tune else {}
     sim.run(s, p, dth, pr, 0, 2)                                   # warm-up
+    torch.cuda.synchronize()
+    for a, b in zip(s + p, s0 + p0):
+        a.copy_(b)
+    for t in dth + pr:
+        t.zero_()
+    maps = [{"kappa": torch.full((nr,), float("nan"), device=dev)} for _ in src]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    print(f"[bench] large: timing the {N}-step schedule", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     e0.record(sim.stream)
-    sim.run(s, p, dth, pr, 2, steps)
+    sim.run(s, p, dth, pr, 0, N, maps=maps)
     e1.record(sim.stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms = e0.elapsed_time(e1) / N
     assert torch.isfinite(dth[0]).all() and torch.isfinite(s[0]).all()
+    kap = {}
+    for z, m in zip(src, maps):
+        k = m["kappa"].double()
+        assert torch.isfinite(k).all(), f"kappa at z = {z} not finite"
+        kap[f"z={z:g}"] = {"mean": float(k.mean()), "rms": float(k.std()), "min": float(k.min()),
+                           "max": float(k.max())}
     sim.close()
     return {"workload": "large1024: 512^3 particles on a 1024^3 mesh, box 1000 Mpc/h, 2048^2 rays "
-                        "over 10 deg, 100-step schedule a = 1 -> 1/3 (steps 2..9 timed after 2 warm-up "
-                        "steps), evolved initial conditions as lcdm256",
+                        f"over 10 deg, the whole {N}-step schedule a = 1 -> 1/3 timed, evolved initial "
+                        "conditions as lcdm256, kappa at source planes z = 1 and z = 2",
             "ray_steps_per_s": nr / (ms * 1e-3), "ms_per_step": round(ms, 3),
-            "launch_variants": tuned}
+            "timed_schedule_steps": f"0..{N - 1}", "kappa": kap, "launch_variants": tuned}
+
+
+def fft_baseline(torch, dev):
+    """rocFFT (through torch.fft) timing of the same transforms as one Poisson solve: a 3D
+    real-to-complex forward and a complex-to-real inverse, FP32, at 256^3 and 1024^3, median
+    of 5 after a warm-up (a cross-check of the hand-written FFT passes, which do the forward
+    transform, the Poisson multiply and the one inverse transform)."""
+    out = {}
+    for n in (256, 1024):
+        x = torch.randn((n, n, n), device=dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        fw, iv = [], []
+        for rep in range(6):
+            ev[0].record()
+            X = torch.fft.rfftn(x)
+            ev[1].record()
+            y = torch.fft.irfftn(X, s=(n, n, n))
+            ev[2].record()
+            torch.cuda.synchronize()
+            if rep:
+                fw.append(ev[0].elapsed_time(ev[1]))
+                iv.append(ev[1].elapsed_time(ev[2]))
+            del X, y
+        fw.sort()
+        iv.sort()
+        out[f"{n}^3"] = {"rocfft_rfftn_ms": round(fw[2], 4), "rocfft_irfftn_ms": round(iv[2], 4),
+                         "rocfft_total_ms": round(fw[2] + iv[2], 4)}
+        del x
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline():
-    """Oracle (FP64 NumPy) time for one co-evolution step on a bounded sample."""
+    """Oracle (FP64 NumPy) time of one co-evolution step of the lcdm256 workload itself:
+    256^3 particles and mesh, box 400 Mpc/h, 512^2 rays over 5 deg, the schedule step with
+    the mean plane count (clustered synthetic displacements; the oracle's cost does not
+    depend on the field). Median of the repetitions that fit in about 30 s."""
     import synth
     from oracle import integrator, tables
-    cfg = synth.lcdm(mesh_n=128, ptcl_n=128, box=200.0, ray_n=256, fov_deg=5.0, n_steps=64,
-                     name="lcdm128-sample")
-    s = synth.clustered_displacements(0, 128, 200.0)
+    cfg = synth.lcdm256()
+    n, box, nr = cfg["mesh_n"], cfg["box"], cfg["ray_n"]
+    s = synth.clustered_displacements(0, n, box)
     p = synth.random_momenta(0, len(s), 3.0)
-    q = integrator.lattice(128, 200.0)
-    tab = tables.build_cosmo(cfg["sched"], 0.3, 128, 200.0, 0.0)
-    th0 = integrator.pixel_angles(256, 256, cfg["fov"], cfg["fov"])
+    q = integrator.lattice(n, box)
+    tab = tables.build_cosmo(cfg["sched"], cfg["omega_m"], n, box, 0.0)
+    counts = [len(pl) for pl in tab.planes[:-1]]
+    k = int(np.argmin(np.abs(np.array(counts) - np.mean(counts))))
+    th0 = integrator.pixel_angles(nr, nr, cfg["fov"], cfg["fov"])
     dth = np.zeros_like(th0)
     pr = np.zeros_like(th0)
-    n = 20
-    t0 = time.perf_counter()
-    grads, _ = integrator.pm_force(q + s, 128, 200.0)
-    integrator.matter_step(s, p, q, grads, tab.K[n], tab.D[n], 200.0)
-    t1 = time.perf_counter()
-    integrator.ray_step(dth, pr, th0, grads[0], grads[1], tab.planes[n], tab.d[n],
-                        cfg["observer"][:2], 200.0)
-    t2 = time.perf_counter()
-    # scale to the 256^3 / 512^2 workload: PM work x 8 (particles and nodes), ray work x 4
-    # (rays; the plane count per shell depends only on the cell size, which is the same)
-    t_full = 8.0 * (t1 - t0) + 4.0 * (t2 - t1)
-    return {"value": 512 * 512 / t_full, "unit": "ray-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one oracle co-evolution step at 128^3 particles/mesh, box 200 Mpc/h, "
-                       f"256^2 rays over 5 deg (same cell and field): PM {t1 - t0:.1f} s, "
-                       f"rays {t2 - t1:.2f} s; scaled x8 (PM) and x4 (rays) to the 256^3 / 512^2 "
-                       f"workload; numpy single-threaded"),
-            "pm_step_ms": 8.0 * (t1 - t0) * 1e3, "ray_step_ms": 4.0 * (t2 - t1) * 1e3,
+    pm, ray = [], []
+    t_start = time.perf_counter()
+    while len(pm) < 3 and (len(pm) == 0 or time.perf_counter() - t_start < 20.0):
+        t0 = time.perf_counter()
+        grads, _ = integrator.pm_force(q + s, n, box)
+        integrator.matter_step(s, p, q, grads, tab.K[k], tab.D[k], box)
+        t1 = time.perf_counter()
+        integrator.ray_step(dth, pr, th0, grads[0], grads[1], tab.planes[k], tab.d[k],
+                            cfg["observer"][:2], box)
+        t2 = time.perf_counter()
+        pm.append(t1 - t0)
+        ray.append(t2 - t1)
+    t_pm, t_ray = float(np.median(pm)), float(np.median(ray))
+    return {"value": nr * nr / (t_pm + t_ray), "unit": "ray-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"lcdm256 itself: one oracle co-evolution step (step {k}, {counts[k]} lens "
+                       f"planes; schedule mean {np.mean(counts):.1f}) at 256^3 particles/mesh and "
+                       f"512^2 rays, median of {len(pm)}: PM {t_pm:.1f} s, rays {t_ray:.2f} s; "
+                       "NumPy (FFT included) single-threaded"),
+            "pm_step_ms": t_pm * 1e3, "ray_step_ms": t_ray * 1e3, "repetitions": len(pm),
             "host_nproc": os.cpu_count()}
 
 
@@ -316,6 +387,7 @@ def main():
                     help="skip the 16-realisation batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 workload")
+    ap.add_argument("--no-fft-baseline", action="store_true", help="skip the rocFFT cross-check")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of launch-shape choices: read if present, written after tuning")
@@ -359,7 +431,8 @@ def main():
     dth = [torch.zeros(nrays, device=dev) for _ in range(2)]
     pr = [torch.zeros(nrays, device=dev) for _ in range(2)]
     kappa = torch.empty(nrays, device=dev)
-    sim = hrt.Simulation(**sim_kwargs(cfg), device=dev)
+    maps = [{"kappa": kappa}]
+    sim = hrt.Simulation(**sim_kwargs(cfg, src=[last_boundary_z(cfg)]), device=dev)
     tuned = {}
     if not args.no_tune:
         print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
@@ -367,14 +440,12 @@ def main():
 
     def steps(K):
         """K co-evolution steps from the start of the schedule (hrt_run over the schedule,
-        cyclically), with the convergence map at the source plane."""
+        cyclically), the convergence map written by hrt_run at the source plane."""
         k = 0
         while k < K:
             m = k % N
             cnt = min(N - m, K - k)
-            sim.run(s, p, dth, pr, m, cnt)
-            if m + cnt == N:
-                sim.ray_convergence(dth, kappa)
+            sim.run(s, p, dth, pr, m, cnt, maps=maps)
             k += cnt
 
     def reset():
@@ -422,9 +493,15 @@ def main():
     prof = sim.profile_read()
     sim.profile_enable(False)
 
-    tab = hrt.hrt_tables(hrt.make_config(**sim_kwargs(cfg))[0])
+    tab_cfg, tab_keep = hrt.make_config(**sim_kwargs(cfg))      # keep the host arrays alive
+    tab = hrt.hrt_tables(tab_cfg)
     plane_launches = int(sum(1 for k in range(N) if tab["plane_count"][k] > 0))
     planes_per_launch = float(sum(tab["plane_count"][:N])) / max(plane_launches, 1)
+    timed = [k % N for k in range(args.steps)]
+    timed_cover = {"steps": f"schedule steps {timed[0]}..{timed[-1]}"
+                            + (" (cyclic)" if args.steps > N else ""),
+                   "lens_planes_per_step": round(float(np.mean([tab["plane_count"][k] for k in timed])), 2),
+                   "schedule_mean_lens_planes_per_step": round(float(np.mean(tab["plane_count"][:N])), 2)}
     kernels = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
@@ -465,6 +542,7 @@ def main():
         "config": {"workload": "lcdm256: LambdaCDM PM + HRT, 256^3 particles on a 256^3 mesh, box "
                                "400 Mpc/h replicated, 512^2 rays over 5x5 deg, 64 steps a=1->0.5",
                    "mesh": n, "particles": P, "rays": nrays, "box": box, "schedule_steps": N},
+        "timed_schedule_steps": timed_cover,
         "pm_step_ms": round(pm_ms, 4),
         "pm_step_ms_note": "sum of the PM kernels' HIP-event times per step (per-kernel pass)",
         "ray_step_ms": round(ray_ms, 4),
@@ -521,8 +599,15 @@ def main():
         out["adjoint"] = adjoint_bench(torch, dev)
     if not args.no_large:
         out["large"] = large_bench(hrt, torch, dev, tune=not args.no_tune)
+    if not args.no_fft_baseline:
+        print("[bench] rocFFT cross-check (torch.fft) at 256^3 and 1024^3", file=sys.stderr, flush=True)
+        fb = fft_baseline(torch, dev)
+        ours = sum(kernels[k]["avg_ms"] for k in ("fft_x_r2c", "fft_y_fwd", "fft_z_poisson", "fft_y_inv",
+                                                   "fft_x_c2r") if k in kernels)
+        fb["256^3"]["hand_written_poisson_ms"] = round(ours, 4)
+        out["fft_baseline"] = fb
     if not args.no_cpu_baseline:
-        print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
+        print("[bench] timing the oracle on the host (lcdm256, one step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 

@@ -72,7 +72,7 @@ typedef struct {
     int32_t n_steps;        /* N >= 1                                                    */
     int32_t dtype;          /* HRT_F32 or HRT_F64                                        */
     int32_t flags;          /* HRT_STATIC and/or HRT_ADJOINT, or 0                      */
-    int32_t reserved;       /* must be 0                                                 */
+    int32_t n_src;          /* number of source planes, 0 <= n_src <= HRT_MAX_SOURCES    */
     double box;             /* periodic box side L [Mpc/h]                               */
     double fov_x, fov_y;    /* field of view [rad]                                       */
     double observer[3];     /* observer position in box coordinates [Mpc/h]              */
@@ -81,7 +81,24 @@ typedef struct {
     const double *sched;    /* N+1 host values: a_0..a_N (cosmological, any direction,
                                0 < a <= 1) or chi_0..chi_N [Mpc/h] when HRT_STATIC;
                                copied at hrt_init                                        */
+    const double *src;      /* n_src host values (NULL if n_src = 0), each a step boundary
+                               1..N of sched: the source redshift z (a = 1/(1+z) must equal
+                               some a_k to 1e-9 relative) or, with HRT_STATIC, the source
+                               distance chi [Mpc/h] (equal to some chi_k to 1e-9 relative);
+                               distinct boundaries; rays required. Alg. 1 observes the rays
+                               at these planes (hrt_run / hrt_graph_capture maps).
+                               HRT_EINVAL if a value is not a boundary. Copied at init.  */
+    const double *src_w;    /* NULL, or n_src weights n_g(chi_i) of the source distribution
+                               (Eq. obs_accum): the maps then also accumulate
+                               sum_i src_w[i] * map_i into one more map set              */
 } hrt_config;
+
+enum { HRT_MAX_SOURCES = 256 };
+
+/* Output maps of one source plane (or of the weighted sum over the source planes): device
+ * arrays of Mx*My values of the config's dtype, caller-owned; any may be NULL (not
+ * written). */
+typedef struct { void *kappa, *gamma1, *gamma2, *omega; } hrt_maps;
 
 typedef struct { void *s[3]; void *p[3]; } hrt_matter;   /* device SoA, np^3 each (x, y, z) */
 typedef struct { void *dth[2]; void *p[2]; } hrt_rays;   /* device SoA, Mx*My each (x, y)   */
@@ -148,6 +165,12 @@ int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *c
 /* Runs steps first_step .. first_step+n_steps-1: pm_step then ray_step for every
  * realisation (r may be NULL for matter only); with HRT_STATIC one pm_force then the ray
  * steps (r required). Results are bit-identical to calling pm_step / ray_step step by step.
+ * maps (NULL, or n_cfg * n_maps entries, realisation-major, n_maps = n_src + 1 with source
+ * weights, else n_src): when a step ends on the boundary of source plane i, the maps of
+ * ray_convergence at that plane go to maps[r * n_maps + i] (NULL members are skipped), and
+ * with src_w the weighted sum of Eq. obs_accum to maps[r * n_maps + n_src] (written at the
+ * first source plane along the schedule, added to at the later ones; every member of that
+ * entry that is not NULL). Requires rays and n_src > 0 (else HRT_EINVAL).
  * Particle order (variant of kernel id kd_tiles): 2 keeps the particles in paint-bin order
  * in the workspace from the call's first step to its last: the first step reads the state
  * arrays, the last writes them back, and each drift counts the particles into the next
@@ -159,16 +182,18 @@ int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *c
  * kernels (with the same fused counting). 0 (default) takes 2 for calls of 8 steps or more
  * and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
  * call's work runs. */
-int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps);
+int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps,
+            const hrt_maps *maps);
 
 /* Captures steps first_step .. first_step+n_steps-1 (pm_step then ray_step for every
- * realisation, as hrt_run does; with HRT_STATIC one pm_force then ray_steps; r may be NULL
- * for matter only) into a HIP graph held by the context, replacing any previous one. Nothing runs
- * during capture; hrt_graph_launch replays the whole sequence with one launch on the
- * context's stream. The state arrays and workspace must stay the same between capture and
- * replays. Profiling must be off while capturing. */
+ * realisation, as hrt_run does, with the same source-plane maps; with HRT_STATIC one
+ * pm_force then ray_steps; r may be NULL for matter only) into a HIP graph held by the
+ * context, replacing any previous one. Nothing runs during capture; hrt_graph_launch
+ * replays the whole sequence with one launch on the context's stream. The state arrays,
+ * map arrays and workspace must stay the same between capture and replays. Profiling must
+ * be off while capturing. */
 int hrt_graph_capture(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step,
-                      int n_steps);
+                      int n_steps, const hrt_maps *maps);
 int hrt_graph_launch(hrt_ctx *ctx);
 
 /* Device pointer to an internal mesh of realisation `realisation`, valid until
@@ -218,19 +243,31 @@ int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out);
  * tracer as future work (Sec. 7, via the adjoint method of its ref. LiEtAl2024); these are
  * the exact transposes of the forward discretisation above. A cotangent array has the
  * shape, layout and dtype of the state array it belongs to; the functions update the
- * cotangents in place (device, caller-owned).
+ * cotangents in place (device, caller-owned). m, r, mc, rc point to n_cfg entries (batched
+ * contexts are supported; their realisations are processed one after another). All of them
+ * need a context created with HRT_ADJOINT (else HRT_ESTATE), recompute the force mesh of
+ * the step from m (so they overwrite it: the next ray_step needs a new pm_force/pm_step),
+ * and sum the force-mesh cotangent in 64-bit fixed point, so results are deterministic.
  *
- * hrt_step_vjp: m (s; p may be NULL) and r (dth; p may be NULL) are the state BEFORE step
- * `step`; on entry mc and rc hold the cotangents of the state AFTER the step, on return
- * those of the state before it. It recomputes the force mesh of the step (pm_force), then
- * runs the transposed ray kick-drift, the transposed matter kick-drift, and the transposed
- * force (fourth-order difference, Poisson solve and CIC paint). The force-mesh cotangent is
- * summed in 64-bit fixed point, so results are deterministic. r and rc are both NULL for
- * matter only. Needs a context with one realisation (else HRT_EUNSUPPORTED) created with
- * HRT_ADJOINT (else HRT_ESTATE); with HRT_STATIC the matter does not move, mc->p may be
- * NULL and mc->s receives the lens-position cotangent. Overwrites the force mesh: the next
- * ray_step needs a new pm_force/pm_step. */
+ * hrt_step_vjp: the whole co-evolution step (pm_step then ray_step). m (s; p may be NULL)
+ * and r (dth; p may be NULL) are the state BEFORE step `step`; on entry mc and rc hold the
+ * cotangents of the state AFTER the step, on return those of the state before it. It runs
+ * the transposed ray kick-drift and the transposed matter kick-drift, and the transposed
+ * force (fourth-order difference, Poisson solve, CIC paint) once on the summed cotangent of
+ * the force mesh. r and rc are both NULL for matter only; with HRT_STATIC the matter does
+ * not move, mc->p may be NULL and mc->s receives the lens-position cotangent.
+ *
+ * pm_step_vjp and ray_step_vjp are the same step split along the contract's two forward
+ * calls: pm_step_vjp is the transpose of pm_step (mc after -> before; not valid with
+ * HRT_STATIC), ray_step_vjp that of ray_step: rc after -> before, and the rays' dependence
+ * on the matter through the force mesh added to mc->s (mc->p untouched, may be NULL).
+ * Applying pm_step_vjp and then ray_step_vjp to the same cotangents gives hrt_step_vjp's
+ * result up to rounding (the force's transpose then runs twice, on each part of the
+ * force-mesh cotangent; hrt_step_vjp sums them first and is the cheaper call). */
 int hrt_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                 const hrt_rays *rc, int step);
+int pm_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_matter *mc, int step);
+int ray_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                  const hrt_rays *rc, int step);
 
 /* Adds the cotangent of the deflections from kappa_bar (n_cfg device pointers to Mx*My

@@ -316,9 +316,9 @@ __global__ __launch_bounds__(kThreads) void convergence_vjp_kernel(const T *__re
 }
 
 template <typename T>
-AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+AdjArgs<T> adj_args(hrt_ctx *c, int k, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                     const hrt_rays *rc, int step, AdjScratch &sc) {
-    const Real &re = c->re[0];
+    const Real &re = c->re[k];
     AdjArgs<T> a{};
     for (int d = 0; d < 3; ++d) {
         a.s[d] = static_cast<const T *>(m->s[d]);
@@ -377,11 +377,14 @@ AdjArgs<T> adj_args(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
 
 inline int nb(int64_t count) { return (int)((count + kThreads - 1) / kThreads); }
 
+// Reverse of step `step` for realisation k (m, r, mc, rc point to that realisation's
+// state and cotangents; r and rc are NULL without the ray part, matter = false leaves out
+// the matter kick-drift).
 template <typename T>
-hipError_t step_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
-                         const hrt_rays *rc, int step, bool matter) {
+hipError_t step_vjp_one(hrt_ctx *c, int k, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                        const hrt_rays *rc, int step, bool matter) {
     AdjScratch sc{};
-    const AdjArgs<T> a = adj_args<T>(c, m, r, mc, rc, step, sc);
+    const AdjArgs<T> a = adj_args<T>(c, k, m, r, mc, rc, step, sc);
     const bool rays = r != nullptr;
     hipStream_t st = c->stream;
     const int64_t n3 = (int64_t)a.n * a.n * a.n;
@@ -389,20 +392,32 @@ hipError_t step_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, con
     adj_zero_kernel<T><<<zero_gbar ? nb(2 * n3) : 1, kThreads, 0, st>>>(a, zero_gbar ? 1 : 0);
     if (rays) ray_vjp_prep_kernel<T><<<nb(a.nrays), kThreads, 0, st>>>(a);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && matter) e = launch_matter_vjp(c, m, mc, step, sc);
+    if (e == hipSuccess && matter) e = launch_matter_vjp(c, k, m, mc, step, sc);
     if (e != hipSuccess) return e;
     if (rays) {
         ray_vjp_kernel<T><<<dim3(nb(a.nrays), a.parts), kThreads, 0, st>>>(a);
         ray_vjp_sum_kernel<T><<<nb(a.nrays), kThreads, 0, st>>>(a);
     }
-    if (matter) e = launch_gbar_tiles(c, rays, sc);
+    if (matter) e = launch_gbar_tiles(c, k, rays, sc);
     else gbar_convert_kernel<T><<<nb(n3), kThreads, 0, st>>>(a);
     if (e != hipSuccess) return e;
     fd4_div_kernel<T><<<nb(n3), kThreads, 0, st>>>(a);
     e = hipGetLastError();
-    if (e == hipSuccess) e = launch_poisson(c);
+    if (e == hipSuccess) e = launch_poisson(c, k);
     if (e == hipSuccess) paint_vjp_kernel<T><<<nb(a.P), kThreads, 0, st>>>(a);
     return e == hipSuccess ? hipGetLastError() : e;
+}
+
+// Every realisation of the context in turn (the force meshes were recomputed for all of
+// them together; each realisation's reverse-mode scratch is its own).
+template <typename T>
+hipError_t step_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                         const hrt_rays *rc, int step, bool matter) {
+    for (int k = 0; k < (int)c->re.size(); ++k)
+        if (hipError_t e = step_vjp_one<T>(c, k, &m[k], r ? &r[k] : nullptr, &mc[k], rc ? &rc[k] : nullptr,
+                                           step, matter))
+            return e;
+    return hipSuccess;
 }
 
 }  // namespace

@@ -159,8 +159,10 @@ static int batch_layouts(const hrt_config *cfg, int n_cfg, std::vector<hrt::Step
     for (int r = 0; r < n_cfg; ++r) {
         const hrt_config &c0 = cfg[0], &c = cfg[r];
         if (c.dtype != c0.dtype || c.n_steps != c0.n_steps || c.flags != c0.flags ||
-            (c.ray_nx > 0) != (c0.ray_nx > 0)) {
-            err = "batched configurations must share dtype, n_steps, flags and whether they have rays";
+            (c.ray_nx > 0) != (c0.ray_nx > 0) || c.n_src != c0.n_src ||
+            (c.src_w == nullptr) != (c0.src_w == nullptr)) {
+            err = "batched configurations must share dtype, n_steps, flags, whether they have rays, "
+                  "n_src and whether they have source weights";
             return HRT_EINVAL;
         }
         hrt::StepTables t;
@@ -237,6 +239,8 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
     c->f64 = cfg[0].dtype == HRT_F64;
     c->is_static = (cfg[0].flags & HRT_STATIC) != 0;
     c->has_rays = cfg[0].ray_nx > 0;
+    c->n_src = cfg[0].n_src;
+    c->n_maps = cfg[0].n_src + (cfg[0].src_w ? 1 : 0);
     c->re.resize(n_cfg);
     char *ws = static_cast<char *>(workspace);
     hipError_t e = hipSuccess;
@@ -245,6 +249,8 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
         re.cfg = cfg[r];
         re.sched.assign(cfg[r].sched, cfg[r].sched + cfg[r].n_steps + 1);
         re.cfg.sched = re.sched.data();
+        re.cfg.src = nullptr;            // copied into the tables (src_step, src_w)
+        re.cfg.src_w = nullptr;
         re.n = cfg[r].mesh_n;
         re.np = cfg[r].ptcl_n;
         re.mx = cfg[r].ray_nx;
@@ -396,13 +402,55 @@ extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *const *kappa
     return check_hip(c, hrt::launch_convergence(c, a), "convergence");
 }
 
+// After the ray step that ends on boundary b: the maps of every source plane at b (Alg. 1
+// `observe`), and the n_g-weighted sum (Eq. obs_accum: the first source plane along the
+// schedule writes it, the later ones add to it). One launch for all realisations that have
+// a source plane at b.
+static int observe(hrt_ctx *c, const hrt_rays *r, int b, const hrt_maps *maps) {
+    if (!maps || c->n_src == 0 || b > c->N) return HRT_OK;
+    const int R = (int)c->re.size();
+    std::vector<hrt_maps> src(R), acc(R);
+    std::vector<double> w(R, 0.0);
+    std::vector<int> mode(R, 0);
+    bool any = false;
+    for (int k = 0; k < R; ++k) {
+        const hrt::StepTables &t = c->re[k].tab;
+        src[k] = hrt_maps{};
+        acc[k] = hrt_maps{};
+        int first = c->N + 1;
+        for (int i = 0; i < c->n_src; ++i) first = std::min(first, (int)t.src_step[i]);
+        for (int i = 0; i < c->n_src; ++i) {
+            if (t.src_step[i] != b) continue;
+            src[k] = maps[(size_t)k * c->n_maps + i];
+            if (t.has_src_w) {
+                acc[k] = maps[(size_t)k * c->n_maps + c->n_src];
+                w[k] = t.src_w[i];
+                mode[k] = b == first ? 1 : 2;
+            }
+            any = any || src[k].kappa || src[k].gamma1 || src[k].gamma2 || src[k].omega || mode[k];
+        }
+    }
+    if (!any) return HRT_OK;
+    hrt::StepArgs a;
+    a.r = r;
+    a.src_maps = src.data();
+    a.acc_maps = acc.data();
+    a.acc_w = w.data();
+    a.acc_mode = mode.data();
+    return check_hip(c, hrt::launch_convergence(c, a), "source-plane maps");
+}
+
 // Steps first..first+n-1 with the matter drift of each step counting the particles into
-// the next step's paint bins (the state is not touched by anyone else in between).
-static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int first, int n) {
+// the next step's paint bins (the state is not touched by anyone else in between); rays
+// observed at the source planes the steps reach (maps may be NULL).
+static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int first, int n,
+                     const hrt_maps *maps) {
     if (c->is_static) {
         if (int rc = pm_force(c, m, first)) return rc;
-        for (int k = first; k < first + n; ++k)
+        for (int k = first; k < first + n; ++k) {
             if (int rc = ray_step(c, r, k)) return rc;
+            if (int rc = observe(c, r, k + 1, maps)) return rc;
+        }
         return HRT_OK;
     }
     // Particle order of the sequence (kd_tiles variant): 1 = Lagrangian order (pm_step's
@@ -437,8 +485,10 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         a.count_next = k + 1 < first + n;
         if (int rc = check_hip(c, hrt::launch_matter_kd(c, a), "matter kick-drift")) return rc;
         counted = a.count_next;
-        if (r)
+        if (r) {
             if (int rc = ray_step(c, r, k)) return rc;
+            if (int rc = observe(c, r, k + 1, maps)) return rc;
+        }
         cur ^= 1;                        // sorted: the next paint bins into the other buffer
     }
     if (sorted) {
@@ -451,8 +501,14 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
     return HRT_OK;
 }
 
+static int check_maps(hrt_ctx *c, const hrt_rays *r, const hrt_maps *maps) {
+    if (maps && !r) return fail(c, HRT_EINVAL, "maps need the rays");
+    if (maps && c->n_src == 0) return fail(c, HRT_EINVAL, "maps given but the configuration has no source planes");
+    return HRT_OK;
+}
+
 extern "C" int hrt_run(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int first_step,
-                       int n_steps) {
+                       int n_steps, const hrt_maps *maps) {
     if (!c) return HRT_EINVAL;
     if (int g = guard(c)) return g;
     if (n_steps < 1 || first_step < 0 || first_step + n_steps > c->N + 1)
@@ -461,11 +517,12 @@ extern "C" int hrt_run(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int f
     if (r)
         if (int rc = check_rays(c, r, true)) return rc;
     if (c->is_static && !r) return fail(c, HRT_EINVAL, "a static run needs rays");
-    return run_steps(c, m, r, first_step, n_steps);
+    if (int rc = check_maps(c, r, maps)) return rc;
+    return run_steps(c, m, r, first_step, n_steps, maps);
 }
 
 extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
-                                 int first_step, int n_steps) {
+                                 int first_step, int n_steps, const hrt_maps *maps) {
     if (!c) return HRT_EINVAL;
     if (int g = guard(c)) return g;
     if (c->prof) return fail(c, HRT_ESTATE, "switch profiling off before capturing a graph");
@@ -474,6 +531,7 @@ extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays
     if (int rc = check_matter(c, m, !c->is_static)) return rc;
     if (r)
         if (int rc = check_rays(c, r, true)) return rc;
+    if (int rc = check_maps(c, r, maps)) return rc;
     if (c->graph) {
         hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
@@ -482,12 +540,17 @@ extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays
     if (int rc = check_hip(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream"))
         return rc;
     c->stream = cap;
+    // nothing runs while capturing: the force mesh the sequence leaves behind becomes
+    // current only when the graph is launched
+    const int force_before = c->force_step;
     int rc = check_hip(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
     if (rc == HRT_OK) rc = (c->is_static && !r) ? pm_force(c, m, first_step)
-                                                : run_steps(c, m, r, first_step, n_steps);
+                                                : run_steps(c, m, r, first_step, n_steps, maps);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cap, &graph);
     c->stream = user;
+    c->graph_force_step = c->force_step;
+    c->force_step = force_before;
     if (rc == HRT_OK) rc = check_hip(c, e, "end capture");
     if (rc == HRT_OK) rc = check_hip(c, hipGraphInstantiate(&c->graph, graph, nullptr, nullptr, 0),
                                      "graph instantiate");
@@ -500,7 +563,9 @@ extern "C" int hrt_graph_launch(hrt_ctx *c) {
     if (!c) return HRT_EINVAL;
     if (int g = guard(c)) return g;
     if (!c->graph) return fail(c, HRT_ESTATE, "no captured graph");
-    return check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
+    if (int rc = check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch")) return rc;
+    c->force_step = c->graph_force_step;
+    return HRT_OK;
 }
 
 extern "C" int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out) {
@@ -540,26 +605,54 @@ extern "C" int hrt_ic_2lpt(hrt_ctx *c, int realisation, const void *noise, const
     return HRT_OK;
 }
 
-extern "C" int hrt_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
-                            const hrt_matter *mc, const hrt_rays *rc, int step) {
-    if (!c) return HRT_EINVAL;
-    if (int g = guard(c)) return g;
-    if (c->re.size() != 1) return fail(c, HRT_EUNSUPPORTED, "reverse mode needs a single realisation");
+// Reverse of step `step` for every realisation: matter kick-drift (matter) and/or ray
+// kick-drift (r, rc non-NULL), with the force mesh recomputed first and the force's
+// transpose applied to the summed force-mesh cotangent.
+static int step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                    const hrt_rays *rc, int step, bool matter) {
     if (!(c->re[0].cfg.flags & HRT_ADJOINT))
         return fail(c, HRT_ESTATE, "context was created without HRT_ADJOINT");
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
     if (int rc0 = check_matter(c, m, false)) return rc0;
-    if (int rc0 = check_matter(c, mc, !c->is_static)) return rc0;
+    if (!mc) return fail(c, HRT_EINVAL, "NULL matter cotangent");
+    for (size_t k = 0; k < c->re.size(); ++k)
+        for (int d = 0; d < 3; ++d) {
+            if (!mc[k].s[d]) return fail(c, HRT_EINVAL, "NULL displacement cotangent array");
+            if (matter && !mc[k].p[d]) return fail(c, HRT_EINVAL, "NULL momentum cotangent array");
+        }
     if ((r == nullptr) != (rc == nullptr))
         return fail(c, HRT_EINVAL, "ray state and ray cotangent must both be given or both be NULL");
     if (r) {
         if (int rc0 = check_rays(c, r, false)) return rc0;
         if (int rc0 = check_rays(c, rc, true)) return rc0;
     }
+    if (!matter && !r) return fail(c, HRT_EINVAL, "nothing to differentiate: no rays and no matter step");
     if (int rc0 = pm_force(c, m, step)) return rc0;
-    int rc0 = check_hip(c, hrt::launch_step_vjp(c, m, r, mc, rc, step, !c->is_static), "step vjp");
+    int rc0 = check_hip(c, hrt::launch_step_vjp(c, m, r, mc, rc, step, matter), "step vjp");
     c->force_step = -1;          // the force mesh now holds the cotangent
     return rc0;
+}
+
+extern "C" int hrt_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
+                            const hrt_matter *mc, const hrt_rays *rc, int step) {
+    if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
+    return step_vjp(c, m, r, mc, rc, step, !c->is_static);
+}
+
+extern "C" int pm_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step) {
+    if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
+    if (c->is_static) return fail(c, HRT_ESTATE, "pm_step_vjp is not valid for a static run");
+    return step_vjp(c, m, nullptr, mc, nullptr, step, true);
+}
+
+extern "C" int ray_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
+                            const hrt_rays *rc, int step) {
+    if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
+    if (!r || !rc) return fail(c, HRT_EINVAL, "ray_step_vjp needs the ray state and its cotangent");
+    return step_vjp(c, m, r, mc, rc, step, false);
 }
 
 extern "C" int ray_convergence_vjp(hrt_ctx *c, void *const *kappa_bar, const hrt_rays *rc) {

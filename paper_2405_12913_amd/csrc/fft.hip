@@ -591,7 +591,8 @@ hipError_t poisson_size(hrt_ctx *c, int n, const std::vector<int> &ids) {
 }
 
 template <typename T>
-hipError_t poisson_impl(hrt_ctx *c) {
+hipError_t poisson_impl(hrt_ctx *c, int only) {
+    if (only >= 0) return poisson_size<T>(c, c->re[only].n, std::vector<int>{only});
     // group realisations by mesh size, in order of first appearance, <= kMaxBatch per launch
     std::vector<int> sizes;
     for (const Real &re : c->re)
@@ -950,8 +951,8 @@ hipError_t ic_impl(hrt_ctx *c, int r, const void *noise, const IcParams &p, cons
 
 }  // namespace
 
-hipError_t launch_poisson(hrt_ctx *c) {
-    return c->f64 ? poisson_impl<double>(c) : poisson_impl<float>(c);
+hipError_t launch_poisson(hrt_ctx *c, int only) {
+    return c->f64 ? poisson_impl<double>(c, only) : poisson_impl<float>(c, only);
 }
 
 hipError_t launch_ic(hrt_ctx *c, int r, const void *noise, const IcParams &p, const hrt_matter *m) {

@@ -18,6 +18,9 @@ struct StepTables {
     std::vector<int32_t> plane_begin, plane_count;   // N+1 each
     std::vector<int32_t> plane_mesh;         // mesh plane index (j mod n) per entry
     std::vector<double> plane_chi, plane_w;  // chi_j and weight w_j per entry
+    std::vector<int32_t> src_step;           // step boundary of each source plane
+    std::vector<double> src_w;               // n_g weights (Eq. obs_accum), if has_src_w
+    bool has_src_w = false;
 };
 
 // Fills t for cfg; returns HRT_OK or an error with a message in err.
@@ -91,6 +94,14 @@ struct StepArgs {
     void *const *g1 = nullptr;
     void *const *g2 = nullptr;
     void *const *om = nullptr;
+    // Source-plane observation (hrt_run maps): per realisation, the maps of this source
+    // plane (entries may be NULL), the accumulated n_g-weighted maps, their weight and mode
+    // (0 = none, 1 = write w * map, 2 = add w * map). A realisation with nothing to write is
+    // skipped. Unused (NULL) for ray_convergence, which writes kappa for every realisation.
+    const hrt_maps *src_maps = nullptr;
+    const hrt_maps *acc_maps = nullptr;
+    const double *acc_w = nullptr;
+    const int *acc_mode = nullptr;
     // Fused bin histogram (hrt_run): the matter kick-drift also counts the drifted
     // particles into the paint bins of the next step, whose paint then skips its own count.
     bool count_next = false;     // launch_matter_kd: zero the counts, count the new positions
@@ -117,10 +128,12 @@ struct hrt_ctx {
     hipStream_t stream = nullptr;
     int N = 0;                   // shared number of steps
     bool f64 = false, is_static = false, has_rays = false;
+    int n_src = 0, n_maps = 0;   // source planes; map sets per realisation (+1 with weights)
     int force_step = -1;         // boundary of the G currently in the workspaces
     std::string err;
     // captured step sequence (hrt_graph_capture / hrt_graph_launch)
     hipGraphExec_t graph = nullptr;
+    int graph_force_step = -1;   // force_step after the captured sequence has run
     // per-kernel timing (off unless hrt_profile_enable)
     bool prof = false;
     std::vector<hrt::ProfRecord> prof_pending;
@@ -155,7 +168,7 @@ namespace hrt {
 void prof_begin(hrt_ctx *c);           // record a start event when profiling is on
 void prof_end(hrt_ctx *c, int id);     // record the stop event of kernel `id`
 hipError_t launch_paint(hrt_ctx *c, const StepArgs &a);
-hipError_t launch_poisson(hrt_ctx *c);
+hipError_t launch_poisson(hrt_ctx *c, int only = -1);   // every realisation, or only `only`
 hipError_t launch_gradient(hrt_ctx *c);
 hipError_t launch_plane_gradient(hrt_ctx *c, int step);      // G on the step's lens planes
 hipError_t launch_state_gather(hrt_ctx *c, const StepArgs &a);   // sorted state -> caller
@@ -164,7 +177,7 @@ hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ic(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
                      const hrt_matter *m);
-// Reverse-mode scratch of realisation 0 (HRT_ADJOINT): fixed-point ray contributions to
+// Reverse-mode scratch of one realisation (HRT_ADJOINT): fixed-point ray contributions to
 // the cotangent of G_x, G_y (2 n^3), the largest contribution (double bits), and the
 // particles' kick weights K p_bar in paint-bin order (P x 4 values of the dtype).
 struct AdjScratch {
@@ -173,14 +186,14 @@ struct AdjScratch {
     void *wsorted;
     int hbits;
 };
-// Matter part of the step VJP: p_bar += D s_bar; s_bar += K (d readout/dx)^T p_bar; the
+// Matter part of the step VJP of realisation k: p_bar += D s_bar; s_bar += K (d readout/dx)^T p_bar; the
 // particles re-binned with their weights; the largest weight into *maxbits.
-hipError_t launch_matter_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+hipError_t launch_matter_vjp(hrt_ctx *c, int k, const hrt_matter *m, const hrt_matter *mc, int step,
                              const AdjScratch &s);
 // Force-mesh cotangent: per tile, the particles' CIC-weighted K p_bar summed in LDS plus
 // the rays' part from s.gbar (if rays), converted into the G mesh slot.
-hipError_t launch_gbar_tiles(hrt_ctx *c, bool rays, const AdjScratch &s);
-// Reverse mode (realisation 0 of a context created with HRT_ADJOINT, see adjoint.hip).
+hipError_t launch_gbar_tiles(hrt_ctx *c, int k, bool rays, const AdjScratch &s);
+// Reverse mode (every realisation of a context created with HRT_ADJOINT, see adjoint.hip).
 hipError_t launch_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                            const hrt_rays *rc, int step, bool matter);
 hipError_t launch_convergence_vjp(hrt_ctx *c, int realisation, const void *kappa_bar,

@@ -1246,11 +1246,11 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
 }
 
 template <typename T>
-MatterAdj<T> matter_adj(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+MatterAdj<T> matter_adj(hrt_ctx *c, int k, const hrt_matter *m, const hrt_matter *mc, int step,
                         const AdjScratch &sc, bool rays) {
-    const Real &re = c->re[0];
+    const Real &re = c->re[k];
     MatterAdj<T> ma{};
-    fill_particles<T>(c, 0, *m, ma.a, 0.0, 0.0);
+    fill_particles<T>(c, k, *m, ma.a, 0.0, 0.0);
     if (mc) {
         for (int d = 0; d < 3; ++d) {
             ma.sb[d] = static_cast<T *>(mc->s[d]);
@@ -1268,18 +1268,18 @@ MatterAdj<T> matter_adj(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, i
 }
 
 template <typename T>
-hipError_t matter_vjp_impl(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+hipError_t matter_vjp_impl(hrt_ctx *c, int k, const hrt_matter *m, const hrt_matter *mc, int step,
                            const AdjScratch &sc) {
-    const MatterAdj<T> ma = matter_adj<T>(c, m, mc, step, sc, false);
+    const MatterAdj<T> ma = matter_adj<T>(c, k, m, mc, step, sc, false);
     cursor_reset_kernel<T><<<(ma.a.nbins + 255) / 256, 256, 0, c->stream>>>(ma);
     matter_vjp_kernel<T><<<particle_blocks(ma.a.P), kThreads, 0, c->stream>>>(ma);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t gbar_tiles_impl(hrt_ctx *c, bool rays, const AdjScratch &sc) {
+hipError_t gbar_tiles_impl(hrt_ctx *c, int k, bool rays, const AdjScratch &sc) {
     hrt_matter none{};
-    const MatterAdj<T> ma = matter_adj<T>(c, &none, nullptr, 0, sc, rays);
+    const MatterAdj<T> ma = matter_adj<T>(c, k, &none, nullptr, 0, sc, rays);
     const int nt = ma.a.n / kTile;
     gbar_tiles_kernel<T><<<nt * nt * nt, kThreads, 0, c->stream>>>(ma);
     return hipGetLastError();
@@ -1287,13 +1287,13 @@ hipError_t gbar_tiles_impl(hrt_ctx *c, bool rays, const AdjScratch &sc) {
 
 }  // namespace
 
-hipError_t launch_matter_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step,
+hipError_t launch_matter_vjp(hrt_ctx *c, int k, const hrt_matter *m, const hrt_matter *mc, int step,
                              const AdjScratch &s) {
-    return c->f64 ? matter_vjp_impl<double>(c, m, mc, step, s) : matter_vjp_impl<float>(c, m, mc, step, s);
+    return c->f64 ? matter_vjp_impl<double>(c, k, m, mc, step, s) : matter_vjp_impl<float>(c, k, m, mc, step, s);
 }
 
-hipError_t launch_gbar_tiles(hrt_ctx *c, bool rays, const AdjScratch &s) {
-    return c->f64 ? gbar_tiles_impl<double>(c, rays, s) : gbar_tiles_impl<float>(c, rays, s);
+hipError_t launch_gbar_tiles(hrt_ctx *c, int k, bool rays, const AdjScratch &s) {
+    return c->f64 ? gbar_tiles_impl<double>(c, k, rays, s) : gbar_tiles_impl<float>(c, k, rays, s);
 }
 
 hipError_t launch_paint(hrt_ctx *c, const StepArgs &a) {

@@ -27,6 +27,9 @@ struct RayR {                  // one realisation, as the ray kernels see it
     const PlaneEntry *planes;
     const v4<T> *g;
     T *kappa, *g1, *g2, *om;
+    T *akappa, *ag1, *ag2, *aom;   // n_g-weighted sums over the source planes (Eq. obs_accum)
+    T aw;                          // weight of this source plane
+    int amode;                     // 0: none, 1: write aw * map, 2: add aw * map
     int begin, count, n, mx, my, nrays;
     double inv_cell, obsx, obsy, mux, muy, half_mx, half_my;
     T d, inv2mux, inv2muy;
@@ -139,14 +142,22 @@ __global__ __launch_bounds__(kThreads) void convergence_kernel(RayBatch<T> b) {
     const T dyx = fd<T>(a.dthy, i, ix, mx, 1) * a.inv2mux;    // A21
     const T dyy = fd<T>(a.dthy, i, iy, my, mx) * a.inv2muy;   // A22 - 1
     const T k = T(-0.5) * (dxx + dyy);                        // kappa = 1 - (A11 + A22)/2
-    a.kappa[i] = k;
-    if (a.g1 || a.g2 || a.om) {
+    if (a.kappa) a.kappa[i] = k;
+    const bool acc = a.amode != 0;
+    if (a.g1 || a.g2 || a.om || (acc && (a.ag1 || a.ag2 || a.aom))) {
         const T c2v = T(0.5) * (dxy - dyx), c3 = T(0.5) * (dyy - dxx), c4 = T(0.5) * (dxy + dyx);
         const T w = c2v / (T(1) - k);
+        const T g1 = c3 + c4 * w, g2 = -c4 + c3 * w;
         if (a.om) a.om[i] = w;
-        if (a.g1) a.g1[i] = c3 + c4 * w;
-        if (a.g2) a.g2[i] = -c4 + c3 * w;
+        if (a.g1) a.g1[i] = g1;
+        if (a.g2) a.g2[i] = g2;
+        if (acc) {
+            if (a.aom) a.aom[i] = (a.amode == 2 ? a.aom[i] : T(0)) + a.aw * w;
+            if (a.ag1) a.ag1[i] = (a.amode == 2 ? a.ag1[i] : T(0)) + a.aw * g1;
+            if (a.ag2) a.ag2[i] = (a.amode == 2 ? a.ag2[i] : T(0)) + a.aw * g2;
+        }
     }
+    if (acc && a.akappa) a.akappa[i] = (a.amode == 2 ? a.akappa[i] : T(0)) + a.aw * k;
 }
 
 template <typename T>
@@ -160,7 +171,21 @@ void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
     a.py = static_cast<T *>(rays.p[1]);
     a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
     a.g = reinterpret_cast<const v4<T> *>(re.ws + re.lay.grad);
-    if (s.kappa) {
+    if (s.src_maps) {
+        const hrt_maps &sm = s.src_maps[r], &am = s.acc_maps[r];
+        a.kappa = static_cast<T *>(sm.kappa);
+        a.g1 = static_cast<T *>(sm.gamma1);
+        a.g2 = static_cast<T *>(sm.gamma2);
+        a.om = static_cast<T *>(sm.omega);
+        a.amode = s.acc_mode[r];
+        if (a.amode) {
+            a.akappa = static_cast<T *>(am.kappa);
+            a.ag1 = static_cast<T *>(am.gamma1);
+            a.ag2 = static_cast<T *>(am.gamma2);
+            a.aom = static_cast<T *>(am.omega);
+            a.aw = (T)s.acc_w[r];
+        }
+    } else if (s.kappa) {
         a.kappa = static_cast<T *>(s.kappa[r]);
         a.g1 = s.g1 ? static_cast<T *>(s.g1[r]) : nullptr;
         a.g2 = s.g2 ? static_cast<T *>(s.g2[r]) : nullptr;
@@ -195,8 +220,12 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
         b.map.start[0] = 0;
         for (int k = 0; k < R; ++k) {
             fill_rays<T>(c, r0 + k, s, k, b.r[k]);
-            b.map.start[k + 1] = b.map.start[k] + (b.r[k].nrays + kThreads - 1) / kThreads;
+            const RayR<T> &q = b.r[k];
+            // a source-plane map launch skips realisations with nothing to write here
+            const bool idle = CONV && !q.kappa && !q.g1 && !q.g2 && !q.om && q.amode == 0;
+            b.map.start[k + 1] = b.map.start[k] + (idle ? 0 : (q.nrays + kThreads - 1) / kThreads);
         }
+        if (b.map.start[R] == 0) continue;
         const int v = c->variant[K_RAY_STEP];
         b.rmap = v % 3;
         b.xcd = v >= 3 ? 0 : 1;

@@ -256,7 +256,13 @@ int validate_config(const hrt_config &c, std::string &err) {
     if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
     if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
     if (c.flags & ~(HRT_STATIC | HRT_ADJOINT)) return bad("unknown flag");
-    if (c.reserved != 0) return bad("reserved must be 0");
+    if (c.n_src < 0 || c.n_src > HRT_MAX_SOURCES) return bad("n_src out of range [0, HRT_MAX_SOURCES]");
+    if (c.n_src > 0 && !c.src) return bad("src is NULL with n_src > 0");
+    if (c.n_src > 0 && c.ray_nx == 0) return bad("source planes need rays");
+    for (int i = 0; i < c.n_src; ++i) {
+        if (!std::isfinite(c.src[i]) || !(c.src[i] > 0)) return bad("source planes must be positive and finite");
+        if (c.src_w && !std::isfinite(c.src_w[i])) return bad("source weights must be finite");
+    }
     if (!(c.box > 0) || !std::isfinite(c.box)) return bad("box must be positive");
     if (c.ray_nx > 0 && (!(c.fov_x > 0) || !(c.fov_y > 0) || c.fov_x > 1.0 || c.fov_y > 1.0))
         return bad("fov must be in (0, 1] rad");
@@ -313,6 +319,32 @@ int build_tables(const hrt_config &c, StepTables &t, std::string &err) {
         }
     }
     if (c.ray_nx == 0) return HRT_OK;
+    // source planes: each must sit on a step boundary 1..N of the schedule (Alg. 1 observes
+    // the rays at the end of a step)
+    t.src_step.assign(c.n_src, -1);
+    t.src_w.assign(c.n_src, 0.0);
+    t.has_src_w = c.src_w != nullptr;
+    for (int i = 0; i < c.n_src; ++i) {
+        const double v = stat ? c.src[i] : 1.0 / (1.0 + c.src[i]);
+        for (int k = 1; k <= N; ++k) {
+            const double b = stat ? t.chi[k] : t.a[k];
+            if (std::fabs(b - v) <= 1e-9 * std::max(std::fabs(b), stat ? 1.0 : 0.0)) {
+                t.src_step[i] = k;
+                break;
+            }
+        }
+        if (t.src_step[i] < 0) {
+            err = std::string("source plane ") + std::to_string(c.src[i]) +
+                  (stat ? " (chi)" : " (z)") + " is not a step boundary of the schedule";
+            return HRT_EINVAL;
+        }
+        for (int j = 0; j < i; ++j)
+            if (t.src_step[j] == t.src_step[i]) {
+                err = "two source planes on the same step boundary";
+                return HRT_EINVAL;
+            }
+        if (c.src_w) t.src_w[i] = c.src_w[i];
+    }
     const double rho_bar = std::pow((double)c.ptcl_n, 3) / std::pow((double)c.mesh_n, 3);
     const double static_pref = -8.0 * kPi * kGoverC2 * c.static_mass * rho_bar / (cell * cell);
     std::vector<int64_t> js;

@@ -26,15 +26,20 @@ EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", 
             "hrt_profile_enable", "hrt_profile_read", "hrt_kernel_name", "hrt_ic_2lpt",
             "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
             "ray_convergence_vjp", "hrt_ic_2lpt_vjp", "hrt_num_variants", "hrt_set_variant",
-            "hrt_get_variant", "hrt_autotune", "hrt_run", "hrt_init_noalloc")
+            "hrt_get_variant", "hrt_autotune", "hrt_run", "hrt_init_noalloc", "pm_step_vjp",
+            "ray_step_vjp")
 
 
 class HrtConfig(ctypes.Structure):
     _fields_ = [("mesh_n", c_int32), ("ptcl_n", c_int32), ("ray_nx", c_int32), ("ray_ny", c_int32),
-                ("n_steps", c_int32), ("dtype", c_int32), ("flags", c_int32), ("reserved", c_int32),
+                ("n_steps", c_int32), ("dtype", c_int32), ("flags", c_int32), ("n_src", c_int32),
                 ("box", c_double), ("fov_x", c_double), ("fov_y", c_double),
                 ("observer", c_double * 3), ("omega_m", c_double), ("static_mass", c_double),
-                ("sched", POINTER(c_double))]
+                ("sched", POINTER(c_double)), ("src", POINTER(c_double)), ("src_w", POINTER(c_double))]
+
+
+class HrtMaps(ctypes.Structure):
+    _fields_ = [("kappa", c_void_p), ("gamma1", c_void_p), ("gamma2", c_void_p), ("omega", c_void_p)]
 
 
 class HrtMatter(ctypes.Structure):
@@ -81,9 +86,9 @@ def lib():
         L.ray_step.argtypes = [c_void_p, P(HrtRays), c_int]
         L.ray_convergence.argtypes = [c_void_p, P(HrtRays), P(c_void_p), P(c_void_p), P(c_void_p),
                                       P(c_void_p)]
-        L.hrt_graph_capture.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int]
+        L.hrt_graph_capture.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int, P(HrtMaps)]
         L.hrt_graph_launch.argtypes = [c_void_p]
-        L.hrt_run.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int]
+        L.hrt_run.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int, P(HrtMaps)]
         L.hrt_mesh_ptr.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
         L.hrt_tables.argtypes = [P(HrtConfig)] + [P(c_double)] * 5 + [P(c_int32)] * 3 + \
             [P(c_double)] * 2 + [c_int32, P(c_int32)]
@@ -92,6 +97,8 @@ def lib():
         L.hrt_ic_2lpt.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter)]
         L.hrt_ic_factors.argtypes = [P(HrtConfig), P(HrtIcParams), P(c_double)]
         L.hrt_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays), c_int]
+        L.pm_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtMatter), c_int]
+        L.ray_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays), c_int]
         L.ray_convergence_vjp.argtypes = [c_void_p, P(c_void_p), P(HrtRays)]
         L.hrt_ic_2lpt_vjp.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter), c_void_p]
         L.hrt_num_variants.argtypes = [c_int]
@@ -115,8 +122,11 @@ def _check(rc, ctx=None):
 
 def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
                 observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0,
-                adjoint=False):
-    """hrt_config from keyword arguments; returns (config, schedule array kept alive)."""
+                adjoint=False, src=None, src_w=None):
+    """hrt_config from keyword arguments; returns (config, host arrays kept alive).
+
+    src: source planes (redshifts, or chi with static=True), each a step boundary;
+    src_w: optional weights n_g of the source planes (Eq. obs_accum)."""
     sched = np.ascontiguousarray(sched, dtype=np.float64)
     if len(sched) != n_steps + 1:
         raise ValueError("sched must have n_steps + 1 entries")
@@ -125,13 +135,26 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     cfg.n_steps = n_steps
     cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
     cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0)
-    cfg.reserved = 0
+    cfg.n_src = 0 if src is None else len(src)
     cfg.box, cfg.fov_x, cfg.fov_y = box, fov_x, fov_y
     for i in range(3):
         cfg.observer[i] = observer[i]
     cfg.omega_m, cfg.static_mass = omega_m, static_mass
     cfg.sched = sched.ctypes.data_as(POINTER(c_double))
-    return cfg, sched
+    keep = [sched]
+    if src is not None:
+        src = np.ascontiguousarray(src, dtype=np.float64)
+        cfg.src = src.ctypes.data_as(POINTER(c_double))
+        keep.append(src)
+        if src_w is not None:
+            src_w = np.ascontiguousarray(src_w, dtype=np.float64)
+            if len(src_w) != len(src):
+                raise ValueError("src_w must have one weight per source plane")
+            cfg.src_w = src_w.ctypes.data_as(POINTER(c_double))
+            keep.append(src_w)
+    elif src_w is not None:
+        raise ValueError("src_w needs src")
+    return cfg, keep
 
 
 def hrt_workspace_bytes(cfg, n_cfg=1):
@@ -213,9 +236,9 @@ class Simulation:
         self.cfgs = (HrtConfig * self.R)()
         self._scheds = []
         for k, kw in enumerate(configs):
-            cfg, sched = make_config(**kw)
+            cfg, keep = make_config(**kw)
             self.cfgs[k] = cfg
-            self._scheds.append(sched)
+            self._scheds.append(keep)
         self.cfg = self.cfgs[0]
         self.dtype = torch.float64 if self.cfg.dtype == HRT_F64 else torch.float32
         self.device = torch.device(device)
@@ -296,17 +319,44 @@ class Simulation:
         _check(lib().ray_convergence(self.ctx, self._rays(dth), ptrs(kappa), ptrs(gamma1),
                                      ptrs(gamma2), ptrs(omega)), self.ctx)
 
-    def run(self, s, p, dth, pr, first_step, n_steps):
-        """Steps [first_step, first_step + n_steps): pm_step + ray_step each (dth, pr may be
-        None for matter only); same results as calling them one by one, one pass less."""
-        r = self._rays(dth, pr) if dth is not None else None
-        _check(lib().hrt_run(self.ctx, self._matter(s, p), r, first_step, n_steps), self.ctx)
+    @property
+    def n_maps(self):
+        """Map sets per realisation of hrt_run: one per source plane, plus the weighted sum."""
+        return self.cfg.n_src + (1 if bool(self.cfg.src_w) else 0)
 
-    def graph_capture(self, s, p, dth, pr, first_step, n_steps):
+    def _maps(self, maps):
+        """maps: per map set (sources in config order, then the weighted sum) a dict with any
+        of kappa, gamma1, gamma2, omega -> device tensor (a list of such lists for batches)."""
+        if maps is None:
+            return None
+        per = [maps] if self.R == 1 and (len(maps) == 0 or isinstance(maps[0], dict)) else list(maps)
+        if len(per) != self.R:
+            raise ValueError(f"expected maps for {self.R} realisations")
+        arr = (HrtMaps * (self.R * self.n_maps))()
+        for k, sets in enumerate(per):
+            if len(sets) != self.n_maps:
+                raise ValueError(f"expected {self.n_maps} map sets per realisation, got {len(sets)}")
+            for i, d in enumerate(sets):
+                for name in ("kappa", "gamma1", "gamma2", "omega"):
+                    t = d.get(name)
+                    if t is not None:
+                        setattr(arr[k * self.n_maps + i], name, _ptr(t, self.dtype, self.n_rays[k], name))
+        return arr
+
+    def run(self, s, p, dth, pr, first_step, n_steps, maps=None):
+        """Steps [first_step, first_step + n_steps): pm_step + ray_step each (dth, pr may be
+        None for matter only); same results as calling them one by one, one pass less.
+        maps: observables written at the source planes the steps reach (see _maps)."""
+        r = self._rays(dth, pr) if dth is not None else None
+        _check(lib().hrt_run(self.ctx, self._matter(s, p), r, first_step, n_steps, self._maps(maps)),
+               self.ctx)
+
+    def graph_capture(self, s, p, dth, pr, first_step, n_steps, maps=None):
         """Capture steps [first_step, first_step + n_steps) into one HIP graph."""
-        self._graph_args = (self._matter(s, p), self._rays(dth, pr) if dth is not None else None)
+        self._graph_args = (self._matter(s, p), self._rays(dth, pr) if dth is not None else None,
+                            self._maps(maps))
         _check(lib().hrt_graph_capture(self.ctx, self._graph_args[0], self._graph_args[1],
-                                       first_step, n_steps), self.ctx)
+                                       first_step, n_steps, self._graph_args[2]), self.ctx)
 
     def graph_launch(self):
         _check(lib().hrt_graph_launch(self.ctx), self.ctx)
@@ -322,19 +372,29 @@ class Simulation:
         _check(lib().hrt_ic_2lpt(self.ctx, k, c_void_p(nz), ctypes.byref(ic), ctypes.byref(m)),
                self.ctx)
 
-    def step_vjp(self, s, dth, s_bar, p_bar, dth_bar, p_ray_bar, step):
-        """Reverse of step `step` (single realisation, created with adjoint=True).
+    def step_vjp(self, s, dth, s_bar, p_bar, dth_bar, p_ray_bar, step, part="step"):
+        """Reverse of step `step` (context created with adjoint=True; per-realisation lists
+        for batches).
 
         s, dth: state before the step; the cotangents (lists of device tensors) hold those
         of the state after the step and are overwritten with those before it. dth and the
-        ray cotangents are None for matter only; p_bar may be None for a static lens."""
+        ray cotangents are None for matter only; p_bar may be None for a static lens (and
+        for part="rays"). part: "step" (hrt_step_vjp), "matter" (pm_step_vjp) or "rays"
+        (ray_step_vjp)."""
         m = self._matter(s)
         mc = self._matter(s_bar, p_bar)
         r = rc = None
         if dth is not None:
             r = self._rays(dth)
             rc = self._rays(dth_bar, p_ray_bar)
-        _check(lib().hrt_step_vjp(self.ctx, m, r, mc, rc, step), self.ctx)
+        if part == "step":
+            _check(lib().hrt_step_vjp(self.ctx, m, r, mc, rc, step), self.ctx)
+        elif part == "matter":
+            _check(lib().pm_step_vjp(self.ctx, m, mc, step), self.ctx)
+        elif part == "rays":
+            _check(lib().ray_step_vjp(self.ctx, m, r, mc, rc, step), self.ctx)
+        else:
+            raise ValueError(f"unknown part {part!r}")
 
     def convergence_vjp(self, kappa_bar, dth_bar):
         """dth_bar += (d kappa / d dth)^T kappa_bar (per realisation lists for batches)."""

@@ -27,6 +27,19 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def per_ray_errors(got, ref, what="deflection"):
+    """Per-ray relative error |got_i - ref_i| / |ref_i| of (M, 2) vectors: (rel-L2 over all
+    rays, 99.9th percentile, maximum), printed. Rays whose reference is below 1e-3 of the
+    rms (none in these inputs) are measured against that floor instead."""
+    got = np.asarray(got, float); ref = np.asarray(ref, float)
+    mag = np.linalg.norm(ref, axis=1)
+    floor = 1e-3 * np.sqrt(np.mean(mag ** 2))
+    e = np.linalg.norm(got - ref, axis=1) / np.maximum(mag, floor)
+    out = (rel_l2(got, ref), float(np.percentile(e, 99.9)), float(e.max()))
+    say(f"  {what}: rel-L2 {out[0]:.2e}, per-ray p99.9 {out[1]:.2e}, max {out[2]:.2e}")
+    return out
+
+
 class Case:
     """A cosmological instance: lattice matter state, rays, schedule, both-side tensors."""
 

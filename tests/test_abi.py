@@ -86,7 +86,8 @@ def test_large_config_table_sizes():
 
 
 @pytest.mark.parametrize("field,value", [("mesh_n", 48), ("mesh_n", 8), ("ptcl_n", 3), ("n_steps", 0),
-                                         ("dtype", 7), ("ray_nx", 2), ("reserved", 1), ("flags", 8)])
+                                         ("dtype", 7), ("ray_nx", 2), ("n_src", -1), ("n_src", 1),
+                                         ("flags", 8)])
 def test_invalid_configs_are_rejected(field, value):
     cfg, keep = _cosmo_cfg(np.linspace(1.0, 0.5, 5))
     setattr(cfg, field, value)
@@ -136,3 +137,33 @@ def test_noalloc_init_rejects_configurations_beyond_the_static_workspace():
     assert rc == hrt.HRT_ENOMEM and not ctx.value
     msg = hrt.lib().hrt_last_error(None).decode()
     assert str(need) in msg and str(hrt.HRT_NOALLOC_MAX_BYTES) in msg
+
+
+def _src_cfg(src, src_w=None, a=None, static=False):
+    a = np.linspace(1.0, 0.5, 9) if a is None else a
+    if static:
+        return hrt.make_config(mesh_n=32, box=100.0, ptcl_n=1, n_steps=8, sched=a, ray_nx=8, ray_ny=8,
+                               fov_x=0.02, fov_y=0.02, observer=(50.0, 50.0, 0.0), dtype="f64",
+                               static=True, static_mass=1e15, src=src, src_w=src_w)
+    return hrt.make_config(mesh_n=32, box=100.0, ptcl_n=16, n_steps=len(a) - 1, sched=a, ray_nx=8,
+                           ray_ny=8, fov_x=0.02, fov_y=0.02, observer=(50.0, 50.0, 0.0), omega_m=0.3,
+                           src=src, src_w=src_w)
+
+
+def test_source_planes_must_be_step_boundaries():
+    # a = 1 - k/16: z = 1/a - 1 on boundaries 4 (a = 0.75) and 8 (a = 0.5) are accepted
+    ok, keep = _src_cfg([1 / 0.75 - 1, 1.0], src_w=[0.25, 0.75])
+    assert hrt.hrt_workspace_bytes(ok) > 0
+    for bad in ([0.5], [1.0, 1.0], [1.0 + 1e-6], [3.0]):        # off boundaries, twice, beyond
+        cfg, keep = _src_cfg(bad)
+        with pytest.raises(hrt.HRTError, match="status -1"):
+            hrt.hrt_workspace_bytes(cfg)
+    static, keep = _src_cfg([50.0, 100.0], a=np.linspace(0.0, 100.0, 9), static=True)
+    assert hrt.hrt_workspace_bytes(static) > 0
+    static, keep = _src_cfg([60.0], a=np.linspace(0.0, 100.0, 9), static=True)
+    with pytest.raises(hrt.HRTError, match="not a step boundary"):
+        hrt.hrt_workspace_bytes(static)
+    norays, keep = hrt.make_config(mesh_n=32, box=100.0, ptcl_n=16, n_steps=8, sched=np.linspace(1.0, 0.5, 9),
+                                   src=[1.0])
+    with pytest.raises(hrt.HRTError, match="need rays"):
+        hrt.hrt_workspace_bytes(norays)

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import Case, rel_l2, require_gpu, say
+from gpu_helpers import Case, per_ray_errors, rel_l2, require_gpu, say
 from oracle import integrator, mesh, observables
 
 pytestmark = pytest.mark.gpu
@@ -127,7 +127,12 @@ def test_ray_step_and_convergence_parity(dtype):
         d_g, p_g = Case.host(dth), Case.host(pr)
         tol = 1e-10 if dtype == "f64" else 1e-4
         assert rel_l2(p_g - c.pr, p_o - c.pr) < tol, step
-        assert rel_l2(d_g, d_o) < tol
+        # every ray, not only the norm: the 99.9th percentile within the bound and the worst
+        # ray within 10x (a defect on a few rays, one plane or the periodic seam shows here)
+        l2, p999, worst = per_ray_errors(d_g, d_o, f"deflection step {step}")
+        assert l2 < tol and p999 < tol and worst < 10 * tol
+        _, p999k, worstk = per_ray_errors(p_g - c.pr, p_o - c.pr, f"kick step {step}")
+        assert p999k < 10 * tol and worstk < 100 * tol
         c.s, c.p = Case.host(s), Case.host(p)
         c.dth, c.pr = d_g, p_g
     kap = torch.empty(c.mx * c.my, dtype=sim.dtype, device="cuda")
@@ -137,9 +142,11 @@ def test_ray_step_and_convergence_parity(dtype):
     mu = cfg["fov"] / c.mx
     ko, g1o, g2o, omo = observables.observables(observables.distortion(c.dth, c.mx, c.my, mu, mu))
     tol = 1e-9 if dtype == "f64" else 1e-3
-    for got, ref in ((kap, ko), (g1, g1o), (g2, g2o)):
+    for name, got, ref in (("kappa", kap, ko), ("gamma1", g1, g1o), ("gamma2", g2, g2o), ("omega", om, omo)):
         got = got.double().cpu().numpy().reshape(c.my, c.mx)
-        assert np.sqrt(np.mean((got - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)) < tol
+        err = np.sqrt(np.mean((got - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+        say(f"  {name}: rel-rms {err:.2e}")
+        assert err < tol, name
 
 
 def test_coevolution_end_to_end_and_bit_identical_rerun():
