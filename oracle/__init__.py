@@ -16,6 +16,7 @@ tracing algorithm for gravitational lensing", arXiv:2405.12913):
 * ``observables``  distortion matrix and kappa/gamma/omega (Eqs. A, obs_first_set, obs_second_set)
 * ``ic``           Gaussian initial conditions and 2LPT (Sec. 6.2; not part of the paper's method)
 * ``pointmass``    point-lens deflection targets (Eqs. pointmass_analytic, pointmass_periodic)
+* ``replicas``     per-replica transforms of the replicated light cone (Sec. 6.2)
 
 Arrays are float64. Meshes are indexed ``[z, y, x]`` with the line of sight
 along +z; particle and ray coordinates are ``(x, y, z)`` / ``(x, y)``.

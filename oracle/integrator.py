@@ -16,6 +16,7 @@ ray i = iy * Mx + ix at pixel centre theta0 = ((ix + 1/2) - Mx/2, (iy + 1/2) - M
 import numpy as np
 
 from . import mesh
+from . import replicas as _replicas
 
 
 def lattice(n_p, box):
@@ -55,24 +56,61 @@ def matter_step(s, p, q, grads, K, D, box):
     return s, p
 
 
-def ray_kick(dth, theta0, gx, gy, planes, observer_xy, box):
-    """Sum over the shell's planes of w_j * bilinear(G_perp on plane j)(X_obs + r_j theta)."""
+def _plane(gx, gy, gz, j, replicas):
+    """(G_u, G_v) of line-of-sight plane j: mesh plane j mod n, or in the frame of its replica."""
     n = gx.shape[0]
+    if replicas is None:
+        return gx[j % n], gy[j % n]
+    return _replicas.lens_plane((gx, gy, gz), j, n, replicas)
+
+
+def ray_kick(dth, theta0, gx, gy, planes, observer_xy, box, gz=None, replicas=None):
+    """Sum over the shell's planes of w_j * bilinear(G_perp on plane j)(X_obs + r_j theta).
+
+    replicas: per-replica transform table (``oracle.replicas``); needs gz."""
     theta = theta0 + dth
     dp = np.zeros_like(dth)
     for j, chi_j, w in planes:
-        m = j % n
+        pu, pv = _plane(gx, gy, gz, j, replicas)
         xy = np.asarray(observer_xy, float)[None, :] + chi_j * theta
-        dp[:, 0] += w * mesh.bilinear_readout(gx[m], xy, box)
-        dp[:, 1] += w * mesh.bilinear_readout(gy[m], xy, box)
+        dp[:, 0] += w * mesh.bilinear_readout(pu, xy, box)
+        dp[:, 1] += w * mesh.bilinear_readout(pv, xy, box)
     return dp
 
 
-def ray_step(dth, p, theta0, gx, gy, planes, d, observer_xy, box):
+def ray_step(dth, p, theta0, gx, gy, planes, d, observer_xy, box, gz=None, replicas=None):
     """Kick over the lens shell at the current angle, then drift dth += d p."""
-    p = p + ray_kick(dth, theta0, gx, gy, planes, observer_xy, box)
+    p = p + ray_kick(dth, theta0, gx, gy, planes, observer_xy, box, gz, replicas)
     dth = dth + d * p
     return dth, p
+
+
+def kick_jacobian(dth, theta0, gx, gy, planes, observer_xy, box, gz=None, replicas=None):
+    """J = d kick / d theta (M, 2, 2) at the current angle: the plane sum of w_j chi_j times
+    the gradient of the bilinear interpolant of (G_u, G_v) on plane j (its exact derivative
+    inside a cell: differences of the corner values)."""
+    theta = theta0 + dth
+    J = np.zeros((len(dth), 2, 2))
+    for j, chi_j, w in planes:
+        pu, pv = _plane(gx, gy, gz, j, replicas)
+        xy = np.asarray(observer_xy, float)[None, :] + chi_j * theta
+        for a, pl in enumerate((pu, pv)):
+            J[:, a, :] += w * chi_j * mesh.bilinear_gradient(pl, xy, box)
+    return J
+
+
+def ray_step_jacobian(dth, p, dA, B, theta0, gx, gy, planes, d, observer_xy, box, gz=None, replicas=None):
+    """One ray step with the forward-mode distortion recursion (Sec. 4, Eqs. obsv_recurse1-3
+    with the fused leapfrog's two half-kicks merged): with A = I + dA = d theta / d theta0 and
+    B = d p / d theta0 (A_0 = I, B_0 = 0),
+        B += J A,   A += d B      (J = d kick / d theta at the step's starting angle),
+    alongside p += kick, dth += d p. dA, B are (M, 2, 2)."""
+    J = kick_jacobian(dth, theta0, gx, gy, planes, observer_xy, box, gz, replicas)
+    p = p + ray_kick(dth, theta0, gx, gy, planes, observer_xy, box, gz, replicas)
+    B = B + np.einsum("mab,mbc->mac", J, np.eye(2)[None] + dA)
+    dA = dA + d * B
+    dth = dth + d * p
+    return dth, p, dA, B
 
 
 def ray_step_analytic(dth, p, theta0, grad_perp, planes, d, observer_xy):
@@ -91,18 +129,31 @@ def ray_step_analytic(dth, p, theta0, grad_perp, planes, d, observer_xy):
 
 
 def coevolve(s, p, q, dth, pr, theta0, tab, n, box, observer, steps=None,
-             matter=True, on_step=None):
+             matter=True, on_step=None, replicas=None, jac=None):
     """Run co-evolution steps (default 0..N-1) over the tables ``tab``.
 
-    ``on_step(n, s, p, dth, pr)`` is called after each step (e.g. to record kappa)."""
+    ``on_step(n, s, p, dth, pr)`` is called after each step (e.g. to record kappa).
+    replicas: per-replica transforms of the line-of-sight planes (``oracle.replicas``).
+    jac: (dA, B) to carry the distortion recursion (``ray_step_jacobian``); then
+    ``on_step(n, s, p, dth, pr, dA, B)`` and the return value gains dA, B."""
     steps = range(tab.n_steps) if steps is None else steps
     for k in steps:
         grads, _ = pm_force(q + s, n, box)
         if matter:
             s, p = matter_step(s, p, q, grads, tab.K[k], tab.D[k], box)
-        if dth is not None:
+        if dth is not None and jac is not None:
+            dth, pr, dA, B = ray_step_jacobian(dth, pr, jac[0], jac[1], theta0, grads[0], grads[1],
+                                               tab.planes[k], tab.d[k], observer[:2], box, grads[2],
+                                               replicas)
+            jac = (dA, B)
+        elif dth is not None:
             dth, pr = ray_step(dth, pr, theta0, grads[0], grads[1], tab.planes[k], tab.d[k],
-                               observer[:2], box)
+                               observer[:2], box, grads[2], replicas)
         if on_step is not None:
-            on_step(k, s, p, dth, pr)
+            if jac is not None:
+                on_step(k, s, p, dth, pr, *jac)
+            else:
+                on_step(k, s, p, dth, pr)
+    if jac is not None:
+        return s, p, dth, pr, jac[0], jac[1]
     return s, p, dth, pr

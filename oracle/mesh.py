@@ -74,6 +74,25 @@ def bilinear_readout(plane, xy, box):
     return out
 
 
+def bilinear_gradient(plane, xy, box):
+    """(d/dX, d/dY) of the bilinear interpolant of a periodic plane [y, x] at points (P, 2):
+    inside cell (i, j) with fractions (fx, fy),
+        d/dX = [(1 - fy) (f[j, i+1] - f[j, i]) + fy (f[j+1, i+1] - f[j+1, i])] / cell,
+    and likewise for d/dY (piecewise constant across cells). Returns (P, 2)."""
+    n = plane.shape[0]
+    u = np.asarray(xy, float) * (n / box)
+    i0 = np.floor(u).astype(np.int64)
+    f = u - i0
+    ix0, iy0 = i0[:, 0] % n, i0[:, 1] % n
+    ix1, iy1 = (ix0 + 1) % n, (iy0 + 1) % n
+    f00, f01 = plane[iy0, ix0], plane[iy0, ix1]       # f[y, x]
+    f10, f11 = plane[iy1, ix0], plane[iy1, ix1]
+    inv = n / box
+    gx = ((1.0 - f[:, 1]) * (f01 - f00) + f[:, 1] * (f11 - f10)) * inv
+    gy = ((1.0 - f[:, 0]) * (f10 - f00) + f[:, 0] * (f11 - f01)) * inv
+    return np.stack([gx, gy], axis=1)
+
+
 def wavenumbers(n, box):
     """Angular wavenumbers (kz, ky, kx) broadcastable to the rfft half spectrum."""
     k = 2.0 * np.pi * np.fft.fftfreq(n, d=box / n)

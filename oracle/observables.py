@@ -55,3 +55,16 @@ def observables(A):
 def convergence(dth, mx, my, mu_x, mu_y):
     """kappa (my, mx) = -(1/2) (d dth_x/d theta0_x + d dth_y/d theta0_y)."""
     return observables(distortion(dth, mx, my, mu_x, mu_y))[0]
+
+
+def from_jacobian(dA):
+    """(kappa, gamma1, gamma2, omega) from the forward-mode distortion A = I + dA (..., 2, 2)
+    (Eqs. obs_first_set, obs_second_set), with 1 - C1 written as -(dA11 + dA22)/2 so the
+    identity part does not cancel."""
+    dA = np.asarray(dA, float)
+    kappa = -0.5 * (dA[..., 0, 0] + dA[..., 1, 1])
+    c2 = 0.5 * (dA[..., 0, 1] - dA[..., 1, 0])
+    c3 = 0.5 * (dA[..., 1, 1] - dA[..., 0, 0])
+    c4 = 0.5 * (dA[..., 0, 1] + dA[..., 1, 0])
+    omega = c2 / (1.0 - kappa)
+    return kappa, c3 + c4 * omega, -c4 + c3 * omega, omega

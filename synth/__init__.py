@@ -142,3 +142,17 @@ def random_rays(seed, n_rays, dth_rms, p_rms):
     """Ray state (dth, p), each (M, 2), with given rms values."""
     rng = np.random.default_rng(seed + 104729)
     return rng.normal(scale=dth_rms, size=(n_rays, 2)), rng.normal(scale=p_rms, size=(n_rays, 2))
+
+
+def replica_table(seed, n, count):
+    """Seeded per-replica transforms of the light cone: `count` rows of
+    (perm0, perm1, perm2, sign0, sign1, sign2, shift0, shift1, shift2), a random axis
+    permutation, random orientations and a random integer node shift in [0, n) per axis."""
+    rng = np.random.default_rng(seed + 31337)
+    rows = []
+    for _ in range(count):
+        perm = rng.permutation(3)
+        sign = rng.choice([-1, 1], size=3)
+        shift = rng.integers(0, n, size=3)
+        rows.append(tuple(int(v) for v in np.concatenate([perm, sign, shift])))
+    return rows
