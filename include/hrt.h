@@ -61,8 +61,13 @@ enum { HRT_F32 = 0, HRT_F64 = 1 };
 enum {
     HRT_STATIC = 1,         /* static point-lens run: a = 1, sched holds chi_n, the mesh
                                source is unit-weight particles of mass static_mass each */
-    HRT_ADJOINT = 2         /* reserve the reverse-mode scratch (hrt_step_vjp) in the
+    HRT_ADJOINT = 2,        /* reserve the reverse-mode scratch (hrt_step_vjp) in the
                                workspace: 16 n^3 + 256 + 4 np^3 sizeof(dtype) bytes more */
+    HRT_JACOBIAN = 4        /* the rays carry the forward-mode distortion recursion of
+                               Sec. 4 (Eqs. A, B, obsv_recurse1-3; Alg. 1 iterate_A,
+                               iterate_B): hrt_rays.jac required by ray_step; source-plane
+                               maps are formed from A instead of finite differences.
+                               Not combinable with HRT_ADJOINT (HRT_EUNSUPPORTED)       */
 };
 
 typedef struct {
@@ -91,9 +96,21 @@ typedef struct {
     const double *src_w;    /* NULL, or n_src weights n_g(chi_i) of the source distribution
                                (Eq. obs_accum): the maps then also accumulate
                                sum_i src_w[i] * map_i into one more map set              */
+    const int32_t *replicas;/* NULL (plain periodic replication), or n_replicas rows of 9
+                               values: the light cone is the box replicated along the line
+                               of sight (Sec. 6.2), replica k holding the planes j with
+                               k n <= j < (k+1) n and using row k mod n_replicas =
+                               (perm0, perm1, perm2, sign0, sign1, sign2, shift0, shift1,
+                               shift2): replica axis a (x, y, z = line of sight) runs along
+                               box axis perm[a] (a permutation of 0, 1, 2) with orientation
+                               sign[a] = +-1, and replica node u sits on box node
+                               x[perm[a]] = sign[a] u[a] + shift[perm[a]] (mod n), 0 <=
+                               shift < n. Copied at init. Not combinable with HRT_ADJOINT
+                               unless every row is the identity (HRT_EUNSUPPORTED)       */
+    int32_t n_replicas;     /* rows in replicas (0 when NULL), <= HRT_MAX_REPLICAS       */
 } hrt_config;
 
-enum { HRT_MAX_SOURCES = 256 };
+enum { HRT_MAX_SOURCES = 256, HRT_MAX_REPLICAS = 4096 };
 
 /* Output maps of one source plane (or of the weighted sum over the source planes): device
  * arrays of Mx*My values of the config's dtype, caller-owned; any may be NULL (not
@@ -101,7 +118,12 @@ enum { HRT_MAX_SOURCES = 256 };
 typedef struct { void *kappa, *gamma1, *gamma2, *omega; } hrt_maps;
 
 typedef struct { void *s[3]; void *p[3]; } hrt_matter;   /* device SoA, np^3 each (x, y, z) */
-typedef struct { void *dth[2]; void *p[2]; } hrt_rays;   /* device SoA, Mx*My each (x, y)   */
+/* device SoA, Mx*My values each: deflection dth = theta - theta0 (x, y), canonical momentum
+ * p (x, y), and with HRT_JACOBIAN the distortion recursion jac = (A - I)_xx, (A - I)_xy,
+ * (A - I)_yx, (A - I)_yy, B_xx, B_xy, B_yx, B_yy with A = d theta / d theta0, B = d p /
+ * d theta0 (A_ab: component a, derivative along b); all zero at the observer (A_0 = I,
+ * B_0 = 0). jac entries are ignored (may be NULL) without HRT_JACOBIAN. */
+typedef struct { void *dth[2]; void *p[2]; void *jac[8]; } hrt_rays;
 
 typedef struct hrt_ctx hrt_ctx;
 
@@ -148,10 +170,14 @@ int pm_force(hrt_ctx *ctx, const hrt_matter *m, int step);
  * HRT_STATIC (returns HRT_ESTATE). */
 int pm_step(hrt_ctx *ctx, const hrt_matter *m, int step);
 
-/* Kick the rays over lens shell `step` with the G left by the last pm_force/pm_step,
- * evaluated at the current angles, then drift (step N: closing half-kick, no drift).
- * Each shell plane j contributes w_j * bilinear(G_x, G_y on mesh plane j mod n) at
- * X_obs + chi_j * theta. */
+/* Kick the rays over lens shell `step` with the potential left by the last pm_force /
+ * pm_step / hrt_run of that step, evaluated at the current angles, then drift (step N:
+ * closing half-kick, no drift). The step's lens planes are first formed from phi: plane j
+ * holds the transverse gradient (G_u, G_v) in the frame of its replica (fourth-order
+ * differences, mesh plane j mod n without replica transforms); each contributes
+ * w_j * bilinear(G_u, G_v)(X_obs + chi_j * theta). With HRT_JACOBIAN also
+ * B += J (I + dA), dA += d_step B with J = d kick / d theta (the plane sum of w_j chi_j
+ * times the gradient of the bilinear interpolant). */
 int ray_step(hrt_ctx *ctx, const hrt_rays *r, int step);
 
 /* Finite-difference distortion matrix of the deflections over the pixel grid
@@ -161,6 +187,11 @@ int ray_step(hrt_ctx *ctx, const hrt_rays *r, int step);
  * momenta in r may be NULL too). */
 int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *const *gamma1,
                     void *const *gamma2, void *const *omega);
+
+/* The same maps from the forward-mode distortion A = I + dA of a context created with
+ * HRT_JACOBIAN (Alg. 1 `observe`, Eqs. obs_first_set, obs_second_set): maps points to
+ * n_cfg entries (members may be NULL). HRT_ESTATE without HRT_JACOBIAN. */
+int ray_observe(hrt_ctx *ctx, const hrt_rays *r, const hrt_maps *maps);
 
 /* Runs steps first_step .. first_step+n_steps-1: pm_step then ray_step for every
  * realisation (r may be NULL for matter only); with HRT_STATIC one pm_force then the ray
@@ -174,9 +205,10 @@ int ray_convergence(hrt_ctx *ctx, const hrt_rays *r, void *const *kappa, void *c
  * Particle order (variant of kernel id kd_tiles): 2 keeps the particles in paint-bin order
  * in the workspace from the call's first step to its last: the first step reads the state
  * arrays, the last writes them back, and each drift counts the particles into the next
- * step's bins. The force is then formed per 8^3 tile inside the kick-drift and, for the
- * rays, on the lens planes only, so after such a call the G mesh is incomplete and
- * ray_step needs a new pm_force / pm_step first. 3 is 2 with the tile kick-drift run as a
+ * step's bins. The force is then formed per 8^3 tile inside the kick-drift (the rays read
+ * their lens planes, formed from phi, as always), so after such a call no G mesh is kept
+ * (hrt_mesh_ptr(HRT_MESH_GRAD) returns HRT_ESTATE; phi of the last step is there, and a
+ * ray_step of that step may follow). 3 is 2 with the tile kick-drift run as a
  * persistent, software-pipelined grid (each workgroup loads its next tile while it moves
  * the current one). 1 runs pm_step's Lagrangian-order
  * kernels (with the same fused counting). 0 (default) takes 2 for calls of 8 steps or more
@@ -198,7 +230,9 @@ int hrt_graph_launch(hrt_ctx *ctx);
 
 /* Device pointer to an internal mesh of realisation `realisation`, valid until
  * hrt_destroy: HRT_MESH_DELTA (n^3, after pm_force: delta), HRT_MESH_PHI (n^3: phi),
- * HRT_MESH_GRAD (n^3 interleaved quadruples (G_x, G_y, G_z, 0)). */
+ * HRT_MESH_GRAD (n^3 interleaved quadruples (G_x, G_y, G_z, 0); HRT_ESTATE after an hrt_run
+ * in paint-bin order, which forms G per tile and keeps no G mesh, until the next
+ * pm_force / pm_step). */
 enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GRAD = 2 };
 int hrt_mesh_ptr(const hrt_ctx *ctx, int realisation, int which, void **ptr);
 

@@ -16,7 +16,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
+Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count) {
     Layout L{};
     const size_t T = cfg.dtype == HRT_F64 ? 8 : 4;
     const size_t n = (size_t)cfg.mesh_n;
@@ -44,6 +44,9 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries) {
     // sorted-state run: the second record buffer (the first is `sorted`) and both momentum
     // buffers, P x (4 + 3 + 3) values; a static run moves no particles
     L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * 10 * T);
+    // lens-plane stack of one shell: (G_u, G_v) per node of each plane, replica frame
+    L.stack = cfg.ray_nx > 0 ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * 2 * T) : off;
+    L.reps = take((size_t)std::max(cfg.n_replicas, 1) * 9 * 4);      // replica transform rows
     L.total = off;
     return L;
 }
@@ -168,7 +171,7 @@ static int batch_layouts(const hrt_config *cfg, int n_cfg, std::vector<hrt::Step
         hrt::StepTables t;
         int rc = hrt::build_tables(c, t, err);
         if (rc) return rc;
-        lays.push_back(hrt::make_layout(c, (int64_t)t.plane_chi.size()));
+        lays.push_back(hrt::make_layout(c, (int64_t)t.plane_chi.size(), t.max_count));
         if (tabs) (*tabs)[r] = std::move(t);
     }
     return HRT_OK;
@@ -239,6 +242,7 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
     c->f64 = cfg[0].dtype == HRT_F64;
     c->is_static = (cfg[0].flags & HRT_STATIC) != 0;
     c->has_rays = cfg[0].ray_nx > 0;
+    c->jacobian = (cfg[0].flags & HRT_JACOBIAN) != 0;
     c->n_src = cfg[0].n_src;
     c->n_maps = cfg[0].n_src + (cfg[0].src_w ? 1 : 0);
     c->re.resize(n_cfg);
@@ -251,6 +255,7 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
         re.cfg.sched = re.sched.data();
         re.cfg.src = nullptr;            // copied into the tables (src_step, src_w)
         re.cfg.src_w = nullptr;
+        re.cfg.replicas = nullptr;       // copied into the workspace
         re.n = cfg[r].mesh_n;
         re.np = cfg[r].ptcl_n;
         re.mx = cfg[r].ray_nx;
@@ -282,11 +287,22 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
         }
         std::vector<hrt::PlaneEntry> pe(re.tab.plane_chi.size());
         for (size_t k = 0; k < pe.size(); ++k)
-            pe[k] = hrt::PlaneEntry{re.tab.plane_chi[k], re.tab.plane_w[k], re.tab.plane_mesh[k], 0};
+            pe[k] = hrt::PlaneEntry{re.tab.plane_chi[k], re.tab.plane_w[k], re.tab.plane_mesh[k],
+                                    re.tab.plane_rep[k]};
+        // replica rows (the identity when the configuration has none)
+        static const int32_t kIdentity[9] = {0, 1, 2, 1, 1, 1, 0, 0, 0};
+        std::vector<int32_t> reps(kIdentity, kIdentity + 9);
+        if (cfg[r].n_replicas > 0) reps.assign(cfg[r].replicas, cfg[r].replicas + 9 * cfg[r].n_replicas);
+        re.identity_reps = true;
+        for (size_t k = 0; k < reps.size(); ++k)
+            if (reps[k] != kIdentity[k % 9]) re.identity_reps = false;
         e = hipMemcpyAsync(re.ws + re.lay.twiddle, twbuf.data(), twbuf.size(), hipMemcpyHostToDevice,
                            c->stream);
         if (e == hipSuccess && !pe.empty())
             e = hipMemcpyAsync(re.ws + re.lay.planes, pe.data(), pe.size() * sizeof(hrt::PlaneEntry),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(re.ws + re.lay.reps, reps.data(), reps.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
@@ -334,14 +350,18 @@ static int check_matter(hrt_ctx *c, const hrt_matter *m, bool need_p) {
     return HRT_OK;
 }
 
-static int check_rays(hrt_ctx *c, const hrt_rays *r, bool need_p) {
+static int check_rays(hrt_ctx *c, const hrt_rays *r, bool need_p, bool need_jac = false) {
     if (!c->has_rays) return fail(c, HRT_ESTATE, "configuration has no rays");
     if (!r) return fail(c, HRT_EINVAL, "NULL ray state");
-    for (size_t k = 0; k < c->re.size(); ++k)
+    for (size_t k = 0; k < c->re.size(); ++k) {
         for (int d = 0; d < 2; ++d) {
             if (!r[k].dth[d]) return fail(c, HRT_EINVAL, "NULL ray deflection array");
             if (need_p && !r[k].p[d]) return fail(c, HRT_EINVAL, "NULL ray momentum array");
         }
+        if (need_jac)
+            for (int q = 0; q < 8; ++q)
+                if (!r[k].jac[q]) return fail(c, HRT_EINVAL, "NULL distortion array (HRT_JACOBIAN)");
+    }
     return HRT_OK;
 }
 
@@ -357,6 +377,7 @@ extern "C" int pm_force(hrt_ctx *c, const hrt_matter *m, int step) {
     if (int rc = check_hip(c, hrt::launch_poisson(c), "poisson")) return rc;
     if (int rc = check_hip(c, hrt::launch_gradient(c), "gradient")) return rc;
     c->force_step = step;
+    c->mesh_g_stale = false;
     return HRT_OK;
 }
 
@@ -375,14 +396,33 @@ extern "C" int ray_step(hrt_ctx *c, const hrt_rays *r, int step) {
     if (!c) return HRT_EINVAL;
     if (int g = guard(c)) return g;
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
-    if (int rc = check_rays(c, r, true)) return rc;
+    if (int rc = check_rays(c, r, true, c->jacobian)) return rc;
     if (c->force_step < 0) return fail(c, HRT_ESTATE, "no force mesh yet: call pm_force or pm_step first");
     if (!c->is_static && c->force_step != step)
         return fail(c, HRT_ESTATE, "ray_step must follow pm_step/pm_force of the same step");
     hrt::StepArgs a;
     a.r = r;
     a.step = step;
+    if (int rc = check_hip(c, hrt::launch_plane_gradient(c, step), "lens planes")) return rc;
     return check_hip(c, hrt::launch_ray_step(c, a), "ray step");
+}
+
+extern "C" int ray_observe(hrt_ctx *c, const hrt_rays *r, const hrt_maps *maps) {
+    if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
+    if (!c->jacobian) return fail(c, HRT_ESTATE, "ray_observe needs a context created with HRT_JACOBIAN");
+    if (int rc = check_rays(c, r, false, true)) return rc;
+    if (!maps) return fail(c, HRT_EINVAL, "NULL maps");
+    std::vector<hrt_maps> none(c->re.size(), hrt_maps{});
+    std::vector<double> w(c->re.size(), 0.0);
+    std::vector<int> mode(c->re.size(), 0);
+    hrt::StepArgs a;
+    a.r = r;
+    a.src_maps = maps;
+    a.acc_maps = none.data();
+    a.acc_w = w.data();
+    a.acc_mode = mode.data();
+    return check_hip(c, hrt::launch_convergence(c, a, true), "observe");
 }
 
 extern "C" int ray_convergence(hrt_ctx *c, const hrt_rays *r, void *const *kappa,
@@ -437,7 +477,7 @@ static int observe(hrt_ctx *c, const hrt_rays *r, int b, const hrt_maps *maps) {
     a.acc_maps = acc.data();
     a.acc_w = w.data();
     a.acc_mode = mode.data();
-    return check_hip(c, hrt::launch_convergence(c, a), "source-plane maps");
+    return check_hip(c, hrt::launch_convergence(c, a, c->jacobian), "source-plane maps");
 }
 
 // Steps first..first+n-1 with the matter drift of each step counting the particles into
@@ -475,11 +515,8 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         }
         if (int rc = check_hip(c, hrt::launch_paint(c, a), "paint")) return rc;
         if (int rc = check_hip(c, hrt::launch_poisson(c), "poisson")) return rc;
-        if (!sorted) {
+        if (!sorted)
             if (int rc = check_hip(c, hrt::launch_gradient(c), "gradient")) return rc;
-        } else if (r) {
-            if (int rc = check_hip(c, hrt::launch_plane_gradient(c, k), "plane gradient")) return rc;
-        }
         c->force_step = k;
         a.counts_ready = false;
         a.count_next = k + 1 < first + n;
@@ -496,7 +533,7 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         a.m = m;
         a.cur = cur ^ 1;                 // the buffer the last step moved
         if (int rc = check_hip(c, hrt::launch_state_gather(c, a), "state gather")) return rc;
-        c->force_step = -1;              // G was formed only on the lens planes
+        c->mesh_g_stale = true;          // G was formed per tile in LDS, not on the mesh
     }
     return HRT_OK;
 }
@@ -543,6 +580,7 @@ extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays
     // nothing runs while capturing: the force mesh the sequence leaves behind becomes
     // current only when the graph is launched
     const int force_before = c->force_step;
+    const bool stale_before = c->mesh_g_stale;
     int rc = check_hip(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
     if (rc == HRT_OK) rc = (c->is_static && !r) ? pm_force(c, m, first_step)
                                                 : run_steps(c, m, r, first_step, n_steps, maps);
@@ -550,7 +588,9 @@ extern "C" int hrt_graph_capture(hrt_ctx *c, const hrt_matter *m, const hrt_rays
     hipError_t e = hipStreamEndCapture(cap, &graph);
     c->stream = user;
     c->graph_force_step = c->force_step;
+    c->graph_g_stale = c->mesh_g_stale;
     c->force_step = force_before;
+    c->mesh_g_stale = stale_before;
     if (rc == HRT_OK) rc = check_hip(c, e, "end capture");
     if (rc == HRT_OK) rc = check_hip(c, hipGraphInstantiate(&c->graph, graph, nullptr, nullptr, 0),
                                      "graph instantiate");
@@ -565,6 +605,7 @@ extern "C" int hrt_graph_launch(hrt_ctx *c) {
     if (!c->graph) return fail(c, HRT_ESTATE, "no captured graph");
     if (int rc = check_hip(c, hipGraphLaunch(c->graph, c->stream), "graph launch")) return rc;
     c->force_step = c->graph_force_step;
+    c->mesh_g_stale = c->graph_g_stale;
     return HRT_OK;
 }
 
@@ -702,7 +743,10 @@ extern "C" int hrt_mesh_ptr(const hrt_ctx *c, int realisation, int which, void *
     switch (which) {
         case HRT_MESH_DELTA: *ptr = re.ws + re.lay.mesh_r; return HRT_OK;
         case HRT_MESH_PHI: *ptr = re.ws + re.lay.mesh_r + n3 * T; return HRT_OK;
-        case HRT_MESH_GRAD: *ptr = re.ws + re.lay.grad; return HRT_OK;
+        case HRT_MESH_GRAD:
+            if (c->mesh_g_stale) return HRT_ESTATE;   // paint-bin-order hrt_run: G only in LDS
+            *ptr = re.ws + re.lay.grad;
+            return HRT_OK;
         default: return HRT_EINVAL;
     }
 }

@@ -491,16 +491,21 @@ __global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(GradBatch<T> b) 
     a.g[idx] = out;
 }
 
-// G on the lens planes of one step only (the sorted-state run forms G tile by tile inside
-// the kick-drift and keeps no G mesh): entry e of the step's plane list, one lane per node
-// of mesh plane z = planes[e].mesh, with the same differences as fd4_gradient_kernel.
-// Entries that share a mesh plane write the same values.
+// The lens planes of one step (Sec. 5.2: the mesh points in the shell): entry e of the
+// step's plane list holds, for every node (u, v) of line-of-sight plane j in the frame of
+// its replica, the transverse gradient (G_u, G_v) of phi by the fourth-order differences of
+// fd4_gradient_kernel. A replica row maps replica node (u, v, w = plane index in the
+// replica) to box node x[perm[a]] = sign[a] u[a] + shift[perm[a]] (mod n), and the
+// difference along replica axis a reads phi at x + sign[a] * k * e_perm[a], k = -2..2, so
+// a mirrored axis gives the exact negative of the box difference. One lane per node, u
+// fastest; the stack is [e][v][u] pairs of the dtype, read by the ray kernels.
 template <typename T>
 struct PlaneGradR {
     const T *phi;
-    v4<T> *g;
+    c2<T> *stack;
     const PlaneEntry *planes;
-    int n, log2n, begin, count;
+    const int32_t *reps;       // replica rows, 9 values each
+    int n, log2n, begin, count, identity;
     T inv12cell;
 };
 template <typename T>
@@ -517,18 +522,30 @@ __global__ __launch_bounds__(kThreads) void plane_gradient_kernel(PlaneGradBatch
     const int64_t idx = (int64_t)(blockIdx.x - b.map.start[r]) * kThreads + threadIdx.x;
     const int e = (int)(idx >> (2 * log2n));
     if (e >= a.count) return;
-    const int z = a.planes[a.begin + e].mesh;
-    const int x = (int)(idx & m), y = (int)((idx >> log2n) & m);
+    const PlaneEntry pe = a.planes[a.begin + e];
+    const int u = (int)(idx & m), v = (int)((idx >> log2n) & m), w = pe.mesh;
     const T *__restrict__ phi = a.phi;
     auto at = [&](int xx, int yy, int zz) {
         return phi[(((size_t)(zz & m) * n + (yy & m)) * n) + (xx & m)];
     };
-    v4<T> out;
-    out.x = fd4<T>(at(x - 2, y, z), at(x - 1, y, z), at(x + 1, y, z), at(x + 2, y, z), a.inv12cell);
-    out.y = fd4<T>(at(x, y - 2, z), at(x, y - 1, z), at(x, y + 1, z), at(x, y + 2, z), a.inv12cell);
-    out.z = fd4<T>(at(x, y, z - 2), at(x, y, z - 1), at(x, y, z + 1), at(x, y, z + 2), a.inv12cell);
-    out.w = T(0);
-    a.g[((size_t)z * n + y) * n + x] = out;
+    c2<T> out;
+    if (a.identity) {
+        out.x = fd4<T>(at(u - 2, v, w), at(u - 1, v, w), at(u + 1, v, w), at(u + 2, v, w), a.inv12cell);
+        out.y = fd4<T>(at(u, v - 2, w), at(u, v - 1, w), at(u, v + 1, w), at(u, v + 2, w), a.inv12cell);
+    } else {
+        const int32_t *row = a.reps + 9 * pe.rep;
+        const int uu[3] = {u, v, w};
+        int xb[3];
+        for (int ax = 0; ax < 3; ++ax) xb[row[ax]] = row[3 + ax] * uu[ax] + row[6 + row[ax]];
+        auto along = [&](int ax, int k) {          // phi at replica node u + k e_ax
+            int c[3] = {xb[0], xb[1], xb[2]};
+            c[row[ax]] += row[3 + ax] * k;
+            return at(c[0], c[1], c[2]);
+        };
+        out.x = fd4<T>(along(0, -2), along(0, -1), along(0, 1), along(0, 2), a.inv12cell);
+        out.y = fd4<T>(along(1, -2), along(1, -1), along(1, 1), along(1, 2), a.inv12cell);
+    }
+    a.stack[idx] = out;
 }
 
 template <typename T, int N>
@@ -651,8 +668,10 @@ hipError_t plane_gradient_impl(hrt_ctx *c, int step) {
             const size_t n3 = (size_t)re.n * re.n * re.n;
             PlaneGradR<T> &a = b.r[k];
             a.phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + n3;
-            a.g = reinterpret_cast<v4<T> *>(re.ws + re.lay.grad);
+            a.stack = reinterpret_cast<c2<T> *>(re.ws + re.lay.stack);
             a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
+            a.reps = reinterpret_cast<const int32_t *>(re.ws + re.lay.reps);
+            a.identity = re.identity_reps ? 1 : 0;
             a.n = re.n;
             a.log2n = ilog2(re.n);
             a.begin = re.tab.plane_begin[step];

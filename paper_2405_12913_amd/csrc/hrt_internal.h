@@ -17,6 +17,8 @@ struct StepTables {
     std::vector<double> a, chi, K, D, d;     // N+1 each
     std::vector<int32_t> plane_begin, plane_count;   // N+1 each
     std::vector<int32_t> plane_mesh;         // mesh plane index (j mod n) per entry
+    std::vector<int32_t> plane_rep;          // replica transform row per entry
+    int32_t max_count = 0;                   // most planes in one shell
     std::vector<double> plane_chi, plane_w;  // chi_j and weight w_j per entry
     std::vector<int32_t> src_step;           // step boundary of each source plane
     std::vector<double> src_w;               // n_g weights (Eq. obs_accum), if has_src_w
@@ -42,16 +44,18 @@ int ic_params(const hrt_config &cfg, const hrt_ic_params &in, IcParams &out, std
 struct PlaneEntry {
     double chi;        // comoving distance of the plane [Mpc/h]
     double w;          // kick weight
-    int32_t mesh;      // mesh plane index
-    int32_t pad;
+    int32_t mesh;      // mesh plane index (line-of-sight node index inside its replica)
+    int32_t rep;       // replica transform row (0 without a replica table)
 };
 
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
-    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, total;
+    size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, stack, reps,
+        total;
     int64_t nbins;
 };
-Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries);
+// max_count: most lens planes in one shell (the lens-plane stack holds one shell's planes)
+Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count);
 
 // Kernel ids for the optional per-kernel HIP-event timing (hrt_profile_*).
 enum KernelId {
@@ -83,6 +87,7 @@ struct Real {
     Layout lay;
     char *ws = nullptr;          // this realisation's part of the workspace
     int fixed_bits = 0;          // paint fixed-point fraction bits
+    bool identity_reps = true;   // every replica uses the identity transform
 };
 
 // Per-call state handed to the launchers: one entry per realisation.
@@ -127,13 +132,15 @@ struct hrt_ctx {
     std::vector<hrt::Real> re;   // realisations (a plain run is a batch of one)
     hipStream_t stream = nullptr;
     int N = 0;                   // shared number of steps
-    bool f64 = false, is_static = false, has_rays = false;
+    bool f64 = false, is_static = false, has_rays = false, jacobian = false;
     int n_src = 0, n_maps = 0;   // source planes; map sets per realisation (+1 with weights)
-    int force_step = -1;         // boundary of the G currently in the workspaces
+    int force_step = -1;         // boundary of the phi (and G) currently in the workspaces
+    bool mesh_g_stale = false;   // after a paint-bin-order hrt_run the G mesh is not current
     std::string err;
     // captured step sequence (hrt_graph_capture / hrt_graph_launch)
     hipGraphExec_t graph = nullptr;
     int graph_force_step = -1;   // force_step after the captured sequence has run
+    bool graph_g_stale = false;  // mesh_g_stale after it
     // per-kernel timing (off unless hrt_profile_enable)
     bool prof = false;
     std::vector<hrt::ProfRecord> prof_pending;
@@ -170,11 +177,11 @@ void prof_end(hrt_ctx *c, int id);     // record the stop event of kernel `id`
 hipError_t launch_paint(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_poisson(hrt_ctx *c, int only = -1);   // every realisation, or only `only`
 hipError_t launch_gradient(hrt_ctx *c);
-hipError_t launch_plane_gradient(hrt_ctx *c, int step);      // G on the step's lens planes
+hipError_t launch_plane_gradient(hrt_ctx *c, int step);      // the step's lens-plane stack
 hipError_t launch_state_gather(hrt_ctx *c, const StepArgs &a);   // sorted state -> caller
 hipError_t launch_matter_kd(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
-hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a);
+hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a, bool from_a = false);
 hipError_t launch_ic(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
                      const hrt_matter *m);
 // Reverse-mode scratch of one realisation (HRT_ADJOINT): fixed-point ray contributions to

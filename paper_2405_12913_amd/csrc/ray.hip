@@ -1,8 +1,10 @@
 // Ray side of the co-evolution step.
 //
 // ray_step_kernel (paper Eqs. symp_1-3, kick, drift; Sec. 5.2): one lane per ray. The
-// kick over lens shell n sums, for every mesh z-plane j in the shell,
-//     w_j * bilinear(G_x, G_y on mesh plane j mod n)(X_obs + chi_j * theta),
+// kick over lens shell n sums, for every line-of-sight plane j in the shell,
+//     w_j * bilinear(G_u, G_v on lens plane j)(X_obs + chi_j * theta),
+// the lens plane being the transverse gradient in the frame of plane j's replica (built for
+// the step by plane_gradient_kernel; 8 or 16 bytes per node),
 // where theta = theta0 + dth is the ray's current angle and w_j carries the line-of-sight
 // element, r_j, the Poisson prefactor and the growth correction of Eq. kick. Then
 // p += dp and dth += d_n p (drift with the midpoint radius, Eq. drift). Positions on a
@@ -12,7 +14,8 @@
 //
 // convergence_kernel (Eqs. A, obs_first_set, obs_second_set): finite differences of the
 // deflections over the pixel grid, central inside and second-order one-sided on the
-// edges; kappa, gamma1, gamma2, omega with omega kept to first order.
+// edges, or the forward-mode distortion A carried by the rays (HRT_JACOBIAN); kappa,
+// gamma1, gamma2, omega with omega kept to first order.
 // Both kernels cover all realisations of a context (uneven ray grids) in one launch.
 #include "device_common.h"
 
@@ -24,8 +27,9 @@ constexpr int kThreads = 256;
 template <typename T>
 struct RayR {                  // one realisation, as the ray kernels see it
     T *dthx, *dthy, *px, *py;
+    T *jac[8];                 // (A - I)_xx, _xy, _yx, _yy, B_xx, _xy, _yx, _yy (HRT_JACOBIAN)
     const PlaneEntry *planes;
-    const v4<T> *g;
+    const c2<T> *stack;        // the step's lens planes: (G_u, G_v) [e - begin][v][u]
     T *kappa, *g1, *g2, *om;
     T *akappa, *ag1, *ag2, *aom;   // n_g-weighted sums over the source planes (Eq. obs_accum)
     T aw;                          // weight of this source plane
@@ -57,7 +61,7 @@ __device__ __forceinline__ int ray_of(int b, int t, int mx, int my, int map) {
     return b * kThreads + t;
 }
 
-template <typename T>
+template <typename T, bool JAC>
 __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     const int blk = logical_block(b.xcd);
     const int r = real_of(b.map, blk);
@@ -69,13 +73,14 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     const double thy = ((iy + 0.5) - a.half_my) * a.muy + (double)a.dthy[i];
     const int n = a.n, m = n - 1;
     T ax = 0, ay = 0;
+    T j00 = 0, j01 = 0, j10 = 0, j11 = 0;        // d kick / d theta (JAC)
     // The kick reads every plane at the step's starting angles, so the planes are
     // independent: kChunk of them have their gathers in flight together, then are added in
     // plane order (the same sums as one plane at a time).
     constexpr int kChunk = 4;
     struct Sample {
-        v4<T> g00, g01, g10, g11;
-        T fx, fy, w;
+        c2<T> g00, g01, g10, g11;
+        T fx, fy, w, wj;
     };
     auto fetch = [&](int e, Sample &q) {
         const PlaneEntry pe = a.planes[e];
@@ -85,9 +90,10 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
         q.fx = (T)frx;
         q.fy = (T)fry;
         q.w = (T)pe.w;
+        if (JAC) q.wj = (T)(pe.w * pe.chi * a.inv_cell);
         const int x0 = (int)((int64_t)flx & m), y0 = (int)((int64_t)fly & m);
         const int x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
-        const v4<T> *plane = a.g + (size_t)pe.mesh * n * n;
+        const c2<T> *plane = a.stack + (size_t)(e - a.begin) * n * n;
         q.g00 = plane[(size_t)y0 * n + x0];
         q.g01 = plane[(size_t)y0 * n + x1];
         q.g10 = plane[(size_t)y1 * n + x0];
@@ -101,6 +107,17 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
         const T gy = w00 * q.g00.y + w01 * q.g01.y + w10 * q.g10.y + w11 * q.g11.y;
         ax += q.w * gx;
         ay += q.w * gy;
+        if (JAC) {
+            // gradient of the bilinear interpolant: differences of the corner values
+            const T dxu = (T(1) - fy) * (q.g01.x - q.g00.x) + fy * (q.g11.x - q.g10.x);
+            const T dyu = (T(1) - fx) * (q.g10.x - q.g00.x) + fx * (q.g11.x - q.g01.x);
+            const T dxv = (T(1) - fy) * (q.g01.y - q.g00.y) + fy * (q.g11.y - q.g10.y);
+            const T dyv = (T(1) - fx) * (q.g10.y - q.g00.y) + fx * (q.g11.y - q.g01.y);
+            j00 += q.wj * dxu;
+            j01 += q.wj * dyu;
+            j10 += q.wj * dxv;
+            j11 += q.wj * dyv;
+        }
     };
     const int e_end = a.begin + a.count;
     int e = a.begin;
@@ -121,6 +138,22 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     a.py[i] = npy;
     a.dthx[i] += a.d * npx;
     a.dthy[i] += a.d * npy;
+    if (JAC) {
+        // B += J (I + dA), then dA += d B (Eqs. obsv_recurse1-3, half-kicks merged)
+        const T d00 = a.jac[0][i], d01 = a.jac[1][i], d10 = a.jac[2][i], d11 = a.jac[3][i];
+        const T b00 = a.jac[4][i] + (j00 * (T(1) + d00) + j01 * d10);
+        const T b01 = a.jac[5][i] + (j00 * d01 + j01 * (T(1) + d11));
+        const T b10 = a.jac[6][i] + (j10 * (T(1) + d00) + j11 * d10);
+        const T b11 = a.jac[7][i] + (j10 * d01 + j11 * (T(1) + d11));
+        a.jac[4][i] = b00;
+        a.jac[5][i] = b01;
+        a.jac[6][i] = b10;
+        a.jac[7][i] = b11;
+        a.jac[0][i] = d00 + a.d * b00;
+        a.jac[1][i] = d01 + a.d * b01;
+        a.jac[2][i] = d10 + a.d * b10;
+        a.jac[3][i] = d11 + a.d * b11;
+    }
 }
 
 template <typename T>
@@ -130,17 +163,27 @@ __device__ __forceinline__ T fd(const T *f, int i, int k, int mk, int stride) {
     return f[i + stride] - f[i - stride];
 }
 
-template <typename T>
+// FROM_A: the derivatives are the forward-mode distortion dA = A - I carried by the rays
+// (HRT_JACOBIAN) instead of finite differences of the deflections.
+template <typename T, bool FROM_A>
 __global__ __launch_bounds__(kThreads) void convergence_kernel(RayBatch<T> b) {
     const int r = real_of(b.map, blockIdx.x);
     const RayR<T> &a = b.r[r];
     const int i = (blockIdx.x - b.map.start[r]) * kThreads + threadIdx.x;
     if (i >= a.nrays) return;
     const int mx = a.mx, my = a.my, ix = i % mx, iy = i / mx;
-    const T dxx = fd<T>(a.dthx, i, ix, mx, 1) * a.inv2mux;    // d dth_x / d theta0_x = A11 - 1
-    const T dxy = fd<T>(a.dthx, i, iy, my, mx) * a.inv2muy;   // A12
-    const T dyx = fd<T>(a.dthy, i, ix, mx, 1) * a.inv2mux;    // A21
-    const T dyy = fd<T>(a.dthy, i, iy, my, mx) * a.inv2muy;   // A22 - 1
+    T dxx, dxy, dyx, dyy;
+    if (FROM_A) {
+        dxx = a.jac[0][i];
+        dxy = a.jac[1][i];
+        dyx = a.jac[2][i];
+        dyy = a.jac[3][i];
+    } else {
+        dxx = fd<T>(a.dthx, i, ix, mx, 1) * a.inv2mux;    // d dth_x / d theta0_x = A11 - 1
+        dxy = fd<T>(a.dthx, i, iy, my, mx) * a.inv2muy;   // A12
+        dyx = fd<T>(a.dthy, i, ix, mx, 1) * a.inv2mux;    // A21
+        dyy = fd<T>(a.dthy, i, iy, my, mx) * a.inv2muy;   // A22 - 1
+    }
     const T k = T(-0.5) * (dxx + dyy);                        // kappa = 1 - (A11 + A22)/2
     if (a.kappa) a.kappa[i] = k;
     const bool acc = a.amode != 0;
@@ -169,8 +212,9 @@ void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
     a.dthy = static_cast<T *>(rays.dth[1]);
     a.px = static_cast<T *>(rays.p[0]);
     a.py = static_cast<T *>(rays.p[1]);
+    for (int q = 0; q < 8; ++q) a.jac[q] = c->jacobian ? static_cast<T *>(rays.jac[q]) : nullptr;
     a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
-    a.g = reinterpret_cast<const v4<T> *>(re.ws + re.lay.grad);
+    a.stack = reinterpret_cast<const c2<T> *>(re.ws + re.lay.stack);
     if (s.src_maps) {
         const hrt_maps &sm = s.src_maps[r], &am = s.acc_maps[r];
         a.kappa = static_cast<T *>(sm.kappa);
@@ -210,8 +254,10 @@ void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
     (void)k;
 }
 
-template <typename T, bool CONV>
+// MODE: 0 = ray step, 1 = maps from finite differences, 2 = maps from A
+template <typename T, int MODE>
 hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
+    constexpr bool CONV = MODE != 0;
     const int nre = (int)c->re.size();
     for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
         const int R = std::min(kMaxBatch, nre - r0);
@@ -230,8 +276,10 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
         b.rmap = v % 3;
         b.xcd = v >= 3 ? 0 : 1;
         prof_begin(c);
-        if (CONV) convergence_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
-        else ray_step_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        if (MODE == 1) convergence_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else if (MODE == 2) convergence_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else if (c->jacobian) ray_step_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else ray_step_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         prof_end(c, CONV ? K_CONVERGENCE : K_RAY_STEP);
     }
     return hipGetLastError();
@@ -240,11 +288,12 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
 }  // namespace
 
 hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &s) {
-    return c->f64 ? rays_impl<double, false>(c, s) : rays_impl<float, false>(c, s);
+    return c->f64 ? rays_impl<double, 0>(c, s) : rays_impl<float, 0>(c, s);
 }
 
-hipError_t launch_convergence(hrt_ctx *c, const StepArgs &s) {
-    return c->f64 ? rays_impl<double, true>(c, s) : rays_impl<float, true>(c, s);
+hipError_t launch_convergence(hrt_ctx *c, const StepArgs &s, bool from_a) {
+    if (from_a) return c->f64 ? rays_impl<double, 2>(c, s) : rays_impl<float, 2>(c, s);
+    return c->f64 ? rays_impl<double, 1>(c, s) : rays_impl<float, 1>(c, s);
 }
 
 }  // namespace hrt

@@ -255,7 +255,31 @@ int validate_config(const hrt_config &c, std::string &err) {
     if ((int64_t)c.ray_nx * c.ray_ny > (int64_t)1 << 26) return bad("too many rays");
     if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
     if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
-    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT)) return bad("unknown flag");
+    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN)) return bad("unknown flag");
+    if ((c.flags & HRT_JACOBIAN) && c.ray_nx == 0) return bad("HRT_JACOBIAN needs rays");
+    if ((c.flags & HRT_JACOBIAN) && (c.flags & HRT_ADJOINT)) {
+        err = "HRT_JACOBIAN with HRT_ADJOINT is not supported";
+        return HRT_EUNSUPPORTED;
+    }
+    if (c.n_replicas < 0 || c.n_replicas > HRT_MAX_REPLICAS) return bad("n_replicas out of range");
+    if ((c.n_replicas > 0) != (c.replicas != nullptr)) return bad("replicas and n_replicas disagree");
+    for (int k = 0; k < c.n_replicas; ++k) {
+        const int32_t *row = c.replicas + 9 * k;
+        int seen = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (row[a] < 0 || row[a] > 2) return bad("replica perm entries must be 0, 1 or 2");
+            seen |= 1 << row[a];
+            if (row[3 + a] != 1 && row[3 + a] != -1) return bad("replica signs must be +1 or -1");
+            if (row[6 + a] < 0 || row[6 + a] >= c.mesh_n) return bad("replica shifts must be in [0, mesh_n)");
+        }
+        if (seen != 7) return bad("replica perm must be a permutation of 0, 1, 2");
+        const bool ident = row[0] == 0 && row[1] == 1 && row[2] == 2 && row[3] == 1 && row[4] == 1 &&
+                           row[5] == 1 && row[6] == 0 && row[7] == 0 && row[8] == 0;
+        if (!ident && (c.flags & HRT_ADJOINT)) {
+            err = "replica transforms with HRT_ADJOINT are not supported";
+            return HRT_EUNSUPPORTED;
+        }
+    }
     if (c.n_src < 0 || c.n_src > HRT_MAX_SOURCES) return bad("n_src out of range [0, HRT_MAX_SOURCES]");
     if (c.n_src > 0 && !c.src) return bad("src is NULL with n_src > 0");
     if (c.n_src > 0 && c.ray_nx == 0) return bad("source planes need rays");
@@ -368,11 +392,19 @@ int build_tables(const hrt_config &c, StepTables &t, std::string &err) {
             }
             int64_t m = j % c.mesh_n;
             if (m < 0) m += c.mesh_n;
+            int64_t rep = 0;                      // table row of replica floor(j / n)
+            if (c.n_replicas > 0) {
+                const int64_t k = (j - m) / c.mesh_n;
+                rep = k % c.n_replicas;
+                if (rep < 0) rep += c.n_replicas;
+            }
             t.plane_mesh.push_back((int32_t)m);
+            t.plane_rep.push_back((int32_t)rep);
             t.plane_chi.push_back(cj);
             t.plane_w.push_back(w);
         }
         t.plane_count[n] = (int32_t)t.plane_chi.size() - t.plane_begin[n];
+        t.max_count = std::max(t.max_count, t.plane_count[n]);
         if (t.plane_chi.size() > (size_t)1 << 28) {
             err = "too many shell planes";
             return HRT_EINVAL;

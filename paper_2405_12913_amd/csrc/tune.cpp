@@ -141,12 +141,19 @@ extern "C" int hrt_autotune(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, 
                 return HRT_EINVAL;
             }
     if (r)
-        for (size_t k = 0; k < c->re.size(); ++k)
+        for (size_t k = 0; k < c->re.size(); ++k) {
             for (int d = 0; d < 2; ++d)
                 if (!r[k].dth[d] || !r[k].p[d]) {
                     c->err = "NULL ray array";
                     return HRT_EINVAL;
                 }
+            if (c->jacobian)
+                for (int q = 0; q < 8; ++q)
+                    if (!r[k].jac[q]) {
+                        c->err = "NULL distortion array (HRT_JACOBIAN)";
+                        return HRT_EINVAL;
+                    }
+        }
     std::map<std::string, Entry> cache;
     if (cache_path) cache = read_cache(cache_path);
     bool dirty = false;
@@ -164,6 +171,8 @@ extern "C" int hrt_autotune(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, 
     hipError_t err = hipSuccess;
     for (int id : ids) {
         if (id == K_RAY_STEP && !r) continue;
+        if (id == K_RAY_STEP) err = hrt::launch_plane_gradient(c, step);   // the lens planes it reads
+        if (err != hipSuccess) break;
         const std::string key = shape_key(c, id);
         auto it = cache.find(key);
         if (it != cache.end() && it->second.variant >= 0 && it->second.variant < variants_of(id)) {

@@ -16,6 +16,7 @@ HRT_OK, HRT_EINVAL, HRT_ENOMEM, HRT_EDEVICE, HRT_ESTATE, HRT_EUNSUPPORTED = 0, -
 HRT_F32, HRT_F64 = 0, 1
 HRT_STATIC = 1
 HRT_ADJOINT = 2
+HRT_JACOBIAN = 4
 HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
 HRT_NUM_KERNELS = 17
@@ -27,7 +28,7 @@ EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", 
             "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
             "ray_convergence_vjp", "hrt_ic_2lpt_vjp", "hrt_num_variants", "hrt_set_variant",
             "hrt_get_variant", "hrt_autotune", "hrt_run", "hrt_init_noalloc", "pm_step_vjp",
-            "ray_step_vjp")
+            "ray_step_vjp", "ray_observe")
 
 
 class HrtConfig(ctypes.Structure):
@@ -35,7 +36,8 @@ class HrtConfig(ctypes.Structure):
                 ("n_steps", c_int32), ("dtype", c_int32), ("flags", c_int32), ("n_src", c_int32),
                 ("box", c_double), ("fov_x", c_double), ("fov_y", c_double),
                 ("observer", c_double * 3), ("omega_m", c_double), ("static_mass", c_double),
-                ("sched", POINTER(c_double)), ("src", POINTER(c_double)), ("src_w", POINTER(c_double))]
+                ("sched", POINTER(c_double)), ("src", POINTER(c_double)), ("src_w", POINTER(c_double)),
+                ("replicas", POINTER(c_int32)), ("n_replicas", c_int32)]
 
 
 class HrtMaps(ctypes.Structure):
@@ -47,7 +49,7 @@ class HrtMatter(ctypes.Structure):
 
 
 class HrtRays(ctypes.Structure):
-    _fields_ = [("dth", c_void_p * 2), ("p", c_void_p * 2)]
+    _fields_ = [("dth", c_void_p * 2), ("p", c_void_p * 2), ("jac", c_void_p * 8)]
 
 
 class HrtIcParams(ctypes.Structure):
@@ -86,6 +88,7 @@ def lib():
         L.ray_step.argtypes = [c_void_p, P(HrtRays), c_int]
         L.ray_convergence.argtypes = [c_void_p, P(HrtRays), P(c_void_p), P(c_void_p), P(c_void_p),
                                       P(c_void_p)]
+        L.ray_observe.argtypes = [c_void_p, P(HrtRays), P(HrtMaps)]
         L.hrt_graph_capture.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int, P(HrtMaps)]
         L.hrt_graph_launch.argtypes = [c_void_p]
         L.hrt_run.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), c_int, c_int, P(HrtMaps)]
@@ -122,11 +125,13 @@ def _check(rc, ctx=None):
 
 def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
                 observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0,
-                adjoint=False, src=None, src_w=None):
+                adjoint=False, src=None, src_w=None, jacobian=False, replicas=None):
     """hrt_config from keyword arguments; returns (config, host arrays kept alive).
 
     src: source planes (redshifts, or chi with static=True), each a step boundary;
-    src_w: optional weights n_g of the source planes (Eq. obs_accum)."""
+    src_w: optional weights n_g of the source planes (Eq. obs_accum);
+    jacobian: the rays carry the forward-mode distortion (HRT_JACOBIAN);
+    replicas: per-replica transform rows (perm0..2, sign0..2, shift0..2) of the light cone."""
     sched = np.ascontiguousarray(sched, dtype=np.float64)
     if len(sched) != n_steps + 1:
         raise ValueError("sched must have n_steps + 1 entries")
@@ -134,7 +139,8 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     cfg.mesh_n, cfg.ptcl_n, cfg.ray_nx, cfg.ray_ny = mesh_n, ptcl_n, ray_nx, ray_ny
     cfg.n_steps = n_steps
     cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
-    cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0)
+    cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0) | \
+        (HRT_JACOBIAN if jacobian else 0)
     cfg.n_src = 0 if src is None else len(src)
     cfg.box, cfg.fov_x, cfg.fov_y = box, fov_x, fov_y
     for i in range(3):
@@ -154,6 +160,11 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
             keep.append(src_w)
     elif src_w is not None:
         raise ValueError("src_w needs src")
+    if replicas is not None:
+        reps = np.ascontiguousarray(np.asarray(replicas, dtype=np.int32).reshape(-1, 9))
+        cfg.replicas = reps.ctypes.data_as(POINTER(c_int32))
+        cfg.n_replicas = len(reps)
+        keep.append(reps)
     return cfg, keep
 
 
@@ -288,12 +299,16 @@ class Simulation:
                 m[k].p[d] = _ptr(pk[d], self.dtype, self.n_particles[k], "p") if pk is not None else None
         return m
 
-    def _rays(self, dth, p=None):
+    def _rays(self, dth, p=None, jac=None):
+        """jac: per realisation 8 tensors (A - I)_xx, _xy, _yx, _yy, B_xx, _xy, _yx, _yy."""
         r = (HrtRays * self.R)()
-        for k, (dk, pk) in enumerate(zip(self._per(dth), self._per(p))):
+        for k, (dk, pk, jk) in enumerate(zip(self._per(dth), self._per(p), self._per(jac))):
             for d in range(2):
                 r[k].dth[d] = _ptr(dk[d], self.dtype, self.n_rays[k], "dth")
                 r[k].p[d] = _ptr(pk[d], self.dtype, self.n_rays[k], "p") if pk is not None else None
+            if jk is not None:
+                for q in range(8):
+                    r[k].jac[q] = _ptr(jk[q], self.dtype, self.n_rays[k], "jac")
         return r
 
     def pm_force(self, s, step):
@@ -302,8 +317,20 @@ class Simulation:
     def pm_step(self, s, p, step):
         _check(lib().pm_step(self.ctx, self._matter(s, p), step), self.ctx)
 
-    def ray_step(self, dth, p, step):
-        _check(lib().ray_step(self.ctx, self._rays(dth, p), step), self.ctx)
+    def ray_step(self, dth, p, step, jac=None):
+        _check(lib().ray_step(self.ctx, self._rays(dth, p, jac), step), self.ctx)
+
+    def observe(self, dth, jac, maps):
+        """Maps from the forward-mode distortion (HRT_JACOBIAN): maps is one dict per
+        realisation (a dict for a single realisation) with any of kappa, gamma1, gamma2,
+        omega -> device tensor."""
+        per = [maps] if isinstance(maps, dict) else list(maps)
+        arr = (HrtMaps * self.R)()
+        for k, d in enumerate(per):
+            for name in ("kappa", "gamma1", "gamma2", "omega"):
+                if d.get(name) is not None:
+                    setattr(arr[k], name, _ptr(d[name], self.dtype, self.n_rays[k], name))
+        _check(lib().ray_observe(self.ctx, self._rays(dth, None, jac), arr), self.ctx)
 
     def ray_convergence(self, dth, kappa, gamma1=None, gamma2=None, omega=None):
         import torch
@@ -343,17 +370,18 @@ class Simulation:
                         setattr(arr[k * self.n_maps + i], name, _ptr(t, self.dtype, self.n_rays[k], name))
         return arr
 
-    def run(self, s, p, dth, pr, first_step, n_steps, maps=None):
+    def run(self, s, p, dth, pr, first_step, n_steps, maps=None, jac=None):
         """Steps [first_step, first_step + n_steps): pm_step + ray_step each (dth, pr may be
         None for matter only); same results as calling them one by one, one pass less.
-        maps: observables written at the source planes the steps reach (see _maps)."""
-        r = self._rays(dth, pr) if dth is not None else None
+        maps: observables written at the source planes the steps reach (see _maps);
+        jac: the rays' distortion state (HRT_JACOBIAN)."""
+        r = self._rays(dth, pr, jac) if dth is not None else None
         _check(lib().hrt_run(self.ctx, self._matter(s, p), r, first_step, n_steps, self._maps(maps)),
                self.ctx)
 
-    def graph_capture(self, s, p, dth, pr, first_step, n_steps, maps=None):
+    def graph_capture(self, s, p, dth, pr, first_step, n_steps, maps=None, jac=None):
         """Capture steps [first_step, first_step + n_steps) into one HIP graph."""
-        self._graph_args = (self._matter(s, p), self._rays(dth, pr) if dth is not None else None,
+        self._graph_args = (self._matter(s, p), self._rays(dth, pr, jac) if dth is not None else None,
                             self._maps(maps))
         _check(lib().hrt_graph_capture(self.ctx, self._graph_args[0], self._graph_args[1],
                                        first_step, n_steps, self._graph_args[2]), self.ctx)
@@ -433,7 +461,7 @@ class Simulation:
                 out[lib().hrt_kernel_name(k).decode()] = v.value
         return out
 
-    def autotune(self, s, p, dth=None, pr=None, step=0, cache=None):
+    def autotune(self, s, p, dth=None, pr=None, step=0, cache=None, jac=None):
         """Time every launch-shape variant on copies of the given state and keep the fastest
         (choices cached in the JSON file `cache` if given). The state is not modified."""
         s2 = [[t.clone() for t in x] for x in self._per(s)]
@@ -443,7 +471,8 @@ class Simulation:
         if dth is not None:
             d2 = [[t.clone() for t in x] for x in self._per(dth)]
             r2 = [[t.clone() for t in x] for x in self._per(pr)]
-            r = self._rays(d2, r2)
+            j2 = None if jac is None else [[t.clone() for t in x] for x in self._per(jac)]
+            r = self._rays(d2, r2, j2)
         path = cache.encode() if cache is not None else None
         _check(lib().hrt_autotune(self.ctx, m, r, step, path), self.ctx)
         return self.variants()

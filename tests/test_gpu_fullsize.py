@@ -167,7 +167,8 @@ def test_lcdm256_sorted_run_bit_identical():
     """At the benchmark size, on a clustered state (dense tiles): hrt_run keeping the
     particles in paint-bin order (the default for long runs) gives the bits of pm_step / ray_step called
     step by step, for every paint_tiles variant, and so does the Lagrangian-order run.
-    Afterwards the G mesh is incomplete, so ray_step refuses to run before a new pm_force."""
+    Afterwards no G mesh is kept, but phi is: a ray_step of the last step gives the bits of
+    the step-by-step calls."""
     import torch
     from paper_2405_12913_amd import hrt
     cfg = synth.lcdm256()
@@ -199,8 +200,19 @@ def test_lcdm256_sorted_run_bit_identical():
             torch.cuda.synchronize()
             for a, b in zip(sum(st, []), ref):
                 assert torch.equal(a, b), (kd, pv)
-    sim.set_variant("kd_tiles", 2)
+    # after a paint-bin-order run no G mesh is kept (phi of the last step is): the mesh view
+    # is refused, and a ray_step of that step forms its lens planes from phi as always
     sim.set_variant("paint_tiles", 0)
-    sim.run(st[0], st[1], None, None, 23, 1)
-    with pytest.raises(hrt.HRTError, match="no force mesh"):
-        sim.ray_step(st[2], st[3], 23)
+    got = [[t.clone() for t in x] for x in base]
+    sim.set_variant("kd_tiles", 2)
+    sim.run(got[0], got[1], None, None, 23, 1)
+    with pytest.raises(hrt.HRTError, match="status -4"):
+        sim.mesh(hrt.HRT_MESH_GRAD)
+    sim.ray_step(got[2], got[3], 23)
+    want = [[t.clone() for t in x] for x in base]
+    sim.set_variant("kd_tiles", 1)
+    sim.pm_step(want[0], want[1], 23)
+    sim.ray_step(want[2], want[3], 23)
+    torch.cuda.synchronize()
+    for a, b in zip(sum(got, []), sum(want, [])):
+        assert torch.equal(a, b)
