@@ -305,6 +305,57 @@ def large_bench(hrt, torch, dev, tune=True):
             "timed_schedule_steps": f"0..{N - 1}", "kappa": kap, "launch_variants": tuned}
 
 
+def ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, steps):
+    """The lcdm256 schedule with the rays' optional features, each against the plain path on
+    the same state: the forward-mode distortion recursion (HRT_JACOBIAN, 8 more values per
+    ray read and written, the plane-sum derivative) and random per-replica transforms of
+    the light cone (lens planes formed through a lattice symmetry and shift)."""
+    import synth
+    nr = cfg["ray_n"] ** 2
+    table = synth.replica_table(0, cfg["mesh_n"], 12)
+    out = {}
+    for name, kw in (("plain", {}), ("jacobian", {"jacobian": True}), ("replicas", {"replicas": table}),
+                     ("jacobian_replicas", {"jacobian": True, "replicas": table})):
+        s = [t.clone() for t in s_init]
+        p = [t.clone() for t in p_init]
+        dth = [torch.zeros(nr, device=dev) for _ in range(2)]
+        pr = [torch.zeros(nr, device=dev) for _ in range(2)]
+        jac = [torch.zeros(nr, device=dev) for _ in range(8)] if kw.get("jacobian") else None
+        sim = hrt.Simulation(**sim_kwargs(cfg), device=dev, **kw)
+        for k, v in tuned.items():
+            sim.set_variant(k, v)
+        sim.run(s, p, dth, pr, 0, 2, jac=jac)                     # warm-up
+        torch.cuda.synchronize()
+        for a, b in zip(s + p, s_init + p_init):
+            a.copy_(b)
+        for t in dth + pr + (jac or []):
+            t.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(sim.stream)
+        sim.run(s, p, dth, pr, 0, steps, jac=jac)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        for a, b in zip(s + p, s_init + p_init):
+            a.copy_(b)
+        for t in dth + pr + (jac or []):
+            t.zero_()
+        sim.profile_enable(True)
+        sim.run(s, p, dth, pr, 0, steps, jac=jac)
+        prof = sim.profile_read()
+        sim.profile_enable(False)
+        assert torch.isfinite(dth[0]).all() and (jac is None or torch.isfinite(jac[0]).all())
+        sim.close()
+        out[name] = {"ms_per_step": round(ms, 4), "ray_steps_per_s": nr / (ms * 1e-3),
+                     "ray_step_ms": round(prof["ray_step"][0] / max(prof["ray_step"][1], 1), 5),
+                     "lens_planes_ms": round(prof["plane_gradient"][0] / max(prof["plane_gradient"][1], 1), 5)}
+    out["note"] = (f"lcdm256, schedule steps 0..{steps - 1}, same evolved state; 12 random replica "
+                   "transforms (synth.replica_table(0, 256, 12)); ray_step_ms and lens_planes_ms "
+                   "are per-launch HIP-event averages")
+    return out
+
+
 def fft_baseline(torch, dev):
     """rocFFT (through torch.fft) timing of the same transforms as one Poisson solve: a 3D
     real-to-complex forward and a complex-to-real inverse, FP32, at 256^3 and 1024^3, median
@@ -388,6 +439,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 workload")
     ap.add_argument("--no-fft-baseline", action="store_true", help="skip the rocFFT cross-check")
+    ap.add_argument("--no-ray-options", action="store_true",
+                    help="skip the forward-mode distortion / replica-transform timings")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of launch-shape choices: read if present, written after tuning")
@@ -593,6 +646,9 @@ def main():
             gsim.close()
         out["graph_ray_steps_per_s"] = nrays * args.steps / (gms * 1e-3)
         out["graph_ms_per_step"] = gms / args.steps
+    if not args.no_ray_options:
+        print("[bench] ray options: jacobian, replicas", file=sys.stderr, flush=True)
+        out["ray_options"] = ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, N)
     if not args.no_batched:
         out["batched"] = batched_bench(hrt, torch, dev, tune=not args.no_tune)
     if not args.no_adjoint:
