@@ -85,6 +85,57 @@ def ray_step(dth, p, theta0, gx, gy, planes, d, observer_xy, box, gz=None, repli
     return dth, p
 
 
+def _scalar_plane(f, j, replicas):
+    """A scalar box mesh on line-of-sight plane j (in its replica's frame)."""
+    n = f.shape[0]
+    if replicas is None:
+        return f[j % n]
+    return _replicas.lens_plane(f, j, n, replicas, grad=False)
+
+
+def ray_step_los(dth, p, delay, los, theta0, gx, gy, planes, d, observer_xy, box, phi,
+                 q=None, los_w=None, gz=None, replicas=None):
+    """One ray step that also accumulates the time delay (Sec. 2, Eq. eom3) and, if q is
+    given, a line-of-sight integral (Sec. 4, Eq. integral).
+
+    Delay (c times the arrival-time delay, Mpc/h): c dtau/dchi = -(1 - 2 Phi/c^2 + p^2/(2 r^2))
+    along the ray, so against the unperturbed light travel the delay grows by
+    p^2/(2 r^2) - 2 Phi/c^2 per unit chi (geometric and Shapiro terms). Split as the
+    leapfrog splits the Hamiltonian: the Shapiro term is a plane sum at the kick's angles,
+    -2 Phi_j/c^2 cell = (w_j / chi_j) phi_j (w_j = -2 r_j cell (Phi/c^2 per unit phi)), and
+    the geometric term is p^2 d / 2 over the drift with the drift momentum (midpoint radius).
+    Line-of-sight integral: los += sum_j los_w_j q_j(X) (``tables.los_weights``)."""
+    theta = theta0 + dth
+    dT = np.zeros(len(dth))
+    dO = np.zeros(len(dth))
+    for k, (j, chi_j, w) in enumerate(planes):
+        xy = np.asarray(observer_xy, float)[None, :] + chi_j * theta
+        dT += (w / chi_j) * mesh.bilinear_readout(_scalar_plane(phi, j, replicas), xy, box)
+        if q is not None:
+            dO += los_w[k] * mesh.bilinear_readout(_scalar_plane(q, j, replicas), xy, box)
+    p = p + ray_kick(dth, theta0, gx, gy, planes, observer_xy, box, gz, replicas)
+    delay = delay + dT + 0.5 * d * np.sum(p * p, axis=1)
+    return dth + d * p, p, delay, los + dO
+
+
+def ray_step_analytic_delay(dth, p, delay, theta0, grad_perp, potential, planes, d, observer_xy):
+    """ray_step_analytic with the time delay of ``ray_step_los`` for an analytic potential:
+    potential(X, Y, chi) is the field whose gradient grad_perp gives, read with the same
+    plane weights w_j (Shapiro term (w_j / chi_j) potential)."""
+    theta = theta0 + dth
+    dp = np.zeros_like(dth)
+    dT = np.zeros(len(dth))
+    for j, chi_j, w in planes:
+        xy = np.asarray(observer_xy, float)[None, :] + chi_j * theta
+        gx, gy = grad_perp(xy[:, 0], xy[:, 1], chi_j)
+        dp[:, 0] += w * gx
+        dp[:, 1] += w * gy
+        dT += (w / chi_j) * potential(xy[:, 0], xy[:, 1], chi_j)
+    p = p + dp
+    delay = delay + dT + 0.5 * d * np.sum(p * p, axis=1)
+    return dth + d * p, p, delay
+
+
 def kick_jacobian(dth, theta0, gx, gy, planes, observer_xy, box, gz=None, replicas=None):
     """J = d kick / d theta (M, 2, 2) at the current angle: the plane sum of w_j chi_j times
     the gradient of the bilinear interpolant of (G_u, G_v) on plane j (its exact derivative

@@ -125,3 +125,36 @@ def build_static(chi_sched, mesh_n, box, z_obs, mass, n_particles):
     pref = -8.0 * math.pi * cosmo.G_OVER_C2 * mass * rho_bar / cell ** 2
     d, planes = ray_tables(chi, cell, z_obs, lambda n, j, chi_j, sgn: sgn * pref * chi_j)
     return StepTable(N, np.ones(N + 1), chi, np.zeros(N + 1), np.zeros(N + 1), d, planes)
+
+
+def los_weights(tab, field, chi_knots, p_knots, cell, omega_m=None):
+    """Per step, per shell plane (aligned with ``tab.planes``): the weight of the field on
+    plane j in a line-of-sight integral O = int dchi P(chi) Q (Sec. 4, Eq. integral),
+    discretised like the kick as the plane sum  O += sum_j weight_j * Q_j(X_obs + chi_j theta).
+
+    P is piecewise linear through the knots (zero outside them). Q is the mesh field of the
+    step's boundary a_n, carried to the plane's time with the linear-growth correction of
+    Eq. kick: for field "density" (delta) weight_j = s P(chi_j) cell D1(a_j) / D1(a_n), for
+    "potential" (Q = Phi/c^2 from the unit potential phi of the mesh, whose kick weight is
+    w_j = -2 r_j cell (Phi/c^2 per unit phi)) weight_j = -P(chi_j) w_j / (2 chi_j); s = +-1
+    is the step's direction. omega_m None: static run (no growth)."""
+    chi = np.asarray(tab.chi, float)
+    lo, hi = _half_points(chi)
+    out = []
+    for n, plist in enumerate(tab.planes):
+        sgn = 1.0 if hi[n] >= lo[n] else -1.0
+        ws = []
+        for j, chi_j, w in plist:
+            P = float(np.interp(chi_j, chi_knots, p_knots, left=0.0, right=0.0))
+            if field == "potential":
+                ws.append(-P * w / (2.0 * chi_j))
+            elif field == "density":
+                g = 1.0
+                if omega_m is not None:
+                    aj = cosmo.a_of_chi(chi_j, omega_m)
+                    g = cosmo.growth_D1(aj, omega_m) / cosmo.growth_D1(tab.a[n], omega_m)
+                ws.append(sgn * P * cell * g)
+            else:
+                raise ValueError(field)
+        out.append(ws)
+    return out

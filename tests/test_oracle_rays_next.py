@@ -145,3 +145,96 @@ def test_replica_of_a_plane_is_its_line_of_sight_index_over_n():
     parts = sum(integrator.ray_kick(dth, th0, moved[(j // n) % 2][0], moved[(j // n) % 2][1], [(j, c, w)],
                                     obs[:2], box) for j, c, w in shell)
     np.testing.assert_allclose(whole, parts, rtol=0, atol=1e-11 * np.abs(parts).max())
+
+
+# ----------------------------------------------------------------------------------
+# time delay (Eq. eom3) and line-of-sight integrals (Eq. integral)
+# ----------------------------------------------------------------------------------
+
+def _static_planes(chi_s, n_steps, cell):
+    # planes at (j + 1/2) cell, weight -2 cell r_j: the kick reads the gradient of Phi/c^2
+    chi = np.linspace(0.0, chi_s, n_steps + 1)
+    return tables.ray_tables(chi, cell, -0.5 * cell, lambda n, j, chi_j, sgn: sgn * (-2.0 * cell * chi_j))
+
+
+def _trace_delay(theta0, d, planes, grad, pot):
+    # steps 0..N: the closing half-kick N adds the planes of the last half shell
+    dth = np.zeros_like(theta0)
+    p = np.zeros_like(theta0)
+    T = np.zeros(len(theta0))
+    for n in range(len(d)):
+        dth, p, T = integrator.ray_step_analytic_delay(dth, p, T, theta0, grad, pot, planes[n], d[n], (0.0, 0.0))
+    return dth, p, T
+
+
+def test_time_delay_of_a_uniform_force_converges_to_the_closed_form():
+    # Phi/c^2 = -g X: p = g chi^2, theta = theta0 + g chi, so the geometric delay is
+    # g^2 chi_s^3 / 6 and the Shapiro delay 2 g int X dchi = g theta0 chi_s^2 + 2/3 g^2 chi_s^3
+    g, chi_s, th = 2e-6, 400.0, 0.01
+    theta0 = np.array([[th, 0.0], [-th, 0.0], [0.0, th]])
+    exact = np.array([g * g * chi_s ** 3 / 6 + g * t * chi_s ** 2 + 2 / 3 * g * g * chi_s ** 3
+                      for t in (th, -th, 0.0)])
+    grad = lambda X, Y, chi: (np.full_like(X, -g), np.zeros_like(Y))
+    pot = lambda X, Y, chi: -g * X
+    errs = []
+    for n in (50, 100, 200):             # shell boundaries on whole cells, planes on half cells
+        d, planes = _static_planes(chi_s, n, 0.0625)
+        dth, p, T = _trace_delay(theta0, d, planes, grad, pot)
+        np.testing.assert_allclose(p[:, 0], g * chi_s ** 2, rtol=1e-12)   # every kick is exact
+        errs.append(np.abs(T - exact).max() / np.abs(exact).max())
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4    # second order
+    assert errs[2] < 1e-4
+
+
+def test_shapiro_delay_of_a_weak_plane_wave():
+    # Phi/c^2 = eps cos(k X), to first order in eps: -2 eps int cos(u chi) dchi = -2 eps sin(u chi_s) / u
+    eps, k, chi_s = 1e-9, 2 * math.pi / 100.0, 500.0
+    d, planes = _static_planes(chi_s, 500, 0.125)
+    theta0 = integrator.pixel_angles(16, 2, 0.06, 0.0075)
+    theta0[:, 0] += 0.01
+    grad = lambda X, Y, chi: (-eps * k * np.sin(k * X), np.zeros_like(Y))
+    pot = lambda X, Y, chi: eps * np.cos(k * X)
+    _, _, T = _trace_delay(theta0, d, planes, grad, pot)
+    u = k * theta0[:, 0]
+    np.testing.assert_allclose(T, -2 * eps * np.sin(u * chi_s) / u, rtol=2e-6)
+
+
+@pytest.mark.parametrize("field", ["density", "potential"])
+def test_los_integral_of_a_plane_wave(field):
+    # O = P int_0^chi_s Q(chi theta0) dchi along undeflected rays (the deflecting potential is
+    # zero) for Q = eps cos(k X): P eps sin(u chi_s) / u with u = k theta0_x; for the potential
+    # Q = Phi/c^2 = -(pref / (2 cell)) phi of the static weights w_j = pref r_j
+    n, box, eps, P = 1024, 400.0, 1e-3, 0.7
+    cell = box / n
+    k = 2 * math.pi / box
+    chi_s = 300.0
+    tab = tables.build_static(np.linspace(0.0, chi_s, 41), n, box, -0.5 * cell, 1e12, 1)
+    lw = tables.los_weights(tab, field, [0.0, chi_s], [P, P], cell)
+    theta0 = integrator.pixel_angles(12, 2, 0.05, 0.05 / 6)
+    theta0[:, 0] += 0.03
+    plane = np.broadcast_to((eps * np.cos(k * np.arange(n) * cell))[None, :], (n, n))
+    q = np.broadcast_to(plane, (n, n, n))
+    zero = np.broadcast_to(np.zeros((n, n)), (n, n, n))
+    dth = np.zeros_like(theta0)
+    p = np.zeros_like(theta0)
+    T = np.zeros(len(theta0))
+    O = np.zeros(len(theta0))
+    for st in range(tab.n_steps + 1):                # with the closing half-kick
+        dth, p, T, O = integrator.ray_step_los(dth, p, T, O, theta0, zero, zero, tab.planes[st], tab.d[st],
+                                               (0.0, 0.0), box, zero, q, lw[st])
+    u = k * theta0[:, 0]
+    ref = P * eps * np.sin(u * chi_s) / u
+    if field == "potential":
+        pref = tab.planes[1][0][2] / tab.planes[1][0][1]            # w_j / r_j
+        ref = -(pref / (2 * cell)) * ref
+    np.testing.assert_allclose(O, ref, rtol=1e-4)
+    np.testing.assert_array_equal(dth, 0.0)
+
+
+def test_identity_replicas_give_the_plain_scalar_planes():
+    cfg, q, s, p, th0, tab, obs = _small(steps=2)
+    n, box = cfg["mesh_n"], cfg["box"]
+    phi = np.random.default_rng(3).normal(size=(n, n, n))
+    for j in (1, n - 1, n + 3, 5 * n + 7):
+        assert np.array_equal(integrator._scalar_plane(phi, j, None),
+                              integrator._scalar_plane(phi, j, [replicas.IDENTITY]))
