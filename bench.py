@@ -308,41 +308,46 @@ def large_bench(hrt, torch, dev, tune=True):
 def ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, steps):
     """The lcdm256 schedule with the rays' optional features, each against the plain path on
     the same state: the forward-mode distortion recursion (HRT_JACOBIAN, 8 more values per
-    ray read and written, the plane-sum derivative) and random per-replica transforms of
-    the light cone (lens planes formed through a lattice symmetry and shift)."""
+    ray read and written, the plane-sum derivative), random per-replica transforms of the
+    light cone (lens planes formed through a lattice symmetry and shift), and the time delay
+    with a density line-of-sight integral (two scalar planes per lens plane gathered too)."""
     import synth
     nr = cfg["ray_n"] ** 2
     table = synth.replica_table(0, cfg["mesh_n"], 12)
     out = {}
+    los = dict(los_field="density", los_chi=[0.0, 1000.0, 2400.0], los_p=[0.0, 1.0, 0.5])
     for name, kw in (("plain", {}), ("jacobian", {"jacobian": True}), ("replicas", {"replicas": table}),
-                     ("jacobian_replicas", {"jacobian": True, "replicas": table})):
+                     ("jacobian_replicas", {"jacobian": True, "replicas": table}),
+                     ("time_delay_los", dict(time_delay=True, **los))):
         s = [t.clone() for t in s_init]
         p = [t.clone() for t in p_init]
         dth = [torch.zeros(nr, device=dev) for _ in range(2)]
         pr = [torch.zeros(nr, device=dev) for _ in range(2)]
         jac = [torch.zeros(nr, device=dev) for _ in range(8)] if kw.get("jacobian") else None
+        extra = [torch.zeros(nr, device=dev) for _ in range(2)] if kw.get("time_delay") else [None, None]
         sim = hrt.Simulation(**sim_kwargs(cfg), device=dev, **kw)
         for k, v in tuned.items():
             sim.set_variant(k, v)
-        sim.run(s, p, dth, pr, 0, 2, jac=jac)                     # warm-up
+        xt = [t for t in extra if t is not None]
+        sim.run(s, p, dth, pr, 0, 2, jac=jac, delay=extra[0], los=extra[1])     # warm-up
         torch.cuda.synchronize()
         for a, b in zip(s + p, s_init + p_init):
             a.copy_(b)
-        for t in dth + pr + (jac or []):
+        for t in dth + pr + (jac or []) + xt:
             t.zero_()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(sim.stream)
-        sim.run(s, p, dth, pr, 0, steps, jac=jac)
+        sim.run(s, p, dth, pr, 0, steps, jac=jac, delay=extra[0], los=extra[1])
         e1.record(sim.stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         for a, b in zip(s + p, s_init + p_init):
             a.copy_(b)
-        for t in dth + pr + (jac or []):
+        for t in dth + pr + (jac or []) + xt:
             t.zero_()
         sim.profile_enable(True)
-        sim.run(s, p, dth, pr, 0, steps, jac=jac)
+        sim.run(s, p, dth, pr, 0, steps, jac=jac, delay=extra[0], los=extra[1])
         prof = sim.profile_read()
         sim.profile_enable(False)
         assert torch.isfinite(dth[0]).all() and (jac is None or torch.isfinite(jac[0]).all())

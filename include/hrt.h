@@ -63,6 +63,9 @@ enum {
                                source is unit-weight particles of mass static_mass each */
     HRT_ADJOINT = 2,        /* reserve the reverse-mode scratch (hrt_step_vjp) in the
                                workspace: 16 n^3 + 256 + 4 np^3 sizeof(dtype) bytes more */
+    HRT_TIME_DELAY = 8,     /* the rays accumulate c times the arrival-time delay (Sec. 2,
+                               Eq. eom3: geometric p^2/(2 r^2) and Shapiro -2 Phi/c^2 per
+                               unit chi) in hrt_rays.delay [Mpc/h]; not with HRT_ADJOINT   */
     HRT_JACOBIAN = 4        /* the rays carry the forward-mode distortion recursion of
                                Sec. 4 (Eqs. A, B, obsv_recurse1-3; Alg. 1 iterate_A,
                                iterate_B): hrt_rays.jac required by ray_step; source-plane
@@ -108,7 +111,19 @@ typedef struct {
                                shift < n. Copied at init. Not combinable with HRT_ADJOINT
                                unless every row is the identity (HRT_EUNSUPPORTED)       */
     int32_t n_replicas;     /* rows in replicas (0 when NULL), <= HRT_MAX_REPLICAS       */
+    int32_t los_field;      /* line-of-sight integral O = int dchi P(chi) Q along the ray
+                               (Sec. 4, Eq. integral), accumulated in hrt_rays.los:
+                               HRT_LOS_NONE, HRT_LOS_DENSITY (Q = delta) or
+                               HRT_LOS_POTENTIAL (Q = Phi/c^2); Q of the step's mesh carried
+                               to each plane's time with the kick's linear-growth
+                               correction (Eq. kick). Not with HRT_ADJOINT                */
+    int32_t los_n;          /* knots of P (>= 2 when los_field != 0)                      */
+    const double *los_chi;  /* los_n increasing chi [Mpc/h]; P is linear between knots and
+                               0 outside them                                             */
+    const double *los_p;    /* los_n values of P; both copied at init                      */
 } hrt_config;
+
+enum { HRT_LOS_NONE = 0, HRT_LOS_DENSITY = 1, HRT_LOS_POTENTIAL = 2 };
 
 enum { HRT_MAX_SOURCES = 256, HRT_MAX_REPLICAS = 4096 };
 
@@ -122,8 +137,12 @@ typedef struct { void *s[3]; void *p[3]; } hrt_matter;   /* device SoA, np^3 eac
  * p (x, y), and with HRT_JACOBIAN the distortion recursion jac = (A - I)_xx, (A - I)_xy,
  * (A - I)_yx, (A - I)_yy, B_xx, B_xy, B_yx, B_yy with A = d theta / d theta0, B = d p /
  * d theta0 (A_ab: component a, derivative along b); all zero at the observer (A_0 = I,
- * B_0 = 0). jac entries are ignored (may be NULL) without HRT_JACOBIAN. */
-typedef struct { void *dth[2]; void *p[2]; void *jac[8]; } hrt_rays;
+ * B_0 = 0). jac entries are ignored (may be NULL) without HRT_JACOBIAN; delay (with
+ * HRT_TIME_DELAY) and los (with a line-of-sight integral) are accumulated in place (zero at
+ * the observer) and ignored otherwise. A quantity read at boundary k holds the planes of the
+ * kicks applied so far: the closing half-kick (step N) adds the last half shell, as it does
+ * for the momentum. */
+typedef struct { void *dth[2]; void *p[2]; void *jac[8]; void *delay; void *los; } hrt_rays;
 
 typedef struct hrt_ctx hrt_ctx;
 

@@ -46,6 +46,11 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_c
     L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * 10 * T);
     // lens-plane stack of one shell: (G_u, G_v) per node of each plane, replica frame
     L.stack = cfg.ray_nx > 0 ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * 2 * T) : off;
+    // scalar lens planes: phi (time delay, potential integrals), delta (density integrals)
+    const bool want_phi = (cfg.flags & HRT_TIME_DELAY) || cfg.los_field == HRT_LOS_POTENTIAL;
+    const bool want_delta = cfg.los_field == HRT_LOS_DENSITY;
+    L.stack_phi = want_phi ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * T) : off;
+    L.stack_delta = want_delta ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * T) : off;
     L.reps = take((size_t)std::max(cfg.n_replicas, 1) * 9 * 4);      // replica transform rows
     L.total = off;
     return L;
@@ -163,9 +168,9 @@ static int batch_layouts(const hrt_config *cfg, int n_cfg, std::vector<hrt::Step
         const hrt_config &c0 = cfg[0], &c = cfg[r];
         if (c.dtype != c0.dtype || c.n_steps != c0.n_steps || c.flags != c0.flags ||
             (c.ray_nx > 0) != (c0.ray_nx > 0) || c.n_src != c0.n_src ||
-            (c.src_w == nullptr) != (c0.src_w == nullptr)) {
+            (c.src_w == nullptr) != (c0.src_w == nullptr) || c.los_field != c0.los_field) {
             err = "batched configurations must share dtype, n_steps, flags, whether they have rays, "
-                  "n_src and whether they have source weights";
+                  "n_src, whether they have source weights and los_field";
             return HRT_EINVAL;
         }
         hrt::StepTables t;
@@ -243,6 +248,8 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
     c->is_static = (cfg[0].flags & HRT_STATIC) != 0;
     c->has_rays = cfg[0].ray_nx > 0;
     c->jacobian = (cfg[0].flags & HRT_JACOBIAN) != 0;
+    c->delay = (cfg[0].flags & HRT_TIME_DELAY) != 0;
+    c->los = cfg[0].los_field;
     c->n_src = cfg[0].n_src;
     c->n_maps = cfg[0].n_src + (cfg[0].src_w ? 1 : 0);
     c->re.resize(n_cfg);
@@ -256,6 +263,8 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
         re.cfg.src = nullptr;            // copied into the tables (src_step, src_w)
         re.cfg.src_w = nullptr;
         re.cfg.replicas = nullptr;       // copied into the workspace
+        re.cfg.los_chi = nullptr;        // folded into the plane weights
+        re.cfg.los_p = nullptr;
         re.n = cfg[r].mesh_n;
         re.np = cfg[r].ptcl_n;
         re.mx = cfg[r].ray_nx;
@@ -288,7 +297,7 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
         std::vector<hrt::PlaneEntry> pe(re.tab.plane_chi.size());
         for (size_t k = 0; k < pe.size(); ++k)
             pe[k] = hrt::PlaneEntry{re.tab.plane_chi[k], re.tab.plane_w[k], re.tab.plane_mesh[k],
-                                    re.tab.plane_rep[k]};
+                                    re.tab.plane_rep[k], re.tab.plane_los[k]};
         // replica rows (the identity when the configuration has none)
         static const int32_t kIdentity[9] = {0, 1, 2, 1, 1, 1, 0, 0, 0};
         std::vector<int32_t> reps(kIdentity, kIdentity + 9);
@@ -358,6 +367,9 @@ static int check_rays(hrt_ctx *c, const hrt_rays *r, bool need_p, bool need_jac 
             if (!r[k].dth[d]) return fail(c, HRT_EINVAL, "NULL ray deflection array");
             if (need_p && !r[k].p[d]) return fail(c, HRT_EINVAL, "NULL ray momentum array");
         }
+        // a ray step also accumulates the time delay / line-of-sight integral when configured
+        if (need_p && c->delay && !r[k].delay) return fail(c, HRT_EINVAL, "NULL delay array (HRT_TIME_DELAY)");
+        if (need_p && c->los && !r[k].los) return fail(c, HRT_EINVAL, "NULL line-of-sight array (los_field)");
         if (need_jac)
             for (int q = 0; q < 8; ++q)
                 if (!r[k].jac[q]) return fail(c, HRT_EINVAL, "NULL distortion array (HRT_JACOBIAN)");

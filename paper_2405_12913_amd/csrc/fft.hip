@@ -502,7 +502,9 @@ __global__ __launch_bounds__(kThreads) void fd4_gradient_kernel(GradBatch<T> b) 
 template <typename T>
 struct PlaneGradR {
     const T *phi;
+    const T *delta;
     c2<T> *stack;
+    T *sphi, *sdelta;          // scalar lens planes of phi and delta (NULL when not needed)
     const PlaneEntry *planes;
     const int32_t *reps;       // replica rows, 9 values each
     int n, log2n, begin, count, identity;
@@ -529,13 +531,13 @@ __global__ __launch_bounds__(kThreads) void plane_gradient_kernel(PlaneGradBatch
         return phi[(((size_t)(zz & m) * n + (yy & m)) * n) + (xx & m)];
     };
     c2<T> out;
+    int xb[3] = {u, v, w};                     // box node of replica node (u, v, w)
     if (a.identity) {
         out.x = fd4<T>(at(u - 2, v, w), at(u - 1, v, w), at(u + 1, v, w), at(u + 2, v, w), a.inv12cell);
         out.y = fd4<T>(at(u, v - 2, w), at(u, v - 1, w), at(u, v + 1, w), at(u, v + 2, w), a.inv12cell);
     } else {
         const int32_t *row = a.reps + 9 * pe.rep;
         const int uu[3] = {u, v, w};
-        int xb[3];
         for (int ax = 0; ax < 3; ++ax) xb[row[ax]] = row[3 + ax] * uu[ax] + row[6 + row[ax]];
         auto along = [&](int ax, int k) {          // phi at replica node u + k e_ax
             int c[3] = {xb[0], xb[1], xb[2]};
@@ -546,6 +548,9 @@ __global__ __launch_bounds__(kThreads) void plane_gradient_kernel(PlaneGradBatch
         out.y = fd4<T>(along(1, -2), along(1, -1), along(1, 1), along(1, 2), a.inv12cell);
     }
     a.stack[idx] = out;
+    if (a.sphi) a.sphi[idx] = at(xb[0], xb[1], xb[2]);
+    if (a.sdelta)
+        a.sdelta[idx] = a.delta[(((size_t)(xb[2] & m) * n + (xb[1] & m)) * n) + (xb[0] & m)];
 }
 
 template <typename T, int N>
@@ -668,7 +673,11 @@ hipError_t plane_gradient_impl(hrt_ctx *c, int step) {
             const size_t n3 = (size_t)re.n * re.n * re.n;
             PlaneGradR<T> &a = b.r[k];
             a.phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + n3;
+            a.delta = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r);
             a.stack = reinterpret_cast<c2<T> *>(re.ws + re.lay.stack);
+            a.sphi = (c->delay || c->los == HRT_LOS_POTENTIAL) ? reinterpret_cast<T *>(re.ws + re.lay.stack_phi)
+                                                               : nullptr;
+            a.sdelta = c->los == HRT_LOS_DENSITY ? reinterpret_cast<T *>(re.ws + re.lay.stack_delta) : nullptr;
             a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
             a.reps = reinterpret_cast<const int32_t *>(re.ws + re.lay.reps);
             a.identity = re.identity_reps ? 1 : 0;

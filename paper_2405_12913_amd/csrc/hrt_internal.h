@@ -18,6 +18,7 @@ struct StepTables {
     std::vector<int32_t> plane_begin, plane_count;   // N+1 each
     std::vector<int32_t> plane_mesh;         // mesh plane index (j mod n) per entry
     std::vector<int32_t> plane_rep;          // replica transform row per entry
+    std::vector<double> plane_los;           // line-of-sight weight per entry
     int32_t max_count = 0;                   // most planes in one shell
     std::vector<double> plane_chi, plane_w;  // chi_j and weight w_j per entry
     std::vector<int32_t> src_step;           // step boundary of each source plane
@@ -46,12 +47,13 @@ struct PlaneEntry {
     double w;          // kick weight
     int32_t mesh;      // mesh plane index (line-of-sight node index inside its replica)
     int32_t rep;       // replica transform row (0 without a replica table)
+    double los_w;      // weight of the line-of-sight field on this plane (0 without one)
 };
 
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
     size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, stack, reps,
-        total;
+        stack_phi, stack_delta, total;
     int64_t nbins;
 };
 // max_count: most lens planes in one shell (the lens-plane stack holds one shell's planes)
@@ -133,6 +135,8 @@ struct hrt_ctx {
     hipStream_t stream = nullptr;
     int N = 0;                   // shared number of steps
     bool f64 = false, is_static = false, has_rays = false, jacobian = false;
+    bool delay = false;          // HRT_TIME_DELAY
+    int los = 0;                 // line-of-sight field (HRT_LOS_*)
     int n_src = 0, n_maps = 0;   // source planes; map sets per realisation (+1 with weights)
     int force_step = -1;         // boundary of the phi (and G) currently in the workspaces
     bool mesh_g_stale = false;   // after a paint-bin-order hrt_run the G mesh is not current

@@ -30,6 +30,8 @@ struct RayR {                  // one realisation, as the ray kernels see it
     T *jac[8];                 // (A - I)_xx, _xy, _yx, _yy, B_xx, _xy, _yx, _yy (HRT_JACOBIAN)
     const PlaneEntry *planes;
     const c2<T> *stack;        // the step's lens planes: (G_u, G_v) [e - begin][v][u]
+    const T *sphi, *sq;        // scalar lens planes: phi (time delay), Q (line-of-sight field)
+    T *delay, *los;            // accumulated per ray (HRT_TIME_DELAY, los_field)
     T *kappa, *g1, *g2, *om;
     T *akappa, *ag1, *ag2, *aom;   // n_g-weighted sums over the source planes (Eq. obs_accum)
     T aw;                          // weight of this source plane
@@ -61,7 +63,10 @@ __device__ __forceinline__ int ray_of(int b, int t, int mx, int my, int map) {
     return b * kThreads + t;
 }
 
-template <typename T, bool JAC>
+// XT: the time delay (phi planes, weight w_j / chi_j: the Shapiro term -2 Phi_j/c^2 cell)
+// and/or the line-of-sight integral (Q planes, weight los_w_j) are accumulated too; the
+// delay also gets the drift's geometric term p^2 d / 2 with the drift momentum.
+template <typename T, bool JAC, bool XT>
 __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     const int blk = logical_block(b.xcd);
     const int r = real_of(b.map, blk);
@@ -74,6 +79,7 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     const int n = a.n, m = n - 1;
     T ax = 0, ay = 0;
     T j00 = 0, j01 = 0, j10 = 0, j11 = 0;        // d kick / d theta (JAC)
+    T shap = 0, losacc = 0;                      // Shapiro and line-of-sight sums (XT)
     // The kick reads every plane at the step's starting angles, so the planes are
     // independent: kChunk of them have their gathers in flight together, then are added in
     // plane order (the same sums as one plane at a time).
@@ -81,6 +87,8 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     struct Sample {
         c2<T> g00, g01, g10, g11;
         T fx, fy, w, wj;
+        T p00, p01, p10, p11, wd;                // phi corners, w_j / chi_j (XT)
+        T q00, q01, q10, q11, lw;                // Q corners, los_w_j (XT)
     };
     auto fetch = [&](int e, Sample &q) {
         const PlaneEntry pe = a.planes[e];
@@ -98,6 +106,25 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
         q.g01 = plane[(size_t)y0 * n + x1];
         q.g10 = plane[(size_t)y1 * n + x0];
         q.g11 = plane[(size_t)y1 * n + x1];
+        if (XT) {
+            const size_t off = (size_t)(e - a.begin) * n * n;
+            if (a.sphi) {
+                const T *ph = a.sphi + off;
+                q.p00 = ph[(size_t)y0 * n + x0];
+                q.p01 = ph[(size_t)y0 * n + x1];
+                q.p10 = ph[(size_t)y1 * n + x0];
+                q.p11 = ph[(size_t)y1 * n + x1];
+                q.wd = (T)(pe.w / pe.chi);
+            }
+            if (a.sq) {
+                const T *qp = a.sq + off;
+                q.q00 = qp[(size_t)y0 * n + x0];
+                q.q01 = qp[(size_t)y0 * n + x1];
+                q.q10 = qp[(size_t)y1 * n + x0];
+                q.q11 = qp[(size_t)y1 * n + x1];
+                q.lw = (T)pe.los_w;
+            }
+        }
     };
     auto add = [&](const Sample &q) {
         const T fx = q.fx, fy = q.fy;
@@ -107,6 +134,10 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
         const T gy = w00 * q.g00.y + w01 * q.g01.y + w10 * q.g10.y + w11 * q.g11.y;
         ax += q.w * gx;
         ay += q.w * gy;
+        if (XT) {
+            if (a.delay) shap += q.wd * (w00 * q.p00 + w01 * q.p01 + w10 * q.p10 + w11 * q.p11);
+            if (a.los) losacc += q.lw * (w00 * q.q00 + w01 * q.q01 + w10 * q.q10 + w11 * q.q11);
+        }
         if (JAC) {
             // gradient of the bilinear interpolant: differences of the corner values
             const T dxu = (T(1) - fy) * (q.g01.x - q.g00.x) + fy * (q.g11.x - q.g10.x);
@@ -138,6 +169,10 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     a.py[i] = npy;
     a.dthx[i] += a.d * npx;
     a.dthy[i] += a.d * npy;
+    if (XT) {
+        if (a.delay) a.delay[i] += shap + T(0.5) * a.d * (npx * npx + npy * npy);
+        if (a.los) a.los[i] += losacc;
+    }
     if (JAC) {
         // B += J (I + dA), then dA += d B (Eqs. obsv_recurse1-3, half-kicks merged)
         const T d00 = a.jac[0][i], d01 = a.jac[1][i], d10 = a.jac[2][i], d11 = a.jac[3][i];
@@ -215,6 +250,15 @@ void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
     for (int q = 0; q < 8; ++q) a.jac[q] = c->jacobian ? static_cast<T *>(rays.jac[q]) : nullptr;
     a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
     a.stack = reinterpret_cast<const c2<T> *>(re.ws + re.lay.stack);
+    if (c->delay) {
+        a.delay = static_cast<T *>(rays.delay);
+        a.sphi = reinterpret_cast<const T *>(re.ws + re.lay.stack_phi);
+    }
+    if (c->los) {
+        a.los = static_cast<T *>(rays.los);
+        a.sq = reinterpret_cast<const T *>(re.ws + (c->los == HRT_LOS_DENSITY ? re.lay.stack_delta
+                                                                            : re.lay.stack_phi));
+    }
     if (s.src_maps) {
         const hrt_maps &sm = s.src_maps[r], &am = s.acc_maps[r];
         a.kappa = static_cast<T *>(sm.kappa);
@@ -278,8 +322,13 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
         prof_begin(c);
         if (MODE == 1) convergence_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         else if (MODE == 2) convergence_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
-        else if (c->jacobian) ray_step_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
-        else ray_step_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else {
+            const bool xt = c->delay || c->los;
+            if (c->jacobian && xt) ray_step_kernel<T, true, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+            else if (c->jacobian) ray_step_kernel<T, true, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+            else if (xt) ray_step_kernel<T, false, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+            else ray_step_kernel<T, false, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        }
         prof_end(c, CONV ? K_CONVERGENCE : K_RAY_STEP);
     }
     return hipGetLastError();

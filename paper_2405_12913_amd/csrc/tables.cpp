@@ -255,7 +255,21 @@ int validate_config(const hrt_config &c, std::string &err) {
     if ((int64_t)c.ray_nx * c.ray_ny > (int64_t)1 << 26) return bad("too many rays");
     if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
     if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
-    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN)) return bad("unknown flag");
+    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN | HRT_TIME_DELAY)) return bad("unknown flag");
+    if ((c.flags & HRT_TIME_DELAY) && c.ray_nx == 0) return bad("HRT_TIME_DELAY needs rays");
+    if (c.los_field < HRT_LOS_NONE || c.los_field > HRT_LOS_POTENTIAL) return bad("unknown los_field");
+    if (c.los_field != HRT_LOS_NONE) {
+        if (c.ray_nx == 0) return bad("a line-of-sight integral needs rays");
+        if (c.los_n < 2 || !c.los_chi || !c.los_p) return bad("los_n >= 2 knots with los_chi and los_p needed");
+        for (int i = 0; i < c.los_n; ++i) {
+            if (!std::isfinite(c.los_chi[i]) || !std::isfinite(c.los_p[i])) return bad("los knots must be finite");
+            if (i > 0 && !(c.los_chi[i] > c.los_chi[i - 1])) return bad("los_chi must increase");
+        }
+    }
+    if ((c.flags & HRT_ADJOINT) && ((c.flags & HRT_TIME_DELAY) || c.los_field != HRT_LOS_NONE)) {
+        err = "time delay and line-of-sight integrals with HRT_ADJOINT are not supported";
+        return HRT_EUNSUPPORTED;
+    }
     if ((c.flags & HRT_JACOBIAN) && c.ray_nx == 0) return bad("HRT_JACOBIAN needs rays");
     if ((c.flags & HRT_JACOBIAN) && (c.flags & HRT_ADJOINT)) {
         err = "HRT_JACOBIAN with HRT_ADJOINT is not supported";
@@ -303,6 +317,17 @@ int validate_config(const hrt_config &c, std::string &err) {
             if (!(c.sched[i] > 0 && c.sched[i] <= 1)) return bad("a schedule must be in (0, 1]");
     }
     return HRT_OK;
+}
+
+// P(chi) of the line-of-sight integral: linear between the knots, 0 outside them.
+static double los_profile(const hrt_config &c, double chi) {
+    if (chi < c.los_chi[0] || chi > c.los_chi[c.los_n - 1]) return 0.0;
+    for (int i = 1; i < c.los_n; ++i)
+        if (chi <= c.los_chi[i]) {
+            const double t = (chi - c.los_chi[i - 1]) / (c.los_chi[i] - c.los_chi[i - 1]);
+            return c.los_p[i - 1] + t * (c.los_p[i] - c.los_p[i - 1]);
+        }
+    return 0.0;
 }
 
 // Fused leapfrog tables (step n runs boundary n -> n+1; step N is the closing
@@ -383,11 +408,12 @@ int build_tables(const hrt_config &c, StepTables &t, std::string &err) {
         for (int64_t j : js) {
             double cj = (double)j * cell - z_obs;
             if (!(cj > 0.0)) continue;            // r = 0 carries no weight
-            double w;
+            double w, growth = 1.0;               // growth: D1(a_j) / D1(a_n)
             if (stat) {
                 w = sgn * static_pref * cj;
             } else {
                 double aj = cos.a_of_chi(cj);
+                growth = cos.D1(aj) / D1n[n];
                 w = sgn * (-3.0 * c.omega_m * cell * cj * cos.D1(aj)) / (kCH0 * kCH0 * D1n[n] * aj);
             }
             int64_t m = j % c.mesh_n;
@@ -398,8 +424,18 @@ int build_tables(const hrt_config &c, StepTables &t, std::string &err) {
                 rep = k % c.n_replicas;
                 if (rep < 0) rep += c.n_replicas;
             }
+            // line-of-sight weight: P(chi_j) cell times the field's growth correction to
+            // the plane's time (density D1(a_j)/D1(a_n); potential -w_j / (2 chi_j cell), the
+            // kick's Phi/c^2 per unit phi)
+            double lw = 0.0;
+            if (c.los_field != HRT_LOS_NONE) {
+                const double P = los_profile(c, cj);
+                if (c.los_field == HRT_LOS_POTENTIAL) lw = -P * w / (2.0 * cj);
+                else lw = sgn * P * cell * growth;
+            }
             t.plane_mesh.push_back((int32_t)m);
             t.plane_rep.push_back((int32_t)rep);
+            t.plane_los.push_back(lw);
             t.plane_chi.push_back(cj);
             t.plane_w.push_back(w);
         }

@@ -153,6 +153,10 @@ extern "C" int hrt_autotune(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, 
                         c->err = "NULL distortion array (HRT_JACOBIAN)";
                         return HRT_EINVAL;
                     }
+            if ((c->delay && !r[k].delay) || (c->los && !r[k].los)) {
+                c->err = "NULL delay or line-of-sight array";
+                return HRT_EINVAL;
+            }
         }
     std::map<std::string, Entry> cache;
     if (cache_path) cache = read_cache(cache_path);

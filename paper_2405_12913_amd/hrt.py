@@ -17,6 +17,8 @@ HRT_F32, HRT_F64 = 0, 1
 HRT_STATIC = 1
 HRT_ADJOINT = 2
 HRT_JACOBIAN = 4
+HRT_TIME_DELAY = 8
+HRT_LOS_NONE, HRT_LOS_DENSITY, HRT_LOS_POTENTIAL = 0, 1, 2
 HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
 HRT_NUM_KERNELS = 17
@@ -37,7 +39,8 @@ class HrtConfig(ctypes.Structure):
                 ("box", c_double), ("fov_x", c_double), ("fov_y", c_double),
                 ("observer", c_double * 3), ("omega_m", c_double), ("static_mass", c_double),
                 ("sched", POINTER(c_double)), ("src", POINTER(c_double)), ("src_w", POINTER(c_double)),
-                ("replicas", POINTER(c_int32)), ("n_replicas", c_int32)]
+                ("replicas", POINTER(c_int32)), ("n_replicas", c_int32), ("los_field", c_int32),
+                ("los_n", c_int32), ("los_chi", POINTER(c_double)), ("los_p", POINTER(c_double))]
 
 
 class HrtMaps(ctypes.Structure):
@@ -49,7 +52,8 @@ class HrtMatter(ctypes.Structure):
 
 
 class HrtRays(ctypes.Structure):
-    _fields_ = [("dth", c_void_p * 2), ("p", c_void_p * 2), ("jac", c_void_p * 8)]
+    _fields_ = [("dth", c_void_p * 2), ("p", c_void_p * 2), ("jac", c_void_p * 8), ("delay", c_void_p),
+                ("los", c_void_p)]
 
 
 class HrtIcParams(ctypes.Structure):
@@ -125,13 +129,17 @@ def _check(rc, ctx=None):
 
 def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
                 observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0,
-                adjoint=False, src=None, src_w=None, jacobian=False, replicas=None):
+                adjoint=False, src=None, src_w=None, jacobian=False, replicas=None, time_delay=False,
+                los_field=None, los_chi=None, los_p=None):
     """hrt_config from keyword arguments; returns (config, host arrays kept alive).
 
     src: source planes (redshifts, or chi with static=True), each a step boundary;
     src_w: optional weights n_g of the source planes (Eq. obs_accum);
     jacobian: the rays carry the forward-mode distortion (HRT_JACOBIAN);
-    replicas: per-replica transform rows (perm0..2, sign0..2, shift0..2) of the light cone."""
+    replicas: per-replica transform rows (perm0..2, sign0..2, shift0..2) of the light cone;
+    time_delay: the rays accumulate c times the arrival-time delay (HRT_TIME_DELAY);
+    los_field: "density" or "potential" line-of-sight integral with kernel P given by the
+    knots (los_chi, los_p)."""
     sched = np.ascontiguousarray(sched, dtype=np.float64)
     if len(sched) != n_steps + 1:
         raise ValueError("sched must have n_steps + 1 entries")
@@ -140,7 +148,7 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     cfg.n_steps = n_steps
     cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
     cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0) | \
-        (HRT_JACOBIAN if jacobian else 0)
+        (HRT_JACOBIAN if jacobian else 0) | (HRT_TIME_DELAY if time_delay else 0)
     cfg.n_src = 0 if src is None else len(src)
     cfg.box, cfg.fov_x, cfg.fov_y = box, fov_x, fov_y
     for i in range(3):
@@ -165,6 +173,16 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
         cfg.replicas = reps.ctypes.data_as(POINTER(c_int32))
         cfg.n_replicas = len(reps)
         keep.append(reps)
+    if los_field is not None:
+        cfg.los_field = {"density": HRT_LOS_DENSITY, "potential": HRT_LOS_POTENTIAL}[los_field]
+        lc = np.ascontiguousarray(los_chi, dtype=np.float64)
+        lp = np.ascontiguousarray(los_p, dtype=np.float64)
+        if len(lc) != len(lp):
+            raise ValueError("los_chi and los_p must have the same length")
+        cfg.los_n = len(lc)
+        cfg.los_chi = lc.ctypes.data_as(POINTER(c_double))
+        cfg.los_p = lp.ctypes.data_as(POINTER(c_double))
+        keep += [lc, lp]
     return cfg, keep
 
 
@@ -299,10 +317,19 @@ class Simulation:
                 m[k].p[d] = _ptr(pk[d], self.dtype, self.n_particles[k], "p") if pk is not None else None
         return m
 
-    def _rays(self, dth, p=None, jac=None):
-        """jac: per realisation 8 tensors (A - I)_xx, _xy, _yx, _yy, B_xx, _xy, _yx, _yy."""
+    def _rays(self, dth, p=None, jac=None, delay=None, los=None):
+        """jac: per realisation 8 tensors (A - I)_xx, _xy, _yx, _yy, B_xx, _xy, _yx, _yy;
+        delay, los: per realisation one tensor (a tensor for a single realisation)."""
+        import torch
+        one = lambda x: [x] if isinstance(x, torch.Tensor) or x is None else list(x)
+        dl = one(delay) if self.R == 1 else (list(delay) if delay is not None else [None] * self.R)
+        ls = one(los) if self.R == 1 else (list(los) if los is not None else [None] * self.R)
         r = (HrtRays * self.R)()
         for k, (dk, pk, jk) in enumerate(zip(self._per(dth), self._per(p), self._per(jac))):
+            if dl[k] is not None:
+                r[k].delay = _ptr(dl[k], self.dtype, self.n_rays[k], "delay")
+            if ls[k] is not None:
+                r[k].los = _ptr(ls[k], self.dtype, self.n_rays[k], "los")
             for d in range(2):
                 r[k].dth[d] = _ptr(dk[d], self.dtype, self.n_rays[k], "dth")
                 r[k].p[d] = _ptr(pk[d], self.dtype, self.n_rays[k], "p") if pk is not None else None
@@ -317,8 +344,8 @@ class Simulation:
     def pm_step(self, s, p, step):
         _check(lib().pm_step(self.ctx, self._matter(s, p), step), self.ctx)
 
-    def ray_step(self, dth, p, step, jac=None):
-        _check(lib().ray_step(self.ctx, self._rays(dth, p, jac), step), self.ctx)
+    def ray_step(self, dth, p, step, jac=None, delay=None, los=None):
+        _check(lib().ray_step(self.ctx, self._rays(dth, p, jac, delay, los), step), self.ctx)
 
     def observe(self, dth, jac, maps):
         """Maps from the forward-mode distortion (HRT_JACOBIAN): maps is one dict per
@@ -370,18 +397,19 @@ class Simulation:
                         setattr(arr[k * self.n_maps + i], name, _ptr(t, self.dtype, self.n_rays[k], name))
         return arr
 
-    def run(self, s, p, dth, pr, first_step, n_steps, maps=None, jac=None):
+    def run(self, s, p, dth, pr, first_step, n_steps, maps=None, jac=None, delay=None, los=None):
         """Steps [first_step, first_step + n_steps): pm_step + ray_step each (dth, pr may be
         None for matter only); same results as calling them one by one, one pass less.
         maps: observables written at the source planes the steps reach (see _maps);
         jac: the rays' distortion state (HRT_JACOBIAN)."""
-        r = self._rays(dth, pr, jac) if dth is not None else None
+        r = self._rays(dth, pr, jac, delay, los) if dth is not None else None
         _check(lib().hrt_run(self.ctx, self._matter(s, p), r, first_step, n_steps, self._maps(maps)),
                self.ctx)
 
-    def graph_capture(self, s, p, dth, pr, first_step, n_steps, maps=None, jac=None):
+    def graph_capture(self, s, p, dth, pr, first_step, n_steps, maps=None, jac=None, delay=None, los=None):
         """Capture steps [first_step, first_step + n_steps) into one HIP graph."""
-        self._graph_args = (self._matter(s, p), self._rays(dth, pr, jac) if dth is not None else None,
+        self._graph_args = (self._matter(s, p),
+                            self._rays(dth, pr, jac, delay, los) if dth is not None else None,
                             self._maps(maps))
         _check(lib().hrt_graph_capture(self.ctx, self._graph_args[0], self._graph_args[1],
                                        first_step, n_steps, self._graph_args[2]), self.ctx)

@@ -87,7 +87,7 @@ def test_large_config_table_sizes():
 
 @pytest.mark.parametrize("field,value", [("mesh_n", 48), ("mesh_n", 8), ("ptcl_n", 3), ("n_steps", 0),
                                          ("dtype", 7), ("ray_nx", 2), ("n_src", -1), ("n_src", 1),
-                                         ("flags", 8)])
+                                         ("flags", 16), ("los_field", 3), ("n_replicas", 2)])
 def test_invalid_configs_are_rejected(field, value):
     cfg, keep = _cosmo_cfg(np.linspace(1.0, 0.5, 5))
     setattr(cfg, field, value)
@@ -167,3 +167,28 @@ def test_source_planes_must_be_step_boundaries():
                                    src=[1.0])
     with pytest.raises(hrt.HRTError, match="need rays"):
         hrt.hrt_workspace_bytes(norays)
+
+
+def test_los_delay_jacobian_and_replica_validation():
+    a = np.linspace(1.0, 0.5, 9)
+    ok, keep = hrt.make_config(mesh_n=32, box=100.0, ptcl_n=16, n_steps=8, sched=a, ray_nx=8, ray_ny=8,
+                               fov_x=0.02, fov_y=0.02, observer=(50.0, 50.0, 0.0), time_delay=True,
+                               jacobian=True, los_field="density", los_chi=[0.0, 3000.0], los_p=[1.0, 1.0],
+                               replicas=[(2, 0, 1, -1, 1, -1, 3, 0, 31)])
+    assert hrt.hrt_workspace_bytes(ok) > 0
+    bad_cases = [dict(los_field="density", los_chi=[0.0], los_p=[1.0]),
+                 dict(los_field="potential", los_chi=[10.0, 5.0], los_p=[1.0, 1.0]),
+                 dict(replicas=[(0, 0, 1, 1, 1, 1, 0, 0, 0)]),           # not a permutation
+                 dict(replicas=[(0, 1, 2, 1, 2, 1, 0, 0, 0)]),           # sign 2
+                 dict(replicas=[(0, 1, 2, 1, 1, 1, 0, 32, 0)])]          # shift out of range
+    for kw in bad_cases:
+        cfg, keep = hrt.make_config(mesh_n=32, box=100.0, ptcl_n=16, n_steps=8, sched=a, ray_nx=8, ray_ny=8,
+                                    fov_x=0.02, fov_y=0.02, observer=(50.0, 50.0, 0.0), **kw)
+        with pytest.raises(hrt.HRTError, match="status -1"):
+            hrt.hrt_workspace_bytes(cfg)
+    for kw in (dict(time_delay=True), dict(jacobian=True), dict(los_field="density", los_chi=[0, 1e4], los_p=[1, 1]),
+               dict(replicas=[(1, 0, 2, 1, 1, 1, 0, 0, 0)])):
+        cfg, keep = hrt.make_config(mesh_n=32, box=100.0, ptcl_n=16, n_steps=8, sched=a, ray_nx=8, ray_ny=8,
+                                    fov_x=0.02, fov_y=0.02, observer=(50.0, 50.0, 0.0), adjoint=True, **kw)
+        with pytest.raises(hrt.HRTError, match="status -5"):
+            hrt.hrt_workspace_bytes(cfg)

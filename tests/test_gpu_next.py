@@ -135,3 +135,56 @@ def test_sorted_run_with_jacobian_and_replicas_equals_step_by_step():
     corr = float(np.corrcoef(ka, kf)[0, 1])
     say(f"  kappa from A vs finite differences: rel-L2 {rel_l2(kf, ka):.2e}, correlation {corr:.3f}")
     assert corr > 0.5
+
+
+@pytest.mark.parametrize("dtype,field", [("f64", "density"), ("f32", "potential"), ("f32", "density")])
+def test_time_delay_and_los_integral_steps_match_oracle(dtype, field):
+    """Per step against the oracle (GPU state fed back): the increments of the time delay
+    (Eq. eom3) and of a line-of-sight integral (Eq. integral) of the density or the
+    potential with a piecewise-linear kernel, through random replicas. Tolerances as for
+    the deflections: these are plane sums of mesh values (no derivative)."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    from oracle import mesh, tables
+    say(f"case time delay + line-of-sight {field} {dtype}")
+    cfg = synth.tiny(mesh_n=32, ptcl_n=32, box=50.0, ray_n=32, fov_deg=3.0, n_steps=8)
+    c = Case(cfg, seed=8, dtype=dtype, dth_rms=1e-4)
+    table = synth.replica_table(8, 32, 3)
+    knots = ([0.0, 800.0, 2400.0], [0.0, 1.0, 0.3])
+    sim = hrt.Simulation(mesh_n=c.n, box=c.box, ptcl_n=c.np_, n_steps=8, sched=cfg["sched"], ray_nx=c.mx,
+                         ray_ny=c.my, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=cfg["observer"],
+                         omega_m=cfg["omega_m"], dtype=dtype, time_delay=True, los_field=field,
+                         los_chi=knots[0], los_p=knots[1], replicas=table)
+    M = c.mx * c.my
+    T0 = np.zeros(M)                 # both start at zero at the observer: in FP32 an O(1) start
+    O0 = np.zeros(M)                 # would round away the first steps' small increments
+    s, p = c.dev(c.s), c.dev(c.p)
+    dth, pr = c.dev(c.dth), c.dev(c.pr)
+    delay = torch.tensor(T0, dtype=c.tdt, device="cuda")
+    los = torch.tensor(O0, dtype=c.tdt, device="cuda")
+    tab = c.oracle_tables()
+    lw = tables.los_weights(tab, field, knots[0], knots[1], c.box / c.n, cfg["omega_m"])
+    obs = np.array(cfg["observer"])
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    T, O = T0, O0
+    for step in range(4):
+        sim.pm_step(s, p, step)
+        sim.ray_step(dth, pr, step, delay=delay, los=los)
+        torch.cuda.synchronize()
+        grads, delta = integrator.pm_force(c.q + c.s, c.n, c.box)
+        phi = mesh.potential(delta, c.box)
+        q = delta if field == "density" else phi
+        d_o, p_o, T_o, O_o = integrator.ray_step_los(c.dth, c.pr, T, O, c.theta0, grads[0], grads[1],
+                                                     tab.planes[step], tab.d[step], obs[:2], c.box, phi, q,
+                                                     lw[step], grads[2], table)
+        d_g = Case.host(dth)
+        T_g = delay.double().cpu().numpy()
+        O_g = los.double().cpu().numpy()
+        l2, p999, worst = per_ray_errors(d_g, d_o, f"deflection step {step}")
+        assert l2 < tol and p999 < tol
+        for name, g, o, prev in (("delay", T_g, T_o, T), ("los", O_g, O_o, O)):
+            err = rel_l2(g - prev, o - prev)
+            say(f"  {name} change step {step}: rel-L2 {err:.2e}")
+            assert err < tol, (name, step)
+        c.s, c.p = Case.host(s), Case.host(p)
+        c.dth, c.pr, T, O = d_g, Case.host(pr), T_g, O_g
