@@ -309,8 +309,10 @@ def ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, steps):
     """The lcdm256 schedule with the rays' optional features, each against the plain path on
     the same state: the forward-mode distortion recursion (HRT_JACOBIAN, 8 more values per
     ray read and written, the plane-sum derivative), random per-replica transforms of the
-    light cone (lens planes formed through a lattice symmetry and shift), and the time delay
-    with a density line-of-sight integral (two scalar planes per lens plane gathered too)."""
+    light cone (lens planes formed through a lattice symmetry and shift), the time delay
+    with a density line-of-sight integral (two scalar planes per lens plane gathered too),
+    and the paper's kick on the adaptive 2D ray mesh ((iota, p_min) = (0.5, 16): projection,
+    FFT deconvolution and smoothing per step, one bilinear readout per ray)."""
     import synth
     nr = cfg["ray_n"] ** 2
     table = synth.replica_table(0, cfg["mesh_n"], 12)
@@ -318,7 +320,9 @@ def ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, steps):
     los = dict(los_field="density", los_chi=[0.0, 1000.0, 2400.0], los_p=[0.0, 1.0, 0.5])
     for name, kw in (("plain", {}), ("jacobian", {"jacobian": True}), ("replicas", {"replicas": table}),
                      ("jacobian_replicas", {"jacobian": True, "replicas": table}),
-                     ("time_delay_los", dict(time_delay=True, **los))):
+                     ("time_delay_los", dict(time_delay=True, **los)),
+                     ("ray_mesh", {"ray_mesh": (0.5, 16.0)}),
+                     ("ray_mesh_jacobian", {"ray_mesh": (0.5, 16.0), "jacobian": True})):
         s = [t.clone() for t in s_init]
         p = [t.clone() for t in p_init]
         dth = [torch.zeros(nr, device=dev) for _ in range(2)]
@@ -355,6 +359,8 @@ def ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, steps):
         out[name] = {"ms_per_step": round(ms, 4), "ray_steps_per_s": nr / (ms * 1e-3),
                      "ray_step_ms": round(prof["ray_step"][0] / max(prof["ray_step"][1], 1), 5),
                      "lens_planes_ms": round(prof["plane_gradient"][0] / max(prof["plane_gradient"][1], 1), 5)}
+        if "ray_mesh" in kw:
+            out[name]["ray_mesh_ms"] = round(prof["ray_mesh"][0] / max(prof["ray_mesh"][1], 1), 5)
     out["note"] = (f"lcdm256, schedule steps 0..{steps - 1}, same evolved state; 12 random replica "
                    "transforms (synth.replica_table(0, 256, 12)); ray_step_ms and lens_planes_ms "
                    "are per-launch HIP-event averages")

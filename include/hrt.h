@@ -66,6 +66,15 @@ enum {
     HRT_TIME_DELAY = 8,     /* the rays accumulate c times the arrival-time delay (Sec. 2,
                                Eq. eom3: geometric p^2/(2 r^2) and Shapiro -2 Phi/c^2 per
                                unit chi) in hrt_rays.delay [Mpc/h]; not with HRT_ADJOINT   */
+    HRT_RAY_MESH = 16,      /* the paper's kick operator (Sec. 5.2, 5.3, App. C): each
+                               step's shell is projected onto an adaptive 2D ray mesh
+                               (CIC), deconvolved (sinc^-4), smoothed at the resolution limit
+                               of Eq. reslim (Gaussian, negative exponent) and read at the
+                               rays (CIC), instead of the plane-sum readout; mesh spacing
+                               ray_mesh_iota * lam per step, size the smallest power of two
+                               (<= 2048, else HRT_EUNSUPPORTED) that holds the field plus
+                               ray_mesh_pmin * lam of padding at every step. Not with
+                               HRT_ADJOINT, HRT_TIME_DELAY or a line-of-sight integral    */
     HRT_JACOBIAN = 4        /* the rays carry the forward-mode distortion recursion of
                                Sec. 4 (Eqs. A, B, obsv_recurse1-3; Alg. 1 iterate_A,
                                iterate_B): hrt_rays.jac required by ray_step; source-plane
@@ -121,6 +130,8 @@ typedef struct {
     const double *los_chi;  /* los_n increasing chi [Mpc/h]; P is linear between knots and
                                0 outside them                                             */
     const double *los_p;    /* los_n values of P; both copied at init                      */
+    double ray_mesh_iota;   /* HRT_RAY_MESH: accuracy parameter iota, 0 < iota <= 1       */
+    double ray_mesh_pmin;   /* HRT_RAY_MESH: minimum padding p_min >= 0 in units of lam   */
 } hrt_config;
 
 enum { HRT_LOS_NONE = 0, HRT_LOS_DENSITY = 1, HRT_LOS_POTENTIAL = 2 };
@@ -366,7 +377,7 @@ int hrt_autotune(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int step,
  * clears the totals and starts recording, 0 stops. hrt_profile_read synchronises the
  * stream and writes, for kernel ids 0..n-1, the summed milliseconds and launch counts.
  * hrt_kernel_name(id) names kernel id (NULL past the last id, HRT_NUM_KERNELS). */
-enum { HRT_NUM_KERNELS = 17 };
+enum { HRT_NUM_KERNELS = 18 };
 int hrt_profile_enable(hrt_ctx *ctx, int on);
 int hrt_profile_read(hrt_ctx *ctx, double *total_ms, int64_t *launches, int n);
 const char *hrt_kernel_name(int id);

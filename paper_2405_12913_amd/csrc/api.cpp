@@ -16,7 +16,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count) {
+Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count, int64_t rm_n) {
     Layout L{};
     const size_t T = cfg.dtype == HRT_F64 ? 8 : 4;
     const size_t n = (size_t)cfg.mesh_n;
@@ -52,6 +52,9 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_c
     L.stack_phi = want_phi ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * T) : off;
     L.stack_delta = want_delta ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * T) : off;
     L.reps = take((size_t)std::max(cfg.n_replicas, 1) * 9 * 4);      // replica transform rows
+    // ray mesh: the complex kick field (N^2) and its twiddles W_N^m (N)
+    L.rm_mesh = rm_n > 0 ? take((size_t)rm_n * rm_n * 2 * T) : off;
+    L.rm_tw = rm_n > 0 ? take((size_t)rm_n * 2 * T) : off;
     L.total = off;
     return L;
 }
@@ -118,7 +121,7 @@ hrt_ctx::~hrt_ctx() {
 static const char *kKernelNames[hrt::K_COUNT] = {
     "bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
     "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd", "ray_step",
-    "convergence", "state_scatter", "kd_tiles", "plane_gradient", "state_gather"};
+    "convergence", "state_scatter", "kd_tiles", "plane_gradient", "state_gather", "ray_mesh"};
 
 extern "C" const char *hrt_kernel_name(int id) {
     return (id >= 0 && id < hrt::K_COUNT) ? kKernelNames[id] : nullptr;
@@ -176,7 +179,7 @@ static int batch_layouts(const hrt_config *cfg, int n_cfg, std::vector<hrt::Step
         hrt::StepTables t;
         int rc = hrt::build_tables(c, t, err);
         if (rc) return rc;
-        lays.push_back(hrt::make_layout(c, (int64_t)t.plane_chi.size(), t.max_count));
+        lays.push_back(hrt::make_layout(c, (int64_t)t.plane_chi.size(), t.max_count, t.rm_n));
         if (tabs) (*tabs)[r] = std::move(t);
     }
     return HRT_OK;
@@ -249,6 +252,7 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
     c->has_rays = cfg[0].ray_nx > 0;
     c->jacobian = (cfg[0].flags & HRT_JACOBIAN) != 0;
     c->delay = (cfg[0].flags & HRT_TIME_DELAY) != 0;
+    c->ray_mesh = (cfg[0].flags & HRT_RAY_MESH) != 0;
     c->los = cfg[0].los_field;
     c->n_src = cfg[0].n_src;
     c->n_maps = cfg[0].n_src + (cfg[0].src_w ? 1 : 0);
@@ -313,6 +317,25 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
         if (e == hipSuccess)
             e = hipMemcpyAsync(re.ws + re.lay.reps, reps.data(), reps.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream);
+        // ray-mesh twiddles W_N^m = exp(-2 pi i m / N)
+        std::vector<char> rmtw;
+        if (re.tab.rm_n > 0) {
+            const int N = re.tab.rm_n;
+            rmtw.resize((size_t)2 * N * (c->f64 ? 8 : 4));
+            for (int m = 0; m < N; ++m) {
+                const double ang = -2.0 * 3.14159265358979323846 * m / N;
+                if (c->f64) {
+                    reinterpret_cast<double *>(rmtw.data())[2 * m] = std::cos(ang);
+                    reinterpret_cast<double *>(rmtw.data())[2 * m + 1] = std::sin(ang);
+                } else {
+                    reinterpret_cast<float *>(rmtw.data())[2 * m] = (float)std::cos(ang);
+                    reinterpret_cast<float *>(rmtw.data())[2 * m + 1] = (float)std::sin(ang);
+                }
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(re.ws + re.lay.rm_tw, rmtw.data(), rmtw.size(), hipMemcpyHostToDevice,
+                                   c->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
     if (e != hipSuccess) {
@@ -416,6 +439,10 @@ extern "C" int ray_step(hrt_ctx *c, const hrt_rays *r, int step) {
     a.r = r;
     a.step = step;
     if (int rc = check_hip(c, hrt::launch_plane_gradient(c, step), "lens planes")) return rc;
+    if (c->ray_mesh) {
+        if (int rc = check_hip(c, hrt::launch_ray_mesh(c, step), "ray mesh")) return rc;
+        return check_hip(c, hrt::launch_ray_mesh_step(c, a), "ray step (ray mesh)");
+    }
     return check_hip(c, hrt::launch_ray_step(c, a), "ray step");
 }
 

@@ -698,6 +698,181 @@ hipError_t plane_gradient_impl(hrt_ctx *c, int step) {
 }
 
 // ---------------------------------------------------------------------------------------
+// The kick operator on the 2D ray mesh (Sec. 5.2, 5.3, App. C; HRT_RAY_MESH). The mesh is
+// square, N x N complex (x = kick along u, y = along v), node k at angle (k - N/2) mu.
+//   rm_paint   each mesh node pulls, from every lens plane of the shell, the plane nodes
+//              whose projected angle (X - X_obs) / chi_j lies within one mesh cell of it,
+//              with CIC weights, the plane's kick weight and the solid-angle ratio
+//              (cell / chi_j)^2 / mu^2 (a fixed summation order: no atomics, exact reruns)
+//   rm_rows    forward FFT of every row (x)
+//   rm_cols    forward FFT of every column (y), times sinc(k_x mu/2)^-4 sinc(k_y mu/2)^-4
+//              exp(-(k_x^2 + k_y^2) lam^2 / 2), inverse FFT of the column
+//   rm_rows    inverse FFT of every row, scaled by 1 / N^2
+// Every pass keeps whole lines in LDS (the Stockham stages of fft_stage).
+struct RmArgs {
+    void *mesh;                // N^2 complex of the dtype
+    const void *tw;            // N twiddles W_N^m
+    const void *stack;         // the step's lens planes (G_u, G_v) [e][v][u]
+    const PlaneEntry *planes;
+    int begin, count, n, N;
+    double mu, lam, cell, obsx, obsy;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void rm_paint_kernel(RmArgs a) {
+    const int N = a.N;
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int kx = (int)(idx % N), ky = (int)(idx / N);
+    const double t0 = -0.5 * N * a.mu;
+    const double tx = t0 + kx * a.mu, ty = t0 + ky * a.mu;
+    const c2<T> *stack = static_cast<const c2<T> *>(a.stack);
+    const int n = a.n, m = n - 1;
+    double su = 0.0, sv = 0.0;
+    for (int e = 0; e < a.count; ++e) {
+        const PlaneEntry pe = a.planes[a.begin + e];
+        const double chi = pe.chi;
+        const double scale = pe.w * (a.cell / chi) * (a.cell / chi) / (a.mu * a.mu);
+        const c2<T> *pl = stack + (size_t)e * n * n;
+        // plane nodes i with |(i cell - X_obs) / chi - t| < mu, along each axis
+        const int ix0 = (int)floor((a.obsx + chi * (tx - a.mu)) / a.cell);
+        const int ix1 = (int)ceil((a.obsx + chi * (tx + a.mu)) / a.cell);
+        const int iy0 = (int)floor((a.obsy + chi * (ty - a.mu)) / a.cell);
+        const int iy1 = (int)ceil((a.obsy + chi * (ty + a.mu)) / a.cell);
+        for (int iy = iy0; iy <= iy1; ++iy) {
+            const double uy = (((double)iy * a.cell - a.obsy) / chi - t0) / a.mu;
+            const double wy = 1.0 - fabs(uy - ky);
+            if (!(wy > 0.0)) continue;
+            const c2<T> *row = pl + (size_t)(iy & m) * n;
+            for (int ix = ix0; ix <= ix1; ++ix) {
+                const double ux = (((double)ix * a.cell - a.obsx) / chi - t0) / a.mu;
+                const double wx = 1.0 - fabs(ux - kx);
+                if (!(wx > 0.0)) continue;
+                const c2<T> g = row[ix & m];
+                const double wgt = scale * wx * wy;
+                su += wgt * (double)g.x;
+                sv += wgt * (double)g.y;
+            }
+        }
+    }
+    static_cast<c2<T> *>(a.mesh)[idx] = c2<T>{(T)su, (T)sv};
+}
+
+// Lines per workgroup of the ray-mesh passes: at most 32 KB of lines in LDS (plus the
+// twiddle table), at most 8 lines.
+template <typename T, int N>
+__host__ __device__ constexpr int rm_lines() {
+    constexpr int b = 32768 / (N * (int)sizeof(c2<T>));
+    return b < 1 ? 1 : (b > 8 ? 8 : b);
+}
+
+// Rows: LINES consecutive rows per workgroup. INV: inverse transform scaled by 1 / N^2.
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(kThreads) void rm_rows_kernel(RmArgs a) {
+    constexpr int LINES = rm_lines<T, N>();
+    __shared__ c2<T> buf[LINES * N];
+    __shared__ c2<T> tw[N];
+    c2<T> *mesh = static_cast<c2<T> *>(a.mesh);
+    const c2<T> *gtw = static_cast<const c2<T> *>(a.tw);
+    const size_t base = (size_t)blockIdx.x * LINES * N;
+    for (int i = threadIdx.x; i < N; i += kThreads) tw[i] = gtw[i];
+    for (int i = threadIdx.x; i < LINES * N; i += kThreads) buf[i] = mesh[base + i];
+    __syncthreads();
+    fft_stage<T, N, LINES, INV, 1>(buf, N, tw, 1);
+    const T sc = INV ? (T)(1.0 / ((double)N * N)) : T(1);
+    for (int i = threadIdx.x; i < LINES * N; i += kThreads) {
+        c2<T> v = buf[i];
+        if (INV) v = c2<T>{v.x * sc, v.y * sc};
+        mesh[base + i] = v;
+    }
+}
+
+// Columns: LINES consecutive columns per workgroup; forward FFT, the filter, inverse FFT.
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void rm_cols_kernel(RmArgs a) {
+    constexpr int LINES = rm_lines<T, N>();
+    __shared__ c2<T> buf[LINES * N];
+    __shared__ c2<T> tw[N];
+    c2<T> *mesh = static_cast<c2<T> *>(a.mesh);
+    const c2<T> *gtw = static_cast<const c2<T> *>(a.tw);
+    const int col0 = blockIdx.x * LINES;
+    for (int i = threadIdx.x; i < N; i += kThreads) tw[i] = gtw[i];
+    for (int i = threadIdx.x; i < LINES * N; i += kThreads) {
+        const int line = i % LINES, y = i / LINES;          // consecutive lanes: adjacent columns
+        buf[line * N + y] = mesh[(size_t)y * N + col0 + line];
+    }
+    __syncthreads();
+    fft_stage<T, N, LINES, false, 1>(buf, N, tw, 1);
+    const double kf = 2.0 * 3.14159265358979323846 / (N * a.mu);
+    for (int i = threadIdx.x; i < LINES * N; i += kThreads) {
+        const int line = i / N, y = i % N;
+        const int fx = col0 + line, fy = y;
+        const double kx = kf * (fx < N / 2 ? fx : fx - N), ky = kf * (fy < N / 2 ? fy : fy - N);
+        const double hx = 0.5 * kx * a.mu, hy = 0.5 * ky * a.mu;
+        const double sx = hx == 0.0 ? 1.0 : sin(hx) / hx, sy = hy == 0.0 ? 1.0 : sin(hy) / hy;
+        const double s2x = sx * sx, s2y = sy * sy;
+        const double h = exp(-0.5 * (kx * kx + ky * ky) * a.lam * a.lam) / (s2x * s2x * s2y * s2y);
+        const c2<T> v = buf[i];
+        buf[i] = c2<T>{(T)((double)v.x * h), (T)((double)v.y * h)};
+    }
+    __syncthreads();
+    fft_stage<T, N, LINES, true, 1>(buf, N, tw, 1);
+    for (int i = threadIdx.x; i < LINES * N; i += kThreads) {
+        const int line = i % LINES, y = i / LINES;
+        mesh[(size_t)y * N + col0 + line] = buf[line * N + y];
+    }
+}
+
+template <typename T, int N>
+hipError_t ray_mesh_n(hrt_ctx *c, const RmArgs &a) {
+    constexpr int LINES = rm_lines<T, N>();
+    rm_rows_kernel<T, N, false><<<N / LINES, kThreads, 0, c->stream>>>(a);
+    rm_cols_kernel<T, N><<<N / LINES, kThreads, 0, c->stream>>>(a);
+    rm_rows_kernel<T, N, true><<<N / LINES, kThreads, 0, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t ray_mesh_impl(hrt_ctx *c, int step) {
+    for (size_t r = 0; r < c->re.size(); ++r) {
+        const Real &re = c->re[r];
+        RmArgs a{};
+        a.mesh = re.ws + re.lay.rm_mesh;
+        a.tw = re.ws + re.lay.rm_tw;
+        a.stack = re.ws + re.lay.stack;
+        a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
+        a.begin = re.tab.plane_begin[step];
+        a.count = re.tab.plane_count[step];
+        a.n = re.n;
+        a.N = re.tab.rm_n;
+        a.mu = re.tab.rm_mu[step];
+        a.lam = re.tab.rm_lam[step];
+        a.cell = re.cell;
+        a.obsx = re.cfg.observer[0];
+        a.obsy = re.cfg.observer[1];
+        if (a.count == 0) continue;              // no planes: the ray step adds no kick
+        const int64_t nodes = (int64_t)a.N * a.N;
+        prof_begin(c);
+        rm_paint_kernel<T><<<(int)((nodes + kThreads - 1) / kThreads), kThreads, 0, c->stream>>>(a);
+        hipError_t e = hipSuccess;
+        switch (a.N) {
+            case 16: e = ray_mesh_n<T, 16>(c, a); break;
+            case 32: e = ray_mesh_n<T, 32>(c, a); break;
+            case 64: e = ray_mesh_n<T, 64>(c, a); break;
+            case 128: e = ray_mesh_n<T, 128>(c, a); break;
+            case 256: e = ray_mesh_n<T, 256>(c, a); break;
+            case 512: e = ray_mesh_n<T, 512>(c, a); break;
+            case 1024: e = ray_mesh_n<T, 1024>(c, a); break;
+            case 2048: e = ray_mesh_n<T, 2048>(c, a); break;
+            default: e = hipErrorInvalidValue;
+        }
+        prof_end(c, K_RAY_MESH);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Initial conditions: Gaussian field with the Eisenstein-Hu no-wiggle spectrum and its
 // 2LPT displacements (standard recipe; the paper starts from 2LPT at a = 1/64, Sec. 6.2).
 // Spectra use the transposed layout [kx][kz][ky] left by the forward passes. Derivatives
@@ -999,6 +1174,10 @@ hipError_t launch_gradient(hrt_ctx *c) {
 
 hipError_t launch_plane_gradient(hrt_ctx *c, int step) {
     return c->f64 ? plane_gradient_impl<double>(c, step) : plane_gradient_impl<float>(c, step);
+}
+
+hipError_t launch_ray_mesh(hrt_ctx *c, int step) {
+    return c->f64 ? ray_mesh_impl<double>(c, step) : ray_mesh_impl<float>(c, step);
 }
 
 }  // namespace hrt

@@ -21,6 +21,8 @@ struct StepTables {
     std::vector<double> plane_los;           // line-of-sight weight per entry
     int32_t max_count = 0;                   // most planes in one shell
     std::vector<double> plane_chi, plane_w;  // chi_j and weight w_j per entry
+    std::vector<double> rm_lam, rm_mu;       // ray mesh (HRT_RAY_MESH): resolution limit and
+    int32_t rm_n = 0;                        //   spacing per step; the run's mesh size
     std::vector<int32_t> src_step;           // step boundary of each source plane
     std::vector<double> src_w;               // n_g weights (Eq. obs_accum), if has_src_w
     bool has_src_w = false;
@@ -53,17 +55,18 @@ struct PlaneEntry {
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
     size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, stack, reps,
-        stack_phi, stack_delta, total;
+        stack_phi, stack_delta, rm_mesh, rm_tw, total;
     int64_t nbins;
 };
-// max_count: most lens planes in one shell (the lens-plane stack holds one shell's planes)
-Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count);
+// max_count: most lens planes in one shell (the lens-plane stack holds one shell's planes);
+// rm_n: ray-mesh size (0 without HRT_RAY_MESH)
+Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count, int64_t rm_n);
 
 // Kernel ids for the optional per-kernel HIP-event timing (hrt_profile_*).
 enum KernelId {
     K_BIN_COUNT = 0, K_BIN_SCAN, K_BIN_SCATTER, K_PAINT, K_FFT_X_R2C, K_FFT_Y_FWD, K_FFT_Z_POISSON,
     K_FFT_Y_INV, K_FFT_X_C2R, K_GRADIENT, K_MATTER_KD, K_RAY_STEP, K_CONVERGENCE,
-    K_STATE_SCATTER, K_KD_TILES, K_PLANE_GRADIENT, K_STATE_GATHER, K_COUNT
+    K_STATE_SCATTER, K_KD_TILES, K_PLANE_GRADIENT, K_STATE_GATHER, K_RAY_MESH, K_COUNT
 };
 struct ProfRecord {
     int id;
@@ -136,6 +139,7 @@ struct hrt_ctx {
     int N = 0;                   // shared number of steps
     bool f64 = false, is_static = false, has_rays = false, jacobian = false;
     bool delay = false;          // HRT_TIME_DELAY
+    bool ray_mesh = false;       // HRT_RAY_MESH
     int los = 0;                 // line-of-sight field (HRT_LOS_*)
     int n_src = 0, n_maps = 0;   // source planes; map sets per realisation (+1 with weights)
     int force_step = -1;         // boundary of the phi (and G) currently in the workspaces
@@ -185,6 +189,10 @@ hipError_t launch_plane_gradient(hrt_ctx *c, int step);      // the step's lens-
 hipError_t launch_state_gather(hrt_ctx *c, const StepArgs &a);   // sorted state -> caller
 hipError_t launch_matter_kd(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
+// HRT_RAY_MESH: the step's kick on the 2D ray mesh (projection of the lens-plane stack,
+// FFT deconvolution and smoothing), then the readout / drift kernel for the rays
+hipError_t launch_ray_mesh(hrt_ctx *c, int step);
+hipError_t launch_ray_mesh_step(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_convergence(hrt_ctx *c, const StepArgs &a, bool from_a = false);
 hipError_t launch_ic(hrt_ctx *c, int realisation, const void *noise, const IcParams &p,
                      const hrt_matter *m);

@@ -32,6 +32,9 @@ struct RayR {                  // one realisation, as the ray kernels see it
     const c2<T> *stack;        // the step's lens planes: (G_u, G_v) [e - begin][v][u]
     const T *sphi, *sq;        // scalar lens planes: phi (time delay), Q (line-of-sight field)
     T *delay, *los;            // accumulated per ray (HRT_TIME_DELAY, los_field)
+    const c2<T> *rm;           // the step's filtered ray-mesh kick (HRT_RAY_MESH), N x N
+    int rm_n;
+    double rm_mu;
     T *kappa, *g1, *g2, *om;
     T *akappa, *ag1, *ag2, *aom;   // n_g-weighted sums over the source planes (Eq. obs_accum)
     T aw;                          // weight of this source plane
@@ -191,6 +194,61 @@ __global__ __launch_bounds__(kThreads) void ray_step_kernel(RayBatch<T> b) {
     }
 }
 
+// The kick read from the step's ray mesh (HRT_RAY_MESH, Sec. 5.2: CIC readout at the rays'
+// current angles), then the drift; JAC: J is the derivative of that bilinear readout
+// (differences of the corner values / mu). Rays stay inside the mesh by its padding; the
+// cell index is clamped to the mesh all the same. A step without lens planes adds no kick.
+template <typename T, bool JAC>
+__global__ __launch_bounds__(kThreads) void ray_mesh_step_kernel(RayBatch<T> b) {
+    const int blk = logical_block(b.xcd);
+    const int r = real_of(b.map, blk);
+    const RayR<T> &a = b.r[r];
+    const int i = ray_of(blk - b.map.start[r], threadIdx.x, a.mx, a.my, b.rmap);
+    if (i >= a.nrays) return;
+    T ax = 0, ay = 0, j00 = 0, j01 = 0, j10 = 0, j11 = 0;
+    if (a.count > 0) {
+        const int ix = i % a.mx, iy = i / a.mx, N = a.rm_n;
+        const double thx = ((ix + 0.5) - a.half_mx) * a.mux + (double)a.dthx[i];
+        const double thy = ((iy + 0.5) - a.half_my) * a.muy + (double)a.dthy[i];
+        const double ux = (thx + 0.5 * N * a.rm_mu) / a.rm_mu, uy = (thy + 0.5 * N * a.rm_mu) / a.rm_mu;
+        const int kx = min(max((int)floor(ux), 0), N - 2), ky = min(max((int)floor(uy), 0), N - 2);
+        const T fx = (T)fmin(fmax(ux - kx, 0.0), 1.0), fy = (T)fmin(fmax(uy - ky, 0.0), 1.0);
+        const c2<T> c00 = a.rm[(size_t)ky * N + kx], c01 = a.rm[(size_t)ky * N + kx + 1];
+        const c2<T> c10 = a.rm[(size_t)(ky + 1) * N + kx], c11 = a.rm[(size_t)(ky + 1) * N + kx + 1];
+        const T w00 = (T(1) - fx) * (T(1) - fy), w01 = fx * (T(1) - fy);
+        const T w10 = (T(1) - fx) * fy, w11 = fx * fy;
+        ax = w00 * c00.x + w01 * c01.x + w10 * c10.x + w11 * c11.x;
+        ay = w00 * c00.y + w01 * c01.y + w10 * c10.y + w11 * c11.y;
+        if (JAC) {
+            const T inv = (T)(1.0 / a.rm_mu);
+            j00 = ((T(1) - fy) * (c01.x - c00.x) + fy * (c11.x - c10.x)) * inv;
+            j01 = ((T(1) - fx) * (c10.x - c00.x) + fx * (c11.x - c01.x)) * inv;
+            j10 = ((T(1) - fy) * (c01.y - c00.y) + fy * (c11.y - c10.y)) * inv;
+            j11 = ((T(1) - fx) * (c10.y - c00.y) + fx * (c11.y - c01.y)) * inv;
+        }
+    }
+    const T npx = a.px[i] + ax, npy = a.py[i] + ay;
+    a.px[i] = npx;
+    a.py[i] = npy;
+    a.dthx[i] += a.d * npx;
+    a.dthy[i] += a.d * npy;
+    if (JAC) {
+        const T d00 = a.jac[0][i], d01 = a.jac[1][i], d10 = a.jac[2][i], d11 = a.jac[3][i];
+        const T b00 = a.jac[4][i] + (j00 * (T(1) + d00) + j01 * d10);
+        const T b01 = a.jac[5][i] + (j00 * d01 + j01 * (T(1) + d11));
+        const T b10 = a.jac[6][i] + (j10 * (T(1) + d00) + j11 * d10);
+        const T b11 = a.jac[7][i] + (j10 * d01 + j11 * (T(1) + d11));
+        a.jac[4][i] = b00;
+        a.jac[5][i] = b01;
+        a.jac[6][i] = b10;
+        a.jac[7][i] = b11;
+        a.jac[0][i] = d00 + a.d * b00;
+        a.jac[1][i] = d01 + a.d * b01;
+        a.jac[2][i] = d10 + a.d * b10;
+        a.jac[3][i] = d11 + a.d * b11;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T fd(const T *f, int i, int k, int mk, int stride) {
     if (k == 0) return T(-3) * f[i] + T(4) * f[i + stride] - f[i + 2 * stride];
@@ -250,6 +308,11 @@ void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
     for (int q = 0; q < 8; ++q) a.jac[q] = c->jacobian ? static_cast<T *>(rays.jac[q]) : nullptr;
     a.planes = reinterpret_cast<const PlaneEntry *>(re.ws + re.lay.planes);
     a.stack = reinterpret_cast<const c2<T> *>(re.ws + re.lay.stack);
+    if (c->ray_mesh) {
+        a.rm = reinterpret_cast<const c2<T> *>(re.ws + re.lay.rm_mesh);
+        a.rm_n = re.tab.rm_n;
+        a.rm_mu = re.tab.rm_mu[s.step];
+    }
     if (c->delay) {
         a.delay = static_cast<T *>(rays.delay);
         a.sphi = reinterpret_cast<const T *>(re.ws + re.lay.stack_phi);
@@ -298,10 +361,11 @@ void fill_rays(hrt_ctx *c, int r, const StepArgs &s, int k, RayR<T> &a) {
     (void)k;
 }
 
-// MODE: 0 = ray step, 1 = maps from finite differences, 2 = maps from A
+// MODE: 0 = ray step, 1 = maps from finite differences, 2 = maps from A, 3 = ray step with
+// the ray-mesh kick
 template <typename T, int MODE>
 hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
-    constexpr bool CONV = MODE != 0;
+    constexpr bool CONV = MODE == 1 || MODE == 2;
     const int nre = (int)c->re.size();
     for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
         const int R = std::min(kMaxBatch, nre - r0);
@@ -322,6 +386,8 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
         prof_begin(c);
         if (MODE == 1) convergence_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         else if (MODE == 2) convergence_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else if (MODE == 3 && c->jacobian) ray_mesh_step_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        else if (MODE == 3) ray_mesh_step_kernel<T, false><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
         else {
             const bool xt = c->delay || c->los;
             if (c->jacobian && xt) ray_step_kernel<T, true, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
@@ -338,6 +404,10 @@ hipError_t rays_impl(hrt_ctx *c, const StepArgs &s) {
 
 hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &s) {
     return c->f64 ? rays_impl<double, 0>(c, s) : rays_impl<float, 0>(c, s);
+}
+
+hipError_t launch_ray_mesh_step(hrt_ctx *c, const StepArgs &s) {
+    return c->f64 ? rays_impl<double, 3>(c, s) : rays_impl<float, 3>(c, s);
 }
 
 hipError_t launch_convergence(hrt_ctx *c, const StepArgs &s, bool from_a) {

@@ -255,7 +255,17 @@ int validate_config(const hrt_config &c, std::string &err) {
     if ((int64_t)c.ray_nx * c.ray_ny > (int64_t)1 << 26) return bad("too many rays");
     if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
     if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
-    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN | HRT_TIME_DELAY)) return bad("unknown flag");
+    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN | HRT_TIME_DELAY | HRT_RAY_MESH))
+        return bad("unknown flag");
+    if (c.flags & HRT_RAY_MESH) {
+        if (c.ray_nx == 0) return bad("HRT_RAY_MESH needs rays");
+        if (!(c.ray_mesh_iota > 0 && c.ray_mesh_iota <= 1)) return bad("ray_mesh_iota must be in (0, 1]");
+        if (!(c.ray_mesh_pmin >= 0) || !std::isfinite(c.ray_mesh_pmin)) return bad("ray_mesh_pmin must be >= 0");
+        if ((c.flags & (HRT_ADJOINT | HRT_TIME_DELAY)) || c.los_field != HRT_LOS_NONE) {
+            err = "HRT_RAY_MESH with HRT_ADJOINT, HRT_TIME_DELAY or a line-of-sight integral is not supported";
+            return HRT_EUNSUPPORTED;
+        }
+    }
     if ((c.flags & HRT_TIME_DELAY) && c.ray_nx == 0) return bad("HRT_TIME_DELAY needs rays");
     if (c.los_field < HRT_LOS_NONE || c.los_field > HRT_LOS_POTENTIAL) return bad("unknown los_field");
     if (c.los_field != HRT_LOS_NONE) {
@@ -368,6 +378,30 @@ int build_tables(const hrt_config &c, StepTables &t, std::string &err) {
         }
     }
     if (c.ray_nx == 0) return HRT_OK;
+    // ray mesh (Sec. 5.2-5.3, App. C): per step lam = max(2 cell / (r_a + r_b), mu_2D) over
+    // the kick's shell [chi_{n-1/2}, chi_{n+1/2}], spacing iota lam, and one mesh size for the
+    // run: the smallest power of two with N mu >= field + p_min lam at every step
+    if (c.flags & HRT_RAY_MESH) {
+        const double mu2d = std::max(c.fov_x / c.ray_nx, c.fov_y / c.ray_ny);
+        const double field = std::max(c.fov_x, c.fov_y);
+        t.rm_lam.assign(N + 1, 0.0);
+        t.rm_mu.assign(N + 1, 0.0);
+        int64_t size = 16;
+        for (int n = 0; n <= N; ++n) {
+            const double lo = std::fabs(n == 0 ? t.chi[0] : 0.5 * (t.chi[n - 1] + t.chi[n]));
+            const double hi = std::fabs(n == N ? t.chi[N] : 0.5 * (t.chi[n] + t.chi[n + 1]));
+            const double lam = lo + hi > 0 ? std::max(2.0 * cell / (lo + hi), mu2d) : mu2d;
+            t.rm_lam[n] = lam;
+            t.rm_mu[n] = c.ray_mesh_iota * lam;
+            const double need = field / t.rm_mu[n] + c.ray_mesh_pmin / c.ray_mesh_iota;
+            if (!(need <= 2048.0)) {
+                err = "the ray mesh would need more than 2048 points per side";
+                return HRT_EUNSUPPORTED;
+            }
+            while ((double)size < need) size *= 2;
+        }
+        t.rm_n = (int32_t)size;
+    }
     // source planes: each must sit on a step boundary 1..N of the schedule (Alg. 1 observes
     // the rays at the end of a step)
     t.src_step.assign(c.n_src, -1);

@@ -18,10 +18,11 @@ HRT_STATIC = 1
 HRT_ADJOINT = 2
 HRT_JACOBIAN = 4
 HRT_TIME_DELAY = 8
+HRT_RAY_MESH = 16
 HRT_LOS_NONE, HRT_LOS_DENSITY, HRT_LOS_POTENTIAL = 0, 1, 2
 HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
 
-HRT_NUM_KERNELS = 17
+HRT_NUM_KERNELS = 18
 HRT_NOALLOC_MAX_BYTES = 67108864
 
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
@@ -40,7 +41,8 @@ class HrtConfig(ctypes.Structure):
                 ("observer", c_double * 3), ("omega_m", c_double), ("static_mass", c_double),
                 ("sched", POINTER(c_double)), ("src", POINTER(c_double)), ("src_w", POINTER(c_double)),
                 ("replicas", POINTER(c_int32)), ("n_replicas", c_int32), ("los_field", c_int32),
-                ("los_n", c_int32), ("los_chi", POINTER(c_double)), ("los_p", POINTER(c_double))]
+                ("los_n", c_int32), ("los_chi", POINTER(c_double)), ("los_p", POINTER(c_double)),
+                ("ray_mesh_iota", c_double), ("ray_mesh_pmin", c_double)]
 
 
 class HrtMaps(ctypes.Structure):
@@ -130,7 +132,7 @@ def _check(rc, ctx=None):
 def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
                 observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0,
                 adjoint=False, src=None, src_w=None, jacobian=False, replicas=None, time_delay=False,
-                los_field=None, los_chi=None, los_p=None):
+                los_field=None, los_chi=None, los_p=None, ray_mesh=None):
     """hrt_config from keyword arguments; returns (config, host arrays kept alive).
 
     src: source planes (redshifts, or chi with static=True), each a step boundary;
@@ -139,7 +141,8 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     replicas: per-replica transform rows (perm0..2, sign0..2, shift0..2) of the light cone;
     time_delay: the rays accumulate c times the arrival-time delay (HRT_TIME_DELAY);
     los_field: "density" or "potential" line-of-sight integral with kernel P given by the
-    knots (los_chi, los_p)."""
+    knots (los_chi, los_p);
+    ray_mesh: (iota, p_min) to kick the rays on the adaptive 2D ray mesh (HRT_RAY_MESH)."""
     sched = np.ascontiguousarray(sched, dtype=np.float64)
     if len(sched) != n_steps + 1:
         raise ValueError("sched must have n_steps + 1 entries")
@@ -148,7 +151,10 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     cfg.n_steps = n_steps
     cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
     cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0) | \
-        (HRT_JACOBIAN if jacobian else 0) | (HRT_TIME_DELAY if time_delay else 0)
+        (HRT_JACOBIAN if jacobian else 0) | (HRT_TIME_DELAY if time_delay else 0) | \
+        (HRT_RAY_MESH if ray_mesh is not None else 0)
+    if ray_mesh is not None:
+        cfg.ray_mesh_iota, cfg.ray_mesh_pmin = float(ray_mesh[0]), float(ray_mesh[1])
     cfg.n_src = 0 if src is None else len(src)
     cfg.box, cfg.fov_x, cfg.fov_y = box, fov_x, fov_y
     for i in range(3):
