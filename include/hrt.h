@@ -240,8 +240,9 @@ int ray_observe(hrt_ctx *ctx, const hrt_rays *r, const hrt_maps *maps);
  * (hrt_mesh_ptr(HRT_MESH_GRAD) returns HRT_ESTATE; phi of the last step is there, and a
  * ray_step of that step may follow). 3 is 2 with the tile kick-drift run as a
  * persistent, software-pipelined grid (each workgroup loads its next tile while it moves
- * the current one). 1 runs pm_step's Lagrangian-order
- * kernels (with the same fused counting). 0 (default) takes 2 for calls of 8 steps or more
+ * the current one). 4 is 2 with one kick-drift workgroup per x-pair of tiles (one phi
+ * block of 24 x 13 x 13 for both; FP32 only, FP64 runs 2). 1 runs pm_step's Lagrangian-order
+ * kernels (with the same fused counting). 0 (default) takes 4 for calls of 8 steps or more
  * and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
  * call's work runs. */
 int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps,
@@ -351,9 +352,9 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
  * group workgroups per XCD or not; every variant computes bit-identical results and they
  * differ only in speed (matter_kd also has shapes with two particles per lane, paint_tiles
  * shapes that paint two or four tiles per workgroup). Tunable kernel ids: bin_count, bin_scatter
- * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (6), kd_tiles (4: the particle order of hrt_run, see
- * there, 3 being the paint-bin order with a persistent pipelined kick-drift; not chosen by
- * hrt_autotune). hrt_num_variants(id) gives the count (1 = not
+ * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (6), kd_tiles (5: the particle order of hrt_run, see
+ * there, 3 and 4 being the paint-bin order with a persistent pipelined kick-drift and with
+ * x-pairs of tiles per workgroup; not chosen by hrt_autotune). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);
  * hrt_get_variant reads it. A new context starts with variant 0 everywhere. */
 int hrt_num_variants(int kernel_id);

@@ -535,7 +535,8 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
     // Particle order of the sequence (kd_tiles variant): 1 = Lagrangian order (pm_step's
     // kernels), 2 = paint-bin order (sorted-state kernels, G formed per tile and on the lens
     // planes only), 3 = the same with the tile kick-drift as a persistent pipelined kernel,
-    // 0 = bin order for sequences of kSortedMinSteps steps or more, whose
+    // 4 = paint-bin order with x-pairs of tiles per kick-drift workgroup (FP32; FP64 runs
+    // variant 2), 0 = bin order (as 4) for sequences of kSortedMinSteps steps or more, whose
     // per-step saving outweighs the one-off cost of entering and leaving the sorted state.
     // All give the same bits.
     constexpr int kSortedMinSteps = 8;

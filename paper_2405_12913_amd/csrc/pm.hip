@@ -665,7 +665,9 @@ __device__ __forceinline__ void kd_fetch(const v4<T> *recs, const T *mom, size_t
 
 // Readout of G (from LDS) at particle j, kick, drift, store in place; with COUNT the moved
 // particle is also counted into its next bin. All 64 lanes of a wave call (j >= j1: none).
-template <typename T, bool COUNT>
+// GX: the G block's x width (9 for one tile, 17 for an x-pair of tiles, whose first tile has
+// an even tile index, so the cell's x within the pair is its x mod 16).
+template <typename T, bool COUNT, int GX = kGN>
 __device__ __forceinline__ void kd_move(v4<T> *recs, T *mom, size_t P, int j, int j1, KdItem<T> &it,
                                         const v4<T> *gl, T K, T D, const CellGeom<T> &cg, int lnt,
                                         unsigned int *count) {
@@ -675,10 +677,11 @@ __device__ __forceinline__ void kd_move(v4<T> *recs, T *mom, size_t P, int j, in
         int c[3];
         T f[3];
         record_cell<T>(cg, rec, c, f);
-        const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGN + (c[0] & 7);
+        constexpr int xm = GX == kGN ? 7 : 15;
+        const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * GX + (c[0] & xm);
         v4<T> g[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGN + (k & 1)];
+        for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * GX + (k & 1)];
         T sv[3] = {rec.x, rec.y, rec.z};
         cic_kick_drift<T>(f, g, K, D, sv, it.p);
         rec.x = sv[0];
@@ -740,6 +743,89 @@ __global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int 
         kd_fetch<T>(recs, mom, P, base + 3 * kThreads + (int)threadIdx.x, j1, nxt1);
         kd_move<T, COUNT>(recs, mom, P, base + (int)threadIdx.x, j1, cur0, gl, K, D, cg, lnt, a.count);
         kd_move<T, COUNT>(recs, mom, P, base + kThreads + (int)threadIdx.x, j1, cur1, gl, K, D, cg, lnt, a.count);
+        cur0 = nxt0;
+        cur1 = nxt1;
+    }
+}
+
+// Two x-adjacent tiles per workgroup of 512 lanes (FP32): tiles 2w and 2w + 1 (their bins
+// are contiguous), one phi block of 24 x 13 x 13 and G at the pair's 17 x 9 x 9 corner nodes,
+// so the halo is read once for both and the block's load and barrier are paid once per two
+// tiles. The differences and every particle's arithmetic are those of kd_tiles_kernel.
+constexpr int kPairThreads = 512;
+constexpr int kPhiX2 = 24, kGX2 = 17;
+constexpr int kPhiQuads2 = kPhiYZ * kPhiYZ * (kPhiX2 / 4);      // 1014 aligned quadruples
+
+__device__ __forceinline__ size_t phi_quad_offset2(int e, int tx0, int ty, int tz, int n) {
+    const int m = n - 1, q = e % (kPhiX2 / 4), row = e / (kPhiX2 / 4), ly = row % kPhiYZ, lz = row / kPhiYZ;
+    const int gx = (tx0 * kTile - 4 + 4 * q) & m;
+    const int gy = (ty * kTile - 2 + ly) & m, gz = (tz * kTile - 2 + lz) & m;
+    return ((size_t)gz * n + gy) * n + gx;
+}
+
+// G at the pair's 17 x 9 x 9 nodes: a lane takes four nodes along x (quadruple q = 1..5 of a
+// row; q = 5 holds only the last node, x = 16): 81 rows x 5 = 405 lanes, one pass.
+template <typename T>
+__device__ __forceinline__ void pair_gradient(const v4<T> *ph4, v4<T> *gl, T inv12cell) {
+    constexpr int kQ = kPhiX2 / 4;
+    constexpr int kTasks = kGN * kGN * (kQ - 1);
+    const int e = threadIdx.x;
+    if (e >= kTasks) return;
+    const int q = e % (kQ - 1) + 1, row = e / (kQ - 1), gy = row % kGN, gz = row / kGN;
+    const int y = gy + 2, z = gz + 2;
+    auto quad = [&](int yy, int zz, int qq) { return ph4[(zz * kPhiYZ + yy) * kQ + qq]; };
+    auto el = [](const v4<T> &v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; };
+    const v4<T> xm = quad(y, z, q - 1), x0 = quad(y, z, q);
+    const v4<T> xp = q < kQ - 1 ? quad(y, z, q + 1) : x0;     // q = 5 needs only x <= 22
+    const v4<T> ym2 = quad(y - 2, z, q), ym1 = quad(y - 1, z, q), yp1 = quad(y + 1, z, q), yp2 = quad(y + 2, z, q);
+    const v4<T> zm2 = quad(y, z - 2, q), zm1 = quad(y, z - 1, q), zp1 = quad(y, z + 1, q), zp2 = quad(y, z + 2, q);
+    const T r[12] = {xm.x, xm.y, xm.z, xm.w, x0.x, x0.y, x0.z, x0.w, xp.x, xp.y, xp.z, xp.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int gx = 4 * q + k - 4;
+        if (gx >= kGX2) break;
+        v4<T> o;
+        o.x = fd4<T>(r[k + 2], r[k + 3], r[k + 5], r[k + 6], inv12cell);
+        o.y = fd4<T>(el(ym2, k), el(ym1, k), el(yp1, k), el(yp2, k), inv12cell);
+        o.z = fd4<T>(el(zm2, k), el(zm1, k), el(zp1, k), el(zp2, k), inv12cell);
+        o.w = T(0);
+        gl[(gz * kGN + gy) * kGX2 + gx] = o;
+    }
+}
+
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(kPairThreads) void kd_pairs_kernel(PartBatch<T> b, int cur) {
+    __shared__ v4<T> ph4[kPhiQuads2];
+    __shared__ v4<T> gl[kGX2 * kGN * kGN];
+    const int blk = logical_block(b.xcd);
+    const int rr = real_of(b.map, blk);
+    const Particles<T> &a = b.r[rr];
+    const int n = a.n, nt = n / kTile;
+    const size_t P = (size_t)a.P;
+    const int t = 2 * (blk - b.map.start[rr]);          // the pair's first tile (even x)
+    const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+    const int j0 = (int)uniform_load(a.offs + t * 8), j1 = (int)uniform_load(a.offs + t * 8 + 16);
+    if (j0 == j1) return;                       // both tiles empty (uniform over the block)
+    v4<T> *const recs = a.rec[cur];
+    T *const mom = a.mom[cur];
+    KdItem<T> cur0, cur1;
+    kd_fetch<T>(recs, mom, P, j0 + (int)threadIdx.x, j1, cur0);
+    kd_fetch<T>(recs, mom, P, j0 + kPairThreads + (int)threadIdx.x, j1, cur1);
+    for (int e = threadIdx.x; e < kPhiQuads2; e += kPairThreads)
+        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset2(e, tx, ty, tz, n));
+    __syncthreads();
+    pair_gradient<T>(ph4, gl, a.inv12cell);
+    __syncthreads();
+    const T K = a.K, D = a.D;
+    const CellGeom<T> cg = geom_of(a);
+    const int lnt = a.lnt;
+    for (int base = j0; base < j1; base += 2 * kPairThreads) {   // same trip count for every lane
+        KdItem<T> nxt0, nxt1;
+        kd_fetch<T>(recs, mom, P, base + 2 * kPairThreads + (int)threadIdx.x, j1, nxt0);
+        kd_fetch<T>(recs, mom, P, base + 3 * kPairThreads + (int)threadIdx.x, j1, nxt1);
+        kd_move<T, COUNT, kGX2>(recs, mom, P, base + (int)threadIdx.x, j1, cur0, gl, K, D, cg, lnt, a.count);
+        kd_move<T, COUNT, kGX2>(recs, mom, P, base + kPairThreads + (int)threadIdx.x, j1, cur1, gl, K, D, cg, lnt,
+                                a.count);
         cur0 = nxt0;
         cur1 = nxt1;
     }
@@ -1216,7 +1302,14 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             set_map(b, R, tiles);
             b.pmap = 0;
             b.xcd = 1;
-            if (c->variant[K_KD_TILES] == 3) {          // persistent, software-pipelined form
+            // FP32: x-pairs of tiles per workgroup unless one tile per workgroup is asked for
+            // (the pair's LDS block would exceed 64 KB in FP64)
+            const int kdv = c->variant[K_KD_TILES];
+            if (sizeof(T) == 4 && (kdv == 0 || kdv == 4)) {
+                set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / 2; });
+                if (args.count_next) kd_pairs_kernel<T, true><<<b.map.start[R], kPairThreads, 0, c->stream>>>(b, args.cur);
+                else kd_pairs_kernel<T, false><<<b.map.start[R], kPairThreads, 0, c->stream>>>(b, args.cur);
+            } else if (c->variant[K_KD_TILES] == 3) {          // persistent, software-pipelined form
                 const int nblk = b.map.start[R];
                 const int grid = std::min(nblk, resident_blocks(kd_stream_per_cu<T>(args.count_next)));
                 if (args.count_next) kd_tiles_stream_kernel<T, true><<<grid, kThreads, 0, c->stream>>>(b, args.cur, nblk);

@@ -263,7 +263,7 @@ def test_paint_fractions_at_cell_edges():
     assert np.max(np.abs(d - d_o) / (1.0 + np.abs(d_o))) < 2e-5
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_gpu_time_reversibility(dtype, order):
     """N co-evolution steps with the closing half-kick, then the reversed schedule, return the

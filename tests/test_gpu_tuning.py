@@ -126,7 +126,7 @@ def test_run_equals_step_by_step():
     say("case hrt_run vs step by step")
     c = _case()
     base = _run(c, c.sim(), steps=5)
-    for kd, variant in ((2, 0), (3, 0), (1, 0), (1, 8)):
+    for kd, variant in ((2, 0), (3, 0), (4, 0), (1, 0), (1, 8)):
         sim = c.sim()
         sim.set_variant("kd_tiles", kd)
         sim.set_variant("matter_kd", variant)
@@ -213,7 +213,7 @@ def test_paint_variants_with_dense_tiles():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("kd", [0, 3])
+@pytest.mark.parametrize("kd", [0, 3, 4])
 def test_sorted_run_default_threshold_and_dtypes(dtype, kd):
     """The automatic particle order of hrt_run (paint-bin order from 8 steps on), and the
     paint-bin order with the persistent pipelined kick-drift, give the bits of step-by-step
@@ -268,7 +268,7 @@ def test_sorted_run_with_empty_and_dense_tiles():
         sim.ray_step(ref[2], ref[3], step)
     torch.cuda.synchronize()
     from paper_2405_12913_amd import hrt
-    cases = [(kd, 0) for kd in (0, 3, 1)] + [(2, pv) for pv in range(hrt.num_variants("paint_tiles"))]
+    cases = [(kd, 0) for kd in (0, 3, 4, 1)] + [(2, pv) for pv in range(hrt.num_variants("paint_tiles"))]
     for kd, pv in cases:
         got = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
         sim2 = c.sim()
