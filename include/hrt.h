@@ -351,8 +351,9 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
  * ways (Lagrangian patches of different shapes, linear order, pixel patches or rows) and
  * group workgroups per XCD or not; every variant computes bit-identical results and they
  * differ only in speed (matter_kd also has shapes with two particles per lane, paint_tiles
- * shapes that paint two or four tiles per workgroup). Tunable kernel ids: bin_count, bin_scatter
- * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (6), kd_tiles (5: the particle order of hrt_run, see
+ * shapes that paint two or four tiles per workgroup or spread the FP32 sums over two to
+ * eight LDS copies). Tunable kernel ids: bin_count, bin_scatter
+ * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (14), kd_tiles (5: the particle order of hrt_run, see
  * there, 3 and 4 being the paint-bin order with a persistent pipelined kick-drift and with
  * x-pairs of tiles per workgroup; not chosen by hrt_autotune). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);

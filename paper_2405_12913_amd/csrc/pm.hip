@@ -368,22 +368,33 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 // nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
 // the bin-range round trip) are shared by several tiles; at one particle per node two tiles
 // per workgroup keep twice as many tiles resident per CU (wave slots, not LDS, limit it).
-// FP32 tiles that pull fewer than 1024 particles use 32-bit LDS sums: a node's sum is at
-// most the tile's particle count `total` (weights <= 1), so with 2^s <= 2^31 / (total + 1)
-// (here s = 21..24) no sum overflows, and each weight is rounded to 2^-(s+1) <= 2.4e-7,
-// the size of the FP32 rounding of the cell fractions themselves: half the LDS bytes per
-// atomic and a two-instruction conversion. Denser tiles, and FP64, keep the exact 64-bit
-// sums with the global scale.
+// FP32: 32-bit LDS sums at the tile's own scale 2^s, s = min(24, 31 - ceil(log2(m + 1))) with
+// m = min(entries, 1024). The entries are added in chunks of 1024, and after each chunk every
+// lane folds the chunk's sums of its nodes into 64-bit LDS sums: a node's chunk sum is at
+// most m 2^s <= 2^31 (weights <= 1), so no 32-bit sum overflows, and each weight is rounded
+// to 2^-(s+1) <= 2^-21, about the FP32 rounding of the cell fractions themselves: half the
+// LDS bytes per atomic of a 64-bit sum and a two-instruction conversion. NC copies of the
+// sums (lane l adds into copy l mod NC, copies 24 banks apart) divide the same-node conflicts
+// of one instruction by about NC; the copies are summed in the fold. FP64: exact 64-bit sums
+// at the global scale, one pass.
 // SORTED: the particles are sorted-state records (buffer cur) rather than the binned
 // (fraction, local cell) entries of the Lagrangian-order scatter.
 // The work of logical block blk (TPB tiles).
 constexpr int kPaintDepth = 4;              // entries in flight per lane
+constexpr int kPaintChunk = 1024;           // FP32 entries per chunk of 32-bit sums
+constexpr int kAccCopy = kAccSize + 8;      // stride of the FP32 copies (600 = 24 mod 64)
 
-template <typename T, int TPB, bool SORTED>
+template <typename T, int TPB, bool SORTED, int NC>
 __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur, int blk) {
     constexpr int G = kThreads / TPB;           // lanes per tile
-    __shared__ unsigned long long acc[TPB][kAccSize];   // 64-bit sums
-    __shared__ unsigned int acc32s[TPB][kAccSize];      // 32-bit sums (separate: no type punning)
+    constexpr bool kWide = sizeof(T) == 8;
+    constexpr int kCopies = kWide ? 1 : NC;
+    constexpr int kStride = kWide ? kAccSize : kAccCopy;
+    constexpr int kNodes = 512 / G;             // nodes per lane in the fold and the stores
+    static_assert(kPaintChunk % (kPaintDepth * G) == 0, "chunks of whole trips");
+    using Acc = typename std::conditional<kWide, unsigned long long, unsigned int>::type;
+    __shared__ Acc acc[TPB][kCopies * kStride];
+    __shared__ unsigned long long sum64[TPB][kWide ? 1 : 512];     // FP32: folded chunk sums
     __shared__ __align__(16) int rstart[TPB][32];
     __shared__ __align__(16) int rpre[TPB][32];
     __shared__ __align__(16) signed char rd[TPB][32][3];
@@ -393,22 +404,25 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int t = (blk - b.map.start[rr]) * TPB + g;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
-    for (int k = lane; k < kAccSize; k += G) {
-        acc[g][k] = 0ull;
-        acc32s[g][k] = 0u;
-    }
+    for (int k = lane; k < kCopies * kStride; k += G) acc[g][k] = Acc(0);
     tile_ranges<T>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane);
     __syncthreads();
     const int total = rpre[g][27];
-    const double scale = a.scale;
-    const bool narrow = sizeof(T) == 4 && total < 1024;          // uniform over the group
-    const int bits = total > 0 ? 32 - __clz(total) : 0;          // ceil(log2(total + 1))
-    const int ts = (31 - bits) < 24 ? 31 - bits : 24;            // narrow scale 2^ts
+    // chunks: uniform over the workgroup (every group passes the same barriers)
+    int nch = 1;                                // at least one pass (its fold writes the sums)
+    if constexpr (!kWide) {
+#pragma unroll
+        for (int gg = 0; gg < TPB; ++gg) nch = max(nch, (rpre[gg][27] + kPaintChunk - 1) / kPaintChunk);
+    }
+    const int m = min(total, kPaintChunk);
+    const int bits = m > 0 ? 32 - __clz(m) : 0;                  // ceil(log2(m + 1))
+    const int ts = (31 - bits) < 24 ? 31 - bits : 24;            // FP32 scale 2^ts
     const float fscale = ldexpf(1.0f, ts);
-    unsigned int *acc32 = acc32s[g];
+    Acc *const mine = acc[g] + (kWide ? 0 : (lane % kCopies) * kStride);
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
+    const double scale = a.scale;
     // idx only grows, so the range index does too: (fr, fhi, fbase) belong to the furthest
     // entry requested and stay in registers until idx leaves that range. Each lane keeps
     // kPaintDepth entries in flight: entry idx + kPaintDepth G is requested before entry idx
@@ -433,47 +447,68 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
         rv[k] = 0;
         if (lane + k * G < total) request(lane + k * G, ev[k], rv[k]);
     }
-    for (int base = lane; base < total; base += kPaintDepth * G) {
+    for (int ch = 0; ch < nch; ++ch) {
+        // a chunk is a whole number of trips, so the ring holds the next chunk's first entries
+        const int cend = kWide ? total : min(total, (ch + 1) * kPaintChunk);
+        for (int base = (kWide ? 0 : ch * kPaintChunk) + lane; base < cend; base += kPaintDepth * G) {
 #pragma unroll
-        for (int k = 0; k < kPaintDepth; ++k) {
-            const int idx = base + k * G;
-            if (idx >= total) break;
-            v4<T> e = ev[k];
-            const int r = rv[k];
-            if (idx + kPaintDepth * G < total) request(idx + kPaintDepth * G, ev[k], rv[k]);
-            if constexpr (SORTED) {             // record -> (fractions, local cell)
-                int c[3];
-                T f[3];
-                record_cell<T>(cg, e, c, f);
-                e.x = f[0];
-                e.y = f[1];
-                e.z = f[2];
-                e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
-            }
-            if (r == 0) {                       // own tile, no upper face: 8 inside corners
-                if (narrow) paint_one<T, unsigned int, true>(fixed_bits, acc32, e, 0, 0, 0, scale, fscale);
-                else paint_one<T, unsigned long long, true>(fixed_bits, acc[g], e, 0, 0, 0, scale, fscale);
-            } else {
-                const int dx = rd[g][r][0], dy = rd[g][r][1], dz = rd[g][r][2];
-                if (narrow) paint_one<T, unsigned int, false>(fixed_bits, acc32, e, dx, dy, dz, scale, fscale);
-                else paint_one<T, unsigned long long, false>(fixed_bits, acc[g], e, dx, dy, dz, scale, fscale);
+            for (int k = 0; k < kPaintDepth; ++k) {
+                const int idx = base + k * G;
+                if (idx >= cend) break;
+                v4<T> e = ev[k];
+                const int r = rv[k];
+                if (idx + kPaintDepth * G < total) request(idx + kPaintDepth * G, ev[k], rv[k]);
+                if constexpr (SORTED) {             // record -> (fractions, local cell)
+                    int c[3];
+                    T f[3];
+                    record_cell<T>(cg, e, c, f);
+                    e.x = f[0];
+                    e.y = f[1];
+                    e.z = f[2];
+                    e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
+                }
+                if (r == 0) {                       // own tile, no upper face: 8 inside corners
+                    paint_one<T, Acc, true>(fixed_bits, mine, e, 0, 0, 0, scale, fscale);
+                } else {
+                    const int dx = rd[g][r][0], dy = rd[g][r][1], dz = rd[g][r][2];
+                    paint_one<T, Acc, false>(fixed_bits, mine, e, dx, dy, dz, scale, fscale);
+                }
             }
         }
+        __syncthreads();
+        if constexpr (!kWide) {                 // fold the chunk's sums into the registers
+#pragma unroll
+            for (int i = 0; i < kNodes; ++i) {
+                const int k = lane + i * G;
+                const int sl = acc_slot(k & 7, (k >> 3) & 7, k >> 6);
+                unsigned long long v = ch > 0 ? sum64[g][k] : 0ull;
+#pragma unroll
+                for (int cc = 0; cc < kCopies; ++cc) v += acc[g][cc * kStride + sl];
+                sum64[g][k] = v;
+                if (ch + 1 < nch) {
+#pragma unroll
+                    for (int cc = 0; cc < kCopies; ++cc) acc[g][cc * kStride + sl] = 0u;
+                }
+            }
+            if (ch + 1 < nch) __syncthreads();
+        }
     }
-    __syncthreads();
     // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
-    const double inv = narrow ? ldexp(a.inv_scale_rho * a.scale, -ts) : a.inv_scale_rho;
-    for (int k = lane; k < 512; k += G) {
+    const double inv = kWide ? a.inv_scale_rho : ldexp(a.inv_scale_rho * a.scale, -ts);
+#pragma unroll
+    for (int i = 0; i < kNodes; ++i) {
+        const int k = lane + i * G;
         const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        const int sl = acc_slot(k & 7, (k >> 3) & 7, k >> 6);
-        const double sum = narrow ? (double)acc32[sl] : (double)(long long)acc[g][sl];
+        double sum;
+        if constexpr (kWide) sum = (double)(long long)acc[g][acc_slot(k & 7, (k >> 3) & 7, k >> 6)];
+        else sum = (double)sum64[g][k];       // written by this lane in the fold
         st_stream((T)fmadd(sum, inv, -1.0), a.delta + ((size_t)z * n + y) * n + x);
     }
 }
 
-template <typename T, int TPB, bool SORTED>
+template <typename T, int TPB, bool SORTED, int NC>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, int cur) {
-    paint_tiles_body<T, TPB, SORTED>(b, cur, logical_block(b.xcd));
+    paint_tiles_body<T, TPB, SORTED, NC>(b, cur, logical_block(b.xcd));
 }
 
 // One lane per ILP particles, particles in Lagrangian order (patch maps), optionally with
@@ -1184,6 +1219,22 @@ void set_variant(PartBatch<T> &b, int v, int default_xcd) {
     b.xcd = (v >= 4) ? 1 - default_xcd : default_xcd;
 }
 
+// Paint launch shapes: (tiles per workgroup, FP32 copies of the LDS sums); the first is the
+// default (the fastest at one particle per node).
+constexpr int kPaintShapes[7][2] = {{2, 2}, {4, 1}, {2, 1}, {1, 1}, {2, 4}, {1, 4}, {1, 8}};
+
+constexpr int kNumPaintShapes = sizeof(kPaintShapes) / sizeof(kPaintShapes[0]);
+
+template <typename T, int I>
+void launch_paint_shape(int shape, dim3 grid, hipStream_t st, const PartBatch<T> &b, int cur, bool sorted) {
+    if constexpr (I + 1 < kNumPaintShapes) {
+        if (shape != I) return launch_paint_shape<T, I + 1>(shape, grid, st, b, cur, sorted);
+    }
+    constexpr int TPB = kPaintShapes[I][0], NC = kPaintShapes[I][1];
+    if (sorted) paint_tiles_kernel<T, TPB, true, NC><<<grid, kThreads, 0, st>>>(b, cur);
+    else paint_tiles_kernel<T, TPB, false, NC><<<grid, kThreads, 0, st>>>(b, cur);
+}
+
 // Exclusive scan of the bin counts into offsets and cursors, every realisation of b.
 template <typename T>
 void launch_scan(hrt_ctx *c, PartBatch<T> &b, int R) {
@@ -1261,24 +1312,16 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
             prof_end(c, K_STATE_SCATTER);
         }
         prof_begin(c);
-        // variant: bit 0 = no XCD grouping; pv >> 1 = tiles per workgroup (0: one, 1: four,
-        // 2: two)
+        // variant: bit 0 = no XCD grouping; pv >> 1 = launch shape kPaintShapes[pv >> 1]
+        // (tiles per workgroup, FP32 copies of the sums)
         const int pv = c->variant[K_PAINT];
         const bool sorted = args.state != STATE_LAGRANGIAN;
-        const int tpb = (pv >> 1) == 1 ? 4 : (pv >> 1) == 2 ? 2 : 1;
+        const int shape = pv >> 1, tpb = kPaintShapes[shape][0];
         set_map(b, R, [tpb](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / tpb; });
         b.pmap = 0;
         b.xcd = (pv & 1) == 0 ? 1 : 0;
-        if (tpb == 4) {
-            if (sorted) paint_tiles_kernel<T, 4, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-            else paint_tiles_kernel<T, 4, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-        } else if (tpb == 2) {
-            if (sorted) paint_tiles_kernel<T, 2, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-            else paint_tiles_kernel<T, 2, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-        } else {
-            if (sorted) paint_tiles_kernel<T, 1, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-            else paint_tiles_kernel<T, 1, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-        }
+        const dim3 grid(b.map.start[R]);
+        launch_paint_shape<T, 0>(shape, grid, st, b, cur, sorted);
         prof_end(c, K_PAINT);
     }
     return hipGetLastError();

@@ -28,7 +28,7 @@ int variants_of(int id) {
         case K_MATTER_KD: return 16;
         case K_BIN_COUNT: case K_BIN_SCATTER: return 8;
         case K_RAY_STEP: return 6;
-        case K_PAINT: return 6;
+        case K_PAINT: return 14;
         case hrt::K_KD_TILES: return 5;      // run order: 0 automatic, 1 Lagrangian, 2 sorted state,
                                              // 3 sorted state with a pipelined persistent kick-drift,
                                              // 4 sorted state with x-pairs of tiles per workgroup

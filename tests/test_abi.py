@@ -119,7 +119,7 @@ def test_ic_factors_match_oracle(om, a):
 def test_variant_counts():
     from paper_2405_12913_amd import hrt
     counts = {hrt.lib().hrt_kernel_name(k).decode(): hrt.num_variants(k) for k in range(hrt.HRT_NUM_KERNELS)}
-    assert counts["matter_kd"] == 16 and counts["ray_step"] == 6 and counts["paint_tiles"] == 6
+    assert counts["matter_kd"] == 16 and counts["ray_step"] == 6 and counts["paint_tiles"] == 14
     assert counts["bin_count"] == 8 and counts["bin_scatter"] == 8
     assert counts["fft_x_r2c"] == 1 and counts["kd_tiles"] == 5 and counts["state_scatter"] == 1
     assert hrt.num_variants(hrt.HRT_NUM_KERNELS) == 0
