@@ -29,10 +29,35 @@ constexpr int kThreads = 256;
 
 // In-register DFT of R points in natural order (X[m] = sum_r v[r] W_R^{rm}, W_R = e^{-2 pi i/R},
 // conjugate for INV). Radix 8 as 4 x 2: DFT4 over the even and the odd samples, twiddles
-// W_8^{m0} on the odd ones (from the LDS table: W_8^q = tw[q * twq]), DFT2 across.
+// W_8^{m0} on the odd ones (from the LDS table: W_R^q = tw[q * twq]), DFT2 across. Radix 16
+// as 4 x 4: DFT4 over each residue n1 of r mod 4, twiddles W_16^{n1 k1}, DFT4 across n1
+// (output k1 + 4 k2).
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft(c2<T> *v, const c2<T> *__restrict__ tw = nullptr, int twq = 0) {
-    if constexpr (R == 8) {
+    if constexpr (R == 16) {
+        c2<T> a[4][4];
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) {
+            c2<T> t[4] = {v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]};
+            dft<T, 4, INV>(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) {
+                if (n1 * k1 > 0) {
+                    c2<T> w = tw[n1 * k1 * twq];
+                    if (INV) w.y = -w.y;
+                    t[k1] = cmul<T>(t[k1], w);
+                }
+                a[n1][k1] = t[k1];
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            c2<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            dft<T, 4, INV>(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    } else if constexpr (R == 8) {
         c2<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
         dft<T, 4, INV>(e);
         dft<T, 4, INV>(o);
@@ -65,10 +90,24 @@ __device__ __forceinline__ void dft(c2<T> *v, const c2<T> *__restrict__ tw = nul
     }
 }
 
+// Fewest stages for 2^e points with radix-8 stages (and radix 16 when allowed), the last
+// one of 2, 4 or 8 points.
+__host__ __device__ constexpr int fewest_stages(int e, bool r16) {
+    if (e <= 3) return e > 0 ? 1 : 0;
+    const int s8 = fewest_stages(e - 3, r16);
+    const int s16 = r16 ? fewest_stages(e - 4, r16) : s8;
+    return 1 + (s16 < s8 ? s16 : s8);
+}
+__host__ __device__ constexpr int log2i(int v) { return v > 1 ? 1 + log2i(v / 2) : 0; }
+
 // Radix of the Stockham stage that starts at span Ns: 8 where it keeps every thread busy
-// (LINES x L/8 butterflies), else 4, a last 2 when needed.
+// (LINES x L/8 butterflies), else 4, a last 2 when needed; 16 where that also keeps every
+// thread busy and saves a stage (a stage is one round trip of the lines through LDS).
 template <int L, int LINES>
 __host__ __device__ constexpr int radix_at(int Ns) {
+    const bool r16 = LINES * (L / 16) >= kThreads;
+    const int e = log2i(L / Ns);
+    if (r16 && e >= 4 && fewest_stages(e - 4, true) < fewest_stages(e - 3, true)) return 16;
     return (Ns * 8 <= L && LINES * (L / 8) >= kThreads) ? 8 : (Ns * 4 <= L) ? 4 : 2;
 }
 // Span of the last stage (the one whose outputs are in natural order).
@@ -91,7 +130,7 @@ __device__ __forceinline__ void butterfly(c2<T> *v, int j, const c2<T> *__restri
         if (INV) w.y = -w.y;
         v[r] = cmul<T>(v[r], w);
     }
-    dft<T, R, INV>(v, tw, twmul * (L / 8));
+    dft<T, R, INV>(v, tw, twmul * (L / R));
 }
 
 // One Stockham stage over LINES lines of length L in LDS (line stride LS), then the next
@@ -247,6 +286,9 @@ struct Cfg {
     static constexpr int EZC = (4096 / F > N) ? 4096 / F : N;
     static constexpr int EZ = EZW < EZC ? EZW : EZC;
     static constexpr int XROWS = (EX / (N / 2)) < 1 ? 1 : ((EX / (N / 2)) < N * N ? EX / (N / 2) : N * N);
+    // x_c2r reads the transposed spectrum in segments of XROWS values: at N >= 1024 twice
+    // the rows (128-byte FP32 segments, 64 KB of LDS) measured faster than more blocks
+    static constexpr int XROWS_INV = N >= 1024 ? 2 * XROWS : XROWS;
     static constexpr int YLINES = EY / N < 1 ? 1 : EY / N;
     static constexpr int ZLINES = EZ / N < 1 ? 1 : EZ / N;
 };
@@ -318,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
 
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
-    constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
+    constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS_INV, LS = L + 1;
     __shared__ c2<T> buf[ROWS * LS];
     __shared__ c2<T> tw[N];
     // XCD-grouped block order only when a block's transposed segments are under 128 bytes
@@ -577,9 +619,10 @@ hipError_t poisson_n(hrt_ctx *c, const std::vector<int> &ids) {
     constexpr int XROWS = Cfg<T, N>::XROWS, YL = Cfg<T, N>::YLINES, ZL = Cfg<T, N>::ZLINES;
     const int xb = N * N / XROWS;
     const int yb = ((N / 2 + 1) * N + YL - 1) / YL, zb = ((N / 2 + 1) * N + ZL - 1) / ZL;
+    const int xbi = N * N / Cfg<T, N>::XROWS_INV;
     const int R = (int)ids.size();
     FftBatch<T> fx = fft_batch<T, N>(c, ids, xb, 1), fy = fft_batch<T, N>(c, ids, yb, 1),
-                fz = fft_batch<T, N>(c, ids, zb, 1);
+                fz = fft_batch<T, N>(c, ids, zb, 1), fxi = fft_batch<T, N>(c, ids, xbi, 1);
     prof_begin(c);
     x_r2c_kernel<T, N><<<xb * R, kThreads, 0, st>>>(fx);
     prof_end(c, K_FFT_X_R2C);
@@ -593,7 +636,7 @@ hipError_t poisson_n(hrt_ctx *c, const std::vector<int> &ids) {
     y_lines_kernel<T, N, true><<<yb * R, kThreads, 0, st>>>(fy);
     prof_end(c, K_FFT_Y_INV);
     prof_begin(c);
-    x_c2r_kernel<T, N><<<xb * R, kThreads, 0, st>>>(fx);
+    x_c2r_kernel<T, N><<<xbi * R, kThreads, 0, st>>>(fxi);
     prof_end(c, K_FFT_X_C2R);
     return hipGetLastError();
 }
@@ -973,8 +1016,7 @@ void fwd3d(hrt_ctx *c, int r, const T *real_in, c2<T> *spec, int tws) {
 
 template <typename T, int N>
 void inv3d(hrt_ctx *c, int r, c2<T> *spec, T *real_out, int tws) {
-    constexpr int XROWS = Cfg<T, N>::XROWS, YL = Cfg<T, N>::YLINES, ZL = Cfg<T, N>::ZLINES;
-    const int xb = N * N / XROWS;
+    constexpr int YL = Cfg<T, N>::YLINES, ZL = Cfg<T, N>::ZLINES;
     const int yb = ((N / 2 + 1) * N + YL - 1) / YL, zb = ((N / 2 + 1) * N + ZL - 1) / ZL;
     FftBatch<T> fb{};
     fb.tws = tws;
@@ -985,8 +1027,8 @@ void inv3d(hrt_ctx *c, int r, c2<T> *spec, T *real_out, int tws) {
     z_lines_kernel<T, N, 1><<<zb, kThreads, 0, c->stream>>>(fb);
     fb.bpr = yb;
     y_lines_kernel<T, N, true><<<yb, kThreads, 0, c->stream>>>(fb);
-    fb.bpr = xb;
-    x_c2r_kernel<T, N><<<xb, kThreads, 0, c->stream>>>(fb);
+    fb.bpr = N * N / Cfg<T, N>::XROWS_INV;
+    x_c2r_kernel<T, N><<<fb.bpr, kThreads, 0, c->stream>>>(fb);
 }
 
 template <typename T, int N>
