@@ -854,15 +854,17 @@ __global__ __launch_bounds__(kPairThreads) void kd_pairs_kernel(PartBatch<T> b, 
     const T K = a.K, D = a.D;
     const CellGeom<T> cg = geom_of(a);
     const int lnt = a.lnt;
+    // No request of the next trip ahead (unlike kd_tiles_kernel): the registers it would hold
+    // cost a wave per SIMD (71 -> 62 VGPRs, 7 -> 8 waves), which measured faster at every
+    // density (256^3 with np = n: 250 -> 239 us; 1024^3 with np = n/2: 6.7 -> 5.7 ms).
     for (int base = j0; base < j1; base += 2 * kPairThreads) {   // same trip count for every lane
-        KdItem<T> nxt0, nxt1;
-        kd_fetch<T>(recs, mom, P, base + 2 * kPairThreads + (int)threadIdx.x, j1, nxt0);
-        kd_fetch<T>(recs, mom, P, base + 3 * kPairThreads + (int)threadIdx.x, j1, nxt1);
+        if (base != j0) {
+            kd_fetch<T>(recs, mom, P, base + (int)threadIdx.x, j1, cur0);
+            kd_fetch<T>(recs, mom, P, base + kPairThreads + (int)threadIdx.x, j1, cur1);
+        }
         kd_move<T, COUNT, kGX2>(recs, mom, P, base + (int)threadIdx.x, j1, cur0, gl, K, D, cg, lnt, a.count);
         kd_move<T, COUNT, kGX2>(recs, mom, P, base + kPairThreads + (int)threadIdx.x, j1, cur1, gl, K, D, cg, lnt,
                                 a.count);
-        cur0 = nxt0;
-        cur1 = nxt1;
     }
 }
 
@@ -1349,9 +1351,12 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             // (the pair's LDS block would exceed 64 KB in FP64)
             const int kdv = c->variant[K_KD_TILES];
             if (sizeof(T) == 4 && (kdv == 0 || kdv == 4)) {
-                set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / 2; });
-                if (args.count_next) kd_pairs_kernel<T, true><<<b.map.start[R], kPairThreads, 0, c->stream>>>(b, args.cur);
-                else kd_pairs_kernel<T, false><<<b.map.start[R], kPairThreads, 0, c->stream>>>(b, args.cur);
+                if constexpr (sizeof(T) == 4) {
+                    set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / 2; });
+                    const dim3 grid(b.map.start[R]);
+                    if (args.count_next) kd_pairs_kernel<T, true><<<grid, kPairThreads, 0, c->stream>>>(b, args.cur);
+                    else kd_pairs_kernel<T, false><<<grid, kPairThreads, 0, c->stream>>>(b, args.cur);
+                }
             } else if (c->variant[K_KD_TILES] == 3) {          // persistent, software-pipelined form
                 const int nblk = b.map.start[R];
                 const int grid = std::min(nblk, resident_blocks(kd_stream_per_cu<T>(args.count_next)));
