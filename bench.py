@@ -95,6 +95,9 @@ def algorithmic_bytes(name, n, P, nrays, planes=0.0):
         "kd_tiles": 28 * P + 28 * P + 4 * n3,          # read+write the state in place; read phi
         "plane_gradient": int(round((4 + 12) * n * n * planes)),   # phi plane, (G_x, G_y), G_z
         "state_gather": 28 * P + 24 * P,               # read the state, write s, p
+        # mover-list run: the bins' settle moves the step's listed particles (a device-side
+        # count) and now and then re-bins the whole state, so it has no fixed volume
+        "list_settle": None,
     }[name]
 
 
@@ -572,20 +575,21 @@ def main():
             continue
         avg_ms = ms / cnt
         b = algorithmic_bytes(name, n, P, nrays, planes_per_launch)
-        gbps = b / (avg_ms * 1e-3) / 1e9
-        kernels[name] = {"launches": cnt, "avg_ms": round(avg_ms, 5), "total_ms": round(ms, 3),
-                         "alg_bytes": b, "alg_GBps": round(gbps, 1),
-                         "pct_hbm_peak": round(100 * gbps / HBM_PEAK_GBS, 1),
-                         "pct_copy_ceiling": round(100 * gbps / copy_gbps, 1)}
+        kernels[name] = {"launches": cnt, "avg_ms": round(avg_ms, 5), "total_ms": round(ms, 3)}
+        if b is not None:
+            gbps = b / (avg_ms * 1e-3) / 1e9
+            kernels[name].update({"alg_bytes": b, "alg_GBps": round(gbps, 1),
+                                  "pct_hbm_peak": round(100 * gbps / HBM_PEAK_GBS, 1),
+                                  "pct_copy_ceiling": round(100 * gbps / copy_gbps, 1)})
         tb = pmc_traffic(name)
         if tb is not None:
             kernels[name]["traffic_GBps"] = round(tb / (avg_ms * 1e-3) / 1e9, 1)
     pm_names = ["bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
                 "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd",
-                "state_scatter", "kd_tiles", "plane_gradient", "state_gather"]
+                "state_scatter", "kd_tiles", "plane_gradient", "state_gather", "list_settle"]
     pm_ms = sum(prof[k][0] for k in pm_names) / args.steps
     ray_ms = prof["ray_step"][0] / max(prof["ray_step"][1], 1)
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    dom = max((k for k in kernels if "alg_bytes" in kernels[k]), key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
     achieved = dk["alg_bytes"] / (dk["avg_ms"] * 1e-3) / 1e9
 
@@ -619,6 +623,17 @@ def main():
         "copy_ceiling_GBps": round(copy_gbps, 1),
         "kernels": kernels,
     }
+    # the mover-list run (FP32 default): re-binnings of the whole state in the last hrt_run
+    # call, read from its control words (the call's last step has parity (N - 1) & 1)
+    try:
+        ctl = sim.mesh(hrt.HRT_MESH_LIST_CTL).cpu().numpy()
+        last = ctl[(min(args.steps, N) - 1) & 1]
+        out["mover_list"] = {"rebinnings": int(last[4]), "settles": min(args.steps, N) - 1,
+                             "limit_entries": int(last[5]), "listed_at_last_step": int(last[1]),
+                             "note": "per hrt_run call: steps whose settle re-binned the whole state "
+                                     "instead of sorting the side list"}
+    except hrt.HRTError:
+        pass
     # PM step alone: one captured pm_step replayed 23 times, HIP events around each replay,
     # median of the last 20
     reset()

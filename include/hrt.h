@@ -241,9 +241,13 @@ int ray_observe(hrt_ctx *ctx, const hrt_rays *r, const hrt_maps *maps);
  * ray_step of that step may follow). 3 is 2 with the tile kick-drift run as a
  * persistent, software-pipelined grid (each workgroup loads its next tile while it moves
  * the current one). 4 is 2 with one kick-drift workgroup per x-pair of tiles (one phi
- * block of 24 x 13 x 13 for both; FP32 only, FP64 runs 2). 1 runs pm_step's Lagrangian-order
- * kernels (with the same fused counting). 0 (default) takes 4 for calls of 8 steps or more
- * and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
+ * block of 24 x 13 x 13 for both; FP32 only, FP64 runs 2). 5 (FP32; FP64 runs 2) is 4
+ * without re-binning the whole state every step: a particle that stays in its paint bin
+ * keeps its slot, one that leaves it leaves a hole and joins a side list sorted by bin,
+ * which the paint and the kick-drift read beside the bins; the whole state is re-binned only
+ * at the end of a step that starts with more than P/16 listed particles. 6 is 5 with a limit
+ * of P/64. 1 runs pm_step's Lagrangian-order kernels (with the same fused counting). 0
+ * (default) takes 5 in FP32 and 2 in FP64 for calls of 8 steps or more, and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
  * call's work runs. */
 int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps,
             const hrt_maps *maps);
@@ -263,8 +267,12 @@ int hrt_graph_launch(hrt_ctx *ctx);
  * hrt_destroy: HRT_MESH_DELTA (n^3, after pm_force: delta), HRT_MESH_PHI (n^3: phi),
  * HRT_MESH_GRAD (n^3 interleaved quadruples (G_x, G_y, G_z, 0); HRT_ESTATE after an hrt_run
  * in paint-bin order, which forms G per tile and keeps no G mesh, until the next
- * pm_force / pm_step). */
-enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GRAD = 2 };
+ * pm_force / pm_step). HRT_MESH_LIST_CTL: the control words of the mover-list run (kd_tiles
+ * variants 5 and 6), two records of 8 uint32 (one per step parity: record buffer holding the
+ * bins' fronts, side-list entries, holes, entries appended in the step, re-binnings so far,
+ * re-binning limit, 2 unused), for tests and statistics; HRT_EINVAL for FP64 and static
+ * contexts, which have none. */
+enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GRAD = 2, HRT_MESH_LIST_CTL = 3 };
 int hrt_mesh_ptr(const hrt_ctx *ctx, int realisation, int which, void **ptr);
 
 /* Host-only step tables for cfg (no GPU use), for checking the table builder.
@@ -353,7 +361,7 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
  * differ only in speed (matter_kd also has shapes with two particles per lane, paint_tiles
  * shapes that paint two or four tiles per workgroup or spread the FP32 sums over two to
  * eight LDS copies). Tunable kernel ids: bin_count, bin_scatter
- * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (14), kd_tiles (5: the particle order of hrt_run, see
+ * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (14), kd_tiles (7: the particle order of hrt_run, see
  * there, 3 and 4 being the paint-bin order with a persistent pipelined kick-drift and with
  * x-pairs of tiles per workgroup; not chosen by hrt_autotune). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);
@@ -379,7 +387,7 @@ int hrt_autotune(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int step,
  * clears the totals and starts recording, 0 stops. hrt_profile_read synchronises the
  * stream and writes, for kernel ids 0..n-1, the summed milliseconds and launch counts.
  * hrt_kernel_name(id) names kernel id (NULL past the last id, HRT_NUM_KERNELS). */
-enum { HRT_NUM_KERNELS = 18 };
+enum { HRT_NUM_KERNELS = 19 };
 int hrt_profile_enable(hrt_ctx *ctx, int on);
 int hrt_profile_read(hrt_ctx *ctx, double *total_ms, int64_t *launches, int n);
 const char *hrt_kernel_name(int id);

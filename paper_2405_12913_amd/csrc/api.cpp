@@ -34,16 +34,21 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_c
     L.twiddle = take(n * 2 * T);
     L.bins = take((size_t)(L.nbins + L.nbins + 1 + nblk + 1) * 4);
     L.cursor = take((size_t)L.nbins * 4);
-    L.sorted = take(P * 4 * T);
+    // mover-list run (FP32 with moving particles): the records lie as [rec0 | S | rec1 | U]
+    // in `sorted` (P, P, P, 2P entries) and the momenta as [mom0 | S | mom1 | U] in `state`
+    // (3P, 3P, 3P, 6P values), all within 32-bit offsets of rec0 and mom0
+    const bool list = !(cfg.flags & HRT_STATIC) && T == 4 && 15 * P < ((size_t)1 << 31);
+    L.sorted = take(P * 4 * T * (list ? 5 : 1));
+    // sorted-state run: the second record buffer (the first is `sorted`) and both momentum
+    // buffers, P x (4 + 3 + 3) values; with the list, the momenta only (15P values); a static
+    // run moves no particles
+    L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * (list ? 15 : 10) * T);
     L.planes = take((size_t)std::max<int64_t>(n_plane_entries, 1) * sizeof(PlaneEntry));
     // reverse mode: 2 x n^3 64-bit fixed-point accumulators (rays' part of the force-mesh
     // cotangent), one 8-byte device scalar (256 bytes reserved), P x 4 kick weights and the
     // ray VJP's per-group partial sums (kRayVjpParts x rays x 2 doubles)
     const size_t M = (size_t)cfg.ray_nx * cfg.ray_ny;
     L.adj = (cfg.flags & HRT_ADJOINT) ? take(2 * n3 * 8 + 256 + P * 4 * T + kRayVjpParts * M * 16) : off;
-    // sorted-state run: the second record buffer (the first is `sorted`) and both momentum
-    // buffers, P x (4 + 3 + 3) values; a static run moves no particles
-    L.state = (cfg.flags & HRT_STATIC) ? 0 : take(P * 10 * T);
     // lens-plane stack of one shell: (G_u, G_v) per node of each plane, replica frame
     L.stack = cfg.ray_nx > 0 ? take((size_t)std::max<int64_t>(max_count, 1) * n * n * 2 * T) : off;
     // scalar lens planes: phi (time delay, potential integrals), delta (density integrals)
@@ -55,6 +60,9 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_c
     // ray mesh: the complex kick field (N^2) and its twiddles W_N^m (N)
     L.rm_mesh = rm_n > 0 ? take((size_t)rm_n * rm_n * 2 * T) : off;
     L.rm_tw = rm_n > 0 ? take((size_t)rm_n * 2 * T) : off;
+    // mover-list run: control words, the mover histogram and list offsets, holes per bin and
+    // the extents of the kick-drift workgroups' parts of U
+    L.list = list ? take(list_offsets((size_t)L.nbins).total) : 0;
     L.total = off;
     return L;
 }
@@ -121,7 +129,8 @@ hrt_ctx::~hrt_ctx() {
 static const char *kKernelNames[hrt::K_COUNT] = {
     "bin_count", "bin_scan", "bin_scatter", "paint_tiles", "fft_x_r2c", "fft_y_fwd",
     "fft_z_poisson", "fft_y_inv", "fft_x_c2r", "fd4_gradient", "matter_kd", "ray_step",
-    "convergence", "state_scatter", "kd_tiles", "plane_gradient", "state_gather", "ray_mesh"};
+    "convergence", "state_scatter", "kd_tiles", "plane_gradient", "state_gather", "ray_mesh",
+    "list_settle"};
 
 extern "C" const char *hrt_kernel_name(int id) {
     return (id >= 0 && id < hrt::K_COUNT) ? kKernelNames[id] : nullptr;
@@ -536,14 +545,25 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
     // kernels), 2 = paint-bin order (sorted-state kernels, G formed per tile and on the lens
     // planes only), 3 = the same with the tile kick-drift as a persistent pipelined kernel,
     // 4 = paint-bin order with x-pairs of tiles per kick-drift workgroup (FP32; FP64 runs
-    // variant 2), 0 = bin order (as 4) for sequences of kSortedMinSteps steps or more, whose
-    // per-step saving outweighs the one-off cost of entering and leaving the sorted state.
-    // All give the same bits.
+    // variant 2), 5 = 4 with the particles that leave their paint bin moved through a side
+    // list instead of re-binning the whole state every step (FP32; re-binned once the list
+    // holds P/16 entries), 6 = 5 with a limit of P/64, 0 = bin order (5 in FP32, 2 in FP64)
+    // for sequences of kSortedMinSteps steps or more, whose per-step saving outweighs the
+    // one-off cost of entering and leaving the sorted state. All give the same bits.
     constexpr int kSortedMinSteps = 8;
     const int order = c->variant[hrt::K_KD_TILES];
     const bool sorted = order >= 2 || (order == 0 && n >= kSortedMinSteps);
+    bool list = sorted && !c->f64 && (order == 5 || order == 6 || order == 0);
+    for (const hrt::Real &re : c->re) list = list && re.lay.list != 0;
     bool counted = false;
     int cur = 0;
+    if (list) {
+        hrt::StepArgs a;
+        a.m = m;
+        a.par = first & 1;
+        a.list_shift = order == 6 ? 6 : 4;
+        if (int rc = check_hip(c, hrt::launch_list_init(c, a), "list init")) return rc;
+    }
     for (int k = first; k < first + n; ++k) {
         hrt::StepArgs a;
         a.m = m;
@@ -552,6 +572,8 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         if (sorted) {
             a.state = k == first ? hrt::STATE_FROM_CALLER : hrt::STATE_SORTED;
             a.cur = cur;
+            a.list = list;
+            a.par = k & 1;
         }
         if (int rc = check_hip(c, hrt::launch_paint(c, a), "paint")) return rc;
         if (int rc = check_hip(c, hrt::launch_poisson(c), "poisson")) return rc;
@@ -561,6 +583,8 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         a.counts_ready = false;
         a.count_next = k + 1 < first + n;
         if (int rc = check_hip(c, hrt::launch_matter_kd(c, a), "matter kick-drift")) return rc;
+        if (list && a.count_next)
+            if (int rc = check_hip(c, hrt::launch_list_settle(c, a), "list settle")) return rc;
         counted = a.count_next;
         if (r) {
             if (int rc = ray_step(c, r, k)) return rc;
@@ -572,6 +596,8 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
         hrt::StepArgs a;
         a.m = m;
         a.cur = cur ^ 1;                 // the buffer the last step moved
+        a.list = list;
+        a.par = (first + n - 1) & 1;     // list: the last step's control words
         if (int rc = check_hip(c, hrt::launch_state_gather(c, a), "state gather")) return rc;
         c->mesh_g_stale = true;          // G was formed per tile in LDS, not on the mesh
     }
@@ -786,6 +812,10 @@ extern "C" int hrt_mesh_ptr(const hrt_ctx *c, int realisation, int which, void *
         case HRT_MESH_GRAD:
             if (c->mesh_g_stale) return HRT_ESTATE;   // paint-bin-order hrt_run: G only in LDS
             *ptr = re.ws + re.lay.grad;
+            return HRT_OK;
+        case HRT_MESH_LIST_CTL:
+            if (!re.lay.list) return HRT_EINVAL;
+            *ptr = re.ws + re.lay.list + hrt::list_offsets(0).ctl;
             return HRT_OK;
         default: return HRT_EINVAL;
     }

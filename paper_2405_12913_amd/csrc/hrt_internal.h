@@ -55,18 +55,59 @@ struct PlaneEntry {
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
     size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, stack, reps,
-        stack_phi, stack_delta, rm_mesh, rm_tw, total;
+        stack_phi, stack_delta, rm_mesh, rm_tw, list, total;
     int64_t nbins;
 };
-// max_count: most lens planes in one shell (the lens-plane stack holds one shell's planes);
-// rm_n: ray-mesh size (0 without HRT_RAY_MESH)
-Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_count, int64_t rm_n);
+
+// Mover-list run (kd_tiles variants 5 and 6, FP32): between re-binnings the particles that
+// stay in their paint bin keep their slot in the bin-ordered record buffer (the bins'
+// "fronts"); a particle that leaves its bin leaves a hole (record index -1) and goes, with
+// every particle of the side list, to the list U, which is then sorted by bin into the side
+// list S read by the next step. Every particle outside the fronts is in the list, so the
+// holes number exactly the list's entries. Control words per step parity: a step with
+// parity q reads ctl[q] and its settle writes ctl[1 - q].
+struct ListCtl {
+    unsigned int cur;        // record buffer holding the fronts
+    unsigned int nlist;      // entries of S
+    unsigned int holes;      // holes in the fronts (= entries of the list)
+    unsigned int ucount;     // entries appended to U by this step's kick-drift
+    unsigned int rebuilds;   // re-binnings so far in this run
+    unsigned int limit;      // a step that starts with more list entries than this re-bins
+    unsigned int pad[2];
+};
+
+// Byte offsets of the mover-list region of one realisation (P particles, nbins paint bins),
+// used by the host layout and by the kernels that carve the region. The particle data of
+// the run lie in the sorted-state regions as records [rec0 | S | rec1 | U] (P, P, P and 2P
+// entries) and momenta [mom0 | S | mom1 | U] (3P, 3P, 3P values, then 3 x 2P: U's axes are
+// 2P apart), so every list kernel indexes them from rec0 and mom0 with non-negative 32-bit
+// offsets (host-checked: 15P < 2^31). U has room for 2P entries: kick-drift workgroup w
+// appends to [ubase[w], ubase[w] + ucnt[w]), ubase[w] being the start of its inputs in the
+// fronts plus in S (disjoint ranges below 2P).
+struct ListOffsets {
+    size_t ctl, lcount, lcursor, loffs, lsums, ubase, ucnt, total;
+};
+__host__ __device__ inline size_t list_al(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ inline ListOffsets list_offsets(size_t nbins) {
+    ListOffsets o{};
+    const size_t nblk = (nbins + 1023) / 1024, npairs = nbins / 16;
+    size_t at = 0;
+    o.ctl = at;     at += list_al(2 * sizeof(ListCtl));
+    o.lcount = at;  at += list_al(nbins * 4);
+    o.lcursor = at; at += list_al(nbins * 4);
+    o.loffs = at;   at += list_al((nbins + 1) * 4);
+    o.lsums = at;   at += list_al((nblk + 1) * 4);
+    o.ubase = at;   at += list_al(npairs * 4);
+    o.ucnt = at;    at += list_al(npairs * 4);
+    o.total = at;
+    return o;
+}
 
 // Kernel ids for the optional per-kernel HIP-event timing (hrt_profile_*).
 enum KernelId {
     K_BIN_COUNT = 0, K_BIN_SCAN, K_BIN_SCATTER, K_PAINT, K_FFT_X_R2C, K_FFT_Y_FWD, K_FFT_Z_POISSON,
     K_FFT_Y_INV, K_FFT_X_C2R, K_GRADIENT, K_MATTER_KD, K_RAY_STEP, K_CONVERGENCE,
-    K_STATE_SCATTER, K_KD_TILES, K_PLANE_GRADIENT, K_STATE_GATHER, K_RAY_MESH, K_COUNT
+    K_STATE_SCATTER, K_KD_TILES, K_PLANE_GRADIENT, K_STATE_GATHER, K_RAY_MESH, K_LIST_SETTLE, K_COUNT
 };
 struct ProfRecord {
     int id;
@@ -122,6 +163,11 @@ struct StepArgs {
     // kick-drift then works on buffer cur in place.
     int state = 0;               // STATE_LAGRANGIAN, STATE_FROM_CALLER or STATE_SORTED
     int cur = 0;
+    // Mover-list run (FP32 kd_tiles variants 0, 5, 6): the record buffer and the list sizes live in
+    // the device control words ctl[par] (par = step parity) instead of `cur`.
+    bool list = false;
+    int par = 0;
+    int list_shift = 4;          // list_init: re-bin beyond P >> list_shift list entries
 };
 enum { STATE_LAGRANGIAN = 0, STATE_FROM_CALLER = 1, STATE_SORTED = 2 };
 
@@ -187,6 +233,11 @@ hipError_t launch_poisson(hrt_ctx *c, int only = -1);   // every realisation, or
 hipError_t launch_gradient(hrt_ctx *c);
 hipError_t launch_plane_gradient(hrt_ctx *c, int step);      // the step's lens-plane stack
 hipError_t launch_state_gather(hrt_ctx *c, const StepArgs &a);   // sorted state -> caller
+// Mover-list run: list_init before the first step (control words of parity a.par, empty S);
+// list_settle after a step's kick-drift: scan of the mover histogram and sort of U into S,
+// or (once the holes or the list pass their limit) a full re-binning into the other buffer.
+hipError_t launch_list_init(hrt_ctx *c, const StepArgs &a);
+hipError_t launch_list_settle(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_matter_kd(hrt_ctx *c, const StepArgs &a);
 hipError_t launch_ray_step(hrt_ctx *c, const StepArgs &a);
 // HRT_RAY_MESH: the step's kick on the 2D ray mesh (projection of the lens-plane stack,

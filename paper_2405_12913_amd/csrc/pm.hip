@@ -38,6 +38,8 @@ struct Particles {             // one realisation, as the particle kernels see i
     T inv_cell, K, D, inv12cell;
     double scale, inv_scale_rho;
     int fixed_bits;            // scale = 2^fixed_bits
+    char *lbase;               // mover-list region (FP32 moving particles), else NULL
+    int par;                   // mover-list run: the step's parity (its control words)
 };
 
 // CIC weight w in [0, 1] as a fixed-point integer round(w 2^F). For float the product is
@@ -65,6 +67,41 @@ struct PartBatch {
     int pmap, xcd;             // launch-shape variant: particle map, XCD block grouping
 };
 static_assert(sizeof(PartBatch<double>) <= 4096, "kernel argument block over 4 KB");
+
+// Mover-list run (kd_tiles variants 5 and 6): the control region at lbase, carved as
+// list_offsets says; the particle data are indexed from rec0 = rec[0] and mom0 = mom[0]:
+// records [rec0 | S | rec1 | U] (fronts of buffer cur from 2P cur, S from P, U from 3P),
+// momenta [mom0 | S | mom1 | U] (axis d of a front slot at 6P cur + d P + slot, of S at
+// 3P + d P + j, of U at 9P + 2P d + u).
+template <typename T>
+struct ListBufs {
+    ListCtl *ctl;              // ctl[0], ctl[1]: control words per step parity
+    unsigned int *lcount, *lcursor, *loffs, *lsums;   // histogram / cursors / offsets of S
+    unsigned int *ubase, *ucnt;   // extent of each kick-drift workgroup's entries of U
+};
+template <typename T>
+__device__ __forceinline__ ListBufs<T> list_bufs(const Particles<T> &a) {
+    const ListOffsets o = list_offsets((size_t)a.nbins);
+    char *const b = a.lbase;
+    auto u32 = [&](size_t off) { return reinterpret_cast<unsigned int *>(b + off); };
+    return ListBufs<T>{reinterpret_cast<ListCtl *>(b + o.ctl), u32(o.lcount), u32(o.lcursor), u32(o.loffs),
+                       u32(o.lsums), u32(o.ubase), u32(o.ucnt)};
+}
+
+// Load of a value that is the same for the whole wave and that no kernel running alongside
+// writes (the bin offsets, written by an earlier launch), through the constant address space,
+// so it is a scalar load: it is not counted with the vector memory operations, and waiting
+// for it does not wait for the stores the wave has issued.
+__device__ __forceinline__ unsigned int uniform_load(const unsigned int *p) {
+    return *(const __attribute__((address_space(4))) unsigned int *)p;
+}
+
+// A step that starts with more entries in S than the run's limit (P/16 by default) ends with
+// a re-binning instead of the sort of U into S; it is known before the step's kick-drift,
+// which then counts every particle into the full histogram (else only U's entries into the
+// mover histogram). The list holds about one step's movers per step since the last
+// re-binning (1-2 % of the particles per step on an evolved field at 256^3).
+__device__ __forceinline__ bool list_rebuild(const ListCtl &q, int) { return q.nlist > q.limit; }
 
 // np is a power of two (it divides the power-of-two mesh size): lattice indices by shifts.
 template <typename T>
@@ -173,16 +210,35 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(PartBatch<T> b) {
 }
 
 // Exclusive scan, 1024 elements per block: local scan + block totals.
-template <typename T>
+// The arrays one scan works on. LIST (the settle of a mover-list step): the full histogram
+// (count -> offs, cursor: a re-binning) or the mover histogram (lcount -> loffs, lcursor:
+// the sort of U), as list_rebuild decides from the step's control words; every block of
+// the scan decides alike (the words are final once the kick-drift has run).
+struct ScanArrays {
+    unsigned int *count, *offs, *sums, *cursor;
+    bool rebuild;
+};
+template <typename T, bool LIST>
+__device__ __forceinline__ ScanArrays scan_arrays(const Particles<T> &a) {
+    if constexpr (LIST) {
+        const ListBufs<T> l = list_bufs(a);
+        if (!list_rebuild(l.ctl[a.par], a.P)) return ScanArrays{l.lcount, l.loffs, l.lsums, l.lcursor, false};
+        return ScanArrays{a.count, a.offs, a.sums, a.cursor, true};
+    }
+    return ScanArrays{a.count, a.offs, a.sums, a.cursor, false};
+}
+
+template <typename T, bool LIST>
 __global__ __launch_bounds__(256) void scan_local_kernel(PartBatch<T> b) {
     __shared__ unsigned int sh[256];
     const int r = real_of(b.map, blockIdx.x);
     const Particles<T> &a = b.r[r];
+    const ScanArrays s = scan_arrays<T, LIST>(a);
     const int blk = blockIdx.x - b.map.start[r];
     const int base = blk * 1024 + threadIdx.x * 4;
     unsigned int v[4], t = 0;
     for (int k = 0; k < 4; ++k) {
-        v[k] = (base + k < a.nbins) ? a.count[base + k] : 0u;
+        v[k] = (base + k < a.nbins) ? s.count[base + k] : 0u;
         t += v[k];
     }
     sh[threadIdx.x] = t;
@@ -195,23 +251,24 @@ __global__ __launch_bounds__(256) void scan_local_kernel(PartBatch<T> b) {
     }
     unsigned int run = sh[threadIdx.x] - t;   // exclusive prefix of this thread
     for (int k = 0; k < 4; ++k) {
-        if (base + k < a.nbins) a.offs[base + k] = run;
+        if (base + k < a.nbins) s.offs[base + k] = run;
         run += v[k];
     }
-    if (threadIdx.x == 255) a.sums[blk] = sh[255];
+    if (threadIdx.x == 255) s.sums[blk] = sh[255];
 }
 
 // Exclusive scan of the block totals, one block of 1024 threads per realisation.
-template <typename T>
+template <typename T, bool LIST>
 __global__ __launch_bounds__(1024) void scan_sums_kernel(PartBatch<T> b) {
     __shared__ unsigned int sh[1024];
     const Particles<T> &a = b.r[blockIdx.x];
+    const ScanArrays s = scan_arrays<T, LIST>(a);
     const int nb = a.nblk;
     const int per = (nb + 1023) / 1024;
     const int b0 = threadIdx.x * per;
     unsigned int t = 0;
     for (int k = 0; k < per; ++k)
-        if (b0 + k < nb) t += a.sums[b0 + k];
+        if (b0 + k < nb) t += s.sums[b0 + k];
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -223,22 +280,24 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(PartBatch<T> b) {
     unsigned int run = sh[threadIdx.x] - t;
     for (int k = 0; k < per; ++k) {
         if (b0 + k < nb) {
-            unsigned int v = a.sums[b0 + k];
-            a.sums[b0 + k] = run;
+            unsigned int v = s.sums[b0 + k];
+            s.sums[b0 + k] = run;
             run += v;
         }
     }
-    if (threadIdx.x == 1023) a.sums[nb] = sh[1023];
+    if (threadIdx.x == 1023) s.sums[nb] = sh[1023];
 }
 
 // FUSED (every realisation has at most 1024 blocks of 1024 bins): the block totals are not
 // scanned by a kernel of their own; each workgroup sums the totals of the blocks before its
 // own (and all of them, for the end offset) from the unscanned array, integer sums in any
 // order. Otherwise scan_sums_kernel has scanned them in place.
-template <typename T, bool FUSED>
+// LIST: both histograms are cleared for the next kick-drift, and a re-binning empties S.
+template <typename T, bool FUSED, bool LIST>
 __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
     const int r = real_of(b.map, blockIdx.x);
     const Particles<T> &a = b.r[r];
+    const ScanArrays s = scan_arrays<T, LIST>(a);
     const int i0 = (blockIdx.x - b.map.start[r]) * 256, i = i0 + threadIdx.x;
     unsigned int pre, total;
     if constexpr (FUSED) {
@@ -246,7 +305,7 @@ __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
         const int grp = i0 / 1024;              // uniform: 1024 is a multiple of 256
         unsigned int v = 0, vt = 0;
         for (int k = threadIdx.x; k < a.nblk; k += 256) {
-            const unsigned int x = a.sums[k];
+            const unsigned int x = s.sums[k];
             v += k < grp ? x : 0u;
             vt += x;
         }
@@ -262,16 +321,21 @@ __global__ __launch_bounds__(256) void scan_add_kernel(PartBatch<T> b) {
         pre = part[0][0] + part[0][1] + part[0][2] + part[0][3];
         total = part[1][0] + part[1][1] + part[1][2] + part[1][3];
     } else {
-        pre = i < a.nbins ? a.sums[i / 1024] : 0u;
-        total = a.sums[a.nblk];
+        pre = i < a.nbins ? s.sums[i / 1024] : 0u;
+        total = s.sums[a.nblk];
     }
     if (i < a.nbins) {
-        const unsigned int v = a.offs[i] + pre;
-        a.offs[i] = v;
-        a.cursor[i] = v;
-        a.count[i] = 0u;       // consumed by scan_local: zero for the next count (kick-drift)
+        const unsigned int v = s.offs[i] + pre;
+        s.offs[i] = v;
+        s.cursor[i] = v;
+        s.count[i] = 0u;       // consumed by scan_local: zero for the next count (kick-drift)
     }
-    if (i == 0) a.offs[a.nbins] = total;
+    if (i == 0) s.offs[a.nbins] = total;
+    if constexpr (LIST) {
+        const ListBufs<T> l = list_bufs(a);
+        if (i < a.nbins && s.rebuild) l.loffs[i] = 0u;    // S is empty after a re-binning
+        if (i == 0 && s.rebuild) l.loffs[a.nbins] = 0u;
+    }
 }
 
 // The 27 bin ranges whose particles reach tile (tx, ty, tz): the tile's own 8 bins and
@@ -291,18 +355,25 @@ __constant__ signed char kRangeTab[27][4] = {
     {-1, -1, 0, 3}, {-1, -1, 0, 7}, {-1, 0, -1, 5}, {-1, 0, -1, 7}, // two axes
     {0, -1, -1, 6}, {0, -1, -1, 7}, {-1, -1, -1, 7}};               // three axes
 
-template <typename T>
+// LIST (mover-list run): 54 ranges, the 27 bins' fronts in the record buffer and then the
+// same 27 bins' entries of the sorted side list S (offsets loffs), as indices from rec0 (the
+// fronts shifted by fo, S by so).
+template <typename T, bool LIST = false>
 __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int ty, int tz, int *rstart,
-                                            int *rpre, signed char (*rd)[3], int k) {
+                                            int *rpre, signed char (*rd)[3], int k,
+                                            const unsigned int *loffs = nullptr, int fo = 0, int so = 0) {
+    constexpr int NR = LIST ? 54 : 27;
     if (k >= 64) return;                        // the group's first wave does it all
     const int nt = a.n / kTile;
     int size = 0;
-    if (k < 27) {
-        const int dx = kRangeTab[k][0], dy = kRangeTab[k][1], dz = kRangeTab[k][2];
+    if (k < NR) {
+        const int kk = k < 27 ? k : k - 27;
+        const int dx = kRangeTab[kk][0], dy = kRangeTab[kk][1], dz = kRangeTab[kk][2];
         const int tn = ((((tz + dz) & (nt - 1)) * nt + ((ty + dy) & (nt - 1))) * nt + ((tx + dx) & (nt - 1)));
-        const int bb = tn * 8 + kRangeTab[k][3];
-        const unsigned int o0 = a.offs[bb], o1 = a.offs[bb + 1];
-        rstart[k] = (int)o0;
+        const int bb = tn * 8 + kRangeTab[kk][3];
+        const unsigned int *const o = (LIST && k >= 27) ? loffs : a.offs;
+        const unsigned int o0 = o[bb], o1 = o[bb + 1];
+        rstart[k] = (int)o0 + (LIST ? (k >= 27 ? so : fo) : 0);    // LIST: indices from rec0
         size = (int)(o1 - o0);
         rd[k][0] = (signed char)dx;
         rd[k][1] = (signed char)dy;
@@ -310,11 +381,11 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
     }
     int incl = size;                            // inclusive prefix over the wave's lanes
 #pragma unroll
-    for (int off = 1; off < 32; off <<= 1) {
+    for (int off = 1; off < (LIST ? 64 : 32); off <<= 1) {
         const int v = __shfl_up(incl, off);
         if (k >= off) incl += v;
     }
-    if (k < 27) rpre[k + 1] = incl;
+    if (k < NR) rpre[k + 1] = incl;
     if (k == 0) rpre[0] = 0;
 }
 
@@ -368,15 +439,15 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
 // nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
 // the bin-range round trip) are shared by several tiles; at one particle per node two tiles
 // per workgroup keep twice as many tiles resident per CU (wave slots, not LDS, limit it).
-// FP32: 32-bit LDS sums at the tile's own scale 2^s, s = min(24, 31 - ceil(log2(m + 1))) with
-// m = min(entries, 1024). The entries are added in chunks of 1024, and after each chunk every
-// lane folds the chunk's sums of its nodes into 64-bit LDS sums: a node's chunk sum is at
-// most m 2^s <= 2^31 (weights <= 1), so no 32-bit sum overflows, and each weight is rounded
-// to 2^-(s+1) <= 2^-21, about the FP32 rounding of the cell fractions themselves: half the
-// LDS bytes per atomic of a 64-bit sum and a two-instruction conversion. NC copies of the
-// sums (lane l adds into copy l mod NC, copies 24 banks apart) divide the same-node conflicts
-// of one instruction by about NC; the copies are summed in the fold. FP64: exact 64-bit sums
-// at the global scale, one pass.
+// FP32: 32-bit LDS sums at the scale 2^20 (weights rounded to 2^-21, about the FP32 rounding
+// of the cell fractions themselves). The entries are added in chunks of 1024, and after each
+// chunk every lane folds the chunk's sums of its nodes into 64-bit LDS sums: a node's chunk
+// sum is at most 1024 2^20 = 2^30 (weights <= 1), so no 32-bit sum overflows: half the LDS
+// bytes per atomic of a 64-bit sum and a two-instruction conversion. The scale is the same
+// for every tile, so it depends on no count (the mover-list run's holes do not change it).
+// NC copies of the sums (lane l adds into copy l mod NC, copies 24 banks apart) divide the
+// same-node conflicts of one instruction by about NC; the copies are summed in the fold.
+// FP64: exact 64-bit sums at the global scale, one pass.
 // SORTED: the particles are sorted-state records (buffer cur) rather than the binned
 // (fraction, local cell) entries of the Lagrangian-order scatter.
 // The work of logical block blk (TPB tiles).
@@ -384,8 +455,11 @@ constexpr int kPaintDepth = 4;              // entries in flight per lane
 constexpr int kPaintChunk = 1024;           // FP32 entries per chunk of 32-bit sums
 constexpr int kAccCopy = kAccSize + 8;      // stride of the FP32 copies (600 = 24 mod 64)
 
-template <typename T, int TPB, bool SORTED, int NC>
+// LIST (mover-list run, SORTED): the front of each bin (holes skipped) in the record buffer
+// of the step's control words, then its entries of the side list S.
+template <typename T, int TPB, bool SORTED, int NC, bool LIST = false>
 __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur, int blk) {
+    constexpr int NR = LIST ? 54 : 27, RS = LIST ? 64 : 32;   // ranges; their arrays' stride
     constexpr int G = kThreads / TPB;           // lanes per tile
     constexpr bool kWide = sizeof(T) == 8;
     constexpr int kCopies = kWide ? 1 : NC;
@@ -395,9 +469,9 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     using Acc = typename std::conditional<kWide, unsigned long long, unsigned int>::type;
     __shared__ Acc acc[TPB][kCopies * kStride];
     __shared__ unsigned long long sum64[TPB][kWide ? 1 : 512];     // FP32: folded chunk sums
-    __shared__ __align__(16) int rstart[TPB][32];
-    __shared__ __align__(16) int rpre[TPB][32];
-    __shared__ __align__(16) signed char rd[TPB][32][3];
+    __shared__ __align__(16) int rstart[TPB][RS];
+    __shared__ __align__(16) int rpre[TPB][RS];
+    __shared__ __align__(16) signed char rd[TPB][RS][3];
     const int rr = real_of(b.map, blk);
     const Particles<T> &a = b.r[rr];
     const int n = a.n, nt = n / kTile;
@@ -405,18 +479,24 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     const int t = (blk - b.map.start[rr]) * TPB + g;
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     for (int k = lane; k < kCopies * kStride; k += G) acc[g][k] = Acc(0);
-    tile_ranges<T>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane);
+    const unsigned int *loffs = nullptr;
+    int fo = 0;                                 // LIST: fronts from rec0 + fo, S from rec0 + P
+    if constexpr (LIST) {
+        const ListBufs<T> l = list_bufs(a);
+        loffs = l.loffs;
+        fo = uniform_load(&l.ctl[a.par].cur) ? 2 * a.P : 0;
+        cur = 0;
+    }
+    tile_ranges<T, LIST>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane, loffs, fo, a.P);
     __syncthreads();
-    const int total = rpre[g][27];
+    const int total = rpre[g][NR];
     // chunks: uniform over the workgroup (every group passes the same barriers)
     int nch = 1;                                // at least one pass (its fold writes the sums)
     if constexpr (!kWide) {
 #pragma unroll
-        for (int gg = 0; gg < TPB; ++gg) nch = max(nch, (rpre[gg][27] + kPaintChunk - 1) / kPaintChunk);
+        for (int gg = 0; gg < TPB; ++gg) nch = max(nch, (rpre[gg][NR] + kPaintChunk - 1) / kPaintChunk);
     }
-    const int m = min(total, kPaintChunk);
-    const int bits = m > 0 ? 32 - __clz(m) : 0;                  // ceil(log2(m + 1))
-    const int ts = (31 - bits) < 24 ? 31 - bits : 24;            // FP32 scale 2^ts
+    constexpr int ts = 20;                      // FP32 scale 2^ts
     const float fscale = ldexpf(1.0f, ts);
     Acc *const mine = acc[g] + (kWide ? 0 : (lane % kCopies) * kStride);
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
@@ -458,6 +538,7 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
                 v4<T> e = ev[k];
                 const int r = rv[k];
                 if (idx + kPaintDepth * G < total) request(idx + kPaintDepth * G, ev[k], rv[k]);
+                if (LIST && rec_index<T>(e) < 0) continue;   // a hole left by a mover
                 if constexpr (SORTED) {             // record -> (fractions, local cell)
                     int c[3];
                     T f[3];
@@ -467,7 +548,9 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
                     e.z = f[2];
                     e.w = index_field<T>(((c[2] & 7) * 8 + (c[1] & 7)) * 8 + (c[0] & 7));
                 }
-                if (r == 0) {                       // own tile, no upper face: 8 inside corners
+                // own tile, no upper face: 8 inside corners (the list's part of that bin,
+                // range 27, takes the checked path: testing for it too costs 5 VGPRs)
+                if (r == 0) {
                     paint_one<T, Acc, true>(fixed_bits, mine, e, 0, 0, 0, scale, fscale);
                 } else {
                     const int dx = rd[g][r][0], dy = rd[g][r][1], dz = rd[g][r][2];
@@ -506,9 +589,9 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     }
 }
 
-template <typename T, int TPB, bool SORTED, int NC>
+template <typename T, int TPB, bool SORTED, int NC, bool LIST = false>
 __global__ __launch_bounds__(kThreads) void paint_tiles_kernel(PartBatch<T> b, int cur) {
-    paint_tiles_body<T, TPB, SORTED, NC>(b, cur, logical_block(b.xcd));
+    paint_tiles_body<T, TPB, SORTED, NC, LIST>(b, cur, logical_block(b.xcd));
 }
 
 // One lane per ILP particles, particles in Lagrangian order (patch maps), optionally with
@@ -734,13 +817,6 @@ __device__ __forceinline__ void kd_move(v4<T> *recs, T *mom, size_t P, int j, in
     if (COUNT) wave_aggregated_increment<false>(count, key);
 }
 
-// Load of a value that is the same for the whole wave and that no kernel running alongside
-// writes (the bin offsets, written by an earlier launch), through the constant address space,
-// so it is a scalar load: it is not counted with the vector memory operations, and waiting
-// for it does not wait for the stores the wave has issued.
-__device__ __forceinline__ unsigned int uniform_load(const unsigned int *p) {
-    return *(const __attribute__((address_space(4))) unsigned int *)p;
-}
 
 // One workgroup per tile (logical block blk).
 template <typename T, bool COUNT>
@@ -868,6 +944,316 @@ __global__ __launch_bounds__(kPairThreads) void kd_pairs_kernel(PartBatch<T> b, 
     }
 }
 
+// Mover-list form of kd_pairs_kernel (kd_tiles variants 5 and 6, FP32). The pair's particles
+// are the fronts of its 16 bins (one contiguous range of the record buffer named by the
+// step's control words; holes skipped) followed by its 16 bins' entries of the side list S
+// (one contiguous range). A front particle whose drifted position keeps its bin is stored in
+// place; every other particle (a front one that changes bin, which leaves a hole, and every
+// entry of S) is appended to the workgroup's part of U, [ubase, ubase + total): its slot
+// comes from a workgroup counter in LDS (one LDS atomic per wave), so no global counter is
+// contended. With COUNT every particle is counted into the full histogram and U's entries
+// into the mover histogram. The arithmetic of a particle is that of kd_move, so the run gives
+// the same bits as the other orders.
+template <typename T, bool COUNT>
+__device__ __forceinline__ void kd_move_list(v4<T> *rec0, T *mom0, int P, int rF, int mF, int F, int i, int total,
+                                             KdItem<T> &it, const v4<T> *gl, T K, T D,
+                                             const CellGeom<T> &cg, int lnt, unsigned int *count,
+                                             const ListBufs<T> &l, unsigned int *nu, int ub, bool rebuild) {
+    int key = -1, okey = -1;
+    bool mover = false, live = false;
+    const bool front = i < F;
+    if (i < total && !(front && rec_index<T>(it.rec) < 0)) {
+        live = true;
+        int c[3];
+        T f[3];
+        record_cell<T>(cg, it.rec, c, f);
+        okey = bin_key(c, lnt);
+        const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGX2 + (c[0] & 15);
+        v4<T> g[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGX2 + (k & 1)];
+        T sv[3] = {it.rec.x, it.rec.y, it.rec.z};
+        cic_kick_drift<T>(f, g, K, D, sv, it.p);
+        it.rec.x = sv[0];
+        it.rec.y = sv[1];
+        it.rec.z = sv[2];
+        record_cell<T>(cg, it.rec, c, f);
+        key = bin_key(c, lnt);
+        mover = !front || key != okey;
+    }
+    // one store of the record and of each momentum per lane: a stayer's to its front slot,
+    // a mover's to its slot u of U (record 3P + u, axis d at 9P + 2P d + u); a front mover
+    // also marks its old slot as a hole
+    int rd = i + rF, md = i + mF, ms = P;
+    const unsigned long long mv = __ballot(mover);
+    if (mv) {                                   // wave-uniform
+        const int lane = __lane_id(), leader = __ffsll((long long)mv) - 1;
+        unsigned int base = 0;
+        if (lane == leader) base = atomicAdd(nu, (unsigned int)__popcll(mv));
+        base = __shfl(base, leader);
+        if (mover) {
+            const int u = ub + (int)base + __popcll(mv & ((1ull << lane) - 1ull));
+            if (front) rec0[rd].w = index_field<T>(-1);     // the hole (index -1)
+            rd = 3 * P + u;
+            md = 9 * P + u;
+            ms = 2 * P;
+        }
+    }
+    if (live) {
+        asm volatile("" : "+v"(it.rec.w));      // store the whole record: no partial lines
+        rec0[rd] = it.rec;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom0 + (md + d * ms));
+    }
+    if (COUNT) {                                // full histogram before a re-binning, else U's
+        if (rebuild) wave_aggregated_increment<false>(count, key);
+        else wave_aggregated_increment<false>(l.lcount, mover ? key : -1);
+    }
+}
+
+// Input i of the pair: front slot f0 + i of buffer cur (record i + rF, momenta d P + i + mF
+// from rec0 / mom0) for i < F, else entry s0 + i - F of S (record i + rS, momenta
+// d P + i + mS).
+template <typename T>
+__device__ __forceinline__ void kd_fetch_list(const v4<T> *rec0, const T *mom0, int P, int rF, int mF, int rS,
+                                              int mS, int F, int i, int total, KdItem<T> &it) {
+    if (i < total) {
+        const bool front = i < F;
+        it.rec = rec0[i + (front ? rF : rS)];
+        const int m = i + (front ? mF : mS);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) it.p[d] = ld_stream(mom0 + (d * P + m));
+    }
+}
+
+template <typename T, bool COUNT>
+__global__ __launch_bounds__(kPairThreads) void kd_pairs_list_kernel(PartBatch<T> b) {
+    __shared__ v4<T> ph4[kPhiQuads2];
+    __shared__ v4<T> gl[kGX2 * kGN * kGN];
+    __shared__ unsigned int nu;                 // entries this workgroup appended to U
+    const int blk = logical_block(b.xcd);
+    const int rr = real_of(b.map, blk);
+    const Particles<T> &a = b.r[rr];
+    const ListBufs<T> l = list_bufs(a);
+    const int n = a.n, nt = n / kTile, P = a.P;
+    const int pw = blk - b.map.start[rr];       // pair index
+    const int t = 2 * pw;                       // the pair's first tile (even x)
+    const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+    const int f0 = (int)uniform_load(a.offs + t * 8), f1 = (int)uniform_load(a.offs + t * 8 + 16);
+    const int s0 = (int)uniform_load(l.loffs + t * 8), s1 = (int)uniform_load(l.loffs + t * 8 + 16);
+    const int F = f1 - f0, total = F + (s1 - s0);
+    if (total == 0) {                           // both tiles empty (uniform over the block)
+        if (threadIdx.x == 0) l.ucnt[pw] = 0u;
+        return;
+    }
+    const int cur = (int)uniform_load(&l.ctl[a.par].cur);
+    const bool rebuild = uniform_load(&l.ctl[a.par].nlist) > uniform_load(&l.ctl[a.par].limit);
+    v4<T> *const rec0 = a.rec[0];
+    T *const mom0 = a.mom[0];
+    const int rF = (cur ? 2 * P : 0) + f0, mF = (cur ? 6 * P : 0) + f0;
+    const int rS = P + s0 - F, mS = 3 * P + s0 - F;
+    const int ub = f0 + s0;                     // this workgroup's part of U
+    if (threadIdx.x == 0) nu = 0u;
+    KdItem<T> c0, c1;
+    kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, (int)threadIdx.x, total, c0);
+    kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, kPairThreads + (int)threadIdx.x, total, c1);
+    for (int e = threadIdx.x; e < kPhiQuads2; e += kPairThreads)
+        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset2(e, tx, ty, tz, n));
+    __syncthreads();
+    pair_gradient<T>(ph4, gl, a.inv12cell);
+    __syncthreads();
+    const T K = a.K, D = a.D;
+    const CellGeom<T> cg = geom_of(a);
+    const int lnt = a.lnt;
+    for (int base = 0; base < total; base += 2 * kPairThreads) {   // same trip count for every lane
+        if (base != 0) {
+            kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, base + (int)threadIdx.x, total, c0);
+            kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, base + kPairThreads + (int)threadIdx.x, total, c1);
+        }
+        kd_move_list<T, COUNT>(rec0, mom0, P, rF, mF, F, base + (int)threadIdx.x, total, c0, gl, K, D, cg, lnt,
+                               a.count, l, &nu, ub, rebuild);
+        kd_move_list<T, COUNT>(rec0, mom0, P, rF, mF, F, base + kPairThreads + (int)threadIdx.x, total, c1, gl, K,
+                               D, cg, lnt, a.count, l, &nu, ub, rebuild);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        l.ubase[pw] = (unsigned int)ub;
+        l.ucnt[pw] = nu;
+        if (nu) atomicAdd(&l.ctl[a.par].ucount, nu);
+    }
+}
+
+// Before the first step of a mover-list run: control words of the first step's parity
+// (fronts in record buffer 0, nothing listed), empty S and mover histogram.
+template <typename T>
+__global__ __launch_bounds__(256) void list_init_kernel(PartBatch<T> b, int shift) {
+    const int r = real_of(b.map, blockIdx.x);
+    const Particles<T> &a = b.r[r];
+    const ListBufs<T> l = list_bufs(a);
+    const int i = (blockIdx.x - b.map.start[r]) * 256 + (int)threadIdx.x;
+    if (i < a.nbins) {
+        l.lcount[i] = 0u;
+        l.loffs[i] = 0u;
+    }
+    if (i == 0) {
+        l.loffs[a.nbins] = 0u;
+        ListCtl z{};
+        z.limit = (unsigned int)a.P >> shift;
+        l.ctl[a.par] = z;
+    }
+}
+
+// Entries of U: the kick-drift workgroup of pair w appended ucnt[w] of them from ubase[w]
+// (record 3P + u, axis d of the momentum at 9P + 2P d + u from rec0 / mom0); the entry's bin
+// is formed again from its position, as the kick-drift formed it.
+template <typename T>
+__device__ __forceinline__ int u_entry(const Particles<T> &a, const CellGeom<T> &cg, int u, v4<T> &rec, T pv[3]) {
+    const size_t P = (size_t)a.P;
+    rec = a.rec[0][3 * P + u];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) pv[d] = a.mom[0][9 * P + 2 * d * P + u];
+    int c[3];
+    T fr[3];
+    record_cell<T>(cg, rec, c, fr);
+    return bin_key(c, a.lnt);
+}
+
+// Settle of a mover-list step, after its kick-drift and the list scan (launch_scan<T,
+// true>), which took the same decision: without a re-binning the entries of U go to their
+// bins' places in S (list cursors); with one, every particle of the fronts (holes skipped)
+// and every entry of U goes to its bin in the other record buffer (bin cursors), which then
+// holds the fronts, with no holes and nothing listed. Workgroup 0 writes the next step's
+// control words. A fixed grid per realisation (the list's size is only known on the device):
+// the fronts in chunks of 1024 consecutive slots per workgroup, four per lane, all loaded
+// before any is placed; U one pair per workgroup at a time, likewise.
+constexpr int kSettleQ = 4;
+constexpr int kSettlePairs = 1024;         // pairs per settle workgroup at most
+template <typename T>
+__global__ __launch_bounds__(kThreads) void list_settle_kernel(PartBatch<T> b) {
+    const int r = real_of(b.map, blockIdx.x);
+    const Particles<T> &a = b.r[r];
+    const ListBufs<T> l = list_bufs(a);
+    const ListCtl q = l.ctl[a.par];
+    const bool rebuild = list_rebuild(q, a.P);
+    const int nb = b.map.start[r + 1] - b.map.start[r];
+    const int blk = (int)blockIdx.x - b.map.start[r];
+    const long long Pl = a.P;
+    const int cur = (int)q.cur, tid = (int)threadIdx.x, npairs = a.nbins / 16;
+    const CellGeom<T> cg = geom_of(a);
+    constexpr int CH = kSettleQ * kThreads;
+    // destination: the other record buffer (re-binning) or S (record P + j, axis d at
+    // 3P + d P + j from rec0 / mom0)
+    unsigned int *const cursor = rebuild ? a.cursor : l.lcursor;
+    v4<T> *const drec = rebuild ? a.rec[1 - cur] : a.rec[0] + a.P;
+    T *const dmo = rebuild ? a.mom[1 - cur] : a.mom[0] + 3 * Pl;
+    auto place = [&](const int (&key)[kSettleQ], const v4<T> (&rec)[kSettleQ], const T (&pv)[kSettleQ][3]) {
+#pragma unroll
+        for (int k = 0; k < kSettleQ; ++k) {
+            const int slot = wave_aggregated_increment<true>(cursor, key[k]);
+            if (key[k] >= 0) {
+                drec[slot] = rec[k];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dmo[d * Pl + slot] = pv[k][d];
+            }
+        }
+    };
+    if (rebuild) {                              // the fronts (whole buffer cur)
+        const v4<T> *const srec = a.rec[cur];
+        const T *const smo = a.mom[cur];
+        for (int base = blk * CH; base < a.P; base += nb * CH) {
+            int key[kSettleQ];
+            v4<T> rec[kSettleQ];
+            T pv[kSettleQ][3];
+#pragma unroll
+            for (int k = 0; k < kSettleQ; ++k) {
+                const int j = base + k * kThreads + tid;
+                key[k] = -1;
+                if (j < a.P) {
+                    rec[k] = srec[j];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) pv[k][d] = ld_stream(smo + d * Pl + j);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kSettleQ; ++k) {
+                const int j = base + k * kThreads + tid;
+                if (j < a.P && rec_index<T>(rec[k]) >= 0) {
+                    int c[3];
+                    T f[3];
+                    record_cell<T>(cg, rec[k], c, f);
+                    key[k] = bin_key(c, a.lnt);
+                }
+            }
+            place(key, rec, pv);
+        }
+    }
+    // U: workgroup blk takes the pairs [p0, p1) (at most kSettlePairs; the grid has at least
+    // npairs / kSettlePairs workgroups), lays their entries end to end by a prefix sum of
+    // their counts in LDS, and places them 1024 at a time; an entry finds its pair by a
+    // binary search over the prefix sums.
+    __shared__ int pre[kSettlePairs + 1];
+    const int per = (npairs + nb - 1) / nb;
+    const int p0 = min(npairs, blk * per), p1 = min(npairs, p0 + per), np = p1 - p0;
+    __shared__ int wsum[kThreads / 64];
+    int cnt_t[kSettlePairs / kThreads], tot = 0;
+#pragma unroll
+    for (int k = 0; k < kSettlePairs / kThreads; ++k) {
+        const int pi = tid * (kSettlePairs / kThreads) + k;
+        cnt_t[k] = pi < np ? (int)l.ucnt[p0 + pi] : 0;
+        tot += cnt_t[k];
+    }
+    int incl = tot;                             // block prefix of the thread totals
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (__lane_id() >= off) incl += v;
+    }
+    if (__lane_id() == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    int run = incl - tot;
+    for (int w = 0; w < (tid >> 6); ++w) run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < kSettlePairs / kThreads; ++k) {
+        pre[tid * (kSettlePairs / kThreads) + k] = run;
+        run += cnt_t[k];
+    }
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) total += wsum[w];
+    if (tid == 0) pre[kSettlePairs] = total;
+    __syncthreads();
+    for (int c0 = 0; c0 < total; c0 += CH) {
+        int key[kSettleQ];
+        v4<T> rec[kSettleQ];
+        T pv[kSettleQ][3];
+#pragma unroll
+        for (int k = 0; k < kSettleQ; ++k) {
+            const int e = c0 + k * kThreads + tid;
+            key[k] = -1;
+            if (e < total) {
+                int lo = 0, hi = np - 1;        // last pair with pre <= e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                const int u = (int)l.ubase[p0 + lo] + (e - pre[lo]);
+                key[k] = u_entry<T>(a, cg, u, rec[k], pv[k]);
+            }
+        }
+        place(key, rec, pv);
+    }
+    if (blk == 0 && tid == 0) {
+        ListCtl nx{};
+        nx.cur = rebuild ? 1u - q.cur : q.cur;
+        nx.nlist = rebuild ? 0u : q.ucount;
+        nx.holes = nx.nlist;                 // every particle outside the fronts is listed
+        nx.ucount = 0u;
+        nx.rebuilds = q.rebuilds + (rebuild ? 1u : 0u);
+        nx.limit = q.limit;
+        l.ctl[1 - a.par] = nx;
+    }
+}
+
 // Requests tile t (realisation rr, sorted slots j0..j1)'s phi block and first 512 particles
 // into registers (nothing for an empty tile).
 template <typename T>
@@ -958,32 +1344,72 @@ __global__ __launch_bounds__(kThreads) void kd_tiles_stream_kernel(PartBatch<T> 
 // particle's record and momenta and writes s and p with contiguous stores. Writing s and p
 // straight from sorted order would scatter six 4-byte stores per particle over partly
 // written lines. Indices outside [0, P) (none in a consistent state) are skipped.
-template <typename T>
+// LIST (mover-list run): the particles are the fronts of the record buffer named by the last
+// step's control words (holes skipped: their index is -1) and the entries of U (list_uperm
+// below); perm holds P + u for entry u of U.
+template <typename T, bool LIST = false>
 __global__ __launch_bounds__(kThreads) void state_perm_kernel(PartBatch<T> b, int cur) {
     const int r = real_of(b.map, blockIdx.x);
     const Particles<T> &a = b.r[r];
     const int j = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
     if (j >= a.P) return;
+    if constexpr (LIST) cur = (int)list_bufs(a).ctl[a.par].cur;
     unsigned int *perm = reinterpret_cast<unsigned int *>(a.rec[1 - cur]);
     const int i = rec_index<T>(a.rec[cur][j]);
     if ((unsigned int)i < (unsigned int)a.P) perm[i] = (unsigned int)j;
 }
 
 template <typename T>
+__global__ __launch_bounds__(kThreads) void list_uperm_kernel(PartBatch<T> b) {
+    const int r = real_of(b.map, blockIdx.x);
+    const Particles<T> &a = b.r[r];
+    const ListBufs<T> l = list_bufs(a);
+    const int nb = b.map.start[r + 1] - b.map.start[r];
+    const int blk = (int)blockIdx.x - b.map.start[r];
+    const int cur = (int)l.ctl[a.par].cur;
+    unsigned int *perm = reinterpret_cast<unsigned int *>(a.rec[1 - cur]);
+    const int lane = __lane_id(), npairs = a.nbins / 16, nwaves = nb * (kThreads / 64);
+    for (int w = blk * (kThreads / 64) + (int)(threadIdx.x >> 6); w < npairs; w += nwaves) {
+        const int ub = (int)l.ubase[w], cnt = (int)l.ucnt[w];
+        for (int k = lane; k < cnt; k += 64) {
+            const int i = rec_index<T>(a.rec[0][3 * (size_t)a.P + ub + k]);
+            if ((unsigned int)i < (unsigned int)a.P) perm[i] = (unsigned int)(a.P + ub + k);
+        }
+    }
+}
+
+template <typename T, bool LIST = false>
 __global__ __launch_bounds__(kThreads) void state_gather_kernel(PartBatch<T> b, int cur) {
     const int r = real_of(b.map, blockIdx.x);
     const Particles<T> &a = b.r[r];
     const size_t P = (size_t)a.P;
     const int i = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
     if (i >= a.P) return;
-    const unsigned int j = reinterpret_cast<const unsigned int *>(a.rec[1 - cur])[i];
-    if (j >= (unsigned int)a.P) return;
-    const v4<T> rec = a.rec[cur][j];
+    const v4<T> *recs = nullptr;
+    const T *mom = nullptr;
+    size_t mstride = P;
+    if constexpr (LIST) cur = (int)list_bufs(a).ctl[a.par].cur;
+    unsigned int j = reinterpret_cast<const unsigned int *>(a.rec[1 - cur])[i];
+    if constexpr (LIST) {
+        if (j >= (unsigned int)a.P) {           // entry j - P of U
+            j -= (unsigned int)a.P;
+            if (j >= 2u * (unsigned int)a.P) return;
+            recs = a.rec[0] + 3 * P;            // U: record 3P + u, axis d at 9P + 2P d + u
+            mom = a.mom[0] + 9 * P;
+            mstride = 2 * P;
+        }
+    }
+    if (!recs) {
+        if (j >= (unsigned int)a.P) return;
+        recs = a.rec[cur];
+        mom = a.mom[cur];
+    }
+    const v4<T> rec = recs[j];
     st_stream(rec.x, a.s[0] + i);
     st_stream(rec.y, a.s[1] + i);
     st_stream(rec.z, a.s[2] + i);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) st_stream(a.mom[cur][d * P + j], a.p[d] + i);
+    for (int d = 0; d < 3; ++d) st_stream(mom[d * mstride + j], a.p[d] + i);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1199,9 +1625,17 @@ void fill_particles(hrt_ctx *c, int r, const hrt_matter &m, Particles<T> &a, dou
     a.inv12cell = (T)(1.0 / (12.0 * re.cell));
     a.phi = reinterpret_cast<const T *>(re.ws + re.lay.mesh_r) + (size_t)n * n * n;
     a.rec[0] = a.sorted;
-    a.rec[1] = re.lay.state ? reinterpret_cast<v4<T> *>(re.ws + re.lay.state) : nullptr;
-    a.mom[0] = re.lay.state ? reinterpret_cast<T *>(a.rec[1] + a.P) : nullptr;
-    a.mom[1] = re.lay.state ? a.mom[0] + (size_t)3 * a.P : nullptr;
+    if (re.lay.list) {                  // records [rec0 | S | rec1 | U], momenta [mom0 | S | mom1 | U]
+        a.rec[1] = a.sorted + (size_t)2 * a.P;
+        a.mom[0] = reinterpret_cast<T *>(re.ws + re.lay.state);
+        a.mom[1] = a.mom[0] + (size_t)6 * a.P;
+    } else {
+        a.rec[1] = re.lay.state ? reinterpret_cast<v4<T> *>(re.ws + re.lay.state) : nullptr;
+        a.mom[0] = re.lay.state ? reinterpret_cast<T *>(a.rec[1] + a.P) : nullptr;
+        a.mom[1] = re.lay.state ? a.mom[0] + (size_t)3 * a.P : nullptr;
+    }
+    a.lbase = re.lay.list ? re.ws + re.lay.list : nullptr;
+    a.par = 0;
 }
 
 template <typename T, typename F>
@@ -1228,29 +1662,36 @@ constexpr int kPaintShapes[7][2] = {{2, 2}, {4, 1}, {2, 1}, {1, 1}, {2, 4}, {1, 
 constexpr int kNumPaintShapes = sizeof(kPaintShapes) / sizeof(kPaintShapes[0]);
 
 template <typename T, int I>
-void launch_paint_shape(int shape, dim3 grid, hipStream_t st, const PartBatch<T> &b, int cur, bool sorted) {
+void launch_paint_shape(int shape, dim3 grid, hipStream_t st, const PartBatch<T> &b, int cur, bool sorted,
+                        bool list = false) {
     if constexpr (I + 1 < kNumPaintShapes) {
-        if (shape != I) return launch_paint_shape<T, I + 1>(shape, grid, st, b, cur, sorted);
+        if (shape != I) return launch_paint_shape<T, I + 1>(shape, grid, st, b, cur, sorted, list);
     }
     constexpr int TPB = kPaintShapes[I][0], NC = kPaintShapes[I][1];
+    if constexpr (sizeof(T) == 4) {
+        if (list) {
+            paint_tiles_kernel<T, TPB, true, NC, true><<<grid, kThreads, 0, st>>>(b, cur);
+            return;
+        }
+    }
     if (sorted) paint_tiles_kernel<T, TPB, true, NC><<<grid, kThreads, 0, st>>>(b, cur);
     else paint_tiles_kernel<T, TPB, false, NC><<<grid, kThreads, 0, st>>>(b, cur);
 }
 
 // Exclusive scan of the bin counts into offsets and cursors, every realisation of b.
-template <typename T>
+template <typename T, bool LIST = false>
 void launch_scan(hrt_ctx *c, PartBatch<T> &b, int R) {
     hipStream_t st = c->stream;
     prof_begin(c);
     set_map(b, R, [](const Particles<T> &a) { return a.nblk; });
-    scan_local_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
+    scan_local_kernel<T, LIST><<<b.map.start[R], 256, 0, st>>>(b);
     int max_nblk = 0;
     for (int k = 0; k < R; ++k) max_nblk = std::max(max_nblk, b.r[k].nblk);
     const bool fused = max_nblk <= 1024;
-    if (!fused) scan_sums_kernel<T><<<R, 1024, 0, st>>>(b);
+    if (!fused) scan_sums_kernel<T, LIST><<<R, 1024, 0, st>>>(b);
     set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
-    if (fused) scan_add_kernel<T, true><<<b.map.start[R], 256, 0, st>>>(b);
-    else scan_add_kernel<T, false><<<b.map.start[R], 256, 0, st>>>(b);
+    if (fused) scan_add_kernel<T, true, LIST><<<b.map.start[R], 256, 0, st>>>(b);
+    else scan_add_kernel<T, false, LIST><<<b.map.start[R], 256, 0, st>>>(b);
     prof_end(c, K_BIN_SCAN);
 }
 
@@ -1290,28 +1731,34 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         PartBatch<T> b{};
         for (int k = 0; k < R; ++k) fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
         const int cur = args.cur;
-        if (!args.counts_ready) {
+        const bool list = args.list && sizeof(T) == 4;
+        for (int k = 0; k < R; ++k) b.r[k].par = args.par;
+        // mover-list run: after its first step the bins are settled by the previous step's
+        // list_settle, so nothing is counted, scanned or scattered here
+        if (!(list && args.state == STATE_SORTED)) {
+            if (!args.counts_ready) {
+                prof_begin(c);
+                set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
+                fill_counts_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
+                set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
+                set_variant(b, c->variant[K_BIN_COUNT], 0);
+                bin_count_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
+                prof_end(c, K_BIN_COUNT);
+            }
+            launch_scan<T>(c, b, R);
             prof_begin(c);
-            set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 255) / 256; });
-            fill_counts_kernel<T><<<b.map.start[R], 256, 0, st>>>(b);
             set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
-            set_variant(b, c->variant[K_BIN_COUNT], 0);
-            bin_count_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
-            prof_end(c, K_BIN_COUNT);
-        }
-        launch_scan<T>(c, b, R);
-        prof_begin(c);
-        set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
-        set_variant(b, c->variant[K_BIN_SCATTER], 0);
-        if (args.state == STATE_LAGRANGIAN) {
-            bin_scatter_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
-            prof_end(c, K_BIN_SCATTER);
-        } else if (args.state == STATE_FROM_CALLER) {
-            state_scatter_kernel<T, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-            prof_end(c, K_STATE_SCATTER);
-        } else {
-            state_scatter_kernel<T, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
-            prof_end(c, K_STATE_SCATTER);
+            set_variant(b, c->variant[K_BIN_SCATTER], 0);
+            if (args.state == STATE_LAGRANGIAN) {
+                bin_scatter_kernel<T><<<b.map.start[R], kThreads, 0, st>>>(b);
+                prof_end(c, K_BIN_SCATTER);
+            } else if (args.state == STATE_FROM_CALLER) {
+                state_scatter_kernel<T, true><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+                prof_end(c, K_STATE_SCATTER);
+            } else {
+                state_scatter_kernel<T, false><<<b.map.start[R], kThreads, 0, st>>>(b, cur);
+                prof_end(c, K_STATE_SCATTER);
+            }
         }
         prof_begin(c);
         // variant: bit 0 = no XCD grouping; pv >> 1 = launch shape kPaintShapes[pv >> 1]
@@ -1323,7 +1770,7 @@ hipError_t paint_impl(hrt_ctx *c, const StepArgs &args) {
         b.pmap = 0;
         b.xcd = (pv & 1) == 0 ? 1 : 0;
         const dim3 grid(b.map.start[R]);
-        launch_paint_shape<T, 0>(shape, grid, st, b, cur, sorted);
+        launch_paint_shape<T, 0>(shape, grid, st, b, cur, sorted, list);
         prof_end(c, K_PAINT);
     }
     return hipGetLastError();
@@ -1350,7 +1797,15 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             // FP32: x-pairs of tiles per workgroup unless one tile per workgroup is asked for
             // (the pair's LDS block would exceed 64 KB in FP64)
             const int kdv = c->variant[K_KD_TILES];
-            if (sizeof(T) == 4 && (kdv == 0 || kdv == 4)) {
+            if (sizeof(T) == 4 && args.list) {          // mover-list run (variant 5)
+                if constexpr (sizeof(T) == 4) {
+                    for (int k = 0; k < R; ++k) b.r[k].par = args.par;
+                    set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / 2; });
+                    const dim3 grid(b.map.start[R]);
+                    if (args.count_next) kd_pairs_list_kernel<T, true><<<grid, kPairThreads, 0, c->stream>>>(b);
+                    else kd_pairs_list_kernel<T, false><<<grid, kPairThreads, 0, c->stream>>>(b);
+                }
+            } else if (sizeof(T) == 4 && (kdv == 0 || kdv == 4)) {
                 if constexpr (sizeof(T) == 4) {
                     set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / 2; });
                     const dim3 grid(b.map.start[R]);
@@ -1437,6 +1892,55 @@ hipError_t launch_gbar_tiles(hrt_ctx *c, int k, bool rays, const AdjScratch &s) 
     return c->f64 ? gbar_tiles_impl<double>(c, k, rays, s) : gbar_tiles_impl<float>(c, k, rays, s);
 }
 
+template <typename T>
+hipError_t list_init_impl(hrt_ctx *c, const StepArgs &args) {
+    const int nre = (int)c->re.size();
+    for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
+        const int R = std::min(kMaxBatch, nre - r0);
+        PartBatch<T> b{};
+        for (int k = 0; k < R; ++k) {
+            fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
+            b.r[k].par = args.par;
+        }
+        set_map(b, R, [](const Particles<T> &a) { return (a.nbins + 1 + 255) / 256; });
+        list_init_kernel<T><<<b.map.start[R], 256, 0, c->stream>>>(b, args.list_shift);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t list_settle_impl(hrt_ctx *c, const StepArgs &args) {
+    const int nre = (int)c->re.size();
+    for (int r0 = 0; r0 < nre; r0 += kMaxBatch) {
+        const int R = std::min(kMaxBatch, nre - r0);
+        PartBatch<T> b{};
+        for (int k = 0; k < R; ++k) {
+            fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
+            b.r[k].par = args.par;
+        }
+        launch_scan<T, true>(c, b, R);
+        prof_begin(c);
+        // up to 2048 workgroups per realisation (eight waves per SIMD on every CU), and at
+        // least one per kSettlePairs pairs
+        set_map(b, R, [](const Particles<T> &a) {
+            return std::max(std::min(2048, particle_blocks(a.P)), (a.nbins / 16 + kSettlePairs - 1) / kSettlePairs);
+        });
+        list_settle_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b);
+        prof_end(c, K_LIST_SETTLE);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_list_init(hrt_ctx *c, const StepArgs &a) {
+    if (c->f64) return hipErrorInvalidValue;
+    return list_init_impl<float>(c, a);
+}
+
+hipError_t launch_list_settle(hrt_ctx *c, const StepArgs &a) {
+    if (c->f64) return hipErrorInvalidValue;
+    return list_settle_impl<float>(c, a);
+}
+
 hipError_t launch_paint(hrt_ctx *c, const StepArgs &a) {
     return c->f64 ? paint_impl<double>(c, a) : paint_impl<float>(c, a);
 }
@@ -1454,8 +1958,17 @@ hipError_t state_gather_impl(hrt_ctx *c, const StepArgs &args) {
         for (int k = 0; k < R; ++k) fill_particles<T>(c, r0 + k, args.m[r0 + k], b.r[k], 0.0, 0.0);
         set_map(b, R, [](const Particles<T> &a) { return particle_blocks(a.P); });
         prof_begin(c);
-        state_perm_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
-        state_gather_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+        if (sizeof(T) == 4 && args.list) {
+            for (int k = 0; k < R; ++k) b.r[k].par = args.par;
+            state_perm_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            PartBatch<T> bu = b;
+            set_map(bu, R, [](const Particles<T> &a) { return std::max(1, std::min(2048, a.nbins / 16 / 4)); });
+            list_uperm_kernel<T><<<bu.map.start[R], kThreads, 0, c->stream>>>(bu);
+            state_gather_kernel<T, true><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+        } else {
+            state_perm_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+            state_gather_kernel<T><<<b.map.start[R], kThreads, 0, c->stream>>>(b, args.cur);
+        }
         prof_end(c, K_STATE_GATHER);
     }
     return hipGetLastError();

@@ -20,9 +20,9 @@ HRT_JACOBIAN = 4
 HRT_TIME_DELAY = 8
 HRT_RAY_MESH = 16
 HRT_LOS_NONE, HRT_LOS_DENSITY, HRT_LOS_POTENTIAL = 0, 1, 2
-HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD = 0, 1, 2
+HRT_MESH_DELTA, HRT_MESH_PHI, HRT_MESH_GRAD, HRT_MESH_LIST_CTL = 0, 1, 2, 3
 
-HRT_NUM_KERNELS = 18
+HRT_NUM_KERNELS = 19
 HRT_NOALLOC_MAX_BYTES = 67108864
 
 EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", "pm_force",
@@ -527,6 +527,10 @@ class Simulation:
             raise HRTError("mesh views need a workspace tensor (not available with static_workspace)")
         ptr = c_void_p(0)
         _check(lib().hrt_mesh_ptr(self.ctx, realisation, which, ctypes.byref(ptr)), self.ctx)
+        if which == HRT_MESH_LIST_CTL:              # two records of 8 uint32 (per step parity)
+            import torch
+            off = ptr.value - self.workspace.data_ptr()
+            return self.workspace[off:off + 64].view(torch.int32).view(2, 8)
         n = self.cfgs[realisation].mesh_n
         comps = 4 if which == HRT_MESH_GRAD else 1
         esize = 8 if self.cfg.dtype == HRT_F64 else 4

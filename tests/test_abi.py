@@ -82,7 +82,7 @@ def test_large_config_table_sizes():
     assert abs(t["chi"][-1] - 2312.7) < 0.1
     assert len(t["plane_chi"]) == int(t["chi"][-1] / (400.0 / 256))    # every plane in (0, chi_s)
     nbytes = hrt.hrt_workspace_bytes(c)
-    assert 0.5e9 < nbytes < 2e9
+    assert 0.5e9 < nbytes < 3e9          # incl. the mover-list region (U and S, P entries each)
 
 
 @pytest.mark.parametrize("field,value", [("mesh_n", 48), ("mesh_n", 8), ("ptcl_n", 3), ("n_steps", 0),
@@ -121,7 +121,7 @@ def test_variant_counts():
     counts = {hrt.lib().hrt_kernel_name(k).decode(): hrt.num_variants(k) for k in range(hrt.HRT_NUM_KERNELS)}
     assert counts["matter_kd"] == 16 and counts["ray_step"] == 6 and counts["paint_tiles"] == 14
     assert counts["bin_count"] == 8 and counts["bin_scatter"] == 8
-    assert counts["fft_x_r2c"] == 1 and counts["kd_tiles"] == 5 and counts["state_scatter"] == 1
+    assert counts["fft_x_r2c"] == 1 and counts["kd_tiles"] == 7 and counts["state_scatter"] == 1
     assert hrt.num_variants(hrt.HRT_NUM_KERNELS) == 0
 
 

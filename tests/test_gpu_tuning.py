@@ -126,7 +126,7 @@ def test_run_equals_step_by_step():
     say("case hrt_run vs step by step")
     c = _case()
     base = _run(c, c.sim(), steps=5)
-    for kd, variant in ((2, 0), (3, 0), (4, 0), (1, 0), (1, 8)):
+    for kd, variant in ((2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (1, 0), (1, 8)):
         sim = c.sim()
         sim.set_variant("kd_tiles", kd)
         sim.set_variant("matter_kd", variant)
@@ -213,12 +213,13 @@ def test_paint_variants_with_dense_tiles():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("kd", [0, 3, 4])
+@pytest.mark.parametrize("kd", [0, 3, 4, 5, 6])
 def test_sorted_run_default_threshold_and_dtypes(dtype, kd):
-    """The automatic particle order of hrt_run (paint-bin order from 8 steps on), and the
-    paint-bin order with the persistent pipelined kick-drift, give the bits of step-by-step
-    pm_step / ray_step calls in FP32 and FP64, over a 9-step call that starts mid-schedule
-    (np = n/2: the sorted kick-drift with 64 particles per tile)."""
+    """The automatic particle order of hrt_run (paint-bin order from 8 steps on), the
+    paint-bin order with the persistent pipelined kick-drift, with x-pairs of tiles, and with
+    the movers in a side list (FP32; FP64 runs the plain paint-bin order) give the bits of
+    step-by-step pm_step / ray_step calls in FP32 and FP64, over a 9-step call that starts
+    mid-schedule (np = n/2: the sorted kick-drift with 64 particles per tile)."""
     import torch
     say(f"case sorted run {dtype} kd_tiles {kd}")
     cfg = synth.tiny(mesh_n=64, ptcl_n=32, box=100.0, ray_n=32, fov_deg=2.0, n_steps=12, seed=23)
@@ -268,7 +269,7 @@ def test_sorted_run_with_empty_and_dense_tiles():
         sim.ray_step(ref[2], ref[3], step)
     torch.cuda.synchronize()
     from paper_2405_12913_amd import hrt
-    cases = [(kd, 0) for kd in (0, 3, 4, 1)] + [(2, pv) for pv in range(hrt.num_variants("paint_tiles"))]
+    cases = [(kd, 0) for kd in (0, 3, 4, 6, 1)] + [(kd, pv) for kd in (2, 5) for pv in range(hrt.num_variants("paint_tiles"))]
     for kd, pv in cases:
         got = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
         sim2 = c.sim()
@@ -278,3 +279,45 @@ def test_sorted_run_with_empty_and_dense_tiles():
         torch.cuda.synchronize()
         for a, b in zip(sum(got, []), sum(ref, [])):
             assert torch.equal(a, b), (kd, pv)
+
+
+def test_mover_list_run_sorts_and_rebins():
+    """The mover-list run (kd_tiles 5 and 6) on a clustered state: the side list is sorted
+    on some steps and the whole state re-binned on others (read from the control words), and
+    both variants give the bits of step-by-step pm_step / ray_step calls; a second call on
+    the same context starts afresh."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    say("case mover-list run")
+    cfg = synth.tiny(mesh_n=64, ptcl_n=64, box=64.0, ray_n=32, fov_deg=3.0, n_steps=12, seed=31)
+    c = Case(cfg, seed=31, dtype="f32", dth_rms=1e-4, p_rms=0.6)
+    # momenta with rms 0.2 Mpc/h: about 1 % of the particles change paint bin per step, so
+    # variant 6 (limit P/64) sorts the list on some settles and re-bins on others
+    c.p = (c.p * 0.1).astype(np.float32).astype(np.float64)
+    first, count = 1, 10
+    ref = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
+    sim = c.sim()
+    for step in range(first, first + count):
+        sim.pm_step(ref[0], ref[1], step)
+        sim.ray_step(ref[2], ref[3], step)
+    torch.cuda.synchronize()
+    seen = {}
+    for kd in (5, 6):
+        sim2 = c.sim()
+        sim2.set_variant("kd_tiles", kd)
+        for rep in range(2):
+            got = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
+            sim2.run(got[0], got[1], got[2], got[3], first, count)
+            torch.cuda.synchronize()
+            for a, b in zip(sum(got, []), sum(ref, [])):
+                assert torch.equal(a, b), (kd, rep)
+            ctl = sim2.mesh(hrt.HRT_MESH_LIST_CTL).cpu().numpy()
+            last = ctl[(first + count - 1) & 1]
+            rebuilds, limit = int(last[4]), int(last[5])
+            say(f"  kd_tiles {kd} call {rep}: re-binnings {rebuilds} of {count - 1} settles, limit {limit}, "
+                f"list {int(last[1])}, holes {int(last[2])}, appended in the last step {int(last[3])}")
+            assert limit == (64 ** 3 >> (4 if kd == 5 else 6))
+            seen[kd] = rebuilds
+    # variant 6 re-bins on some settles and sorts the list on others
+    assert 1 <= seen[6] <= count - 2, seen
+    assert seen[5] <= seen[6], seen
