@@ -268,8 +268,8 @@ int hrt_graph_launch(hrt_ctx *ctx);
  * HRT_MESH_GRAD (n^3 interleaved quadruples (G_x, G_y, G_z, 0); HRT_ESTATE after an hrt_run
  * in paint-bin order, which forms G per tile and keeps no G mesh, until the next
  * pm_force / pm_step). HRT_MESH_LIST_CTL: the control words of the mover-list run (kd_tiles
- * variants 5 and 6), two records of 8 uint32 (one per step parity: record buffer holding the
- * bins' fronts, side-list entries, holes, entries appended in the step, re-binnings so far,
+ * variants 0, 5 and 6 in FP32), two records of 8 uint32 (one per step parity: record buffer
+ * holding the bins' fronts, side-list entries, holes, 0, re-binnings so far in the call,
  * re-binning limit, 2 unused), for tests and statistics; HRT_EINVAL for FP64 and static
  * contexts, which have none. */
 enum { HRT_MESH_DELTA = 0, HRT_MESH_PHI = 1, HRT_MESH_GRAD = 2, HRT_MESH_LIST_CTL = 3 };

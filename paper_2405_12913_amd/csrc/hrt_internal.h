@@ -70,7 +70,7 @@ struct ListCtl {
     unsigned int cur;        // record buffer holding the fronts
     unsigned int nlist;      // entries of S
     unsigned int holes;      // holes in the fronts (= entries of the list)
-    unsigned int ucount;     // entries appended to U by this step's kick-drift
+    unsigned int ucount;     // unused (0)
     unsigned int rebuilds;   // re-binnings so far in this run
     unsigned int limit;      // a step that starts with more list entries than this re-bins
     unsigned int pad[2];

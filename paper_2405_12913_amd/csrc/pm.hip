@@ -385,7 +385,27 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
         const int v = __shfl_up(incl, off);
         if (k >= off) incl += v;
     }
-    if (k < NR) rpre[k + 1] = incl;
+    if constexpr (LIST) {
+        // only the ranges that hold entries (and range 0, so that it stays range 0), so
+        // that a lane's walk over the ranges skips the many empty ones of sparse tiles and
+        // short lists; the entries' total is in rpre[63]
+        const bool keep = k < NR && (size > 0 || k == 0);
+        const unsigned long long km = __ballot(keep);
+        const int kc = __popcll(km & ((1ull << k) - 1ull));
+        const int s0 = rstart[k];
+        const signed char d0 = rd[k][0], d1 = rd[k][1], d2 = rd[k][2];
+        __builtin_amdgcn_wave_barrier();
+        if (keep) {
+            rstart[kc] = s0;
+            rd[kc][0] = d0;
+            rd[kc][1] = d1;
+            rd[kc][2] = d2;
+            rpre[kc + 1] = incl;
+        }
+        if (k == NR - 1) rpre[63] = incl;
+    } else {
+        if (k < NR) rpre[k + 1] = incl;
+    }
     if (k == 0) rpre[0] = 0;
 }
 
@@ -489,12 +509,12 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     }
     tile_ranges<T, LIST>(a, tx, ty, tz, rstart[g], rpre[g], rd[g], lane, loffs, fo, a.P);
     __syncthreads();
-    const int total = rpre[g][NR];
+    const int total = rpre[g][LIST ? 63 : NR];
     // chunks: uniform over the workgroup (every group passes the same barriers)
     int nch = 1;                                // at least one pass (its fold writes the sums)
     if constexpr (!kWide) {
 #pragma unroll
-        for (int gg = 0; gg < TPB; ++gg) nch = max(nch, (rpre[gg][NR] + kPaintChunk - 1) / kPaintChunk);
+        for (int gg = 0; gg < TPB; ++gg) nch = max(nch, (rpre[gg][LIST ? 63 : NR] + kPaintChunk - 1) / kPaintChunk);
     }
     constexpr int ts = 20;                      // FP32 scale 2^ts
     const float fscale = ldexpf(1.0f, ts);
@@ -1076,10 +1096,9 @@ __global__ __launch_bounds__(kPairThreads) void kd_pairs_list_kernel(PartBatch<T
                                D, cg, lnt, a.count, l, &nu, ub, rebuild);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        l.ubase[pw] = (unsigned int)ub;
+    if (threadIdx.x == 0) {                     // (no global total: one atomic per workgroup on
+        l.ubase[pw] = (unsigned int)ub;         // one address serialises at 1024^3, 10^6 of them)
         l.ucnt[pw] = nu;
-        if (nu) atomicAdd(&l.ctl[a.par].ucount, nu);
     }
 }
 
@@ -1243,10 +1262,12 @@ __global__ __launch_bounds__(kThreads) void list_settle_kernel(PartBatch<T> b) {
         place(key, rec, pv);
     }
     if (blk == 0 && tid == 0) {
+        // without a re-binning S now holds U's entries: the list scan's total
+        const unsigned int listed = rebuild ? 0u : l.loffs[a.nbins];
         ListCtl nx{};
         nx.cur = rebuild ? 1u - q.cur : q.cur;
-        nx.nlist = rebuild ? 0u : q.ucount;
-        nx.holes = nx.nlist;                 // every particle outside the fronts is listed
+        nx.nlist = listed;
+        nx.holes = listed;                   // every particle outside the fronts is listed
         nx.ucount = 0u;
         nx.rebuilds = q.rebuilds + (rebuild ? 1u : 0u);
         nx.limit = q.limit;

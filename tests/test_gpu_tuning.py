@@ -315,7 +315,7 @@ def test_mover_list_run_sorts_and_rebins():
             last = ctl[(first + count - 1) & 1]
             rebuilds, limit = int(last[4]), int(last[5])
             say(f"  kd_tiles {kd} call {rep}: re-binnings {rebuilds} of {count - 1} settles, limit {limit}, "
-                f"list {int(last[1])}, holes {int(last[2])}, appended in the last step {int(last[3])}")
+                f"list {int(last[1])}, holes {int(last[2])}")
             assert limit == (64 ** 3 >> (4 if kd == 5 else 6))
             seen[kd] = rebuilds
     # variant 6 re-bins on some settles and sorts the list on others
