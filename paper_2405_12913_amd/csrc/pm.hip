@@ -9,8 +9,9 @@
 //   3. bin_scatter write (cell fraction, local cell) of every particle into its bin
 //   4. paint_tiles each tile (one, two or four per workgroup) pulls the particles of its
 //                  own bins and of the upper-face bins of its 7 lower neighbours, and sums
-//                  their CIC weights into the tile's 8^3 nodes in LDS as fixed point (32-bit
-//                  at a per-tile scale for FP32 tiles under 1024 particles, else 64-bit).
+//                  their CIC weights into the tile's 8^3 nodes in LDS as fixed point (FP32:
+//                  32-bit sums of x-pairs of nodes at the scale 2^20, folded into 64-bit
+//                  sums; FP64: 64-bit sums at the global scale).
 // Integer sums are exact and order-independent, so the mesh is bit-identical across
 // runs whatever the atomics' interleaving; each node is written by exactly one
 // workgroup with a plain store. The result is delta = rho / rho_bar - 1.
@@ -415,12 +416,50 @@ __device__ __forceinline__ void tile_ranges(const Particles<T> &a, int tx, int t
 constexpr int kAccPlane = 74, kAccRow = 9, kAccSize = kTile * kAccPlane;
 __device__ __forceinline__ int acc_slot(int x, int y, int z) { return z * kAccPlane + y * kAccRow + x; }
 
+// FP32 sums as node pairs: slot (cx, y, z), cx = -1..7, holds the sums of nodes cx (low 32
+// bits) and cx + 1 (high 32 bits) of row (y, z), so one 64-bit LDS add takes a particle's two
+// x corners. A pair's low sum stays below 2^32 within a chunk (at most 1024 weights of at
+// most 2^20 each), so no carry reaches the high sum and both are exact. Node x is the low
+// half of slot x plus the high half of slot x - 1; nodes -1 and 8 (outside the tile) are
+// never read. Rows of 9 slots, planes of 72.
+constexpr int kPairRow = 9, kPairPlane = 72, kPairSize = kTile * kPairPlane;
+__device__ __forceinline__ int pair_slot(int cx, int y, int z) { return z * kPairPlane + y * kPairRow + cx + 1; }
+
 // Adds the CIC weights of one binned particle to the tile's LDS sums. INSIDE: the particle
 // is in the tile's own bin that touches no upper face (range 0), so its 8 corners are all
 // tile nodes and need no checks; otherwise corners outside the tile (a neighbour's face-bin
 // particle, or an upper face) are skipped. FP32: 32-bit sums with the tile's own scale 2^s
 // (round(w 2^s)); FP64 and dense tiles: 64-bit sums with the global scale. No contraction,
 // so every instantiation of the paint kernel forms the same weights.
+// FP32 form over node pairs (pair_slot): four 64-bit adds per particle, each of the two
+// weights round(w 2^20) of one (y, z) corner row, with the same products as paint_one; only
+// the y and z corners outside the tile are skipped.
+template <bool INSIDE>
+__device__ __forceinline__ void paint_pair(unsigned long long *acc, const v4<float> &e, int dx, int dy, int dz,
+                                           float fscale) {
+#pragma clang fp contract(off)
+    const int lcell = __float_as_int(e.w);
+    const int bx = (INSIDE ? 0 : kTile * dx) + (lcell & 7);
+    const int by = (INSIDE ? 0 : kTile * dy) + ((lcell >> 3) & 7);
+    const int bz = (INSIDE ? 0 : kTile * dz) + (lcell >> 6);
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz) {
+        const int nz = bz + cz;
+        if (!INSIDE && (nz < 0 || nz >= kTile)) continue;
+        const float wz = cz ? e.z : 1.0f - e.z;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+            const int ny = by + cy;
+            if (!INSIDE && (ny < 0 || ny >= kTile)) continue;
+            const float wyz = wz * (cy ? e.y : 1.0f - e.y);
+            const float w0 = wyz * (1.0f - e.x), w1 = wyz * e.x;
+            const unsigned long long v = ((unsigned long long)(unsigned int)rintf(w1 * fscale) << 32) |
+                                         (unsigned long long)(unsigned int)rintf(w0 * fscale);
+            atomicAdd(&acc[pair_slot(bx, ny, nz)], v);
+        }
+    }
+}
+
 template <typename T, typename A, bool INSIDE>
 __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e, int dx, int dy,
                                           int dz, double scale, float fscale) {
@@ -455,25 +494,35 @@ __device__ __forceinline__ void paint_one(int fixed_bits, A *acc, const v4<T> &e
     }
 }
 
+// delta = sum inv - 1 (one rounding) at node k (x fastest) of tile (tx, ty, tz).
+template <typename T>
+__device__ __forceinline__ void store_delta(const Particles<T> &a, int tx, int ty, int tz, int k, double sum,
+                                            double inv) {
+    const int n = a.n;
+    const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
+    st_stream((T)fmadd(sum, inv, -1.0), a.delta + ((size_t)z * n + y) * n + x);
+}
+
 // TPB tiles per workgroup (256 / TPB lanes each): when particles are sparse relative to
 // nodes (np = n/2: 64 per tile) a workgroup's fixed costs (clearing and storing 512 nodes,
 // the bin-range round trip) are shared by several tiles; at one particle per node two tiles
 // per workgroup keep twice as many tiles resident per CU (wave slots, not LDS, limit it).
-// FP32: 32-bit LDS sums at the scale 2^20 (weights rounded to 2^-21, about the FP32 rounding
-// of the cell fractions themselves). The entries are added in chunks of 1024, and after each
-// chunk every lane folds the chunk's sums of its nodes into 64-bit LDS sums: a node's chunk
-// sum is at most 1024 2^20 = 2^30 (weights <= 1), so no 32-bit sum overflows: half the LDS
-// bytes per atomic of a 64-bit sum and a two-instruction conversion. The scale is the same
-// for every tile, so it depends on no count (the mover-list run's holes do not change it).
-// NC copies of the sums (lane l adds into copy l mod NC, copies 24 banks apart) divide the
-// same-node conflicts of one instruction by about NC; the copies are summed in the fold.
+// FP32: 32-bit sums at the scale 2^20 (weights rounded to 2^-21, about the FP32 rounding of
+// the cell fractions themselves), kept as x-pairs of nodes (pair_slot), so a particle takes
+// four 64-bit LDS adds instead of eight 32-bit ones. The entries are added in chunks of 3072:
+// a node's chunk sum is below 3072 2^20 < 2^32 (weights <= 1), so no low half carries into
+// its high neighbour. After each chunk every lane folds its nodes' two halves into 64-bit
+// node sums (a tile of more than one chunk keeps them in the last copy's region). The scale
+// is the same for every tile, so it depends on no count (the mover-list run's holes do not
+// change it). NC copies of the sums (lane l adds into copy l mod NC, copies 24 banks apart)
+// divide the same-node conflicts of one instruction by about NC; the fold sums the copies.
 // FP64: exact 64-bit sums at the global scale, one pass.
 // SORTED: the particles are sorted-state records (buffer cur) rather than the binned
 // (fraction, local cell) entries of the Lagrangian-order scatter.
 // The work of logical block blk (TPB tiles).
-constexpr int kPaintDepth = 4;              // entries in flight per lane
-constexpr int kPaintChunk = 1024;           // FP32 entries per chunk of 32-bit sums
-constexpr int kAccCopy = kAccSize + 8;      // stride of the FP32 copies (600 = 24 mod 64)
+constexpr int kPaintDepth = 2;              // entries in flight per lane (more cost a wave per SIMD)
+constexpr int kPaintChunk = 3072;           // FP32 entries per chunk of 32-bit sums
+constexpr int kAccCopy = kPairSize + 12;    // stride of the FP32 copies (1176 words = 24 mod 64)
 
 // LIST (mover-list run, SORTED): the front of each bin (holes skipped) in the record buffer
 // of the step's control words, then its entries of the side list S.
@@ -485,10 +534,14 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     constexpr int kCopies = kWide ? 1 : NC;
     constexpr int kStride = kWide ? kAccSize : kAccCopy;
     constexpr int kNodes = 512 / G;             // nodes per lane in the fold and the stores
+    constexpr int ts = 20;                      // FP32 scale 2^ts
     static_assert(kPaintChunk % (kPaintDepth * G) == 0, "chunks of whole trips");
-    using Acc = typename std::conditional<kWide, unsigned long long, unsigned int>::type;
+    static_assert((unsigned long long)kPaintChunk << ts < (1ull << 32), "a chunk's pair sums carry");
+    using Acc = unsigned long long;             // FP64: node sums; FP32: node-pair sums
     __shared__ Acc acc[TPB][kCopies * kStride];
-    __shared__ unsigned long long sum64[TPB][kWide ? 1 : 512];     // FP32: folded chunk sums
+    // FP32 tiles of more than one chunk: the node sums of the chunks so far, in the last
+    // copy's region (later chunks add into the other copies), or here with one copy
+    __shared__ unsigned long long sum64[TPB][kWide || kCopies > 1 ? 1 : 512];
     __shared__ __align__(16) int rstart[TPB][RS];
     __shared__ __align__(16) int rpre[TPB][RS];
     __shared__ __align__(16) signed char rd[TPB][RS][3];
@@ -516,9 +569,9 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
 #pragma unroll
         for (int gg = 0; gg < TPB; ++gg) nch = max(nch, (rpre[gg][LIST ? 63 : NR] + kPaintChunk - 1) / kPaintChunk);
     }
-    constexpr int ts = 20;                      // FP32 scale 2^ts
     const float fscale = ldexpf(1.0f, ts);
-    Acc *const mine = acc[g] + (kWide ? 0 : (lane % kCopies) * kStride);
+    Acc *mine = acc[g] + (kWide ? 0 : (lane % kCopies) * kStride);
+    unsigned long long *const sums = kCopies > 1 ? acc[g] + (kCopies - 1) * kStride : sum64[g];
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
@@ -571,41 +624,53 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
                 // own tile, no upper face: 8 inside corners (the list's part of that bin,
                 // range 27, takes the checked path: testing for it too costs 5 VGPRs)
                 if (r == 0) {
-                    paint_one<T, Acc, true>(fixed_bits, mine, e, 0, 0, 0, scale, fscale);
+                    if constexpr (kWide) paint_one<T, Acc, true>(fixed_bits, mine, e, 0, 0, 0, scale, fscale);
+                    else paint_pair<true>(mine, e, 0, 0, 0, fscale);
                 } else {
                     const int dx = rd[g][r][0], dy = rd[g][r][1], dz = rd[g][r][2];
-                    paint_one<T, Acc, false>(fixed_bits, mine, e, dx, dy, dz, scale, fscale);
+                    if constexpr (kWide) paint_one<T, Acc, false>(fixed_bits, mine, e, dx, dy, dz, scale, fscale);
+                    else paint_pair<false>(mine, e, dx, dy, dz, fscale);
                 }
             }
         }
         __syncthreads();
-        if constexpr (!kWide) {                 // fold the chunk's sums into the registers
+        if constexpr (!kWide) {                 // fold the chunk's sums (x = k & 7: low half)
+            const int nc = ch == 0 ? kCopies : (kCopies > 1 ? kCopies - 1 : 1);
+            unsigned long long v[kNodes];
 #pragma unroll
             for (int i = 0; i < kNodes; ++i) {
                 const int k = lane + i * G;
-                const int sl = acc_slot(k & 7, (k >> 3) & 7, k >> 6);
-                unsigned long long v = ch > 0 ? sum64[g][k] : 0ull;
+                const int sl = pair_slot(k & 7, (k >> 3) & 7, k >> 6);
+                v[i] = ch > 0 ? sums[k] : 0ull;
 #pragma unroll
-                for (int cc = 0; cc < kCopies; ++cc) v += acc[g][cc * kStride + sl];
-                sum64[g][k] = v;
-                if (ch + 1 < nch) {
-#pragma unroll
-                    for (int cc = 0; cc < kCopies; ++cc) acc[g][cc * kStride + sl] = 0u;
-                }
+                for (int cc = 0; cc < kCopies; ++cc)
+                    if (cc < nc)
+                        v[i] += (acc[g][cc * kStride + sl] & 0xffffffffull) + (acc[g][cc * kStride + sl - 1] >> 32);
             }
-            if (ch + 1 < nch) __syncthreads();
+            if (kCopies > 1) __syncthreads();   // the sums overwrite the last copy
+#pragma unroll
+            for (int i = 0; i < kNodes; ++i) sums[lane + i * G] = v[i];
+            if (ch + 1 < nch) {                 // clear the copies still added to
+                if (kCopies == 1) __syncthreads();
+                for (int k = lane; k < (kCopies > 1 ? kCopies - 1 : 1) * kStride; k += G) acc[g][k] = 0ull;
+                mine = acc[g] + (kCopies > 1 ? lane % (kCopies - 1) : 0) * kStride;
+                __syncthreads();
+            }
         }
     }
-    // delta = sum / (scale rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
-    const double inv = kWide ? a.inv_scale_rho : ldexp(a.inv_scale_rho * a.scale, -ts);
+    if constexpr (!kWide) {
+        // delta = sum / (2^ts rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
+        const double inv = ldexp(a.inv_scale_rho * a.scale, -ts);
 #pragma unroll
-    for (int i = 0; i < kNodes; ++i) {
-        const int k = lane + i * G;
-        const int x = tx * kTile + (k & 7), y = ty * kTile + ((k >> 3) & 7), z = tz * kTile + (k >> 6);
-        double sum;
-        if constexpr (kWide) sum = (double)(long long)acc[g][acc_slot(k & 7, (k >> 3) & 7, k >> 6)];
-        else sum = (double)sum64[g][k];       // written by this lane in the fold
-        st_stream((T)fmadd(sum, inv, -1.0), a.delta + ((size_t)z * n + y) * n + x);
+        for (int i = 0; i < kNodes; ++i) store_delta<T>(a, tx, ty, tz, lane + i * G, (double)sums[lane + i * G], inv);
+    }
+    if constexpr (kWide) {
+        const double inv = a.inv_scale_rho;
+#pragma unroll
+        for (int i = 0; i < kNodes; ++i) {
+            const int k = lane + i * G;
+            store_delta<T>(a, tx, ty, tz, k, (double)(long long)acc[g][acc_slot(k & 7, (k >> 3) & 7, k >> 6)], inv);
+        }
     }
 }
 
