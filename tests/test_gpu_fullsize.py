@@ -11,7 +11,9 @@ large (1024^3 mesh, 512^3 particles, 2048^2 rays): properties that hold at any s
 need no full oracle solve: the paint of the unperturbed lattice is exact (delta = 7 on the
 even nodes, -1 elsewhere, G = 0 up to rounding), mass is conserved, and handing every
 particle the displacement of its lattice neighbour (the whole particle set moves by one
-lattice spacing, two cells) shifts delta exactly and G to rounding.
+lattice spacing, two cells) shifts delta exactly and G to rounding, along each axis; and a
+field that varies along one axis only (each axis in turn) matches the oracle's potential
+and gradient reduced to that axis (on every node for delta, on sampled lines for phi, G).
 """
 import numpy as np
 import pytest
@@ -122,7 +124,107 @@ def test_large_config_properties():
     # FP32 FFT round-off over log2(n^3) = 30 butterfly levels, forward and inverse, in both
     # solves: ~6e-8 x 30 x 2 x sqrt(2) x a few ~ 3e-5
     assert float((torch.roll(g0, 2, dims=2) - g1).norm() / g0.norm()) < 5e-5
+    # the same along y and z (the y and z passes at 1024^3)
+    for dim in (1, 0):
+        say(f"  lattice shift along mesh dim {dim}")
+        s_shift = [torch.roll(t.view(np_, np_, np_), 1, dims=dim).reshape(-1).contiguous() for t in s]
+        sim.pm_force(s_shift, 0)
+        assert torch.equal(torch.roll(d0, 2, dims=dim), delta)
+        g1 = sim.mesh(hrt.HRT_MESH_GRAD)[..., :3]
+        assert float((torch.roll(g0, 2, dims=dim) - g1).norm() / g0.norm()) < 5e-5
+    del s, s_shift, d0, g0, g1
+    _plane_waves(sim, n, np_, box)
     torch.cuda.synchronize()
+
+
+def _potential_1d(delta, box):
+    """phi with phi'' = delta on a periodic line: the oracle's Green's function -1/k^2
+    (k = 0 mode zero) for a field that varies along one axis only."""
+    n = len(delta)
+    k = 2.0 * np.pi * np.fft.rfftfreq(n, d=box / n)
+    k[0] = 1.0
+    f = -np.fft.rfft(delta) / k ** 2
+    f[0] = 0.0
+    return np.fft.irfft(f, n)
+
+
+def _fd4_1d(phi, box):
+    cell = box / len(phi)
+    return (8.0 * (np.roll(phi, -1) - np.roll(phi, 1)) - (np.roll(phi, -2) - np.roll(phi, 2))) / (12.0 * cell)
+
+
+def _lattice_line_density(s_line, n, box):
+    """delta along the wave's axis for np = n/2 particles per axis displaced by s_line[j]
+    along it (lattice spacing two cells) and by half a cell along the two other axes: CIC
+    along the axis, while across it every node gets weight 1/4 from exactly one lattice
+    column (rho = rho1d / 4 against rho_bar = 1/8)."""
+    np_ = len(s_line)
+    cell = box / n
+    x = (np.arange(np_) * (box / np_) + s_line.astype(np.float64)) / cell
+    i0 = np.floor(x).astype(np.int64)
+    f = x - i0
+    rho = np.bincount(i0 % n, weights=1.0 - f, minlength=n) + np.bincount((i0 + 1) % n, weights=f, minlength=n)
+    return 2.0 * rho - 1.0
+
+
+def _plane_waves(sim, n, np_, box):
+    """A field that varies along one axis only, at the full 1024^3 size, against the
+    oracle's potential and gradient of that field (reduced to the one axis: the reduction is
+    checked against the oracle's 3D solve at 32^3 first). Each axis in turn: a Zel'dovich-like
+    displacement of amplitude 2.5 cells (no crossing) along it, half a cell across it."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    from oracle import mesh
+    # the 1D reduction equals the oracle's 3D solve of a field uniform across two axes
+    n_s, box_s = 32, 50.0
+    rng = np.random.default_rng(5)
+    d1 = rng.normal(size=n_s)
+    d1 -= d1.mean()
+    phi3 = mesh.potential(np.broadcast_to(d1[None, None, :], (n_s,) * 3).copy(), box_s)
+    g3 = mesh.fd4_gradient(phi3, box_s)
+    p1 = _potential_1d(d1, box_s)
+    assert np.max(np.abs(phi3 - p1[None, None, :])) < 1e-12 * np.max(np.abs(p1))
+    assert np.max(np.abs(g3[0] - _fd4_1d(p1, box_s)[None, None, :])) < 1e-12 * np.max(np.abs(g3[0]))
+    cell = box / n
+    lnp = int(np_).bit_length() - 1
+    idx = torch.arange(np_ ** 3, device="cuda", dtype=torch.int64)
+    half = torch.full((np_ ** 3,), 0.5 * cell, dtype=torch.float32, device="cuda")
+    delta = sim.mesh(hrt.HRT_MESH_DELTA)
+    for axis, m in ((0, 3), (1, 5), (2, 7)):
+        say(f"  field along axis {axis} (mode {m}) at {n}^3")
+        j = np.arange(np_)
+        s_line = ((0.5 + 2.5 * np.sin(2.0 * np.pi * m * j / np_)) * cell).astype(np.float32)
+        lat = (idx >> (axis * lnp)) & (np_ - 1)
+        s = [half] * 3
+        s[axis] = torch.tensor(s_line, device="cuda")[lat].contiguous()
+        sim.pm_force(s, 0)
+        torch.cuda.synchronize()
+        d1 = _lattice_line_density(s_line, n, box)
+        p1 = _potential_1d(d1, box)
+        g1 = _fd4_1d(p1, box)
+        dim = 2 - axis                          # meshes are [z, y, x]
+        shape = [1, 1, 1]
+        shape[dim] = n
+        exp = torch.tensor(d1, dtype=torch.float32, device="cuda").view(shape)
+        # delta: as in test_gpu_parity, max |error| / (1 + |delta|) < 2e-5, every node
+        assert float(((delta - exp).abs() / (1.0 + exp.abs())).max()) < 2e-5
+        # phi and G on 64 random lines along the axis (their values on every line are the
+        # same up to the FFT's rounding)
+        phi = sim.mesh(hrt.HRT_MESH_PHI)
+        grad = sim.mesh(hrt.HRT_MESH_GRAD)
+        for t in range(64):
+            a, b = (int(v) for v in rng.integers(0, n, size=2))
+            sl = [a, b]
+            sl.insert(dim, slice(None))
+            ph = phi[tuple(sl)].double().cpu().numpy()
+            gr = grad[tuple(sl)].double().cpu().numpy()
+            assert np.sqrt(np.mean((ph - p1) ** 2)) < 5e-5 * np.sqrt(np.mean(p1 ** 2))
+            assert np.sqrt(np.mean((gr[:, axis] - g1) ** 2)) < 5e-5 * np.sqrt(np.mean(g1 ** 2))
+            for o in range(3):
+                if o != axis:
+                    assert np.max(np.abs(gr[:, o])) < 5e-5 * np.max(np.abs(g1))
+            assert np.all(gr[:, 3] == 0.0)
+        del s, lat
 
 
 def test_lcdm256_every_variant_bit_identical():
