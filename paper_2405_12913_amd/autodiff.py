@@ -3,7 +3,7 @@
 The paper leaves gradients through the ray tracer to future work (Sec. 7, by the adjoint
 method of its ref. LiEtAl2024). ``Pipeline.kappa`` is a ``torch.autograd.Function`` whose
 forward and backward passes issue only C-ABI calls of libhrt.so (hrt_ic_2lpt, pm_step,
-ray_step, ray_convergence and their VJPs hrt_step_vjp, ray_convergence_vjp,
+ray_step, hrt_run, ray_convergence and their VJPs hrt_step_vjp, ray_convergence_vjp,
 hrt_ic_2lpt_vjp); PyTorch holds the arrays and chains the loss.
 
 Memory: the forward pass keeps the full state every ``every`` steps (default 4). The
@@ -59,16 +59,17 @@ class Pipeline:
         s, p = self._zeros(3, self.P), self._zeros(3, self.P)
         self.fwd.ic_2lpt(nz, s, p, self.ic)
         ck_f, ck_c = {}, {}
-        for k in range(self.n_fwd):
-            if keep and k % self.every == 0:
-                ck_f[k] = (_clone(s), _clone(p))
-            self.fwd.pm_step(s, p, k)
+        # each checkpoint segment in one hrt_run call (the same bits as step by step, with
+        # the drift counting the next paint's bins)
+        for k0 in range(0, self.n_fwd, self.every):
+            if keep:
+                ck_f[k0] = (_clone(s), _clone(p))
+            self.fwd.run(s, p, None, None, k0, min(self.every, self.n_fwd - k0))
         dth, pr = self._zeros(2, self.M), self._zeros(2, self.M)
-        for k in range(self.n_co):
-            if keep and k % self.every == 0:
-                ck_c[k] = (_clone(s), _clone(p), _clone(dth), _clone(pr))
-            self.co.pm_step(s, p, k)
-            self.co.ray_step(dth, pr, k)
+        for k0 in range(0, self.n_co, self.every):
+            if keep:
+                ck_c[k0] = (_clone(s), _clone(p), _clone(dth), _clone(pr))
+            self.co.run(s, p, dth, pr, k0, min(self.every, self.n_co - k0))
         kappa = torch.empty(self.M, dtype=self.dtype, device=self.device)
         self.co.ray_convergence(dth, kappa)
         return kappa, ck_f, ck_c
