@@ -82,6 +82,12 @@ enum {
                                Not combinable with HRT_ADJOINT (HRT_EUNSUPPORTED)       */
 };
 
+/* HRT_FORCE_SLOTS(k), 1 <= k <= 15, or'ed into flags together with HRT_ADJOINT: reserve k
+ * force slots for hrt_force_save / hrt_step_vjp_saved, k (16 n^3 sizeof(dtype) +
+ * 4 (n^3/64 + 1)) bytes more per realisation (each slot rounded up to 256 bytes per part). */
+#define HRT_FORCE_SLOTS(k) ((int32_t)(k) << 8)
+#define HRT_FORCE_SLOTS_MASK 0xf00
+
 typedef struct {
     int32_t mesh_n;         /* n: power of two, 16 <= n <= 1024                         */
     int32_t ptcl_n;         /* np particles per side, n % np == 0 (np = 1: one particle) */
@@ -339,6 +345,22 @@ int hrt_ic_factors(const hrt_config *cfg, const hrt_ic_params *ic, double *out);
  * force-mesh cotangent; hrt_step_vjp sums them first and is the cheaper call). */
 int hrt_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                  const hrt_rays *rc, int step);
+
+/* Reverse mode without forming the force a second time, for callers that recompute a
+ * checkpoint segment forward (pm_step of each step but the last, then the VJPs of the
+ * segment's steps in reverse). hrt_force_save copies the force the last pm_step / pm_force
+ * formed (the G mesh and the paint-bin offsets of every realisation) into slot `slot`
+ * (0 <= slot < k of HRT_FORCE_SLOTS(k): HRT_EINVAL otherwise, or HRT_ESTATE for a context
+ * without slots) and records its step; HRT_ESTATE if there is no current force (none formed
+ * yet, or a paint-bin-order hrt_run, which keeps no G mesh). hrt_step_vjp_saved is
+ * hrt_step_vjp with the force copied back from slot `slot`, which must hold the force of
+ * `step` (HRT_ESTATE otherwise), instead of painted and solved again; m must be the state
+ * that force was formed from (not checked: the caller keeps the two together). Given that,
+ * its results equal hrt_step_vjp's bit for bit. A slot keeps its content until the next
+ * hrt_force_save to it; saving and the VJP overwrite the context's force meshes only. */
+int hrt_force_save(hrt_ctx *ctx, int slot);
+int hrt_step_vjp_saved(hrt_ctx *ctx, int slot, const hrt_matter *m, const hrt_rays *r,
+                       const hrt_matter *mc, const hrt_rays *rc, int step);
 int pm_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_matter *mc, int step);
 int ray_step_vjp(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
                  const hrt_rays *rc, int step);

@@ -8,9 +8,11 @@ hrt_ic_2lpt_vjp); PyTorch holds the arrays and chains the loss.
 
 Memory: the forward pass keeps the full state every ``every`` steps (default 4). The
 backward pass walks the segments in reverse: it restores a segment's checkpoint,
-recomputes the segment's steps while keeping the state before each, and runs the step VJPs
-backwards. Peak memory is (steps / every + every) states instead of one per step; the cost
-is one extra forward step per step.
+recomputes the segment's steps while keeping the state before each and, in the context's
+force slots, the force each step formed, and runs the step VJPs backwards on those forces
+(hrt_force_save, hrt_step_vjp_saved; only a segment's last step forms its force in the VJP).
+Peak memory is (steps / every + every) states and every - 1 forces instead of one state per
+step; the cost is one extra forward step per step.
 
 Step ranges: forward PM steps 0..N_f including the closing half-kick (momenta synchronised
 at a = 1); co-evolution steps 0..N_c - 1 from dth = p_ray = 0 (the closing half-kick of the
@@ -34,8 +36,10 @@ class Pipeline:
                  omega_b=0.045, h=0.7, n_s=0.96, sigma8=0.8, dtype="f32", every=4, device="cuda"):
         if every < 1:
             raise ValueError("every must be >= 1")
+        # force slots: the recomputed steps of a segment keep their force for the VJPs
+        self.slots = every if every <= 15 else 0
         common = dict(mesh_n=mesh_n, box=box, ptcl_n=ptcl_n, omega_m=omega_m, dtype=dtype,
-                      device=device, adjoint=True)
+                      device=device, adjoint=True, force_slots=self.slots)
         self.fwd = hrt.Simulation(n_steps=len(fwd_sched) - 1, sched=fwd_sched, **common)
         self.co = hrt.Simulation(n_steps=len(sched) - 1, sched=sched, ray_nx=ray_n, ray_ny=ray_n,
                                  fov_x=fov, fov_y=fov, observer=observer, **common)
@@ -83,23 +87,34 @@ class Pipeline:
             s, p, dth, pr = (_clone(x) for x in ck_c[k0])
             steps = list(range(k0, min(k0 + self.every, self.n_co)))
             before = []
-            for k in steps:
+            for j, k in enumerate(steps):
                 before.append((_clone(s), _clone(dth)))
                 if k != steps[-1]:
                     self.co.pm_step(s, p, k)
+                    if self.slots:
+                        self.co.force_save(j)
                     self.co.ray_step(dth, pr, k)
-            for k, (sk, dk) in zip(reversed(steps), reversed(before)):
-                self.co.step_vjp(sk, dk, sb, pb, db, prb, k)
+            for j in reversed(range(len(steps))):
+                sk, dk = before[j]
+                if self.slots and j < len(steps) - 1:
+                    self.co.step_vjp(sk, dk, sb, pb, db, prb, steps[j], part="saved", slot=j)
+                else:
+                    self.co.step_vjp(sk, dk, sb, pb, db, prb, steps[j])
         for k0 in sorted(ck_f, reverse=True):
             s, p = (_clone(x) for x in ck_f[k0])
             steps = list(range(k0, min(k0 + self.every, self.n_fwd)))
             before = []
-            for k in steps:
+            for j, k in enumerate(steps):
                 before.append(_clone(s))
                 if k != steps[-1]:
                     self.fwd.pm_step(s, p, k)
-            for k, sk in zip(reversed(steps), reversed(before)):
-                self.fwd.step_vjp(sk, None, sb, pb, None, None, k)
+                    if self.slots:
+                        self.fwd.force_save(j)
+            for j in reversed(range(len(steps))):
+                if self.slots and j < len(steps) - 1:
+                    self.fwd.step_vjp(before[j], None, sb, pb, None, None, steps[j], part="saved", slot=j)
+                else:
+                    self.fwd.step_vjp(before[j], None, sb, pb, None, None, steps[j])
         nb = torch.empty(self.P, dtype=self.dtype, device=self.device)
         self.fwd.ic_2lpt_vjp(noise.reshape(-1).contiguous(), sb, pb, self.ic, nb)
         return nb

@@ -63,6 +63,11 @@ Layout make_layout(const hrt_config &cfg, int64_t n_plane_entries, int64_t max_c
     // mover-list run: control words, the mover histogram and list offsets, holes per bin and
     // the extents of the kick-drift workgroups' parts of U
     L.list = list ? take(list_offsets((size_t)L.nbins).total) : 0;
+    // force slots (HRT_FORCE_SLOTS): per slot a copy of G and of the paint-bin offsets
+    const int slots = (cfg.flags & HRT_FORCE_SLOTS_MASK) >> 8;
+    L.fslot_g = align_up(n3 * 4 * T);
+    L.fslot_bytes = L.fslot_g + align_up((size_t)(L.nbins + 1) * 4);
+    L.fslots = slots ? take(slots * L.fslot_bytes) : off;
     L.total = off;
     return L;
 }
@@ -265,6 +270,7 @@ int hrt::init_context(const hrt_config *cfg, int n_cfg, void *workspace, size_t 
     c->los = cfg[0].los_field;
     c->n_src = cfg[0].n_src;
     c->n_maps = cfg[0].n_src + (cfg[0].src_w ? 1 : 0);
+    c->slot_step.assign((cfg[0].flags & HRT_FORCE_SLOTS_MASK) >> 8, -1);
     c->re.resize(n_cfg);
     char *ws = static_cast<char *>(workspace);
     hipError_t e = hipSuccess;
@@ -715,8 +721,11 @@ extern "C" int hrt_ic_2lpt(hrt_ctx *c, int realisation, const void *noise, const
 // Reverse of step `step` for every realisation: matter kick-drift (matter) and/or ray
 // kick-drift (r, rc non-NULL), with the force mesh recomputed first and the force's
 // transpose applied to the summed force-mesh cotangent.
+static int force_copy(hrt_ctx *c, int slot, bool save);
+
+// slot >= 0: the force comes from that force slot instead of a paint and Poisson solve.
 static int step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hrt_matter *mc,
-                    const hrt_rays *rc, int step, bool matter) {
+                    const hrt_rays *rc, int step, bool matter, int slot = -1) {
     if (!(c->re[0].cfg.flags & HRT_ADJOINT))
         return fail(c, HRT_ESTATE, "context was created without HRT_ADJOINT");
     if (step < 0 || step > c->N) return fail(c, HRT_EINVAL, "step out of range [0, n_steps]");
@@ -734,7 +743,13 @@ static int step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, const hr
         if (int rc0 = check_rays(c, rc, true)) return rc0;
     }
     if (!matter && !r) return fail(c, HRT_EINVAL, "nothing to differentiate: no rays and no matter step");
-    if (int rc0 = pm_force(c, m, step)) return rc0;
+    if (slot >= 0) {
+        if (int rc0 = force_copy(c, slot, false)) return rc0;
+        c->force_step = step;
+        c->mesh_g_stale = false;
+    } else if (int rc0 = pm_force(c, m, step)) {
+        return rc0;
+    }
     int rc0 = check_hip(c, hrt::launch_step_vjp(c, m, r, mc, rc, step, matter), "step vjp");
     c->force_step = -1;          // the force mesh now holds the cotangent
     return rc0;
@@ -745,6 +760,44 @@ extern "C" int hrt_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r,
     if (!c) return HRT_EINVAL;
     if (int g = guard(c)) return g;
     return step_vjp(c, m, r, mc, rc, step, !c->is_static);
+}
+
+// Copies between the context's force (G mesh, paint-bin offsets) and force slot `slot`.
+static int force_copy(hrt_ctx *c, int slot, bool save) {
+    for (hrt::Real &re : c->re) {
+        char *sl = re.ws + re.lay.fslots + (size_t)slot * re.lay.fslot_bytes;
+        char *g = re.ws + re.lay.grad;
+        char *offs = re.ws + re.lay.bins + (size_t)re.lay.nbins * 4;    // after the counts
+        const size_t gb = (size_t)re.n * re.n * re.n * 4 * (c->f64 ? 8 : 4), ob = (size_t)(re.lay.nbins + 1) * 4;
+        hipError_t e = hipMemcpyAsync(save ? sl : g, save ? g : sl, gb, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(save ? sl + re.lay.fslot_g : offs, save ? offs : sl + re.lay.fslot_g, ob,
+                               hipMemcpyDeviceToDevice, c->stream);
+        if (int rc = check_hip(c, e, "force slot copy")) return rc;
+    }
+    return HRT_OK;
+}
+
+extern "C" int hrt_force_save(hrt_ctx *c, int slot) {
+    if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
+    if (c->slot_step.empty()) return fail(c, HRT_ESTATE, "context has no force slots (HRT_FORCE_SLOTS)");
+    if (slot < 0 || slot >= (int)c->slot_step.size()) return fail(c, HRT_EINVAL, "force slot out of range");
+    if (c->force_step < 0 || c->mesh_g_stale)
+        return fail(c, HRT_ESTATE, "no current force mesh to save (pm_step or pm_force first)");
+    if (int rc = force_copy(c, slot, true)) return rc;
+    c->slot_step[slot] = c->force_step;
+    return HRT_OK;
+}
+
+extern "C" int hrt_step_vjp_saved(hrt_ctx *c, int slot, const hrt_matter *m, const hrt_rays *r,
+                                  const hrt_matter *mc, const hrt_rays *rc, int step) {
+    if (!c) return HRT_EINVAL;
+    if (int g = guard(c)) return g;
+    if (c->slot_step.empty()) return fail(c, HRT_ESTATE, "context has no force slots (HRT_FORCE_SLOTS)");
+    if (slot < 0 || slot >= (int)c->slot_step.size()) return fail(c, HRT_EINVAL, "force slot out of range");
+    if (c->slot_step[slot] != step) return fail(c, HRT_ESTATE, "force slot does not hold this step's force");
+    return step_vjp(c, m, r, mc, rc, step, !c->is_static, slot);
 }
 
 extern "C" int pm_step_vjp(hrt_ctx *c, const hrt_matter *m, const hrt_matter *mc, int step) {

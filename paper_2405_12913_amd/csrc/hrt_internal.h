@@ -55,7 +55,8 @@ struct PlaneEntry {
 // Workspace carve-up of one realisation, identical in hrt_workspace_bytes and hrt_init.
 struct Layout {
     size_t mesh_r, spec, spec2, grad, twiddle, bins, cursor, sorted, planes, adj, state, stack, reps,
-        stack_phi, stack_delta, rm_mesh, rm_tw, list, total;
+        stack_phi, stack_delta, rm_mesh, rm_tw, list, fslots, total;
+    size_t fslot_g, fslot_bytes;   // force slot: its G part's size, the whole slot's stride
     int64_t nbins;
 };
 
@@ -189,6 +190,7 @@ struct hrt_ctx {
     int los = 0;                 // line-of-sight field (HRT_LOS_*)
     int n_src = 0, n_maps = 0;   // source planes; map sets per realisation (+1 with weights)
     int force_step = -1;         // boundary of the phi (and G) currently in the workspaces
+    std::vector<int> slot_step;  // force slots (HRT_FORCE_SLOTS): the step each holds, or -1
     bool mesh_g_stale = false;   // after a paint-bin-order hrt_run the G mesh is not current
     std::string err;
     // captured step sequence (hrt_graph_capture / hrt_graph_launch)

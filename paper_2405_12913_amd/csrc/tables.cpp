@@ -255,8 +255,10 @@ int validate_config(const hrt_config &c, std::string &err) {
     if ((int64_t)c.ray_nx * c.ray_ny > (int64_t)1 << 26) return bad("too many rays");
     if (c.n_steps < 1 || c.n_steps > 100000) return bad("n_steps out of range");
     if (c.dtype != HRT_F32 && c.dtype != HRT_F64) return bad("dtype must be HRT_F32 or HRT_F64");
-    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN | HRT_TIME_DELAY | HRT_RAY_MESH))
+    if (c.flags & ~(HRT_STATIC | HRT_ADJOINT | HRT_JACOBIAN | HRT_TIME_DELAY | HRT_RAY_MESH | HRT_FORCE_SLOTS_MASK))
         return bad("unknown flag");
+    if ((c.flags & HRT_FORCE_SLOTS_MASK) && !(c.flags & HRT_ADJOINT))
+        return bad("HRT_FORCE_SLOTS needs HRT_ADJOINT");
     if (c.flags & HRT_RAY_MESH) {
         if (c.ray_nx == 0) return bad("HRT_RAY_MESH needs rays");
         if (!(c.ray_mesh_iota > 0 && c.ray_mesh_iota <= 1)) return bad("ray_mesh_iota must be in (0, 1]");

@@ -31,7 +31,7 @@ EXPORTED = ("hrt_workspace_bytes", "hrt_init", "hrt_destroy", "hrt_last_error", 
             "hrt_ic_factors", "hrt_graph_capture", "hrt_graph_launch", "hrt_step_vjp",
             "ray_convergence_vjp", "hrt_ic_2lpt_vjp", "hrt_num_variants", "hrt_set_variant",
             "hrt_get_variant", "hrt_autotune", "hrt_run", "hrt_init_noalloc", "pm_step_vjp",
-            "ray_step_vjp", "ray_observe")
+            "ray_step_vjp", "ray_observe", "hrt_force_save", "hrt_step_vjp_saved")
 
 
 class HrtConfig(ctypes.Structure):
@@ -107,6 +107,9 @@ def lib():
         L.hrt_ic_factors.argtypes = [P(HrtConfig), P(HrtIcParams), P(c_double)]
         L.hrt_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays), c_int]
         L.pm_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtMatter), c_int]
+        L.hrt_force_save.argtypes = [c_void_p, c_int]
+        L.hrt_step_vjp_saved.argtypes = [c_void_p, c_int, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays),
+                                         c_int]
         L.ray_step_vjp.argtypes = [c_void_p, P(HrtMatter), P(HrtRays), P(HrtMatter), P(HrtRays), c_int]
         L.ray_convergence_vjp.argtypes = [c_void_p, P(c_void_p), P(HrtRays)]
         L.hrt_ic_2lpt_vjp.argtypes = [c_void_p, c_int, c_void_p, P(HrtIcParams), P(HrtMatter), c_void_p]
@@ -132,7 +135,7 @@ def _check(rc, ctx=None):
 def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_x=0.0, fov_y=0.0,
                 observer=(0.0, 0.0, 0.0), omega_m=0.3, dtype="f32", static=False, static_mass=0.0,
                 adjoint=False, src=None, src_w=None, jacobian=False, replicas=None, time_delay=False,
-                los_field=None, los_chi=None, los_p=None, ray_mesh=None):
+                los_field=None, los_chi=None, los_p=None, ray_mesh=None, force_slots=0):
     """hrt_config from keyword arguments; returns (config, host arrays kept alive).
 
     src: source planes (redshifts, or chi with static=True), each a step boundary;
@@ -142,7 +145,8 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     time_delay: the rays accumulate c times the arrival-time delay (HRT_TIME_DELAY);
     los_field: "density" or "potential" line-of-sight integral with kernel P given by the
     knots (los_chi, los_p);
-    ray_mesh: (iota, p_min) to kick the rays on the adaptive 2D ray mesh (HRT_RAY_MESH)."""
+    ray_mesh: (iota, p_min) to kick the rays on the adaptive 2D ray mesh (HRT_RAY_MESH);
+    force_slots: with adjoint, the number of force slots (HRT_FORCE_SLOTS, at most 15)."""
     sched = np.ascontiguousarray(sched, dtype=np.float64)
     if len(sched) != n_steps + 1:
         raise ValueError("sched must have n_steps + 1 entries")
@@ -152,7 +156,7 @@ def make_config(*, mesh_n, box, ptcl_n, n_steps, sched, ray_nx=0, ray_ny=0, fov_
     cfg.dtype = HRT_F64 if dtype in ("f64", "float64") else HRT_F32
     cfg.flags = (HRT_STATIC if static else 0) | (HRT_ADJOINT if adjoint else 0) | \
         (HRT_JACOBIAN if jacobian else 0) | (HRT_TIME_DELAY if time_delay else 0) | \
-        (HRT_RAY_MESH if ray_mesh is not None else 0)
+        (HRT_RAY_MESH if ray_mesh is not None else 0) | (int(force_slots) << 8)
     if ray_mesh is not None:
         cfg.ray_mesh_iota, cfg.ray_mesh_pmin = float(ray_mesh[0]), float(ray_mesh[1])
     cfg.n_src = 0 if src is None else len(src)
@@ -434,15 +438,19 @@ class Simulation:
         _check(lib().hrt_ic_2lpt(self.ctx, k, c_void_p(nz), ctypes.byref(ic), ctypes.byref(m)),
                self.ctx)
 
-    def step_vjp(self, s, dth, s_bar, p_bar, dth_bar, p_ray_bar, step, part="step"):
+    def force_save(self, slot):
+        """Keep the force the last pm_step / pm_force formed in force slot `slot`."""
+        _check(lib().hrt_force_save(self.ctx, slot), self.ctx)
+
+    def step_vjp(self, s, dth, s_bar, p_bar, dth_bar, p_ray_bar, step, part="step", slot=-1):
         """Reverse of step `step` (context created with adjoint=True; per-realisation lists
         for batches).
 
         s, dth: state before the step; the cotangents (lists of device tensors) hold those
         of the state after the step and are overwritten with those before it. dth and the
         ray cotangents are None for matter only; p_bar may be None for a static lens (and
-        for part="rays"). part: "step" (hrt_step_vjp), "matter" (pm_step_vjp) or "rays"
-        (ray_step_vjp)."""
+        for part="rays"). part: "step" (hrt_step_vjp), "matter" (pm_step_vjp), "rays"
+        (ray_step_vjp) or "saved" (hrt_step_vjp_saved with the force kept in slot `slot`)."""
         m = self._matter(s)
         mc = self._matter(s_bar, p_bar)
         r = rc = None
@@ -451,6 +459,8 @@ class Simulation:
             rc = self._rays(dth_bar, p_ray_bar)
         if part == "step":
             _check(lib().hrt_step_vjp(self.ctx, m, r, mc, rc, step), self.ctx)
+        elif part == "saved":
+            _check(lib().hrt_step_vjp_saved(self.ctx, slot, m, r, mc, rc, step), self.ctx)
         elif part == "matter":
             _check(lib().pm_step_vjp(self.ctx, m, mc, step), self.ctx)
         elif part == "rays":

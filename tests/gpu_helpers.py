@@ -65,13 +65,14 @@ class Case:
             self.pr = pr.astype(npdt).astype(np.float64)
         self.dtype = dtype
 
-    def sim(self, sched=None, adjoint=False):
+    def sim(self, sched=None, adjoint=False, force_slots=0):
         from paper_2405_12913_amd import hrt
         sched = self.cfg["sched"] if sched is None else sched
         return hrt.Simulation(mesh_n=self.n, box=self.box, ptcl_n=self.np_, n_steps=len(sched) - 1,
                               sched=sched, ray_nx=self.mx, ray_ny=self.my, fov_x=self.cfg["fov"],
                               fov_y=self.cfg["fov"], observer=self.cfg["observer"],
-                              omega_m=self.cfg["omega_m"], dtype=self.dtype, adjoint=adjoint)
+                              omega_m=self.cfg["omega_m"], dtype=self.dtype, adjoint=adjoint,
+                              force_slots=force_slots)
 
     def oracle_tables(self, sched=None):
         sched = self.cfg["sched"] if sched is None else sched

@@ -95,6 +95,21 @@ def test_invalid_configs_are_rejected(field, value):
         hrt.hrt_workspace_bytes(cfg)
 
 
+def test_force_slots_need_adjoint_and_size_the_workspace():
+    cfg, keep = _cosmo_cfg(np.linspace(1.0, 0.5, 5))
+    cfg.flags = 2 << 8                          # HRT_FORCE_SLOTS(2) without HRT_ADJOINT
+    with pytest.raises(hrt.HRTError, match="HRT_ADJOINT"):
+        hrt.hrt_workspace_bytes(cfg)
+    cfg.flags = hrt.HRT_ADJOINT
+    base = hrt.hrt_workspace_bytes(cfg)
+    n = cfg.mesh_n
+    al = lambda x: (x + 255) // 256 * 256
+    slot = al(16 * n ** 3) + al(4 * (n ** 3 // 64 + 1))
+    for k in (1, 3, 15):
+        cfg.flags = hrt.HRT_ADJOINT | (k << 8)
+        assert hrt.hrt_workspace_bytes(cfg) == base + k * slot
+
+
 def test_bad_schedule_rejected():
     cfg, keep = _cosmo_cfg(np.array([1.0, 0.8, 1.2]))
     with pytest.raises(hrt.HRTError, match="a schedule"):

@@ -83,6 +83,40 @@ def test_step_vjp_matter_only_and_rerun_bit_identical():
     assert rel_l2(Case.host(a[1]), o[1]) < 1e-5
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_step_vjp_from_force_slot_equals_step_vjp(dtype):
+    """hrt_step_vjp_saved on the force that pm_step formed and hrt_force_save kept gives
+    hrt_step_vjp's bits; the slot's step, its range and a context without slots are checked."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    say(f"case step vjp from a force slot {dtype}")
+    c = _case(dtype)
+    sim = c.sim(adjoint=True, force_slots=2)
+    step = 2
+    s, p, dth, pr = c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)
+    sim.pm_step(s, p, step)                     # the force of the state c.s at `step`
+    sim.force_save(1)
+    sim.ray_step(dth, pr, step)
+    sim.pm_step(s, p, step + 1)                 # another force in the meshes meanwhile
+    sim.force_save(0)
+    cot = _cot(c, 13)
+    sb, pb, db, prb = (c.dev(x) for x in cot)
+    sim.step_vjp(c.dev(c.s), c.dev(c.dth), sb, pb, db, prb, step, part="saved", slot=1)
+    ref = _gpu_step_vjp(c, sim, step, cot)
+    torch.cuda.synchronize()
+    for x, y in zip((sb, pb, db, prb), ref):
+        for u, v in zip(x, y):
+            assert torch.equal(u, v)
+    with pytest.raises(hrt.HRTError, match="status -4"):      # slot 0 holds step + 1
+        sim.step_vjp(c.dev(c.s), c.dev(c.dth), sb, pb, db, prb, step, part="saved", slot=0)
+    with pytest.raises(hrt.HRTError, match="status -1"):
+        sim.force_save(2)
+    plain = c.sim(adjoint=True)
+    plain.pm_force(c.dev(c.s), step)
+    with pytest.raises(hrt.HRTError, match="status -4"):
+        plain.force_save(0)
+
+
 def test_step_vjp_matches_gpu_finite_differences():
     """<cot, J v> from central differences of the GPU forward step (float64)."""
     import torch
