@@ -1066,10 +1066,19 @@ __device__ __forceinline__ void kd_move_list(v4<T> *rec0, T *mom0, int P, int rF
         key = bin_key(c, lnt);
         mover = !front || key != okey;
     }
-    // one store of the record and of each momentum per lane: a stayer's to its front slot,
-    // a mover's to its slot u of U (record 3P + u, axis d at 9P + 2P d + u); a front mover
-    // also marks its old slot as a hole
-    int rd = i + rF, md = i + mF, ms = P;
+    // A front input rewrites its slot whole, every step: a stayer with its new state, a mover
+    // (now a hole: index -1) or an earlier hole with what it holds, so that no line of the
+    // fronts' records and momenta is left partly written (a partial line costs the memory a
+    // read before the write). A mover's state also goes to its slot u of U (record 3P + u,
+    // axis d at 9P + 2P d + u).
+    if (front) {
+        v4<T> r = it.rec;
+        if (mover) r.w = index_field<T>(-1);
+        asm volatile("" : "+v"(r.w));           // store the whole record
+        rec0[i + rF] = r;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom0 + (i + mF + d * P));
+    }
     const unsigned long long mv = __ballot(mover);
     if (mv) {                                   // wave-uniform
         const int lane = __lane_id(), leader = __ffsll((long long)mv) - 1;
@@ -1078,17 +1087,11 @@ __device__ __forceinline__ void kd_move_list(v4<T> *rec0, T *mom0, int P, int rF
         base = __shfl(base, leader);
         if (mover) {
             const int u = ub + (int)base + __popcll(mv & ((1ull << lane) - 1ull));
-            if (front) rec0[rd].w = index_field<T>(-1);     // the hole (index -1)
-            rd = 3 * P + u;
-            md = 9 * P + u;
-            ms = 2 * P;
-        }
-    }
-    if (live) {
-        asm volatile("" : "+v"(it.rec.w));      // store the whole record: no partial lines
-        rec0[rd] = it.rec;
+            asm volatile("" : "+v"(it.rec.w));
+            rec0[3 * P + u] = it.rec;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom0 + (md + d * ms));
+            for (int d = 0; d < 3; ++d) st_stream(it.p[d], mom0 + (9 * P + 2 * P * d + u));
+        }
     }
     if (COUNT) {                                // full histogram before a re-binning, else U's
         if (rebuild) wave_aggregated_increment<false>(count, key);
