@@ -128,6 +128,37 @@ __device__ __forceinline__ int wave_aggregated_increment(unsigned int *counter, 
     return key >= 0 ? (int)base + rank : -1;
 }
 
+// wave_aggregated_increment<true> in two halves, so that a lane can have several such
+// reservations in flight: wave_reserve groups the keys and issues the leaders' atomic (its
+// old value is not waited for), wave_reserved_slot then returns the lane's slot.
+struct WaveReservation {
+    unsigned int old;        // the leader's atomic result (leader lanes)
+    int leader, rank;
+};
+__device__ __forceinline__ WaveReservation wave_reserve(unsigned int *counter, int key) {
+    const int lane = __lane_id();
+    unsigned long long remaining = __ballot(key >= 0);
+    WaveReservation w{0u, lane, 0};
+    unsigned int count = 0;
+    while (remaining) {
+        const int leader = __ffsll((long long)remaining) - 1;
+        const int lkey = __builtin_amdgcn_readlane(key, leader);
+        const unsigned long long grp = __ballot(key == lkey);
+        if (key == lkey) {
+            w.leader = leader;
+            w.rank = __popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) count = (unsigned int)__popcll(grp);
+        remaining &= ~grp;
+    }
+    if (count) w.old = atomicAdd(&counter[key], count);
+    return w;
+}
+__device__ __forceinline__ int wave_reserved_slot(const WaveReservation &w, int key) {
+    const unsigned int base = __shfl(w.old, w.leader);
+    return key >= 0 ? (int)base + w.rank : -1;
+}
+
 // Streaming accesses that are touched once per kernel use non-temporal loads and stores so
 // they do not evict gathered data (mesh nodes) from L2.
 template <typename T>

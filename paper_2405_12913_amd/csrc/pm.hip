@@ -1234,9 +1234,12 @@ __global__ __launch_bounds__(kThreads) void list_settle_kernel(PartBatch<T> b) {
     v4<T> *const drec = rebuild ? a.rec[1 - cur] : a.rec[0] + a.P;
     T *const dmo = rebuild ? a.mom[1 - cur] : a.mom[0] + 3 * Pl;
     auto place = [&](const int (&key)[kSettleQ], const v4<T> (&rec)[kSettleQ], const T (&pv)[kSettleQ][3]) {
+        WaveReservation w[kSettleQ];            // all of a lane's reservations in flight at once
+#pragma unroll
+        for (int k = 0; k < kSettleQ; ++k) w[k] = wave_reserve(cursor, key[k]);
 #pragma unroll
         for (int k = 0; k < kSettleQ; ++k) {
-            const int slot = wave_aggregated_increment<true>(cursor, key[k]);
+            const int slot = wave_reserved_slot(w[k], key[k]);
             if (key[k] >= 0) {
                 drec[slot] = rec[k];
 #pragma unroll
