@@ -1470,12 +1470,17 @@ __global__ __launch_bounds__(kThreads) void list_uperm_kernel(PartBatch<T> b) {
     }
 }
 
+// A workgroup takes a Lagrangian patch of 32 x 8 particles (whole 128-byte lines of s and p;
+// their sorted slots lie in a few tiles' bins, whose lines the patch shares), XCD-grouped so
+// that neighbouring patches, which gather from the same tiles, share one L2: 568 -> 437 us at
+// 256^3 against lattice-linear rows.
 template <typename T, bool LIST = false>
 __global__ __launch_bounds__(kThreads) void state_gather_kernel(PartBatch<T> b, int cur) {
-    const int r = real_of(b.map, blockIdx.x);
+    const int blk = xcd_block(gridDim.x);
+    const int r = real_of(b.map, blk);
     const Particles<T> &a = b.r[r];
     const size_t P = (size_t)a.P;
-    const int i = (blockIdx.x - b.map.start[r]) * kThreads + (int)threadIdx.x;
+    const int i = particle_of(blk - b.map.start[r], (int)threadIdx.x, a.lnp, 2);
     if (i >= a.P) return;
     const v4<T> *recs = nullptr;
     const T *mom = nullptr;
