@@ -25,8 +25,9 @@ import torch
 from . import hrt
 
 
-def _clone(ts):
-    return [t.clone() for t in ts]
+def _rows(t):
+    """The rows of a contiguous 2D tensor as a list of 1D views (each contiguous)."""
+    return list(t.unbind(0))
 
 
 class Pipeline:
@@ -57,22 +58,29 @@ class Pipeline:
     def _zeros(self, k, n):
         return [torch.zeros(n, dtype=self.dtype, device=self.device) for _ in range(k)]
 
+    def _block(self, k, n):
+        """k state components of n values as the rows of one tensor: a checkpoint of them is
+        one device copy."""
+        return torch.zeros(k, n, dtype=self.dtype, device=self.device)
+
     def run(self, noise, keep=False):
         """Forward pass: kappa (My*Mx,) and, with keep, the checkpoints of both stages."""
         nz = noise.reshape(-1)
-        s, p = self._zeros(3, self.P), self._zeros(3, self.P)
+        X = self._block(6, self.P)              # s (rows 0-2) and p (rows 3-5)
+        s, p = _rows(X[:3]), _rows(X[3:])
         self.fwd.ic_2lpt(nz, s, p, self.ic)
         ck_f, ck_c = {}, {}
         # each checkpoint segment in one hrt_run call (the same bits as step by step, with
         # the drift counting the next paint's bins)
         for k0 in range(0, self.n_fwd, self.every):
             if keep:
-                ck_f[k0] = (_clone(s), _clone(p))
+                ck_f[k0] = X.clone()
             self.fwd.run(s, p, None, None, k0, min(self.every, self.n_fwd - k0))
-        dth, pr = self._zeros(2, self.M), self._zeros(2, self.M)
+        Y = self._block(4, self.M)              # dth (rows 0-1) and p_ray (rows 2-3)
+        dth, pr = _rows(Y[:2]), _rows(Y[2:])
         for k0 in range(0, self.n_co, self.every):
             if keep:
-                ck_c[k0] = (_clone(s), _clone(p), _clone(dth), _clone(pr))
+                ck_c[k0] = (X.clone(), Y.clone())
             self.co.run(s, p, dth, pr, k0, min(self.every, self.n_co - k0))
         kappa = torch.empty(self.M, dtype=self.dtype, device=self.device)
         self.co.ray_convergence(dth, kappa)
@@ -84,11 +92,12 @@ class Pipeline:
         db, prb = self._zeros(2, self.M), self._zeros(2, self.M)
         self.co.convergence_vjp(kappa_bar.reshape(-1).contiguous(), db)
         for k0 in sorted(ck_c, reverse=True):
-            s, p, dth, pr = (_clone(x) for x in ck_c[k0])
+            X, Y = ck_c[k0][0].clone(), ck_c[k0][1].clone()
+            s, p, dth, pr = _rows(X[:3]), _rows(X[3:]), _rows(Y[:2]), _rows(Y[2:])
             steps = list(range(k0, min(k0 + self.every, self.n_co)))
             before = []
             for j, k in enumerate(steps):
-                before.append((_clone(s), _clone(dth)))
+                before.append((_rows(X[:3].clone()), _rows(Y[:2].clone())))
                 if k != steps[-1]:
                     self.co.pm_step(s, p, k)
                     if self.slots:
@@ -101,11 +110,12 @@ class Pipeline:
                 else:
                     self.co.step_vjp(sk, dk, sb, pb, db, prb, steps[j])
         for k0 in sorted(ck_f, reverse=True):
-            s, p = (_clone(x) for x in ck_f[k0])
+            X = ck_f[k0].clone()
+            s, p = _rows(X[:3]), _rows(X[3:])
             steps = list(range(k0, min(k0 + self.every, self.n_fwd)))
             before = []
             for j, k in enumerate(steps):
-                before.append(_clone(s))
+                before.append(_rows(X[:3].clone()))
                 if k != steps[-1]:
                     self.fwd.pm_step(s, p, k)
                     if self.slots:
