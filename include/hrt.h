@@ -252,8 +252,10 @@ int ray_observe(hrt_ctx *ctx, const hrt_rays *r, const hrt_maps *maps);
  * keeps its slot, one that leaves it leaves a hole and joins a side list sorted by bin,
  * which the paint and the kick-drift read beside the bins; the whole state is re-binned only
  * at the end of a step that starts with more than P/16 listed particles. 6 is 5 with a limit
- * of P/64. 1 runs pm_step's Lagrangian-order kernels (with the same fused counting). 0
- * (default) takes 5 in FP32 and 2 in FP64 for calls of 8 steps or more, and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
+ * of P/64. 7 is 5 with G formed per particle from the pair's phi block (no G block; 256 lanes
+ * per pair), faster when particles are sparse (np <= n/2). 1 runs pm_step's Lagrangian-order
+ * kernels (with the same fused counting). 0 (default) takes, for calls of 8 steps or more,
+ * 5 in FP32 (7 when every realisation has np <= n/2) and 2 in FP64, and 1 otherwise. Either way the state arrays must not be modified by anyone else while the
  * call's work runs. */
 int hrt_run(hrt_ctx *ctx, const hrt_matter *m, const hrt_rays *r, int first_step, int n_steps,
             const hrt_maps *maps);
@@ -383,7 +385,7 @@ int hrt_ic_2lpt_vjp(hrt_ctx *ctx, int realisation, const void *noise, const hrt_
  * differ only in speed (matter_kd also has shapes with two particles per lane, paint_tiles
  * shapes that paint two or four tiles per workgroup or spread the FP32 sums over two to
  * eight LDS copies). Tunable kernel ids: bin_count, bin_scatter
- * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (14), kd_tiles (7: the particle order of hrt_run, see
+ * (8 variants each), ray_step (6), matter_kd (16), paint_tiles (14), kd_tiles (8: the particle order of hrt_run, see
  * there, 3 and 4 being the paint-bin order with a persistent pipelined kick-drift and with
  * x-pairs of tiles per workgroup; not chosen by hrt_autotune). hrt_num_variants(id) gives the count (1 = not
  * tunable, 0 = no such id); hrt_set_variant forces a choice (HRT_EINVAL out of range);

@@ -553,13 +553,15 @@ static int run_steps(hrt_ctx *c, const hrt_matter *m, const hrt_rays *r, int fir
     // 4 = paint-bin order with x-pairs of tiles per kick-drift workgroup (FP32; FP64 runs
     // variant 2), 5 = 4 with the particles that leave their paint bin moved through a side
     // list instead of re-binning the whole state every step (FP32; re-binned once the list
-    // holds P/16 entries), 6 = 5 with a limit of P/64, 0 = bin order (5 in FP32, 2 in FP64)
+    // holds P/16 entries), 6 = 5 with a limit of P/64, 7 = 5 with G formed per particle from
+    // the pair's phi block (256 lanes per pair; sparse particle sets), 0 = bin order (5 in
+    // FP32, 2 in FP64)
     // for sequences of kSortedMinSteps steps or more, whose per-step saving outweighs the
     // one-off cost of entering and leaving the sorted state. All give the same bits.
     constexpr int kSortedMinSteps = 8;
     const int order = c->variant[hrt::K_KD_TILES];
     const bool sorted = order >= 2 || (order == 0 && n >= kSortedMinSteps);
-    bool list = sorted && !c->f64 && (order == 5 || order == 6 || order == 0);
+    bool list = sorted && !c->f64 && (order == 5 || order == 6 || order == 7 || order == 0);
     for (const hrt::Real &re : c->re) list = list && re.lay.list != 0;
     bool counted = false;
     int cur = 0;

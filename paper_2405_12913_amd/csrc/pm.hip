@@ -1039,11 +1039,43 @@ __global__ __launch_bounds__(kPairThreads) void kd_pairs_kernel(PartBatch<T> b, 
 // contended. With COUNT every particle is counted into the full histogram and U's entries
 // into the mover histogram. The arithmetic of a particle is that of kd_move, so the run gives
 // the same bits as the other orders.
-template <typename T, bool COUNT>
+// G at the 8 corner nodes of pair-frame cell (x, y, z) (x in 0..15, y and z in 0..7),
+// formed from the pair's phi block (24 x 13 x 13 values, x from the pair's x0 - 4, y and z
+// from y0 - 2 and z0 - 2) with the differences pair_gradient takes at those nodes: the
+// same operands in the same order, so the same values as the G block holds.
+// The readout, kick and drift of cic_kick_drift (same operations in the same order) with
+// each corner's G formed when it is added, so only one corner's values are held at a time.
+template <typename T>
+__device__ __forceinline__ void cic_kick_drift_phi(const T f[3], const T *ph, int x, int y, int z, T inv12cell, T K,
+                                                   T D, T s[3], T p[3]) {
+#pragma clang fp contract(off)
+    constexpr int SY = kPhiX2, SZ = kPhiYZ * kPhiX2;
+    const int n0 = ((z + 2) * kPhiYZ + (y + 2)) * kPhiX2 + (x + 4);
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {               // one corner's loads at a time (registers)
+        const int n = n0 + (k >> 2) * SZ + ((k >> 1) & 1) * SY + (k & 1);
+        const T wz = (k >> 2) ? f[2] : T(1) - f[2];
+        const T wyz = wz * (((k >> 1) & 1) ? f[1] : T(1) - f[1]);
+        const T w = wyz * ((k & 1) ? f[0] : T(1) - f[0]);
+        gx = fmadd(w, fd4<T>(ph[n - 2], ph[n - 1], ph[n + 1], ph[n + 2], inv12cell), gx);
+        gy = fmadd(w, fd4<T>(ph[n - 2 * SY], ph[n - SY], ph[n + SY], ph[n + 2 * SY], inv12cell), gy);
+        gz = fmadd(w, fd4<T>(ph[n - 2 * SZ], ph[n - SZ], ph[n + SZ], ph[n + 2 * SZ], inv12cell), gz);
+    }
+    const T gg[3] = {gx, gy, gz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        p[d] = fmadd(K, gg[d], p[d]);
+        s[d] = fmadd(D, p[d], s[d]);
+    }
+}
+
+template <typename T, bool COUNT, bool DIRECT = false>
 __device__ __forceinline__ void kd_move_list(v4<T> *rec0, T *mom0, int P, int rF, int mF, int F, int i, int total,
                                              KdItem<T> &it, const v4<T> *gl, T K, T D,
                                              const CellGeom<T> &cg, int lnt, unsigned int *count,
-                                             const ListBufs<T> &l, unsigned int *nu, int ub, bool rebuild) {
+                                             const ListBufs<T> &l, unsigned int *nu, int ub, bool rebuild,
+                                             const T *ph = nullptr, T inv12cell = T(0)) {
     int key = -1, okey = -1;
     bool mover = false, live = false;
     const bool front = i < F;
@@ -1053,12 +1085,16 @@ __device__ __forceinline__ void kd_move_list(v4<T> *rec0, T *mom0, int P, int rF
         T f[3];
         record_cell<T>(cg, it.rec, c, f);
         okey = bin_key(c, lnt);
-        const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGX2 + (c[0] & 15);
-        v4<T> g[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGX2 + (k & 1)];
         T sv[3] = {it.rec.x, it.rec.y, it.rec.z};
-        cic_kick_drift<T>(f, g, K, D, sv, it.p);
+        if constexpr (DIRECT) {
+            cic_kick_drift_phi<T>(f, ph, c[0] & 15, c[1] & 7, c[2] & 7, inv12cell, K, D, sv, it.p);
+        } else {
+            const int l0 = ((c[2] & 7) * kGN + (c[1] & 7)) * kGX2 + (c[0] & 15);
+            v4<T> g[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) g[k] = gl[l0 + ((k >> 2) * kGN + ((k >> 1) & 1)) * kGX2 + (k & 1)];
+            cic_kick_drift<T>(f, g, K, D, sv, it.p);
+        }
         it.rec.x = sv[0];
         it.rec.y = sv[1];
         it.rec.z = sv[2];
@@ -1114,10 +1150,16 @@ __device__ __forceinline__ void kd_fetch_list(const v4<T> *rec0, const T *mom0, 
     }
 }
 
-template <typename T, bool COUNT>
-__global__ __launch_bounds__(kPairThreads) void kd_pairs_list_kernel(PartBatch<T> b) {
+// DIRECT (kd_tiles variant 7, for sparse particle sets): 256 lanes per pair and no G block:
+// each particle forms G at its 8 corners from the phi block (corner_gradients), so the
+// workgroup holds 16 KB of LDS instead of 38 KB and skips the G set-up and its barrier;
+// eight workgroups fit on a CU instead of four. With few particles per pair (np = n/2:
+// 128) the per-particle differences cost less than the set-up of all 1377 nodes.
+template <typename T, bool COUNT, bool DIRECT = false>
+__global__ __launch_bounds__(DIRECT ? 256 : kPairThreads) void kd_pairs_list_kernel(PartBatch<T> b) {
+    constexpr int TH = DIRECT ? 256 : kPairThreads;
     __shared__ v4<T> ph4[kPhiQuads2];
-    __shared__ v4<T> gl[kGX2 * kGN * kGN];
+    __shared__ v4<T> gl[DIRECT ? 1 : kGX2 * kGN * kGN];
     __shared__ unsigned int nu;                 // entries this workgroup appended to U
     const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
@@ -1144,24 +1186,27 @@ __global__ __launch_bounds__(kPairThreads) void kd_pairs_list_kernel(PartBatch<T
     if (threadIdx.x == 0) nu = 0u;
     KdItem<T> c0, c1;
     kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, (int)threadIdx.x, total, c0);
-    kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, kPairThreads + (int)threadIdx.x, total, c1);
-    for (int e = threadIdx.x; e < kPhiQuads2; e += kPairThreads)
+    kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, TH + (int)threadIdx.x, total, c1);
+    for (int e = threadIdx.x; e < kPhiQuads2; e += TH)
         ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset2(e, tx, ty, tz, n));
     __syncthreads();
-    pair_gradient<T>(ph4, gl, a.inv12cell);
-    __syncthreads();
-    const T K = a.K, D = a.D;
+    if constexpr (!DIRECT) {
+        pair_gradient<T>(ph4, gl, a.inv12cell);
+        __syncthreads();
+    }
+    const T *const ph = reinterpret_cast<const T *>(ph4);
+    const T K = a.K, D = a.D, inv12 = a.inv12cell;
     const CellGeom<T> cg = geom_of(a);
     const int lnt = a.lnt;
-    for (int base = 0; base < total; base += 2 * kPairThreads) {   // same trip count for every lane
+    for (int base = 0; base < total; base += 2 * TH) {   // same trip count for every lane
         if (base != 0) {
             kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, base + (int)threadIdx.x, total, c0);
-            kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, base + kPairThreads + (int)threadIdx.x, total, c1);
+            kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, base + TH + (int)threadIdx.x, total, c1);
         }
-        kd_move_list<T, COUNT>(rec0, mom0, P, rF, mF, F, base + (int)threadIdx.x, total, c0, gl, K, D, cg, lnt,
-                               a.count, l, &nu, ub, rebuild);
-        kd_move_list<T, COUNT>(rec0, mom0, P, rF, mF, F, base + kPairThreads + (int)threadIdx.x, total, c1, gl, K,
-                               D, cg, lnt, a.count, l, &nu, ub, rebuild);
+        kd_move_list<T, COUNT, DIRECT>(rec0, mom0, P, rF, mF, F, base + (int)threadIdx.x, total, c0, gl, K, D, cg,
+                                       lnt, a.count, l, &nu, ub, rebuild, ph, inv12);
+        kd_move_list<T, COUNT, DIRECT>(rec0, mom0, P, rF, mF, F, base + TH + (int)threadIdx.x, total, c1, gl, K, D,
+                                       cg, lnt, a.count, l, &nu, ub, rebuild, ph, inv12);
     }
     __syncthreads();
     if (threadIdx.x == 0) {                     // (no global total: one atomic per workgroup on
@@ -1894,13 +1939,23 @@ hipError_t matter_impl(hrt_ctx *c, const StepArgs &args) {
             // FP32: x-pairs of tiles per workgroup unless one tile per workgroup is asked for
             // (the pair's LDS block would exceed 64 KB in FP64)
             const int kdv = c->variant[K_KD_TILES];
-            if (sizeof(T) == 4 && args.list) {          // mover-list run (variant 5)
+            if (sizeof(T) == 4 && args.list) {          // mover-list run (variants 5, 6, 7)
                 if constexpr (sizeof(T) == 4) {
                     for (int k = 0; k < R; ++k) b.r[k].par = args.par;
                     set_map(b, R, [](const Particles<T> &a) { const int nt = a.n / kTile; return nt * nt * nt / 2; });
                     const dim3 grid(b.map.start[R]);
-                    if (args.count_next) kd_pairs_list_kernel<T, true><<<grid, kPairThreads, 0, c->stream>>>(b);
-                    else kd_pairs_list_kernel<T, false><<<grid, kPairThreads, 0, c->stream>>>(b);
+                    // G per particle from phi: variant 7, and the automatic choice when every
+                    // realisation has at most one particle per 8 mesh nodes (np <= n/2)
+                    bool sparse = true;
+                    for (int k = 0; k < R; ++k) sparse = sparse && (2 << b.r[k].lnp) <= b.r[k].n;
+                    if (kdv == 7 || (kdv == 0 && sparse)) {
+                        if (args.count_next) kd_pairs_list_kernel<T, true, true><<<grid, 256, 0, c->stream>>>(b);
+                        else kd_pairs_list_kernel<T, false, true><<<grid, 256, 0, c->stream>>>(b);
+                    } else if (args.count_next) {
+                        kd_pairs_list_kernel<T, true><<<grid, kPairThreads, 0, c->stream>>>(b);
+                    } else {
+                        kd_pairs_list_kernel<T, false><<<grid, kPairThreads, 0, c->stream>>>(b);
+                    }
                 }
             } else if (sizeof(T) == 4 && (kdv == 0 || kdv == 4)) {
                 if constexpr (sizeof(T) == 4) {

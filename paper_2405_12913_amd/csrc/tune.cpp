@@ -29,11 +29,12 @@ int variants_of(int id) {
         case K_BIN_COUNT: case K_BIN_SCATTER: return 8;
         case K_RAY_STEP: return 6;
         case K_PAINT: return 14;
-        case hrt::K_KD_TILES: return 7;      // run order: 0 automatic, 1 Lagrangian, 2 sorted state,
+        case hrt::K_KD_TILES: return 8;      // run order: 0 automatic, 1 Lagrangian, 2 sorted state,
                                              // 3 sorted state with a pipelined persistent kick-drift,
                                              // 4 sorted state with x-pairs of tiles per workgroup,
                                              // 5 as 4 with the movers in a side list (FP32),
-                                             // 6 as 5 with re-binnings eight times as often
+                                             // 6 as 5 with re-binnings eight times as often,
+                                             // 7 as 5 with G formed per particle from phi
         default: return (id >= 0 && id < K_COUNT) ? 1 : 0;
     }
 }

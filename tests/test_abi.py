@@ -136,7 +136,7 @@ def test_variant_counts():
     counts = {hrt.lib().hrt_kernel_name(k).decode(): hrt.num_variants(k) for k in range(hrt.HRT_NUM_KERNELS)}
     assert counts["matter_kd"] == 16 and counts["ray_step"] == 6 and counts["paint_tiles"] == 14
     assert counts["bin_count"] == 8 and counts["bin_scatter"] == 8
-    assert counts["fft_x_r2c"] == 1 and counts["kd_tiles"] == 7 and counts["state_scatter"] == 1
+    assert counts["fft_x_r2c"] == 1 and counts["kd_tiles"] == 8 and counts["state_scatter"] == 1
     assert hrt.num_variants(hrt.HRT_NUM_KERNELS) == 0
 
 

@@ -90,7 +90,7 @@ def test_batched_equals_plain_and_oracle():
     assert rel_l2(Case.host(states[1][2]), d_o) < 1e-3
 
 
-@pytest.mark.parametrize("order", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5, 6, 7])
 def test_graph_replay_matches_eager(order):
     """Replays of a captured batched sequence (Lagrangian or sorted-state particle order)
     match eager step-by-step calls bit for bit, with eager work between the replays."""

@@ -293,7 +293,7 @@ def test_lcdm256_sorted_run_bit_identical():
     torch.cuda.synchronize()
     ref = sum(st, [])
     for kd, paints in ((2, range(hrt.num_variants("paint_tiles"))), (3, (0, 2)), (4, (0, 2)), (5, (0, 2)),
-                       (6, (0,)), (1, (0,))):
+                       (6, (0,)), (7, (0,)), (1, (0,))):
         sim.set_variant("kd_tiles", kd)
         for pv in paints:
             say(f"  kd_tiles = {kd}, paint_tiles = {pv}")

@@ -126,7 +126,7 @@ def test_run_equals_step_by_step():
     say("case hrt_run vs step by step")
     c = _case()
     base = _run(c, c.sim(), steps=5)
-    for kd, variant in ((2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (1, 0), (1, 8)):
+    for kd, variant in ((2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (7, 0), (1, 0), (1, 8)):
         sim = c.sim()
         sim.set_variant("kd_tiles", kd)
         sim.set_variant("matter_kd", variant)
@@ -213,7 +213,7 @@ def test_paint_variants_with_dense_tiles():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("kd", [0, 3, 4, 5, 6])
+@pytest.mark.parametrize("kd", [0, 3, 4, 5, 6, 7])
 def test_sorted_run_default_threshold_and_dtypes(dtype, kd):
     """The automatic particle order of hrt_run (paint-bin order from 8 steps on), the
     paint-bin order with the persistent pipelined kick-drift, with x-pairs of tiles, and with
@@ -302,7 +302,7 @@ def test_mover_list_run_sorts_and_rebins():
         sim.ray_step(ref[2], ref[3], step)
     torch.cuda.synchronize()
     seen = {}
-    for kd in (5, 6):
+    for kd in (5, 6, 7):
         sim2 = c.sim()
         sim2.set_variant("kd_tiles", kd)
         for rep in range(2):
@@ -316,7 +316,7 @@ def test_mover_list_run_sorts_and_rebins():
             rebuilds, limit = int(last[4]), int(last[5])
             say(f"  kd_tiles {kd} call {rep}: re-binnings {rebuilds} of {count - 1} settles, limit {limit}, "
                 f"list {int(last[1])}, holes {int(last[2])}")
-            assert limit == (64 ** 3 >> (4 if kd == 5 else 6))
+            assert limit == (64 ** 3 >> (6 if kd == 6 else 4))
             seen[kd] = rebuilds
     # variant 6 re-bins on some settles and sorts the list on others
     assert 1 <= seen[6] <= count - 2, seen
