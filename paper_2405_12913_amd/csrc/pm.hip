@@ -539,9 +539,10 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     static_assert((unsigned long long)kPaintChunk << ts < (1ull << 32), "a chunk's pair sums carry");
     using Acc = unsigned long long;             // FP64: node sums; FP32: node-pair sums
     __shared__ Acc acc[TPB][kCopies * kStride];
-    // FP32 tiles of more than one chunk: the node sums of the chunks so far, in the last
-    // copy's region (later chunks add into the other copies), or here with one copy
-    __shared__ unsigned long long sum64[TPB][kWide || kCopies > 1 ? 1 : 512];
+    // FP32 tiles of more than one chunk keep the node sums of the chunks so far in the last
+    // copy's region (later chunks add into the other copies), or, with one copy, in the
+    // tile's own nodes of the mesh (low halves in the delta slot, high halves in the phi
+    // slot: neither holds anything yet)
     __shared__ __align__(16) int rstart[TPB][RS];
     __shared__ __align__(16) int rpre[TPB][RS];
     __shared__ __align__(16) signed char rd[TPB][RS][3];
@@ -571,7 +572,7 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
     }
     const float fscale = ldexpf(1.0f, ts);
     Acc *mine = acc[g] + (kWide ? 0 : (lane % kCopies) * kStride);
-    unsigned long long *const sums = kCopies > 1 ? acc[g] + (kCopies - 1) * kStride : sum64[g];
+    unsigned long long *const sums = acc[g] + (kCopies > 1 ? (kCopies - 1) * kStride : 0);
     const v4<T> *const src = SORTED ? a.rec[cur] : a.sorted;
     const CellGeom<T> cg = geom_of(a);
     const int fixed_bits = a.fixed_bits;
@@ -636,20 +637,41 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
         __syncthreads();
         if constexpr (!kWide) {                 // fold the chunk's sums (x = k & 7: low half)
             const int nc = ch == 0 ? kCopies : (kCopies > 1 ? kCopies - 1 : 1);
-            unsigned long long v[kNodes];
-#pragma unroll
-            for (int i = 0; i < kNodes; ++i) {
-                const int k = lane + i * G;
+            auto fold = [&](int k, unsigned long long v) {     // v: the sum of the chunks before
                 const int sl = pair_slot(k & 7, (k >> 3) & 7, k >> 6);
-                v[i] = ch > 0 ? sums[k] : 0ull;
 #pragma unroll
                 for (int cc = 0; cc < kCopies; ++cc)
                     if (cc < nc)
-                        v[i] += (acc[g][cc * kStride + sl] & 0xffffffffull) + (acc[g][cc * kStride + sl - 1] >> 32);
-            }
-            if (kCopies > 1) __syncthreads();   // the sums overwrite the last copy
+                        v += (acc[g][cc * kStride + sl] & 0xffffffffull) + (acc[g][cc * kStride + sl - 1] >> 32);
+                return v;
+            };
+            if constexpr (kCopies > 1) {        // the sums overwrite the last copy: all reads first
+                unsigned long long v[kNodes];
 #pragma unroll
-            for (int i = 0; i < kNodes; ++i) sums[lane + i * G] = v[i];
+                for (int i = 0; i < kNodes; ++i) v[i] = fold(lane + i * G, ch > 0 ? sums[lane + i * G] : 0ull);
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kNodes; ++i) sums[lane + i * G] = v[i];
+            } else {                            // one copy: node by node, through the mesh
+                const double inv = ldexp(a.inv_scale_rho * a.scale, -ts);
+                const size_t n3 = (size_t)n * n * n;
+                unsigned int *const lo = reinterpret_cast<unsigned int *>(a.delta);
+#pragma unroll 1
+                for (int i = 0; i < kNodes; ++i) {
+                    const int k = lane + i * G;
+                    const size_t at = ((size_t)(tz * kTile + (k >> 6)) * n + (ty * kTile + ((k >> 3) & 7))) * n +
+                                      tx * kTile + (k & 7);
+                    const unsigned long long prev =
+                        ch > 0 ? ((unsigned long long)lo[n3 + at] << 32) | lo[at] : 0ull;
+                    const unsigned long long v = fold(k, prev);
+                    if (ch + 1 < nch) {
+                        lo[at] = (unsigned int)v;
+                        lo[n3 + at] = (unsigned int)(v >> 32);
+                    } else {
+                        store_delta<T>(a, tx, ty, tz, k, (double)v, inv);
+                    }
+                }
+            }
             if (ch + 1 < nch) {                 // clear the copies still added to
                 if (kCopies == 1) __syncthreads();
                 for (int k = lane; k < (kCopies > 1 ? kCopies - 1 : 1) * kStride; k += G) acc[g][k] = 0ull;
@@ -658,7 +680,7 @@ __device__ __forceinline__ void paint_tiles_body(const PartBatch<T> &b, int cur,
             }
         }
     }
-    if constexpr (!kWide) {
+    if constexpr (!kWide && kCopies > 1) {
         // delta = sum / (2^ts rho_bar) - 1; inv_scale_rho = 1 / (2^fixed_bits rho_bar)
         const double inv = ldexp(a.inv_scale_rho * a.scale, -ts);
 #pragma unroll
