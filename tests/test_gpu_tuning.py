@@ -257,10 +257,11 @@ def test_sorted_run_with_empty_and_dense_tiles():
     blob = r.integers(0, 2, size=len(q))
     x = centres[blob] + r.normal(scale=1.5, size=(len(q), 3))
     c.s = (x - q).astype(np.float32).astype(np.float64)
-    # most tiles empty, some tiles over 1024 particles
+    # most tiles empty, some tiles over two FP32 paint chunks of 3072 entries (sums carried
+    # from chunk to chunk in every paint shape)
     cells = np.floor(np.mod(x, c.box) / (c.box / c.n)).astype(int) // 8
     counts = np.bincount((cells[:, 2] * 8 + cells[:, 1]) * 8 + cells[:, 0], minlength=512)
-    assert (counts == 0).sum() > 400 and counts.max() > 1024
+    assert (counts == 0).sum() > 400 and counts.max() > 2 * 3072
     first, count = 0, 9
     ref = [c.dev(c.s), c.dev(c.p), c.dev(c.dth), c.dev(c.pr)]
     sim = c.sim()
