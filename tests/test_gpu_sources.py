@@ -163,6 +163,35 @@ def test_batched_step_vjp_equals_single_realisations():
             assert rel_l2(Case.host(g), x) < 1e-8
 
 
+def test_batched_step_vjp_from_force_slot():
+    """A batched context with a force slot: hrt_force_save after pm_step keeps both
+    realisations' forces, and hrt_step_vjp_saved gives hrt_step_vjp's bits for each."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    say("case batched step vjp from a force slot")
+    cases = [_vjp_case(32, 7), _vjp_case(16, 8)]
+    cots = [_cot(c, 40 + k) for k, c in enumerate(cases)]
+    step = 2
+    kw = [dict(_kw(c), force_slots=1) for c in cases]
+    batch = hrt.Simulation(configs=kw)
+    s = [c.dev(c.s) for c in cases]
+    p = [c.dev(c.p) for c in cases]
+    batch.pm_step(s, p, step)
+    batch.force_save(0)
+    saved = [[c.dev(x) for x in cot] for c, cot in zip(cases, cots)]
+    batch.step_vjp([c.dev(c.s) for c in cases], [c.dev(c.dth) for c in cases], [b[0] for b in saved],
+                   [b[1] for b in saved], [b[2] for b in saved], [b[3] for b in saved], step, part="saved",
+                   slot=0)
+    ref = [[c.dev(x) for x in cot] for c, cot in zip(cases, cots)]
+    batch.step_vjp([c.dev(c.s) for c in cases], [c.dev(c.dth) for c in cases], [b[0] for b in ref],
+                   [b[1] for b in ref], [b[2] for b in ref], [b[3] for b in ref], step)
+    torch.cuda.synchronize()
+    for k in range(len(cases)):
+        for x, y in zip(saved[k], ref[k]):
+            for u, v in zip(x, y):
+                assert torch.equal(u, v), k
+
+
 def test_split_vjps_compose_to_the_step_vjp():
     import torch
     say("case pm_step_vjp then ray_step_vjp")
