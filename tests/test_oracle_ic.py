@@ -6,8 +6,10 @@ oracle follows the standard one (see oracle.ic). Pins:
 * 2LPT: a single plane wave has zero second-order displacement, two orthogonal waves
   have a closed-form second-order displacement;
 * Einstein-de Sitter growth: s = a s1 - (3/7) a^2 s2 and p = a^{1/2} (a s1 - (6/7) a^2 s2).
-The Eisenstein-Hu no-wiggle transfer function itself is parity unpinned beyond its
-large-scale limit T -> 1 and the sigma_8 normalisation."""
+The Eisenstein-Hu no-wiggle transfer function is pinned loosely: its large-scale limit
+T -> 1, the sigma_8 normalisation, and, without baryons, agreement within 8 % with the
+independent Bardeen-Bond-Kaiser-Szalay (1986) fit of the same CDM transfer function (the two
+fits differ by at most ~5.5 %). Its baryon suppression is parity unpinned."""
 import math
 
 import numpy as np
@@ -28,6 +30,28 @@ def test_transfer_large_scale_limit_and_sigma8():
     w = 3 * (np.sin(x) - x * np.cos(x)) / x ** 3
     s2 = np.trapezoid(k ** 3 * pk(k) * w * w, lnk) / (2 * math.pi ** 2)
     assert math.sqrt(s2) == pytest.approx(0.8, rel=1e-6)
+
+
+def _bbks(k, gamma):
+    """Bardeen, Bond, Kaiser & Szalay (1986) CDM transfer function, q = k / Gamma (k in h/Mpc)."""
+    q = np.asarray(k, float) / gamma
+    return (np.log(1.0 + 2.34 * q) / (2.34 * q)
+            * (1.0 + 3.89 * q + (16.1 * q) ** 2 + (5.46 * q) ** 3 + (6.71 * q) ** 4) ** -0.25)
+
+
+@pytest.mark.parametrize("om,h", [(0.3, 0.7), (0.25, 0.7), (0.3, 0.6), (1.0, 0.5)])
+def test_transfer_without_baryons_matches_bbks(om, h):
+    """With a vanishing baryon fraction the no-wiggle shape is the CDM transfer function of
+    shape parameter Gamma = Omega_m h: it must follow the BBKS fit to within 8 % from 10^-3 to
+    10 h/Mpc. Catches a wrong power of h or of the CMB temperature in q, a coefficient off by
+    a power of ten, a dropped logarithm, or k taken in 1/Mpc instead of h/Mpc."""
+    k = np.logspace(-3, 1, 200)
+    t = ic.eh_nowiggle_transfer(k, om, 1e-9, h)
+    ratio = t / _bbks(k, om * h)
+    assert np.max(np.abs(ratio - 1.0)) < 0.08
+    # and the planted mistake (k in 1/Mpc) fails it
+    wrong = ic.eh_nowiggle_transfer(k * h, om, 1e-9, h)
+    assert np.max(np.abs(wrong / _bbks(k, om * h) - 1.0)) > 0.08
 
 
 def test_linear_field_has_requested_power():
