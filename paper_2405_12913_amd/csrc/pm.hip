@@ -925,6 +925,25 @@ __device__ __forceinline__ void kd_move(v4<T> *recs, T *mom, size_t P, int j, in
 }
 
 
+// A phi block of NQ quadruples into LDS by TH lanes: every lane requests all of its
+// quadruples before it stores the first, so the block costs one memory latency rather than
+// one per pass of the workgroup over it (a store waits for its own load, and the wait
+// covers every older request, the particle loads included).
+template <typename T, int TH, int NQ, typename Off>
+__device__ __forceinline__ void phi_block_load(v4<T> *ph4, const T *phi, Off off) {
+    constexpr int R = (NQ + TH - 1) / TH;
+    v4<T> v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        v[j] = *reinterpret_cast<const v4<T> *>(phi + off(min((int)threadIdx.x + j * TH, NQ - 1)));
+#pragma unroll
+    for (int j = 0; j < R; ++j)     // all requested before any store (else each load would sink
+        asm volatile("" : "+v"(v[j].x), "+v"(v[j].y), "+v"(v[j].z), "+v"(v[j].w));   // into its store's branch)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if ((int)threadIdx.x + j * TH < NQ) ph4[threadIdx.x + j * TH] = v[j];
+}
+
 // One workgroup per tile (logical block blk).
 template <typename T, bool COUNT>
 __global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int cur) {
@@ -947,8 +966,7 @@ __global__ __launch_bounds__(kThreads) void kd_tiles_kernel(PartBatch<T> b, int 
     KdItem<T> cur0, cur1;
     kd_fetch<T>(recs, mom, P, j0 + (int)threadIdx.x, j1, cur0);
     kd_fetch<T>(recs, mom, P, j0 + kThreads + (int)threadIdx.x, j1, cur1);
-    for (int e = threadIdx.x; e < kPhiQuads; e += kThreads)
-        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset(e, tx, ty, tz, n));
+    phi_block_load<T, kThreads, kPhiQuads>(ph4, a.phi, [&](int e) { return phi_quad_offset(e, tx, ty, tz, n); });
     __syncthreads();
     tile_gradient<T>(ph4, gl, a.inv12cell);
     __syncthreads();
@@ -979,6 +997,24 @@ __device__ __forceinline__ size_t phi_quad_offset2(int e, int tx0, int ty, int t
     const int gx = (tx0 * kTile - 4 + 4 * q) & m;
     const int gy = (ty * kTile - 2 + ly) & m, gz = (tz * kTile - 2 + lz) & m;
     return ((size_t)gz * n + gy) * n + gx;
+}
+
+// The pair's phi block straight into LDS (global_load_lds, 16 bytes a lane: no registers
+// and no LDS stores): each request of a wave fills 64 consecutive quadruples, so the block
+// is held as 16 rows of 64 (the lanes past its 1014 quadruples repeat the last one into the
+// padding). The caller waits for its requests (vmcnt) and then for the workgroup's (barrier).
+constexpr int kPhiPad2 = 1024;
+template <int TH>
+__device__ __forceinline__ void phi_block_to_lds(v4<float> *ph4, const float *phi, int tx, int ty, int tz, int n) {
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = __lane_id();
+#pragma unroll
+    for (int j = 0; j < kPhiPad2 / TH; ++j) {
+        const int row = j * (TH / 64) + w;
+        const int e = min(row * 64 + lane, kPhiQuads2 - 1);
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(phi + phi_quad_offset2(e, tx, ty, tz, n)),
+            (__attribute__((address_space(3))) void *)(ph4 + row * 64), 16, 0, 0);
+    }
 }
 
 // G at the pair's 17 x 9 x 9 nodes: a lane takes four nodes along x (quadruple q = 1..5 of a
@@ -1013,7 +1049,7 @@ __device__ __forceinline__ void pair_gradient(const v4<T> *ph4, v4<T> *gl, T inv
 
 template <typename T, bool COUNT>
 __global__ __launch_bounds__(kPairThreads) void kd_pairs_kernel(PartBatch<T> b, int cur) {
-    __shared__ v4<T> ph4[kPhiQuads2];
+    __shared__ v4<T> ph4[kPhiPad2];
     __shared__ v4<T> gl[kGX2 * kGN * kGN];
     const int blk = logical_block(b.xcd);
     const int rr = real_of(b.map, blk);
@@ -1029,9 +1065,9 @@ __global__ __launch_bounds__(kPairThreads) void kd_pairs_kernel(PartBatch<T> b, 
     KdItem<T> cur0, cur1;
     kd_fetch<T>(recs, mom, P, j0 + (int)threadIdx.x, j1, cur0);
     kd_fetch<T>(recs, mom, P, j0 + kPairThreads + (int)threadIdx.x, j1, cur1);
-    for (int e = threadIdx.x; e < kPhiQuads2; e += kPairThreads)
-        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset2(e, tx, ty, tz, n));
-    __syncthreads();
+    phi_block_to_lds<kPairThreads>(ph4, a.phi, tx, ty, tz, n);
+    __builtin_amdgcn_s_waitcnt(0);              // this wave's requests are in LDS
+    __syncthreads();                            // ... and every wave's
     pair_gradient<T>(ph4, gl, a.inv12cell);
     __syncthreads();
     const T K = a.K, D = a.D;
@@ -1180,7 +1216,7 @@ __device__ __forceinline__ void kd_fetch_list(const v4<T> *rec0, const T *mom0, 
 template <typename T, bool COUNT, bool DIRECT = false>
 __global__ __launch_bounds__(DIRECT ? 256 : kPairThreads) void kd_pairs_list_kernel(PartBatch<T> b) {
     constexpr int TH = DIRECT ? 256 : kPairThreads;
-    __shared__ v4<T> ph4[kPhiQuads2];
+    __shared__ v4<T> ph4[kPhiPad2];
     __shared__ v4<T> gl[DIRECT ? 1 : kGX2 * kGN * kGN];
     __shared__ unsigned int nu;                 // entries this workgroup appended to U
     const int blk = logical_block(b.xcd);
@@ -1209,9 +1245,9 @@ __global__ __launch_bounds__(DIRECT ? 256 : kPairThreads) void kd_pairs_list_ker
     KdItem<T> c0, c1;
     kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, (int)threadIdx.x, total, c0);
     kd_fetch_list<T>(rec0, mom0, P, rF, mF, rS, mS, F, TH + (int)threadIdx.x, total, c1);
-    for (int e = threadIdx.x; e < kPhiQuads2; e += TH)
-        ph4[e] = *reinterpret_cast<const v4<T> *>(a.phi + phi_quad_offset2(e, tx, ty, tz, n));
-    __syncthreads();
+    phi_block_to_lds<TH>(ph4, a.phi, tx, ty, tz, n);
+    __builtin_amdgcn_s_waitcnt(0);              // this wave's requests are in LDS
+    __syncthreads();                            // ... and every wave's
     if constexpr (!DIRECT) {
         pair_gradient<T>(ph4, gl, a.inv12cell);
         __syncthreads();
