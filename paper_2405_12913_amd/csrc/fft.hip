@@ -133,9 +133,15 @@ __device__ __forceinline__ void butterfly(c2<T> *v, int j, const c2<T> *__restri
     dft<T, R, INV>(v, tw, twmul * (L / R));
 }
 
+// Position of element i within a line in LDS: one padding element after every 2^SK
+// (SK = 0: none), so that the strided writes of the Stockham stages (lane j writing
+// j R + r, or groups of Ns consecutive elements Ns R apart) spread over more LDS banks.
+template <int SK>
+__host__ __device__ constexpr int skw(int i) { return SK ? i + (i >> SK) : i; }
+
 // One Stockham stage over LINES lines of length L in LDS (line stride LS), then the next
 // (up to the last stage, or up to but not including it when STOP_BEFORE_LAST).
-template <typename T, int L, int LINES, bool INV, int Ns, bool STOP_BEFORE_LAST = false>
+template <typename T, int L, int LINES, bool INV, int Ns, bool STOP_BEFORE_LAST = false, int SK = 0>
 __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
                                           int twmul) {
     if constexpr (Ns < L && !(STOP_BEFORE_LAST && Ns == last_span<L, LINES>())) {
@@ -150,7 +156,7 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__res
                 const int line = b / (L / R), j = b % (L / R);
                 const c2<T> *src = buf + line * LS;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[k][r] = src[j + r * (L / R)];
+                for (int r = 0; r < R; ++r) v[k][r] = src[skw<SK>(j + r * (L / R))];
                 butterfly<T, L, R, INV, Ns>(v[k], j, tw, twmul);
             }
         }
@@ -161,13 +167,14 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int LS, const c2<T> *__res
             if (b < NB) {
                 const int line = b / (L / R), j = b % (L / R);
                 const int kk = j % Ns;
-                c2<T> *dst = buf + line * LS + (j / Ns) * Ns * R + kk;
+                c2<T> *dst = buf + line * LS;
+                const int o = (j / Ns) * Ns * R + kk;
 #pragma unroll
-                for (int r = 0; r < R; ++r) dst[r * Ns] = v[k][r];
+                for (int r = 0; r < R; ++r) dst[skw<SK>(o + r * Ns)] = v[k][r];
             }
         }
         __syncthreads();
-        fft_stage<T, L, LINES, INV, Ns * R, STOP_BEFORE_LAST>(buf, LS, tw, twmul);
+        fft_stage<T, L, LINES, INV, Ns * R, STOP_BEFORE_LAST, SK>(buf, LS, tw, twmul);
     }
 }
 
@@ -190,7 +197,7 @@ __device__ __forceinline__ void global_bfly(int b, int &line, int &j) {
 // block's line `line` (never called for lines with !valid(line)); the outputs go to LDS.
 // The loads are issued first, then the block synchronises (which also makes the twiddles
 // the caller staged visible), then the butterflies run.
-template <typename T, int L, int LINES, bool INV, bool LINE_FAST, class Ld, class Valid>
+template <typename T, int L, int LINES, bool INV, bool LINE_FAST, int SK = 0, class Ld, class Valid>
 __device__ __forceinline__ void first_stage_global(c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
                                                    int twmul, Ld ld, Valid valid) {
     constexpr int R = radix_at<L, LINES>(1);
@@ -215,9 +222,9 @@ __device__ __forceinline__ void first_stage_global(c2<T> *buf, int LS, const c2<
         global_bfly<L, LINES, R, LINE_FAST>(b, line, j);
         if (b < NB && valid(line)) {
             butterfly<T, L, R, INV, 1>(v[k], j, tw, twmul);
-            c2<T> *dst = buf + line * LS + j * R;
+            c2<T> *dst = buf + line * LS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r] = v[k][r];
+            for (int r = 0; r < R; ++r) dst[skw<SK>(j * R + r)] = v[k][r];
         }
     }
     __syncthreads();
@@ -226,7 +233,7 @@ __device__ __forceinline__ void first_stage_global(c2<T> *buf, int LS, const c2<
 // Last stage, inputs from LDS, outputs handed to st(line, m, value) in natural order m
 // (never for lines with !valid(line)). With SYNC the block synchronises between reading
 // and handing out (for a st that writes the same LDS buffer).
-template <typename T, int L, int LINES, bool INV, bool LINE_FAST, bool SYNC, class St, class Valid>
+template <typename T, int L, int LINES, bool INV, bool LINE_FAST, bool SYNC, int SK = 0, class St, class Valid>
 __device__ __forceinline__ void last_stage_out(const c2<T> *buf, int LS, const c2<T> *__restrict__ tw,
                                                int twmul, St st, Valid valid) {
     constexpr int Ns = last_span<L, LINES>();
@@ -243,7 +250,7 @@ __device__ __forceinline__ void last_stage_out(const c2<T> *buf, int LS, const c
         if (b < NB && valid(line)) {
             const c2<T> *src = buf + line * LS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[k][r] = src[j + r * (L / R)];
+            for (int r = 0; r < R; ++r) v[k][r] = src[skw<SK>(j + r * (L / R))];
             butterfly<T, L, R, INV, Ns>(v[k], j, tw, twmul);
         }
     }
@@ -290,6 +297,11 @@ struct Cfg {
     // the rows (128-byte FP32 segments, 64 KB of LDS) measured faster than more blocks
     static constexpr int XROWS_INV = N >= 1024 ? 2 * XROWS : XROWS;
     static constexpr int YLINES = EY / N < 1 ? 1 : EY / N;
+    // LDS padding of the lines (skw): one element per 32 in FP32 (measured on gfx950: z pass
+    // 38.5 -> 34.6 us, x_c2r 27.2 -> 25.1 us at 256^3; every pass 1-5 % faster at 1024^3);
+    // x_r2c only from N = 512 on (at 256^3 its rows measured 30.4 us unpadded, 32.2 padded)
+    static constexpr int SK = sizeof(T) == 4 && N >= 64 ? 5 : 0;
+    static constexpr int SKX = sizeof(T) == 4 && N >= 512 ? 5 : 0;
     static constexpr int ZLINES = EZ / N < 1 ? 1 : EZ / N;
 };
 
@@ -309,7 +321,7 @@ struct FftBatch {
 // than the mesh the table was built for.
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
-    constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, LS = L + 1;
+    constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS, SK = Cfg<T, N>::SKX, LS = skw<SK>(L) + 1;
     __shared__ c2<T> buf[ROWS * LS];
     __shared__ c2<T> tw[N];
     // XCD-grouped block order only when a block's transposed segments are under 128 bytes
@@ -322,45 +334,45 @@ __global__ __launch_bounds__(kThreads) void x_r2c_kernel(FftBatch<T> fb) {
     auto ld = [&](int rr, int m) { return reinterpret_cast<const c2<T> *>(in + (size_t)(row0 + rr) * N)[m]; };
     if constexpr (last_span<L, ROWS>() > 1) {
         // the first stage reads the packed rows from HBM directly, the rest run in LDS
-        first_stage_global<T, L, ROWS, false, false>(buf, LS, tw, N / L, ld, [](int) { return true; });
-        fft_stage<T, L, ROWS, false, radix_at<L, ROWS>(1)>(buf, LS, tw, N / L);
+        first_stage_global<T, L, ROWS, false, false, SK>(buf, LS, tw, N / L, ld, [](int) { return true; });
+        fft_stage<T, L, ROWS, false, radix_at<L, ROWS>(1), false, SK>(buf, LS, tw, N / L);
     } else {                                    // one stage (N = 16): staged through LDS
-        for (int e = threadIdx.x; e < ROWS * L; e += kThreads) buf[(e / L) * LS + e % L] = ld(e / L, e % L);
+        for (int e = threadIdx.x; e < ROWS * L; e += kThreads) buf[(e / L) * LS + skw<SK>(e % L)] = ld(e / L, e % L);
         __syncthreads();
-        fft_stage<T, L, ROWS, false, 1>(buf, LS, tw, N / L);
+        fft_stage<T, L, ROWS, false, 1, false, SK>(buf, LS, tw, N / L);
     }
     // split step: X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) W_N^k (Z[k] - conj Z[L-k]),
     // each thread owns the pair (k, L-k); X[L] (Nyquist) comes from Z[0].
     for (int e = threadIdx.x; e < ROWS * (L / 2 + 1); e += kThreads) {
         const int rr = e / (L / 2 + 1), k = e % (L / 2 + 1);
         c2<T> *line = buf + rr * LS;
-        const c2<T> zk = line[k];
-        const c2<T> zp = line[k == 0 ? 0 : L - k];
+        const c2<T> zk = line[skw<SK>(k)];
+        const c2<T> zp = line[skw<SK>(k == 0 ? 0 : L - k)];
         const c2<T> w = tw[k];
         // A = zk + conj(zp), B = zk - conj(zp); X[k] = A/2 - (i/2) w B
         const c2<T> A{zk.x + zp.x, zk.y - zp.y}, B{zk.x - zp.x, zk.y + zp.y};
         const c2<T> wB = cmul<T>(w, B);
-        line[k] = c2<T>{T(0.5) * (A.x + wB.y), T(0.5) * (A.y - wB.x)};
+        line[skw<SK>(k)] = c2<T>{T(0.5) * (A.x + wB.y), T(0.5) * (A.y - wB.x)};
         if (k == 0) {
-            line[L] = c2<T>{T(0.5) * (A.x - wB.y), T(0.5) * (A.y + wB.x)};   // W_N^L = -1
+            line[skw<SK>(L)] = c2<T>{T(0.5) * (A.x - wB.y), T(0.5) * (A.y + wB.x)};   // W_N^L = -1
         } else if (k != L - k) {
             // X[L-k] = A'/2 - (i/2) W_N^{L-k} B', A' = conj(A), B' = -conj(B), W_N^{L-k} = -conj(w)
             const c2<T> Ap{A.x, -A.y}, Bp{-B.x, B.y}, wp{-w.x, w.y};
             const c2<T> wBp = cmul<T>(wp, Bp);
-            line[L - k] = c2<T>{T(0.5) * (Ap.x + wBp.y), T(0.5) * (Ap.y - wBp.x)};
+            line[skw<SK>(L - k)] = c2<T>{T(0.5) * (Ap.x + wBp.y), T(0.5) * (Ap.y - wBp.x)};
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ROWS * (L + 1); e += kThreads) {
         const int kx = e / ROWS, rr = e % ROWS;
         const int row = row0 + rr, z = row / N, y = row % N;
-        out[((size_t)kx * N + z) * N + y] = buf[rr * LS + kx];
+        out[((size_t)kx * N + z) * N + y] = buf[rr * LS + skw<SK>(kx)];
     }
 }
 
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
-    constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS_INV, LS = L + 1;
+    constexpr int L = N / 2, ROWS = Cfg<T, N>::XROWS_INV, SK = Cfg<T, N>::SK, LS = skw<SK>(L) + 1;
     __shared__ c2<T> buf[ROWS * LS];
     __shared__ c2<T> tw[N];
     // XCD-grouped block order only when a block's transposed segments are under 128 bytes
@@ -400,12 +412,12 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
             const c2<T> wc{w.x, -w.y};
             const c2<T> A{xk[q].x + xp[q].x, xk[q].y - xp[q].y}, B{xk[q].x - xp[q].x, xk[q].y + xp[q].y};
             const c2<T> wB = cmul<T>(wc, B);
-            line[k] = c2<T>{A.x - wB.y, A.y + wB.x};
+            line[skw<SK>(k)] = c2<T>{A.x - wB.y, A.y + wB.x};
             if (k != 0 && k != L - k) {
                 // Z[L-k] = conj(A) + i (-w) (-conj(B))
                 const c2<T> Ap{A.x, -A.y}, Bp{-B.x, B.y}, wp{-w.x, -w.y};
                 const c2<T> wBp = cmul<T>(wp, Bp);
-                line[L - k] = c2<T>{Ap.x - wBp.y, Ap.y + wBp.x};
+                line[skw<SK>(L - k)] = c2<T>{Ap.x - wBp.y, Ap.y + wBp.x};
             }
         }
     }
@@ -413,11 +425,11 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
     auto st = [&](int rr, int m, const c2<T> &v) { reinterpret_cast<c2<T> *>(out + (size_t)(row0 + rr) * N)[m] = v; };
     if constexpr (last_span<L, ROWS>() > 1) {
         // all stages but the last in LDS; the last writes the rows of phi to HBM directly
-        fft_stage<T, L, ROWS, true, 1, true>(buf, LS, tw, N / L);
-        last_stage_out<T, L, ROWS, true, false, false>(buf, LS, tw, N / L, st, [](int) { return true; });
+        fft_stage<T, L, ROWS, true, 1, true, SK>(buf, LS, tw, N / L);
+        last_stage_out<T, L, ROWS, true, false, false, SK>(buf, LS, tw, N / L, st, [](int) { return true; });
     } else {                                    // one stage (N = 16): staged through LDS
-        fft_stage<T, L, ROWS, true, 1>(buf, LS, tw, N / L);
-        for (int e = threadIdx.x; e < ROWS * L; e += kThreads) st(e / L, e % L, buf[(e / L) * LS + e % L]);
+        fft_stage<T, L, ROWS, true, 1, false, SK>(buf, LS, tw, N / L);
+        for (int e = threadIdx.x; e < ROWS * L; e += kThreads) st(e / L, e % L, buf[(e / L) * LS + skw<SK>(e % L)]);
     }
 }
 
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(kThreads) void x_c2r_kernel(FftBatch<T> fb) {
 // LDS); the stages in between work in LDS.
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
-    constexpr int LINES = Cfg<T, N>::YLINES, LS = N + 1;
+    constexpr int LINES = Cfg<T, N>::YLINES, SK = Cfg<T, N>::SK, LS = skw<SK>(N) + 1;
     constexpr int TOTAL = (N / 2 + 1) * N;
     static_assert(last_span<N, LINES>() > 1, "at least two stages");
     __shared__ c2<T> buf[LINES * LS];
@@ -436,10 +448,10 @@ __global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
     const int l0 = (blockIdx.x % fb.bpr) * LINES;
     stage_twiddles<T, N>(tw, fb.tw[r], fb.tws);
     auto valid = [&](int li) { return l0 + li < TOTAL; };
-    first_stage_global<T, N, LINES, INV, false>(
+    first_stage_global<T, N, LINES, INV, false, SK>(
         buf, LS, tw, 1, [&](int li, int m) { return data[(size_t)(l0 + li) * N + m]; }, valid);
-    fft_stage<T, N, LINES, INV, radix_at<N, LINES>(1), true>(buf, LS, tw, 1);
-    last_stage_out<T, N, LINES, INV, false, false>(
+    fft_stage<T, N, LINES, INV, radix_at<N, LINES>(1), true, SK>(buf, LS, tw, 1);
+    last_stage_out<T, N, LINES, INV, false, false, SK>(
         buf, LS, tw, 1, [&](int li, int m, const c2<T> &v) { data[(size_t)(l0 + li) * N + m] = v; },
         valid);
 }
@@ -452,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void y_lines_kernel(FftBatch<T> fb) {
 // Stockham accesses over the LDS banks.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
-    constexpr int LINES = Cfg<T, N>::ZLINES, LS = N + 9;
+    constexpr int LINES = Cfg<T, N>::ZLINES, SK = Cfg<T, N>::SK, LS = SK ? skw<SK>(N) + 1 : N + 9;
     constexpr int TOTAL = (N / 2 + 1) * N;
     static_assert(last_span<N, LINES>() > 1, "at least two stages");
     __shared__ c2<T> buf[LINES * LS];
@@ -471,26 +483,26 @@ __global__ __launch_bounds__(kThreads) void z_lines_kernel(FftBatch<T> fb) {
     };
     auto valid = [&](int li) { return l0 + li < TOTAL; };
     auto store = [&](int li, int z, const c2<T> &v) { data[at(li, z)] = v; };
-    first_stage_global<T, N, LINES, MODE == 1, true>(
+    first_stage_global<T, N, LINES, MODE == 1, true, SK>(
         buf, LS, tw, 1, [&](int li, int z) { return data[at(li, z)]; }, valid);
-    fft_stage<T, N, LINES, MODE == 1, radix_at<N, LINES>(1), true>(buf, LS, tw, 1);
+    fft_stage<T, N, LINES, MODE == 1, radix_at<N, LINES>(1), true, SK>(buf, LS, tw, 1);
     if constexpr (MODE == 2) {
         const double kf2 = fb.kf2[r], inv_n3 = 1.0 / ((double)N * N * N);
-        last_stage_out<T, N, LINES, false, false, true>(
+        last_stage_out<T, N, LINES, false, false, true, SK>(
             buf, LS, tw, 1,
             [&](int li, int kz, const c2<T> &v) {
                 const int l = l0 + li, kx = l / N, ky = l % N;
                 const int fy = ky <= N / 2 ? ky : ky - N, fz = kz <= N / 2 ? kz : kz - N;
                 const double k2 = kf2 * (double)(kx * kx + fy * fy + fz * fz);
                 const T g = k2 > 0.0 ? (T)(-inv_n3 / k2) : T(0);
-                buf[li * LS + kz] = c2<T>{v.x * g, v.y * g};
+                buf[li * LS + skw<SK>(kz)] = c2<T>{v.x * g, v.y * g};
             },
             valid);
         __syncthreads();
-        fft_stage<T, N, LINES, true, 1, true>(buf, LS, tw, 1);
-        last_stage_out<T, N, LINES, true, true, false>(buf, LS, tw, 1, store, valid);
+        fft_stage<T, N, LINES, true, 1, true, SK>(buf, LS, tw, 1);
+        last_stage_out<T, N, LINES, true, true, false, SK>(buf, LS, tw, 1, store, valid);
     } else {
-        last_stage_out<T, N, LINES, MODE == 1, true, false>(buf, LS, tw, 1, store, valid);
+        last_stage_out<T, N, LINES, MODE == 1, true, false, SK>(buf, LS, tw, 1, store, valid);
     }
 }
 
