@@ -137,6 +137,29 @@ def test_large_config_properties():
     torch.cuda.synchronize()
 
 
+def test_mesh512_plane_waves():
+    """The FFT passes at 512^3 (their own launch shapes and LDS layout: 16-row x passes with
+    padded rows, 2-line y and 8-line z blocks), 256^3 particles: the lattice paint and the
+    one-axis fields against the oracle's reduced potential and gradient, each axis."""
+    import torch
+    from paper_2405_12913_amd import hrt
+    cfg = synth.large1024()
+    n, np_, box, M = 512, 256, cfg["box"] / 2, 256
+    say(f"case mesh512: mesh {n}^3, {np_}^3 particles")
+    sim = hrt.Simulation(mesh_n=n, box=box, ptcl_n=np_, n_steps=len(cfg["sched"]) - 1, sched=cfg["sched"],
+                         ray_nx=M, ray_ny=M, fov_x=cfg["fov"], fov_y=cfg["fov"], observer=(box / 2, box / 2, 0.0),
+                         omega_m=cfg["omega_m"], dtype="f32")
+    P = np_ ** 3
+    sim.pm_force([torch.zeros(P, device="cuda") for _ in range(3)], 0)
+    delta = sim.mesh(hrt.HRT_MESH_DELTA)
+    assert bool((delta[0::2, 0::2, 0::2] == 7.0).all())
+    assert float(delta.double().sum()) == 7.0 * P - (n ** 3 - P)
+    assert float(sim.mesh(hrt.HRT_MESH_GRAD)[..., :3].abs().max()) < 1e-3
+    _plane_waves(sim, n, np_, box)
+    torch.cuda.synchronize()
+    sim.close()
+
+
 def _potential_1d(delta, box):
     """phi with phi'' = delta on a periodic line: the oracle's Green's function -1/k^2
     (k = 0 mode zero) for a field that varies along one axis only."""
@@ -168,7 +191,7 @@ def _lattice_line_density(s_line, n, box):
 
 
 def _plane_waves(sim, n, np_, box):
-    """A field that varies along one axis only, at the full 1024^3 size, against the
+    """A field that varies along one axis only, at the mesh's full size, against the
     oracle's potential and gradient of that field (reduced to the one axis: the reduction is
     checked against the oracle's 3D solve at 32^3 first). Each axis in turn: a Zel'dovich-like
     displacement of amplitude 2.5 cells (no crossing) along it, half a cell across it."""
