@@ -300,12 +300,25 @@ def large_bench(hrt, torch, dev, tune=True):
         assert torch.isfinite(k).all(), f"kappa at z = {z} not finite"
         kap[f"z={z:g}"] = {"mean": float(k.mean()), "rms": float(k.std()), "min": float(k.min()),
                            "max": float(k.max())}
+    # per-kernel HIP events over the first 4 steps of the schedule (after the timed run): the
+    # five FFT passes of one Poisson solve at 1024^3, for the rocFFT cross-check
+    for a, b in zip(s + p, s0 + p0):
+        a.copy_(b)
+    for t in dth + pr:
+        t.zero_()
+    sim.profile_enable(True)
+    sim.run(s, p, dth, pr, 0, 4)
+    prof = sim.profile_read()
+    sim.profile_enable(False)
+    fft_ms = sum(prof[k][0] / max(prof[k][1], 1) for k in ("fft_x_r2c", "fft_y_fwd", "fft_z_poisson", "fft_y_inv",
+                                                           "fft_x_c2r") if k in prof)
     sim.close()
     return {"workload": "large1024: 512^3 particles on a 1024^3 mesh, box 1000 Mpc/h, 2048^2 rays "
                         f"over 10 deg, the whole {N}-step schedule a = 1 -> 1/3 timed, evolved initial "
                         "conditions as lcdm256, kappa at source planes z = 1 and z = 2",
             "ray_steps_per_s": nr / (ms * 1e-3), "ms_per_step": round(ms, 3),
-            "timed_schedule_steps": f"0..{N - 1}", "kappa": kap, "launch_variants": tuned}
+            "timed_schedule_steps": f"0..{N - 1}", "kappa": kap, "launch_variants": tuned,
+            "poisson_fft_ms": round(fft_ms, 4)}
 
 
 def ray_options_bench(hrt, torch, dev, cfg, s_init, p_init, tuned, steps):
@@ -687,6 +700,8 @@ def main():
         ours = sum(kernels[k]["avg_ms"] for k in ("fft_x_r2c", "fft_y_fwd", "fft_z_poisson", "fft_y_inv",
                                                    "fft_x_c2r") if k in kernels)
         fb["256^3"]["hand_written_poisson_ms"] = round(ours, 4)
+        if "large" in out:
+            fb["1024^3"]["hand_written_poisson_ms"] = out["large"]["poisson_fft_ms"]
         out["fft_baseline"] = fb
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host (lcdm256, one step)", file=sys.stderr, flush=True)
